@@ -1,0 +1,163 @@
+/*
+ * FP64 CPU oracle for the point-cloud hologram sum.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library.  It shares no code,
+ * header, table or constant with the GPU library, and the GPU library never
+ * calls it.
+ *
+ * What it computes (Section 2.1, "Direct calculation"):
+ *
+ *   Eq. (2), the Fresnel approximation of the spherical wave of N point
+ *   sources,  O(x_h, y_h) = sum_j A_j exp( i (2 pi / lambda)
+ *                            (z_j + ((x_h - x_j)^2 + (y_h - y_j)^2) / (2 z_j)) ),
+ *   read with the imaginary unit in the exponent (the printed equation drops
+ *   it), and Eq. (5), the amplitude hologram I = sum_j A_j cos(phase_j + phi_r)
+ *   with the constant 2 A_r dropped.  The hot path takes phi_r = 0 and drops
+ *   the per-point constant 2 pi z_j / lambda (as the paper's own programs do,
+ *   List 1 to List 3), which leaves
+ *
+ *     I(x_h, y_h) = sum_j A_j cos( pi / (lambda z_j) ((x_h - x_j)^2 + (y_h - y_j)^2) ).
+ *
+ *   cgh_oracle_fresnel returns that real part and, on request, the imaginary
+ *   part sum_j A_j sin(...) of the same complex sum, which Eq. (3) needs for a
+ *   phase-only hologram.
+ *
+ * Reading of the coordinates: pixel (ix, iy) of a W x H hologram with pitch p
+ * sits at x_h = (ix - (W-1)/2) p, y_h = (iy - (H-1)/2) p, i.e. the point
+ * coordinates are measured from the hologram centre (the paper's programs put
+ * pixel 0 at the origin; a centred grid is what makes clouds of +-mm extent in
+ * front of a mm-sized hologram meaningful, and it makes x/y mirror symmetry
+ * exact).  Output is row-major, x fastest, as in the paper's programs.
+ *
+ * It is a plain triple loop: rows x columns x points, FP64, libm cos/sin, a
+ * sequential sum over the points in index order, no separability, no
+ * tables, no fast-math.  Rows of the evaluation set are split over threads.
+ */
+#include <math.h>
+#include <pthread.h>
+#include <stdint.h>
+#include <stdlib.h>
+
+typedef struct {
+    /* evaluation set: all (row, column) pairs of rows[] x cols[] */
+    const int32_t *cols, *rows;
+    int64_t n_cols, n_rows;
+    int32_t width, height;
+    double pitch, wavelength;
+    const double *x, *y, *z, *a;
+    int64_t n_points;
+    double *out_re, *out_im;     /* [n_rows][n_cols]; out_im may be NULL */
+    int64_t row_begin, row_end;  /* this worker's share of rows[] */
+    int spherical;               /* 0: Eq. (2) Fresnel form; 1: Eq. (1) exact distance */
+} job_t;
+
+static void *worker(void *arg)
+{
+    const job_t *jb = (const job_t *)arg;
+    const double pi = 3.14159265358979323846;
+    const double half_w = 0.5 * (double)(jb->width - 1);
+    const double half_h = 0.5 * (double)(jb->height - 1);
+    for (int64_t r = jb->row_begin; r < jb->row_end; ++r) {
+        const double yh = ((double)jb->rows[r] - half_h) * jb->pitch;
+        for (int64_t c = 0; c < jb->n_cols; ++c) {
+            const double xh = ((double)jb->cols[c] - half_w) * jb->pitch;
+            double re = 0.0, im = 0.0;
+            for (int64_t j = 0; j < jb->n_points; ++j) {
+                const double dx = xh - jb->x[j];
+                const double dy = yh - jb->y[j];
+                double theta;
+                if (jb->spherical) {
+                    /* Eq. (1): 2 pi / lambda * sqrt(dx^2 + dy^2 + z^2) */
+                    theta = 2.0 * pi / jb->wavelength *
+                            sqrt(dx * dx + dy * dy + jb->z[j] * jb->z[j]);
+                } else {
+                    /* Eq. (2) without the per-point z_j term:
+                     * (2 pi / lambda) (dx^2 + dy^2) / (2 z_j) */
+                    theta = pi * (dx * dx + dy * dy) / (jb->wavelength * jb->z[j]);
+                }
+                re += jb->a[j] * cos(theta);
+                if (jb->out_im)
+                    im += jb->a[j] * sin(theta);
+            }
+            jb->out_re[r * jb->n_cols + c] = re;
+            if (jb->out_im)
+                jb->out_im[r * jb->n_cols + c] = im;
+        }
+    }
+    return NULL;
+}
+
+static int run(int32_t width, int32_t height, double pitch, double wavelength,
+               int64_t n_points, const double *x, const double *y, const double *z,
+               const double *a, int64_t n_cols, const int32_t *cols, int64_t n_rows,
+               const int32_t *rows, double *out_re, double *out_im, int32_t n_threads,
+               int spherical)
+{
+    if (width <= 0 || height <= 0 || n_points < 0 || n_cols < 0 || n_rows < 0)
+        return 1;
+    if (!(pitch > 0.0) || !(wavelength > 0.0) || !out_re)
+        return 1;
+    if (n_points > 0 && (!x || !y || !z || !a))
+        return 1;
+    if ((n_cols > 0 && !cols) || (n_rows > 0 && !rows))
+        return 1;
+    if (n_threads < 1)
+        n_threads = 1;
+    if (n_threads > n_rows)
+        n_threads = n_rows > 0 ? (int32_t)n_rows : 1;
+
+    job_t *jobs = (job_t *)calloc((size_t)n_threads, sizeof(job_t));
+    pthread_t *tids = (pthread_t *)calloc((size_t)n_threads, sizeof(pthread_t));
+    if (!jobs || !tids) {
+        free(jobs);
+        free(tids);
+        return 2;
+    }
+    for (int32_t t = 0; t < n_threads; ++t) {
+        job_t *jb = &jobs[t];
+        jb->cols = cols; jb->rows = rows; jb->n_cols = n_cols; jb->n_rows = n_rows;
+        jb->width = width; jb->height = height; jb->pitch = pitch; jb->wavelength = wavelength;
+        jb->x = x; jb->y = y; jb->z = z; jb->a = a; jb->n_points = n_points;
+        jb->out_re = out_re; jb->out_im = out_im; jb->spherical = spherical;
+        jb->row_begin = n_rows * t / n_threads;
+        jb->row_end = n_rows * (t + 1) / n_threads;
+    }
+    int rc = 0;
+    int32_t started = 0;
+    for (int32_t t = 1; t < n_threads; ++t) {
+        if (pthread_create(&tids[t], NULL, worker, &jobs[t]) != 0) {
+            rc = 3;
+            break;
+        }
+        started = t;
+    }
+    if (rc == 0)
+        worker(&jobs[0]);
+    for (int32_t t = 1; t <= started; ++t)
+        pthread_join(tids[t], NULL);
+    free(jobs);
+    free(tids);
+    return rc;
+}
+
+/* Fresnel form, Eq. (2)/(5) as described above.  Returns 0 on success. */
+int cgh_oracle_fresnel(int32_t width, int32_t height, double pitch, double wavelength,
+                       int64_t n_points, const double *x, const double *y, const double *z,
+                       const double *a, int64_t n_cols, const int32_t *cols, int64_t n_rows,
+                       const int32_t *rows, double *out_re, double *out_im, int32_t n_threads)
+{
+    return run(width, height, pitch, wavelength, n_points, x, y, z, a, n_cols, cols, n_rows,
+               rows, out_re, out_im, n_threads, 0);
+}
+
+/* Exact spherical wave, Eq. (1): phase (2 pi / lambda) * distance, including
+ * the z_j part of the distance.  Returns 0 on success. */
+int cgh_oracle_spherical(int32_t width, int32_t height, double pitch, double wavelength,
+                         int64_t n_points, const double *x, const double *y, const double *z,
+                         const double *a, int64_t n_cols, const int32_t *cols, int64_t n_rows,
+                         const int32_t *rows, double *out_re, double *out_im, int32_t n_threads)
+{
+    return run(width, height, pitch, wavelength, n_points, x, y, z, a, n_cols, cols, n_rows,
+               rows, out_re, out_im, n_threads, 1);
+}
