@@ -1,0 +1,180 @@
+/*
+ * cgh.h -- C-ABI of the MI355X (gfx950) point-cloud hologram library.
+ *
+ * The library computes the amplitude computer-generated hologram of a cloud
+ * of N point light sources (Section 2.1, "Direct calculation"): Eq. (2), the
+ * Fresnel approximation of the spherical wave of each point, inserted in the
+ * interference hologram of Eq. (5) with the reference-wave phase taken as 0,
+ * the constant 2 A_r dropped (as Eq. (5) allows) and the per-point constant
+ * phase 2 pi z_j / lambda dropped (as the paper's direct-calculation
+ * programs do), which leaves
+ *
+ *     I(x_h, y_h) = sum_j A_j cos( pi / (lambda z_j) ((x_h - x_j)^2 + (y_h - y_j)^2) ).
+ *
+ * Problem statement (Section 2.1 and the direct-calculation programs of
+ * Section 4.1): a W x H hologram of square pixel pitch p, one wavelength
+ * lambda, and N points (x_j, y_j, z_j) with amplitudes A_j, given as four
+ * float arrays (structure of arrays, as the paper's programs hold them).
+ *
+ * Units and conventions
+ *   - SI metres throughout.
+ *   - Pixel (ix, iy), 0 <= ix < W, 0 <= iy < H, sits at
+ *       x_h = (ix - (W-1)/2) p,   y_h = (iy - (H-1)/2) p,
+ *     i.e. x_j, y_j are measured from the hologram centre.
+ *   - z_j > 0 is the distance of point j from the hologram plane.
+ *   - Output holograms are float32, row-major, x fastest: out[iy*W + ix]
+ *     (the paper's layout), raw sums with no normalisation or quantisation.
+ *
+ * Threads and streams
+ *   - A context is not thread-safe: use one per host thread.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Compute calls only enqueue work and never block the host; their
+ *     results are ready when the stream reaches them.
+ *   - Same inputs, mode and device give bitwise-identical output on every run
+ *     (no floating-point atomics; all reductions run in a fixed order).
+ *
+ * Errors
+ *   - Every function returns a cgh_status.  Argument checks run before any
+ *     HIP call, so they behave the same on a host with no GPU.
+ *   - On failure, cgh_last_error() returns a thread-local text with detail
+ *     (for CGH_EDEVICE: the HIP error string).  No C++ exception crosses the
+ *     ABI.
+ */
+#ifndef CGH_H
+#define CGH_H
+
+#include <stdint.h>
+
+#if defined(__GNUC__) || defined(__clang__)
+#define CGH_API __attribute__((visibility("default")))
+#else
+#define CGH_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cgh_ctx cgh_ctx; /* opaque; owned by the library */
+
+typedef enum {
+    CGH_OK = 0,
+    CGH_EINVAL = 1,  /* an argument is out of its documented range            */
+    CGH_ENOMEM = 2,  /* host or device allocation failed                      */
+    CGH_EDEVICE = 3, /* no usable gfx950 device, or a HIP call failed         */
+    CGH_ENOTSUP = 4, /* valid request this build does not support             */
+    CGH_ESTATE = 5   /* call out of order (e.g. compute before any upload)    */
+} cgh_status;
+
+/* How the sum is evaluated.  All modes return the same quantity, I above.
+ *
+ * CGH_DIRECT_FP32   Per point and pixel, one cosine of the phase.  The large
+ *                   phase is range-reduced in FP64 per (pixel column, point)
+ *                   and (pixel row, point) -- the square (x_h - x_j)^2 +
+ *                   (y_h - y_j)^2 splits into a column part and a row part --
+ *                   so the FP32 cosine only sees a phase in [0, 2)
+ *                   revolutions.  FP32 accumulation.
+ * CGH_SPLIT_BF16    The same split written as a product of complex factors,
+ *                   exp(i a) exp(i b) = exp(i (a + b)): a real matrix product
+ *                   over the point axis (K = 2N), run on the matrix cores in
+ *                   BF16 with FP32 accumulation; each factor is stored as a
+ *                   hi + lo pair of BF16 numbers and three products
+ *                   (hi*hi + hi*lo + lo*hi) win back the precision.
+ * CGH_SPLIT_FP16    As CGH_SPLIT_BF16 with FP16 hi + lo factors.
+ * CGH_FP16          One FP16 product (no lo part): a third of the matrix work.
+ * CGH_SEPARABLE_FP32  The factor product evaluated in FP32 on the vector
+ *                   units (no per-pixel cosine, no reduced-precision operand).
+ */
+typedef enum {
+    CGH_DIRECT_FP32 = 0,
+    CGH_SPLIT_BF16 = 1,
+    CGH_SPLIT_FP16 = 2,
+    CGH_FP16 = 3,
+    CGH_SEPARABLE_FP32 = 4
+} cgh_mode;
+
+typedef enum { CGH_MEM_HOST = 0, CGH_MEM_DEVICE = 1 } cgh_mem;
+
+/* One hologram of a batch: points [point_offset, point_offset + point_count)
+ * of the uploaded cloud, seen at its own wavelength (metres). */
+typedef struct {
+    int64_t point_offset;
+    int64_t point_count;
+    double wavelength;
+} cgh_frame;
+
+/* Create a context for W x H holograms of pitch `pitch_m` at wavelength
+ * `wavelength_m` on HIP device `device` (an index as hipSetDevice takes).
+ *   out           receives the context (set to NULL on failure); non-NULL.
+ *   width, height in [1, 65536].
+ *   pitch_m, wavelength_m  finite and > 0.
+ * Errors: CGH_EINVAL for a bad argument; CGH_EDEVICE if the device does not
+ * exist or is not gfx950; CGH_ENOMEM.  The caller frees it with cgh_destroy. */
+CGH_API cgh_status cgh_create(cgh_ctx **out, int32_t width, int32_t height, double pitch_m,
+                      double wavelength_m, int32_t device);
+
+/* Copy N points into library-owned device memory (replacing any previous
+ * cloud).  x, y, z, amp: float32 arrays of length n, in host memory
+ * (where = CGH_MEM_HOST) or device memory (CGH_MEM_DEVICE).
+ *   n >= 0; the four pointers are non-NULL when n > 0.
+ *   Host data is checked: every value finite and z > 0, else CGH_EINVAL and
+ *   the previous cloud is kept.  Device data is not inspected (a z <= 0
+ *   there gives non-finite output).
+ * A host upload is complete on return.  A device upload is ordered on
+ * `stream`; the caller may reuse its arrays once the stream passes it.
+ * n = 0 is valid and makes every later hologram zero. */
+CGH_API cgh_status cgh_points_upload(cgh_ctx *c, const float *x, const float *y, const float *z,
+                             const float *amp, int64_t n, cgh_mem where, void *stream);
+
+/* Compute the hologram of the whole uploaded cloud at the context's
+ * wavelength into `out_dev`, a device buffer of height*width floats
+ * (row-major, x fastest) owned by the caller.
+ * Errors: CGH_EINVAL (NULL out_dev, unknown mode), CGH_ESTATE (no upload
+ * yet), CGH_ENOMEM (workspace), CGH_EDEVICE (launch failure). */
+CGH_API cgh_status cgh_compute(cgh_ctx *c, cgh_mode mode, float *out_dev, void *stream);
+
+/* Compute n_frames holograms in one go: frame f covers the points and the
+ * wavelength of frames[f] (a host array) and lands in
+ * out_dev[f*height*width ...] (device, caller-owned).  The frames may
+ * overlap, repeat, or be empty (a zero hologram).  Work of all frames is
+ * balanced across the device by one persistent kernel launch per stage, and
+ * a repeated call with the same frame table replays a captured HIP graph.
+ *   n_frames in [1, 65536]; each frame's points lie within the upload and
+ *   its wavelength is finite and > 0.
+ * Modes: all of cgh_mode.  Errors as cgh_compute. */
+CGH_API cgh_status cgh_batch_compute(cgh_ctx *c, const cgh_frame *frames, int32_t n_frames,
+                             cgh_mode mode, float *out_dev, void *stream);
+
+/* Free the context and all its device memory (synchronises the device it
+ * used first).  NULL-safe. */
+CGH_API void cgh_destroy(cgh_ctx *c);
+
+/* Static text for a status code. */
+CGH_API const char *cgh_strerror(cgh_status s);
+
+/* Thread-local detail of the last failure in this thread ("" if none). */
+CGH_API const char *cgh_last_error(void);
+
+/* ---------------------------------------------------------------------
+ * Measurement support (not part of the hologram arithmetic).
+ *
+ * With profiling on, every kernel the context enqueues is bracketed by HIP
+ * events on its stream.  cgh_profile_read() waits for those events and
+ * returns, per kernel name, the number of launches and their total time in
+ * milliseconds since the last reset; names[i] are static strings.
+ *   capacity: entries the caller's arrays hold; *count receives the number
+ *   written (at most capacity).
+ * ------------------------------------------------------------------- */
+CGH_API cgh_status cgh_profile_enable(cgh_ctx *c, int32_t on);
+CGH_API cgh_status cgh_profile_reset(cgh_ctx *c);
+CGH_API cgh_status cgh_profile_read(cgh_ctx *c, const char **names, int64_t *launches, double *total_ms,
+                            int32_t capacity, int32_t *count);
+
+/* Library version as MAJOR*10000 + MINOR*100 + PATCH. */
+CGH_API int32_t cgh_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CGH_H */

@@ -1,0 +1,239 @@
+"""Python binding of libcgh.so, the gfx950 point-cloud hologram library.
+
+Argument marshalling only: every step of the evaluation runs in the HIP
+kernels of the C library (include/cgh.h).  PyTorch supplies device memory and
+streams; numpy arrays are accepted for host-side point uploads.
+
+    import paper_1309_2734_amd as cgh
+    ctx = cgh.Context(1920, 1080, pitch=8e-6, wavelength=532e-9)
+    ctx.upload(x, y, z, amp)                     # float32 arrays (host or device)
+    out = torch.empty((1080, 1920), device="cuda")
+    ctx.compute(out, cgh.SPLIT_BF16)
+
+The library must have been built (``python -m paper_1309_2734_amd.build``);
+loading fails loudly otherwise -- there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Iterable, Optional, Sequence, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcgh.so")
+
+# cgh_mode
+DIRECT_FP32 = 0
+SPLIT_BF16 = 1
+SPLIT_FP16 = 2
+FP16 = 3
+SEPARABLE_FP32 = 4
+MODES = {"direct_fp32": DIRECT_FP32, "split_bf16": SPLIT_BF16, "split_fp16": SPLIT_FP16,
+         "fp16": FP16, "separable_fp32": SEPARABLE_FP32}
+
+# cgh_status
+OK, EINVAL, ENOMEM, EDEVICE, ENOTSUP, ESTATE = range(6)
+STATUS_NAMES = {OK: "CGH_OK", EINVAL: "CGH_EINVAL", ENOMEM: "CGH_ENOMEM",
+                EDEVICE: "CGH_EDEVICE", ENOTSUP: "CGH_ENOTSUP", ESTATE: "CGH_ESTATE"}
+
+MEM_HOST = 0
+MEM_DEVICE = 1
+
+# every symbol include/cgh.h declares
+EXPORTS = ("cgh_create", "cgh_points_upload", "cgh_compute", "cgh_batch_compute",
+           "cgh_destroy", "cgh_strerror", "cgh_last_error", "cgh_profile_enable",
+           "cgh_profile_reset", "cgh_profile_read", "cgh_version")
+
+
+class CghError(RuntimeError):
+    """A cgh_* call returned a status other than CGH_OK."""
+
+    def __init__(self, status: int, call: str, detail: str):
+        self.status = status
+        super().__init__(f"{call}: {STATUS_NAMES.get(status, status)}: {detail}")
+
+
+class Frame(ctypes.Structure):
+    _fields_ = [("point_offset", ctypes.c_int64), ("point_count", ctypes.c_int64),
+                ("wavelength", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libcgh.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_1309_2734_amd.build` (no fallback exists)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    st = ctypes.c_int
+    L.cgh_create.argtypes = [ctypes.POINTER(vp), i32, i32, dbl, dbl, i32]
+    L.cgh_create.restype = st
+    L.cgh_points_upload.argtypes = [vp, vp, vp, vp, vp, i64, ctypes.c_int, vp]
+    L.cgh_points_upload.restype = st
+    L.cgh_compute.argtypes = [vp, ctypes.c_int, vp, vp]
+    L.cgh_compute.restype = st
+    L.cgh_batch_compute.argtypes = [vp, ctypes.POINTER(Frame), i32, ctypes.c_int, vp, vp]
+    L.cgh_batch_compute.restype = st
+    L.cgh_destroy.argtypes = [vp]
+    L.cgh_destroy.restype = None
+    L.cgh_strerror.argtypes = [ctypes.c_int]
+    L.cgh_strerror.restype = ctypes.c_char_p
+    L.cgh_last_error.argtypes = []
+    L.cgh_last_error.restype = ctypes.c_char_p
+    L.cgh_profile_enable.argtypes = [vp, i32]
+    L.cgh_profile_enable.restype = st
+    L.cgh_profile_reset.argtypes = [vp]
+    L.cgh_profile_reset.restype = st
+    L.cgh_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(i64),
+                                   ctypes.POINTER(dbl), i32, ctypes.POINTER(i32)]
+    L.cgh_profile_read.restype = st
+    L.cgh_version.argtypes = []
+    L.cgh_version.restype = i32
+    _lib = L
+    return L
+
+
+def _check(status: int, call: str) -> None:
+    if status != OK:
+        detail = lib().cgh_last_error()
+        raise CghError(status, call, detail.decode() if detail else "")
+
+
+def _is_torch(a) -> bool:
+    return type(a).__module__.startswith("torch")
+
+
+def _stream_handle(stream, tensors: Iterable = ()) -> Optional[int]:
+    """hipStream_t for a call: an explicit stream (torch.cuda.Stream or raw
+    handle), else torch's current stream when device tensors take part."""
+    if stream is not None:
+        return int(getattr(stream, "cuda_stream", stream))
+    for t in tensors:
+        if _is_torch(t) and t.is_cuda:
+            import torch
+            return int(torch.cuda.current_stream(t.device).cuda_stream)
+    return None
+
+
+class Context:
+    """One W x H hologram configuration on one device (a cgh_ctx)."""
+
+    def __init__(self, width: int, height: int, pitch: float, wavelength: float,
+                 device: int = 0):
+        h = ctypes.c_void_p()
+        _check(lib().cgh_create(ctypes.byref(h), int(width), int(height), float(pitch),
+                                float(wavelength), int(device)), "cgh_create")
+        self._h = h
+        self.width, self.height = int(width), int(height)
+        self.pitch, self.wavelength, self.device = float(pitch), float(wavelength), int(device)
+        self._keep = None
+
+    # -- lifetime
+    def close(self) -> None:
+        if getattr(self, "_h", None) and self._h.value:
+            lib().cgh_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- points
+    def upload(self, x, y, z, amp, stream=None) -> None:
+        """Copy a float32 SoA point cloud into the library (host numpy / CPU
+        tensors: complete on return; CUDA tensors: ordered on the stream)."""
+        arrs = [x, y, z, amp]
+        if all(_is_torch(a) and a.is_cuda for a in arrs):
+            import torch
+            ts = [a.detach().to(torch.float32).contiguous() for a in arrs]
+            n = ts[0].numel()
+            if any(t.numel() != n for t in ts):
+                raise ValueError("x, y, z, amp must have one length")
+            self._keep = ts   # keep alive until the stream has copied them
+            _check(lib().cgh_points_upload(self._h, *[t.data_ptr() for t in ts], n, MEM_DEVICE,
+                                           _stream_handle(stream, ts)), "cgh_points_upload")
+            return
+        hs = [np.ascontiguousarray(a.detach().cpu().numpy() if _is_torch(a) else a,
+                                   dtype=np.float32) for a in arrs]
+        n = hs[0].shape[0]
+        if any(h.ndim != 1 or h.shape[0] != n for h in hs):
+            raise ValueError("x, y, z, amp must be 1-D arrays of one length")
+        ptrs = [h.ctypes.data if n else None for h in hs]
+        _check(lib().cgh_points_upload(self._h, *ptrs, n, MEM_HOST, _stream_handle(stream)),
+               "cgh_points_upload")
+
+    def upload_cloud(self, cloud, stream=None) -> None:
+        """upload() the arrays of a cghgen.Cloud / Batch."""
+        self.upload(cloud.x, cloud.y, cloud.z, cloud.amp, stream)
+
+    # -- evaluation
+    def _out_ptr(self, out, planes: int) -> int:
+        if not (_is_torch(out) and out.is_cuda):
+            raise TypeError("out must be a CUDA float32 torch tensor")
+        import torch
+        if out.dtype != torch.float32 or not out.is_contiguous():
+            raise TypeError("out must be contiguous float32")
+        if out.numel() != planes * self.width * self.height:
+            raise ValueError(f"out must hold {planes} x {self.height} x {self.width} floats")
+        return out.data_ptr()
+
+    def compute(self, out, mode: int = DIRECT_FP32, stream=None):
+        """Hologram of the uploaded cloud into `out` ([H, W] float32, device)."""
+        _check(lib().cgh_compute(self._h, int(mode), self._out_ptr(out, 1),
+                                 _stream_handle(stream, [out])), "cgh_compute")
+        return out
+
+    def batch_compute(self, frames: Sequence[Tuple[int, int, float]], out,
+                      mode: int = DIRECT_FP32, stream=None):
+        """Holograms of frames (offset, count, wavelength) into out [F, H, W]."""
+        F = len(frames)
+        arr = (Frame * max(F, 1))()
+        for i, (o, c, lam) in enumerate(frames):
+            arr[i] = Frame(int(o), int(c), float(lam))
+        _check(lib().cgh_batch_compute(self._h, arr, F, int(mode), self._out_ptr(out, F),
+                                       _stream_handle(stream, [out])), "cgh_batch_compute")
+        return out
+
+    # -- measurement
+    def profile(self, on: bool = True) -> None:
+        _check(lib().cgh_profile_enable(self._h, 1 if on else 0), "cgh_profile_enable")
+
+    def profile_reset(self) -> None:
+        _check(lib().cgh_profile_reset(self._h), "cgh_profile_reset")
+
+    def profile_read(self) -> dict:
+        """{kernel name: (launches, total ms)} since the last reset."""
+        cap = 32
+        names = (ctypes.c_char_p * cap)()
+        launches = (ctypes.c_int64 * cap)()
+        ms = (ctypes.c_double * cap)()
+        cnt = ctypes.c_int32()
+        _check(lib().cgh_profile_read(self._h, names, launches, ms, cap, ctypes.byref(cnt)),
+               "cgh_profile_read")
+        return {names[i].decode(): (int(launches[i]), float(ms[i])) for i in range(cnt.value)}
+
+
+def version() -> int:
+    return int(lib().cgh_version())
+
+
+def batch_frames(batch) -> list:
+    """(offset, count, wavelength) triples of a cghgen.Batch."""
+    return [(int(o), int(c), float(l)) for o, c, l in
+            zip(batch.offsets, batch.counts, batch.wavelengths)]

@@ -1,0 +1,107 @@
+// Internal declarations shared by the host library and the gfx950 kernels.
+//
+// Notation (Section 2.1, Eq. (2)): pixel (ix, iy), point j with (x_j, y_j,
+// z_j, A_j), wavelength lambda, pitch p.  In pixel units the Fresnel phase of
+// point j at pixel (ix, iy), in revolutions, is
+//
+//     phi_j(ix, iy) = beta_j (ix - cx_j)^2 + beta_j (iy - cy_j)^2,
+//     beta_j = p^2 / (2 lambda z_j),  cx_j = (W-1)/2 + x_j / p,  cy_j = (H-1)/2 + y_j / p,
+//
+// because pi r^2 / (lambda z) radians = r^2 / (2 lambda z) revolutions.  The
+// sum of Eq. (5) is I = sum_j A_j cos(2 pi phi_j).  The square splits into a
+// column part and a row part; every kernel here works on those two "line
+// phases", reduced modulo one revolution in FP64:
+//
+//     U[ix, j] = frac(beta_j (ix - cx_j)^2),   V[iy, j] = frac(beta_j (iy - cy_j)^2),
+//
+// so that cos(2 pi phi_j) = cos(2 pi (U + V)).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cgh {
+
+// Points are processed in groups of this many (tables are blocked by group).
+constexpr int kGroup = 16;
+// Every segment's slots are padded (with zero-amplitude points) to a multiple
+// of this, so each frame has an even number of groups.
+constexpr int kSlotAlign = 32;
+// Line tables are padded to a multiple of this many columns / rows.
+constexpr int kLinePad = 64;
+
+// Per-point constants of one evaluation segment, structure of arrays.
+struct PointConsts {
+    double *beta;  // revolutions per pixel^2
+    double *cx;    // point position in pixel units along x
+    double *cy;    // ... along y
+    float *amp;    // A_j
+};
+
+// A run of points to prepare: source points [src, src + count) of the
+// uploaded cloud, seen at wavelength `wavelength`, written to constant slots
+// [dst, dst + count) and zero-padded to a multiple of kSlotAlign.
+struct Segment {
+    int64_t src;
+    int64_t count;
+    int64_t dst;       // multiple of kSlotAlign
+    double wavelength;
+};
+
+// One hologram of a (possibly batched) evaluation.
+struct FrameDesc {
+    int64_t first;     // first constant slot (multiple of kSlotAlign)
+    int64_t groups;    // point groups: count padded to kSlotAlign, / kGroup (even)
+    int64_t out_off;   // offset of the frame's output in floats
+};
+
+// ---------------------------------------------------------------- launchers
+// Each returns the hipError_t of the launch.
+
+// a1: per-point constants for a list of segments.
+hipError_t launch_point_consts(const float *x, const float *y, const float *z, const float *amp,
+                               const Segment *segs_dev, int n_segs, int64_t max_count,
+                               int width, int height, double pitch, PointConsts pc,
+                               hipStream_t s);
+
+// a2: line-phase tables for the direct kernel, blocked as [group][line][kGroup]:
+// U over `wpad` columns, V over `hpad` rows (lines past the hologram are
+// evaluated like the others and never stored), for slots [0, n_slots).
+hipError_t launch_phase_tables(PointConsts pc, int64_t n_slots, int wpad, int hpad,
+                               float *U, float *V, hipStream_t s);
+
+// a3: direct FP32 accumulation for frames[0 .. n_frames) (tables from a2,
+// padded to wpad columns and hpad rows, multiples of kLinePad).
+hipError_t launch_direct(const float *U, const float *V, const float *amp,
+                         const FrameDesc *frames_dev, int n_frames, int width, int height,
+                         int wpad, int hpad, int rows_per_wave, float *out, bool accumulate,
+                         hipStream_t s);
+
+// F2: FP32 separable product on the vector units, same tables plus factors.
+hipError_t launch_separable_fp32(const float *U, const float *V, const float *amp,
+                                 int64_t n_slots, const FrameDesc *frames_dev, int n_frames,
+                                 int64_t max_groups, int width, int height, float *out,
+                                 hipStream_t s);
+
+// a4: factor build.  Writes the hi (and, if lo_* != nullptr, lo) factors of
+// L (rows) and R (columns) in the MFMA fragment order described in factors.hip.
+enum class FactorType { BF16 = 0, FP16 = 1 };
+hipError_t launch_factors(PointConsts pc, int64_t slot0, int64_t n_slots, int width, int height,
+                          int64_t kblocks, int mblocks, int nblocks, FactorType ft,
+                          void *Lh, void *Ll, void *Rh, void *Rl, hipStream_t s);
+
+// a5: split GEMM on MFMA.  See gemm.hip for the tiling.
+struct GemmPlan {
+    int bm, bn;          // macro tile (multiples of 32)
+    int splits;          // K splits (1 = write the output directly)
+    int64_t kblocks;     // K / 16 (padded)
+    int mblocks, nblocks;// rows / 32, cols / 32 (padded)
+    int products;        // 3 = hi*hi + hi*lo + lo*hi, 1 = hi*hi only
+};
+hipError_t launch_gemm(const GemmPlan &plan, FactorType ft, const void *Lh, const void *Ll,
+                       const void *Rh, const void *Rl, int M, int N, float *out, int64_t ldo,
+                       float *partials, bool accumulate, hipStream_t s);
+hipError_t launch_splitk_reduce(const float *partials, int splits, int M, int N, float *out,
+                                int64_t ldo, bool accumulate, hipStream_t s);
+
+}  // namespace cgh

@@ -1,0 +1,190 @@
+// Direct FP32 evaluation of the amplitude hologram (Section 2.1, Eq. (5) with
+// the Fresnel phase of Eq. (2)): one cosine per point and pixel.
+//
+// Mapping on gfx950.  A wave's 64 lanes own 64 consecutive pixel columns
+// (coalesced loads of the column table and coalesced stores), and each lane
+// owns R rows.  Points are taken 16 at a time (one table group):
+//   - the lane loads its column's 16 reduced column phases U[ix, j] with four
+//     16-byte loads (table blocked as [group][column][16]);
+//   - lane l also loads, for each of its R rows, the row phase V[iy, j] of
+//     point j = 16 g + (l mod 16); each 16-lane DPP row thus holds the row
+//     phases of all 16 points.  The 16 amplitudes are wave-uniform and go to
+//     scalar registers;
+//   - for point k of the group, the row phase is broadcast from lane k of
+//     each 16-lane row with DPP row_newbcast, folded into the add:
+//         t = V[row, k] (broadcast) + U[col, k]      v_add_f32_dpp
+//         c = cos(2 pi t)                            v_cos_f32 (input in revolutions)
+//         acc = fma(A_k (scalar), c, acc)            v_fmac_f32
+//     t lies in [0, 2] because U and V were reduced in FP64, which is inside
+//     the hardware cosine's domain and keeps its absolute error ~1e-7.
+// No LDS, no barrier: the four waves of a workgroup take the same 64 columns
+// and consecutive row bands, so their column-table loads hit in L1.
+// Accumulation: a fresh FP32 partial per 64 points, added to the running sum.
+#include "common.h"
+
+namespace cgh {
+namespace {
+
+constexpr int kWaves = 4;
+
+template <int K>
+__device__ __forceinline__ float row_bcast(float v)
+{
+    // DPP row_newbcast:K -- every lane of a 16-lane row reads lane K of that
+    // row.  The compiler folds this move into the consuming v_add_f32.
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
+                                                                 0x150 + K, 0xF, 0xF, false));
+}
+
+template <int R>
+struct GroupRegs {
+    float4 u[4];      // U[col, 16g + 0..15]
+    float v[R];       // V[row_r, 16g + lane%16]
+    float a[kGroup];  // A[16g + 0..15]: wave-uniform, held in scalar registers
+};
+
+// Tables are padded to whole 64-column / 64-row blocks, so no load needs a
+// bounds clamp: the R row phases of a lane are R consecutive table lines.
+template <int R>
+__device__ __forceinline__ void load_group(GroupRegs<R> &G, const float *__restrict__ Ug,
+                                           const float *__restrict__ Vg,
+                                           const float *__restrict__ Ag)
+{
+    const float4 *up = reinterpret_cast<const float4 *>(Ug);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        G.u[i] = up[i];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        G.v[r] = Vg[r * kGroup];
+#pragma unroll
+    for (int k = 0; k < kGroup; ++k)
+        G.a[k] = Ag[k];
+}
+
+template <int K, int R>
+__device__ __forceinline__ void point_step(const GroupRegs<R> &G, float *part)
+{
+    const float uk = reinterpret_cast<const float *>(G.u)[K];
+    const float ak = G.a[K];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const float t = row_bcast<K>(G.v[r]) + uk;
+        part[r] = __builtin_fmaf(ak, __builtin_amdgcn_cosf(t), part[r]);
+    }
+}
+
+template <int R>
+__device__ __forceinline__ void group_step(const GroupRegs<R> &G, float *part)
+{
+    point_step<0, R>(G, part);   point_step<1, R>(G, part);
+    point_step<2, R>(G, part);   point_step<3, R>(G, part);
+    point_step<4, R>(G, part);   point_step<5, R>(G, part);
+    point_step<6, R>(G, part);   point_step<7, R>(G, part);
+    point_step<8, R>(G, part);   point_step<9, R>(G, part);
+    point_step<10, R>(G, part);  point_step<11, R>(G, part);
+    point_step<12, R>(G, part);  point_step<13, R>(G, part);
+    point_step<14, R>(G, part);  point_step<15, R>(G, part);
+}
+
+// Grid: x = column blocks of 64, y = row bands of kWaves * R rows, z = frame.
+// Tables: U [groups][wpad][16], V [groups][hpad][16]; wpad, hpad multiples of
+// 64; every frame's group count is even.
+template <int R>
+__global__ __launch_bounds__(256) void k_direct(const float *__restrict__ U,
+                                                const float *__restrict__ V,
+                                                const float *__restrict__ amp,
+                                                const FrameDesc *__restrict__ frames, int width,
+                                                int height, int wpad, int hpad,
+                                                float *__restrict__ out, int accumulate)
+{
+    const FrameDesc fd = frames[blockIdx.z];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int col = blockIdx.x * 64 + lane;
+    const int row0 = (blockIdx.y * kWaves + wave) * R;
+
+    // group g of this frame: U at Ug + g*ustep, V at Vg + g*vstep, A at Ag + 16 g
+    const int64_t ustep = (int64_t)wpad * kGroup;
+    const int64_t vstep = (int64_t)hpad * kGroup;
+    const float *Ug = U + fd.first * wpad + (int64_t)col * kGroup;
+    const float *Vg = V + fd.first * hpad + (int64_t)row0 * kGroup + (lane & (kGroup - 1));
+    const float *Ag = amp + fd.first;
+
+    float acc[R];
+    float part[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        acc[r] = 0.0f;
+        part[r] = 0.0f;
+    }
+    // Two register sets in ping-pong: the loads of the next group are in
+    // flight while the current one is evaluated.  The last prefetch re-reads
+    // the final group (in bounds, unused) so the loop body has no branch.
+    const int64_t G = fd.groups;
+    GroupRegs<R> ga, gb;
+    if (G > 0)
+        load_group<R>(ga, Ug, Vg, Ag);
+    // G is even (slots are padded to kSlotAlign = 2 groups); the clamp only
+    // keeps the loads inside the frame's tables should that ever not hold.
+    for (int64_t g = 0; g < G; g += 2) {
+        const int64_t g1 = g + 1 < G ? g + 1 : G - 1;
+        load_group<R>(gb, Ug + g1 * ustep, Vg + g1 * vstep, Ag + g1 * kGroup);
+        group_step<R>(ga, part);
+        const int64_t gn = g + 2 < G ? g + 2 : G - 1;
+        load_group<R>(ga, Ug + gn * ustep, Vg + gn * vstep, Ag + gn * kGroup);
+        group_step<R>(gb, part);
+        // a fresh partial every 64 points keeps the FP32 running sum's
+        // rounding error small
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            acc[r] += part[r];
+            part[r] = 0.0f;
+        }
+    }
+    if (col < width) {
+        float *o = out + fd.out_off;
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            if (row0 + r < height) {
+                float *p = o + (int64_t)(row0 + r) * width + col;
+                *p = accumulate ? *p + acc[r] : acc[r];
+            }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_direct(const float *U, const float *V, const float *amp,
+                         const FrameDesc *frames_dev, int n_frames, int width, int height,
+                         int wpad, int hpad, int rows_per_wave, float *out, bool accumulate,
+                         hipStream_t s)
+{
+    const int acc = accumulate ? 1 : 0;
+    if (n_frames <= 0)
+        return hipSuccess;
+    const unsigned bx = (unsigned)((width + 63) / 64);
+    switch (rows_per_wave) {
+    case 8: {
+        const unsigned by = (unsigned)((height + kWaves * 8 - 1) / (kWaves * 8));
+        hipLaunchKernelGGL(k_direct<8>, dim3(bx, by, (unsigned)n_frames), dim3(256), 0, s, U, V,
+                           amp, frames_dev, width, height, wpad, hpad, out, acc);
+        break;
+    }
+    case 16: {
+        const unsigned by = (unsigned)((height + kWaves * 16 - 1) / (kWaves * 16));
+        hipLaunchKernelGGL(k_direct<16>, dim3(bx, by, (unsigned)n_frames), dim3(256), 0, s, U,
+                           V, amp, frames_dev, width, height, wpad, hpad, out, acc);
+        break;
+    }
+    default: {
+        const unsigned by = (unsigned)((height + kWaves * 4 - 1) / (kWaves * 4));
+        hipLaunchKernelGGL(k_direct<4>, dim3(bx, by, (unsigned)n_frames), dim3(256), 0, s, U, V,
+                           amp, frames_dev, width, height, wpad, hpad, out, acc);
+        break;
+    }
+    }
+    return hipGetLastError();
+}
+
+}  // namespace cgh

@@ -1,0 +1,124 @@
+// Complex line factors of the separable form, split into hi + lo halves.
+//
+// With the FP64-reduced line phases U[ix, j], V[iy, j] (revolutions),
+//     A_j cos(2 pi (U + V)) = A_j cos(2 pi V) cos(2 pi U) - A_j sin(2 pi V) sin(2 pi U),
+// so the hologram of Eq. (5) is the real matrix product I = L R^T over
+// K = 2N interleaved columns:
+//     L[iy, 2j] =  A_j cos(2 pi V[iy, j]),   L[iy, 2j+1] = -A_j sin(2 pi V[iy, j]),
+//     R[ix, 2j] =      cos(2 pi U[ix, j]),   R[ix, 2j+1] =      sin(2 pi U[ix, j]).
+// Each value v is stored as hi = round(v) and lo = round(v - hi) in the
+// 16-bit type (round to nearest even; v - hi is exact in FP32).
+//
+// Storage order = the operand order of v_mfma_f32_32x32x16_{bf16,f16}: the
+// matrix is cut into blocks of 32 lines x 16 K-columns (8 points); a block
+// is 64 lanes x 8 values = 1 KB, lane l holding line (l mod 32) and
+// K-columns 8 (l / 32) .. 8 (l / 32) + 7 of the block, i.e. 4 points'
+// (cos, sin) pairs.  Blocks are ordered [line block][K block], so a GEMM
+// stage copies whole 1 KB blocks straight into LDS.  Lines past the
+// hologram are written as zeros.
+#include "common.h"
+
+namespace cgh {
+namespace {
+
+template <typename T>
+__device__ __forceinline__ T to16(float v);
+template <>
+__device__ __forceinline__ __bf16 to16<__bf16>(float v) { return (__bf16)v; }
+template <>
+__device__ __forceinline__ _Float16 to16<_Float16>(float v) { return (_Float16)v; }
+
+template <typename T>
+struct alignas(16) Vec8 {
+    T v[8];
+};
+
+// Grid: x = K block * 64 + lane, y = line block (L blocks first, then R).
+template <typename T, bool SPLIT>
+__global__ __launch_bounds__(256) void k_factors(PointConsts pc, int64_t slot0, int64_t kblocks,
+                                                 int height, int width, int mblocks,
+                                                 Vec8<T> *__restrict__ Lh, Vec8<T> *__restrict__ Ll,
+                                                 Vec8<T> *__restrict__ Rh, Vec8<T> *__restrict__ Rl)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= kblocks * 64)
+        return;
+    const int lane = (int)(t & 63);
+    const int64_t kb = t >> 6;
+    const bool is_l = (int)blockIdx.y < mblocks;
+    const int rb = is_l ? (int)blockIdx.y : (int)blockIdx.y - mblocks;
+    const int line = rb * 32 + (lane & 31);
+    const int lines = is_l ? height : width;
+    const int64_t j0 = slot0 + kb * 8 + 4 * (lane >> 5);
+
+    Vec8<T> hi, lo;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        float c = 0.0f, s = 0.0f;
+        if (line < lines) {
+            const int64_t j = j0 + p;
+            const double ctr = is_l ? pc.cy[j] : pc.cx[j];
+            const double d = (double)line - ctr;
+            const float ph = (float)__builtin_amdgcn_fract(pc.beta[j] * (d * d));
+            c = __builtin_amdgcn_cosf(ph);     // cos(2 pi ph)
+            s = __builtin_amdgcn_sinf(ph);     // sin(2 pi ph)
+            if (is_l) {
+                const float a = pc.amp[j];
+                c = a * c;
+                s = -a * s;
+            }
+        }
+        const T ch = to16<T>(c), sh = to16<T>(s);
+        hi.v[2 * p] = ch;
+        hi.v[2 * p + 1] = sh;
+        if (SPLIT) {
+            lo.v[2 * p] = to16<T>(c - (float)ch);
+            lo.v[2 * p + 1] = to16<T>(s - (float)sh);
+        }
+    }
+    const int64_t idx = ((int64_t)rb * kblocks + kb) * 64 + lane;
+    if (is_l) {
+        Lh[idx] = hi;
+        if (SPLIT)
+            Ll[idx] = lo;
+    } else {
+        Rh[idx] = hi;
+        if (SPLIT)
+            Rl[idx] = lo;
+    }
+}
+
+template <typename T>
+hipError_t launch_t(PointConsts pc, int64_t slot0, int64_t n_slots, int width, int height,
+                    int64_t kblocks, int mblocks, int nblocks, void *Lh, void *Ll, void *Rh,
+                    void *Rl, hipStream_t s)
+{
+    (void)n_slots;
+    dim3 grid((unsigned)((kblocks * 64 + 255) / 256), (unsigned)(mblocks + nblocks));
+    if (Ll != nullptr)
+        hipLaunchKernelGGL((k_factors<T, true>), grid, dim3(256), 0, s, pc, slot0, kblocks, height,
+                           width, mblocks, (Vec8<T> *)Lh, (Vec8<T> *)Ll, (Vec8<T> *)Rh,
+                           (Vec8<T> *)Rl);
+    else
+        hipLaunchKernelGGL((k_factors<T, false>), grid, dim3(256), 0, s, pc, slot0, kblocks,
+                           height, width, mblocks, (Vec8<T> *)Lh, (Vec8<T> *)nullptr,
+                           (Vec8<T> *)Rh, (Vec8<T> *)nullptr);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_factors(PointConsts pc, int64_t slot0, int64_t n_slots, int width, int height,
+                          int64_t kblocks, int mblocks, int nblocks, FactorType ft, void *Lh,
+                          void *Ll, void *Rh, void *Rl, hipStream_t s)
+{
+    if (kblocks <= 0)
+        return hipSuccess;
+    if (ft == FactorType::BF16)
+        return launch_t<__bf16>(pc, slot0, n_slots, width, height, kblocks, mblocks, nblocks, Lh,
+                                Ll, Rh, Rl, s);
+    return launch_t<_Float16>(pc, slot0, n_slots, width, height, kblocks, mblocks, nblocks, Lh,
+                              Ll, Rh, Rl, s);
+}
+
+}  // namespace cgh

@@ -1,0 +1,95 @@
+"""The C-ABI library loads, exports what include/cgh.h declares, and rejects
+bad arguments before touching the GPU (so these run on a host without one)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1309_2734_amd as cgh
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cgh.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"CGH_API\s+[^;(]*?\b(cgh_\w+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(cgh.LIB_PATH):
+        from paper_1309_2734_amd import build
+        build.build()
+    return cgh.lib()
+
+
+def test_header_declares_the_binding_exports():
+    assert _declared_functions() == sorted(cgh.EXPORTS)
+
+
+def test_every_declared_symbol_is_exported(L):
+    for name in _declared_functions():
+        assert hasattr(L, name), name
+    # nothing else leaks out of the library
+    out = os.popen(f"nm -D --defined-only {cgh.LIB_PATH}").read()
+    exported = sorted(l.split()[-1] for l in out.splitlines() if " T " in l)
+    assert exported == _declared_functions()
+
+
+def test_strerror_and_version(L):
+    assert L.cgh_strerror(0) == b"success"
+    assert L.cgh_strerror(1) == b"invalid argument"
+    assert L.cgh_strerror(5) == b"invalid call order"
+    assert L.cgh_strerror(99) == b"unknown status"
+    assert L.cgh_version() == 10000
+
+
+def _create(L, w=64, h=32, p=8e-6, lam=5e-7, dev=0, null_out=False):
+    out = ctypes.c_void_p(123)
+    st = L.cgh_create(None if null_out else ctypes.byref(out), w, h, p, lam, dev)
+    return st, out
+
+
+@pytest.mark.parametrize("kw", [
+    dict(null_out=True), dict(w=0), dict(h=0), dict(w=65537), dict(h=-3),
+    dict(p=0.0), dict(p=-1e-6), dict(p=float("nan")), dict(p=float("inf")),
+    dict(lam=0.0), dict(lam=float("nan")), dict(dev=-1),
+])
+def test_create_rejects_bad_arguments(L, kw):
+    st, out = _create(L, **kw)
+    assert st == cgh.EINVAL
+    if not kw.get("null_out"):
+        assert out.value is None       # *out is cleared on failure
+    assert len(L.cgh_last_error()) > 0
+
+
+def test_create_without_gpu_reports_device_error(L):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is visible")
+    st, out = _create(L)
+    assert st == cgh.EDEVICE and out.value is None
+    with pytest.raises(cgh.CghError) as e:
+        cgh.Context(64, 32, 8e-6, 5e-7)
+    assert e.value.status == cgh.EDEVICE
+
+
+def test_null_context_is_rejected_everywhere(L):
+    f = (cgh.Frame * 1)()
+    assert L.cgh_points_upload(None, None, None, None, None, 0, 0, None) == cgh.EINVAL
+    assert L.cgh_compute(None, 0, ctypes.c_void_p(16), None) == cgh.EINVAL
+    assert L.cgh_batch_compute(None, f, 1, 0, ctypes.c_void_p(16), None) == cgh.EINVAL
+    assert L.cgh_profile_enable(None, 1) == cgh.EINVAL
+    assert L.cgh_profile_reset(None) == cgh.EINVAL
+    cnt = ctypes.c_int32()
+    assert L.cgh_profile_read(None, None, None, None, 0, ctypes.byref(cnt)) == cgh.EINVAL
+    L.cgh_destroy(None)   # NULL-safe
+
+
+def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
+    monkeypatch.setattr(cgh, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(cgh, "_lib", None)
+    with pytest.raises(RuntimeError, match="no fallback"):
+        cgh.lib()

@@ -1,0 +1,285 @@
+"""GPU parity: every evaluation mode of libcgh.so against the FP64 oracle.
+
+Tolerances (normalised RMS error vs the FP64 oracle, over the evaluation set):
+  direct FP32 .............. 1e-5
+  BF16 / FP16 hi+lo split .. 1e-3
+  FP16 single product ...... 1e-3
+The first two are the target accuracies of the two forms; the single-product
+FP16 form is held to the split forms' bound.
+Full-size workloads are compared on strided pixel subsets the oracle
+evaluates pixel by pixel; small ones on the full grid.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import cghgen
+import oracle
+import paper_1309_2734_amd as cgh
+
+pytestmark = pytest.mark.gpu
+
+TOL = {cgh.DIRECT_FP32: 1e-5, cgh.SPLIT_BF16: 1e-3, cgh.SPLIT_FP16: 1e-3, cgh.FP16: 1e-3}
+NAMES = {v: k for k, v in cgh.MODES.items()}
+GEMM_MODES = (cgh.SPLIT_BF16, cgh.SPLIT_FP16, cgh.FP16)
+ALL_MODES = (cgh.DIRECT_FP32,) + GEMM_MODES
+
+
+def say(*a):
+    print("[parity]", *a, flush=True)
+
+
+def gpu_hologram(cloud, mode, ctx=None):
+    import torch
+    own = ctx is None
+    if own:
+        ctx = cgh.Context(cloud.width, cloud.height, cloud.pitch, cloud.wavelength)
+        ctx.upload_cloud(cloud)
+    out = torch.empty((cloud.height, cloud.width), dtype=torch.float32, device="cuda")
+    ctx.compute(out, mode)
+    torch.cuda.synchronize()
+    res = out.cpu().numpy().astype(np.float64)
+    if own:
+        ctx.close()
+    return res
+
+
+def check(name, got, ref, mode):
+    e = oracle.nrms(got, ref)
+    m = oracle.max_err(got, ref)
+    say(f"{name} {NAMES[mode]}: nrms={e:.3e} max={m:.3e}")
+    assert np.all(np.isfinite(got))
+    assert e <= TOL[mode], f"{name} {NAMES[mode]} nrms {e:.3e} > {TOL[mode]:.0e}"
+    return e
+
+
+# ------------------------------------------------------------ full grids
+@pytest.mark.parametrize("mode", ALL_MODES, ids=[NAMES[m] for m in ALL_MODES])
+def test_c1_full_grid(mode):
+    c = cghgen.make_config(1)
+    say(f"C1 {c.width}x{c.height} N={c.n} {NAMES[mode]}")
+    ref = oracle.cloud_fresnel(c)
+    got = gpu_hologram(c, mode)
+    e = check("C1", got, ref, mode)
+    if mode == cgh.DIRECT_FP32:
+        assert e < 2e-6
+    if mode in (cgh.SPLIT_BF16, cgh.SPLIT_FP16):
+        assert e < 1e-4
+
+
+def test_zone_plate_layout_and_orientation():
+    """One point on a pixel centre with beta = 1/8 rev/px^2 (as in the oracle's
+    closed-form pin): every mode must give cos(pi ((ix-ix0)^2+(iy-iy0)^2)/4),
+    which fixes the row-major layout, orientation and centre convention.
+    p = 2^-17 m, z = 2^-11 m and the point offsets are exact in float32, so
+    the float32 inputs carry no rounding."""
+    p, z = 2.0 ** -17, 2.0 ** -11
+    lam = 4.0 * p * p / z          # 2^-21 m = 476.8 nm
+    W, H = 97, 45
+    ix0, iy0 = 48 + 7, 22 - 4
+    c = cghgen.Cloud("zone", W, H, p, lam, np.array([7 * p], np.float32),
+                     np.array([-4 * p], np.float32), np.array([z], np.float32),
+                     np.array([1.0], np.float32))
+    n = np.arange(W)[None, :] - ix0
+    m = np.arange(H)[:, None] - iy0
+    exp = np.cos(np.pi * ((n * n + m * m) % 8) / 4.0)
+    for mode in ALL_MODES:
+        say(f"zone plate {NAMES[mode]}")
+        got = gpu_hologram(c, mode)
+        tol = 2e-6 if mode == cgh.DIRECT_FP32 else (1e-2 if mode == cgh.FP16 else 1e-4)
+        assert np.max(np.abs(got - exp)) < tol, NAMES[mode]
+
+
+# ------------------------------------------------------- full-size samples
+def _strided(c, step):
+    cols = sorted(set(range(0, c.width, step)) | {c.width - 1})
+    rows = sorted(set(range(0, c.height, step)) | {c.height - 1})
+    return np.array(cols), np.array(rows)
+
+
+@pytest.mark.parametrize("mode", ALL_MODES, ids=[NAMES[m] for m in ALL_MODES])
+def test_c2_full_size_strided(mode):
+    c = cghgen.make_config(2)
+    cols, rows = _strided(c, 8)
+    say(f"C2 {c.width}x{c.height} N={c.n} {NAMES[mode]} sample {len(rows)}x{len(cols)}")
+    ref = oracle.cloud_fresnel(c, cols=cols, rows=rows)
+    got = gpu_hologram(c, mode)[np.ix_(rows, cols)]
+    check("C2", got, ref, mode)
+
+
+@pytest.mark.parametrize("mode", (cgh.DIRECT_FP32, cgh.SPLIT_BF16),
+                         ids=["direct_fp32", "split_bf16"])
+def test_c3_full_size_strided(mode):
+    c = cghgen.make_config(3)
+    cols, rows = _strided(c, 64)
+    say(f"C3 {c.width}x{c.height} N={c.n} {NAMES[mode]} sample {len(rows)}x{len(cols)}")
+    ref = oracle.cloud_fresnel(c, cols=cols, rows=rows)
+    got = gpu_hologram(c, mode)[np.ix_(rows, cols)]
+    check("C3", got, ref, mode)
+
+
+# ------------------------------------------------------------ edge cases
+@pytest.mark.parametrize("n", [1, 2, 31, 33, 100])
+def test_ragged_point_counts(n):
+    c = cghgen.make_config(1, n=n)
+    ref = oracle.cloud_fresnel(c)
+    for mode in ALL_MODES:
+        say(f"ragged N={n} {NAMES[mode]}")
+        check(f"N={n}", gpu_hologram(c, mode), ref, mode)
+
+
+@pytest.mark.parametrize("wh", [(1, 1), (65, 33), (300, 7), (7, 300), (129, 257)])
+def test_ragged_hologram_sizes(wh):
+    W, H = wh
+    c0 = cghgen.make_config(1, n=77)
+    c = cghgen.Cloud("ragged", W, H, c0.pitch, c0.wavelength, c0.x, c0.y, c0.z, c0.amp)
+    ref = oracle.cloud_fresnel(c)
+    for mode in ALL_MODES:
+        say(f"size {W}x{H} {NAMES[mode]}")
+        got = gpu_hologram(c, mode)
+        if W * H == 1:
+            assert abs(got[0, 0] - ref[0, 0]) <= TOL[mode] * max(1.0, abs(ref[0, 0])) * 10
+        else:
+            check(f"{W}x{H}", got, ref, mode)
+
+
+def test_empty_cloud_and_zero_amplitudes_give_zero():
+    import torch
+    c = cghgen.make_config(1, n=40)
+    ctx = cgh.Context(c.width, c.height, c.pitch, c.wavelength)
+    for mode in ALL_MODES:
+        say(f"empty cloud {NAMES[mode]}")
+        ctx.upload(np.zeros(0, np.float32), np.zeros(0, np.float32), np.zeros(0, np.float32),
+                   np.zeros(0, np.float32))
+        out = torch.full((c.height, c.width), 7.0, device="cuda")
+        ctx.compute(out, mode)
+        assert torch.count_nonzero(out).item() == 0
+        ctx.upload(c.x, c.y, c.z, np.zeros(c.n, np.float32))
+        out.fill_(7.0)
+        ctx.compute(out, mode)
+        assert torch.count_nonzero(out).item() == 0
+    ctx.close()
+
+
+def test_point_chunking_matches_oracle(monkeypatch):
+    """A workspace budget far below the cloud's needs forces many point
+    chunks that accumulate into the output in order."""
+    c = cghgen.make_config(1, n=3000)
+    ref = oracle.cloud_fresnel(c, rows=range(0, 256, 3))
+    monkeypatch.setenv("CGH_WORKSPACE_BYTES", str(1 << 20))
+    for mode in ALL_MODES:
+        say(f"chunked N=3000 {NAMES[mode]}")
+        got = gpu_hologram(c, mode)[0::3]
+        check("chunked", got, ref, mode)
+
+
+def test_bitwise_repeatable():
+    c = cghgen.make_config(2, n=2000)
+    for mode in ALL_MODES:
+        say(f"repeat {NAMES[mode]}")
+        a = gpu_hologram(c, mode)
+        b = gpu_hologram(c, mode)
+        assert np.array_equal(a, b), NAMES[mode]
+
+
+def test_mirror_symmetry_on_gpu():
+    c = cghgen.make_config(1, n=64)
+    m = cghgen.Cloud("mirror", c.width, c.height, c.pitch, c.wavelength, -c.x, c.y, c.z, c.amp)
+    for mode in ALL_MODES:
+        say(f"mirror {NAMES[mode]}")
+        a = gpu_hologram(c, mode)
+        b = gpu_hologram(m, mode)
+        assert oracle.nrms(b[:, ::-1], a) <= TOL[mode]
+
+
+def test_device_upload_matches_host_upload():
+    import torch
+    c = cghgen.make_config(1, n=500)
+    for mode in ALL_MODES:
+        say(f"device upload {NAMES[mode]}")
+        host = gpu_hologram(c, mode)
+        ctx = cgh.Context(c.width, c.height, c.pitch, c.wavelength)
+        ctx.upload(*[torch.from_numpy(a).cuda() for a in (c.x, c.y, c.z, c.amp)])
+        dev = gpu_hologram(c, mode, ctx)
+        ctx.close()
+        assert np.array_equal(host, dev)
+
+
+# ------------------------------------------------------------ batches
+def _batch_case():
+    counts = [0, 1, 37, 500, 2000, 33, 700]
+    return cghgen.make_batch(n_frames=len(counts), width=200, height=120, counts=counts)
+
+
+@pytest.mark.parametrize("mode", ALL_MODES, ids=[NAMES[m] for m in ALL_MODES])
+def test_batch_frames_match_oracle_and_single(mode):
+    import torch
+    b = _batch_case()
+    frames = cgh.batch_frames(b)
+    # an overlapping frame and a repeated frame
+    frames.append((int(b.offsets[3]) + 100, 1500, 532e-9))
+    frames.append(frames[4])
+    say(f"batch {len(frames)} frames {NAMES[mode]}")
+    ctx = cgh.Context(b.width, b.height, b.pitch, 532e-9)
+    ctx.upload_cloud(b)
+    out = torch.empty((len(frames), b.height, b.width), device="cuda")
+    ctx.batch_compute(frames, out, mode)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().astype(np.float64)
+    for f, (o, n, lam) in enumerate(frames):
+        sl = slice(o, o + n)
+        ref = oracle.fresnel(b.width, b.height, b.pitch, lam, b.x[sl], b.y[sl], b.z[sl],
+                             b.amp[sl])
+        if n == 0:
+            assert np.all(got[f] == 0.0)
+            continue
+        check(f"batch frame {f} N={n}", got[f], ref, mode)
+        # same numbers as a single-hologram evaluation of that frame
+        single = cgh.Context(b.width, b.height, b.pitch, lam)
+        single.upload(b.x[sl], b.y[sl], b.z[sl], b.amp[sl])
+        one = torch.empty((b.height, b.width), device="cuda")
+        single.compute(one, mode)
+        torch.cuda.synchronize()
+        assert np.array_equal(one.cpu().numpy(), out[f].cpu().numpy()), f"frame {f}"
+        single.close()
+    ctx.close()
+
+
+# ------------------------------------------------------------ error paths
+def test_error_paths_with_device():
+    import torch
+    c = cghgen.make_config(1, n=8)
+    ctx = cgh.Context(c.width, c.height, c.pitch, c.wavelength)
+    out = torch.empty((c.height, c.width), device="cuda")
+    with pytest.raises(cgh.CghError) as e:
+        ctx.compute(out, cgh.DIRECT_FP32)
+    assert e.value.status == cgh.ESTATE
+    bad_z = c.z.copy(); bad_z[3] = 0.0
+    with pytest.raises(cgh.CghError) as e:
+        ctx.upload(c.x, c.y, bad_z, c.amp)
+    assert e.value.status == cgh.EINVAL
+    bad_x = c.x.copy(); bad_x[0] = np.nan
+    with pytest.raises(cgh.CghError) as e:
+        ctx.upload(bad_x, c.y, c.z, c.amp)
+    assert e.value.status == cgh.EINVAL
+    ctx.upload_cloud(c)
+    with pytest.raises(cgh.CghError) as e:
+        ctx.compute(out, 17)
+    assert e.value.status == cgh.EINVAL
+    L = cgh.lib()
+    assert L.cgh_compute(ctx._h, 0, None, None) == cgh.EINVAL
+    with pytest.raises(cgh.CghError) as e:
+        ctx.batch_compute([(5, 4, 5e-7)], out.view(1, c.height, c.width))
+    assert e.value.status == cgh.EINVAL
+    with pytest.raises(cgh.CghError) as e:
+        ctx.batch_compute([(0, 4, -5e-7)], out.view(1, c.height, c.width))
+    assert e.value.status == cgh.EINVAL
+    f = (cgh.Frame * 1)()
+    assert L.cgh_batch_compute(ctx._h, f, 0, 0, ctypes_ptr(out), None) == cgh.EINVAL
+    ctx.close()
+
+
+def ctypes_ptr(t):
+    import ctypes
+    return ctypes.c_void_p(t.data_ptr())
