@@ -1,0 +1,184 @@
+"""Benchmark: point*pixel/s of the hologram hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Workload: a 1920 x 1080 hologram of 10,000 points (8 um pitch, 532 nm,
+x, y ~ U(+-3 mm), z ~ U[0.5, 0.6] m, A ~ U[0, 1]; seeded synthetic cloud,
+cghgen config 2), points resident in HBM before timing.  One step = one
+cgh_compute of the whole cloud in the headline mode (BF16 hi/lo split on the
+matrix cores: per-point constants, factor build, split GEMM, split-K reduce).
+The direct FP32 kernel and the other modes are timed the same way and
+reported under "modes".  NRMS and max error of every mode are measured
+against the FP64 oracle on the CPU-baseline sample (every 4th row).
+
+Prints one JSON line (rank 0).  --gpus N > 1 is refused: this build runs on
+one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# Published MI355X peaks (dense) and the issue-rate roofline of the direct kernel.
+PEAK_MFMA_BF16_TFLOPS = 2500.0
+PEAK_MFMA_FP16_TFLOPS = 2500.0
+CUS, CLOCK_HZ, LANES = 256, 2.4e9, 64
+# direct kernel: v_add_f32 (1 slot) + v_cos_f32 (2 slots, half rate) + v_fmac_f32 (1 slot)
+DIRECT_SLOTS_PER_PP = 4
+PEAK_DIRECT_PPS = CUS * CLOCK_HZ * LANES / DIRECT_SLOTS_PER_PP      # 9.83e12 point*pixel/s
+
+# executed matrix flops per point*pixel: K = 2N columns, 2 flop per MAC, x products
+FLOP_PER_PP = {"split_bf16": 12, "split_fp16": 12, "fp16": 4}
+GEMM_KERNEL = {"split_bf16": "gemm_split_mfma", "split_fp16": "gemm_split_mfma",
+               "fp16": "gemm_mfma"}
+MODE_DTYPE = {"split_bf16": "bf16", "split_fp16": "f16", "fp16": "f16", "direct_fp32": "f32"}
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--modes", default="split_bf16,direct_fp32,split_fp16,fp16",
+                    help="comma list; the first is the headline mode")
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the oracle (profiling runs)")
+    ap.add_argument("--sample-row-step", type=int, default=4)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
+        return 2
+
+    import torch
+
+    import cghgen
+    import paper_1309_2734_amd as cgh
+
+    modes = [m.strip() for m in args.modes.split(",") if m.strip()]
+    head = modes[0]
+    torch.cuda.set_device(0)
+    c = cghgen.make_config(2)
+    W, H, N = c.width, c.height, c.n
+    pp = W * H * N
+    ctx = cgh.Context(W, H, c.pitch, c.wavelength, device=0)
+    ctx.upload_cloud(c)
+    out = torch.empty((H, W), dtype=torch.float32, device="cuda:0")
+    stream = torch.cuda.current_stream()
+    rows = np.arange(0, H, args.sample_row_step)
+
+    results = {}
+    for m in modes:
+        mode = cgh.MODES[m]
+        log(f"mode {m}: warmup {args.warmup}")
+        for _ in range(args.warmup):
+            ctx.compute(out, mode, stream)
+        torch.cuda.synchronize()
+        # timed region: K whole steps between two device-wide synchronisations
+        log(f"mode {m}: timing {args.steps} steps")
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e0.record(stream)
+        for _ in range(args.steps):
+            ctx.compute(out, mode, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        wall_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        ev_ms = e0.elapsed_time(e1) / args.steps
+        # per-kernel durations: HIP events around each launch on the same stream
+        ctx.profile(True)
+        ctx.profile_reset()
+        for _ in range(args.steps):
+            ctx.compute(out, mode, stream)
+        kern = ctx.profile_read()
+        ctx.profile(False)
+        ctx.compute(out, mode, stream)
+        torch.cuda.synchronize()
+        sample = out.cpu().numpy()[rows].astype(np.float64)
+        r = {"ms_per_step": wall_ms, "ms_per_step_events": ev_ms, "pp_per_s": pp / (wall_ms * 1e-3),
+             "kernels_ms": {k: v[1] / v[0] for k, v in kern.items()}, "sample": sample,
+             "dtype": MODE_DTYPE[m]}
+        if m == "direct_fp32":
+            t = r["kernels_ms"].get("direct_fp32")
+            if t:
+                ach = pp / (t * 1e-3)
+                r["roofline"] = {"bound": "alu", "achieved": ach, "peak": PEAK_DIRECT_PPS,
+                                 "unit": "point*pixel/s", "frac": ach / PEAK_DIRECT_PPS,
+                                 "traffic": None, "kernel": "direct_fp32",
+                                 "kernel_ms": t}
+        else:
+            kname = GEMM_KERNEL[m]
+            t = r["kernels_ms"].get(kname)
+            if t:
+                flops = FLOP_PER_PP[m] * pp
+                ach = flops / (t * 1e-3) / 1e12
+                peak = PEAK_MFMA_BF16_TFLOPS if m == "split_bf16" else PEAK_MFMA_FP16_TFLOPS
+                r["roofline"] = {"bound": "mfma", "achieved": ach, "peak": peak,
+                                 "unit": "TFLOP/s", "frac": ach / peak, "traffic": None,
+                                 "kernel": kname, "kernel_ms": t}
+        log(f"mode {m}: {wall_ms:.4f} ms/step, {r['pp_per_s']:.3e} pp/s, kernels {r['kernels_ms']}")
+        results[m] = r
+    ctx.close()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        threads = oracle.host_threads()
+        log(f"oracle on {len(rows)} rows x {W} cols x {N} points, {threads} threads")
+        t0 = time.perf_counter()
+        ref = oracle.cloud_fresnel(c, rows=rows, threads=threads)
+        dt = time.perf_counter() - t0
+        sample_pp = len(rows) * W * N
+        cpu = {"value": sample_pp / dt, "unit": "point*pixel/s", "cores": threads,
+               "kind": "oracle",
+               "sample": f"every {args.sample_row_step}th row ({len(rows)} rows x {W} columns) "
+                         f"of the {W}x{H} hologram, all {N} points: {sample_pp:.3e} "
+                         f"point*pixels in {dt:.1f} s (FP64, libm cos)"}
+        import oracle as orc
+        for m, r in results.items():
+            r["nrms"] = orc.nrms(r["sample"], ref)
+            r["max_err"] = orc.max_err(r["sample"], ref)
+            log(f"mode {m}: nrms {r['nrms']:.3e} max {r['max_err']:.3e}")
+
+    h = results[head]
+    line = {
+        "metric": "point*pixel/s at 1920x1080, 10k points (direct FP32 vs MFMA split); NRMS vs FP64",
+        "value": h["pp_per_s"],
+        "unit": "point*pixel/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": h["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": h["dtype"],
+        "data": "synthetic",
+        "config": {"workload": "1920x1080 hologram, 10000 points, pitch 8 um, 532 nm, "
+                               "x,y ~ U(+-3 mm), z ~ U[0.5,0.6] m, A ~ U[0,1] (seed 2)",
+                   "mode": head, "point_pixels_per_step": pp},
+        "roofline": h.get("roofline"),
+        "cpu_baseline": cpu,
+        "modes": {m: {k: v for k, v in r.items() if k != "sample"} for m, r in results.items()},
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -24,10 +24,6 @@
 
 using namespace cgh;
 
-namespace cgh {
-bool gemm_tile_supported(int bm, int bn);
-}
-
 // ------------------------------------------------------------------ errors
 namespace {
 thread_local std::string g_last_error;
@@ -300,38 +296,57 @@ struct Plan {
     int tiles_m = 0, tiles_n = 0;
 };
 
+// Tile shape and split count for an M x N output over `slots` points.
+// CGH_GEMM_PLAN="bm,bn,stages,wg_per_cu,splits" overrides the choice (used
+// to sweep shapes; an unsupported shape is ignored).
 Plan plan_gemm(int M, int N, int64_t slots, int products)
 {
-    static const int cand[][2] = {{256, 192}, {192, 256}, {192, 192}, {256, 128},
-                                  {128, 256}, {128, 128}};
+    struct Shape {
+        int bm, bn, stages, wg;
+    };
+    static const Shape cand[] = {{192, 192, 3, 2}, {256, 128, 3, 2}, {128, 256, 3, 2},
+                                 {128, 128, 4, 2}};
     Plan best;
-    double best_cost = 1e300;
-    for (auto &t : cand) {
-        const int bm = t[0], bn = t[1];
-        if (!gemm_tile_supported(bm, bn))
-            continue;
-        const int tm = (M + bm - 1) / bm, tn = (N + bn - 1) / bn;
-        const double padded = (double)tm * bm * (double)tn * bn;
-        // prefer big tiles (operand reuse): cost = padded work / reuse factor
-        const double reuse = 2.0 * bm * bn / (bm + bn);
-        const double cost = padded * (1.0 + 64.0 / reuse);
-        if (cost < best_cost) {
-            best_cost = cost;
-            best.g.bm = bm;
-            best.g.bn = bn;
-            best.tiles_m = tm;
-            best.tiles_n = tn;
+    int forced_splits = 0;
+    const char *env = std::getenv("CGH_GEMM_PLAN");
+    Shape forced = {0, 0, 0, 0};
+    if (env && std::sscanf(env, "%d,%d,%d,%d,%d", &forced.bm, &forced.bn, &forced.stages,
+                           &forced.wg, &forced_splits) >= 4 &&
+        gemm_tile_supported(forced.bm, forced.bn, forced.stages, forced.wg)) {
+        best.g.bm = forced.bm;
+        best.g.bn = forced.bn;
+        best.g.stages = forced.stages;
+        best.g.wg_per_cu = forced.wg;
+    } else {
+        forced_splits = 0;
+        double best_cost = 1e300;
+        for (auto &t : cand) {
+            const int tm = (M + t.bm - 1) / t.bm, tn = (N + t.bn - 1) / t.bn;
+            const double padded = (double)tm * t.bm * (double)tn * t.bn;
+            // operand bytes per flop fall with the tile's harmonic size
+            const double reuse = 2.0 * t.bm * t.bn / (t.bm + t.bn);
+            const double cost = padded * (1.0 + 64.0 / reuse);
+            if (cost < best_cost) {
+                best_cost = cost;
+                best.g.bm = t.bm;
+                best.g.bn = t.bn;
+                best.g.stages = t.stages;
+                best.g.wg_per_cu = t.wg;
+            }
         }
     }
+    best.tiles_m = (M + best.g.bm - 1) / best.g.bm;
+    best.tiles_n = (N + best.g.bn - 1) / best.g.bn;
     const int tiles = best.tiles_m * best.tiles_n;
-    const int64_t stages = slots / 16;               // 2 K blocks = 16 points per stage
-    int splits = std::max(1, (256 + tiles / 2) / tiles);
-    while (splits > 1 && stages / splits < 8)
+    const int64_t kblocks = slots / 8;               // one K block = 8 points
+    // as many K splits as fit the device in one wave of workgroups
+    int splits = forced_splits > 0 ? forced_splits : std::max(1, 256 * best.g.wg_per_cu / tiles);
+    while (splits > 1 && kblocks / splits < 16)
         --splits;
     best.g.splits = splits;
     best.g.mblocks = best.tiles_m * (best.g.bm / 32);
     best.g.nblocks = best.tiles_n * (best.g.bn / 32);
-    best.g.kblocks = slots / 8;
+    best.g.kblocks = kblocks;
     best.g.products = products;
     return best;
 }

@@ -92,7 +92,9 @@ hipError_t launch_factors(PointConsts pc, int64_t slot0, int64_t n_slots, int wi
 
 // a5: split GEMM on MFMA.  See gemm.hip for the tiling.
 struct GemmPlan {
-    int bm, bn;          // macro tile (multiples of 32)
+    int bm, bn;          // macro tile (multiples of 64)
+    int stages;          // LDS ring depth (copies run stages-1 K blocks ahead)
+    int wg_per_cu;       // workgroups sharing a CU (occupancy target)
     int splits;          // K splits (1 = write the output directly)
     int64_t kblocks;     // K / 16 (padded)
     int mblocks, nblocks;// rows / 32, cols / 32 (padded)
@@ -101,6 +103,7 @@ struct GemmPlan {
 hipError_t launch_gemm(const GemmPlan &plan, FactorType ft, const void *Lh, const void *Ll,
                        const void *Rh, const void *Rl, int M, int N, float *out, int64_t ldo,
                        float *partials, bool accumulate, hipStream_t s);
+bool gemm_tile_supported(int bm, int bn, int stages, int wg_per_cu);
 hipError_t launch_splitk_reduce(const float *partials, int splits, int M, int N, float *out,
                                 int64_t ldo, bool accumulate, hipStream_t s);
 

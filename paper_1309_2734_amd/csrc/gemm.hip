@@ -8,14 +8,21 @@
 // Tiling (256 threads = 4 waves as 2 x 2):
 //   - a workgroup computes a BM x BN output tile over one K range (split-K);
 //     each wave owns a (BM/2) x (BN/2) sub-tile of 32 x 32 MFMA blocks;
-//   - a stage covers 2 K blocks (32 K-columns = 16 points); its operand
-//     blocks (1 KB each, already in MFMA lane order in memory) are copied
-//     straight into LDS with global_load_lds_dwordx4 (no register staging),
-//     two stages in flight (double buffer, one barrier per stage);
+//   - one stage = one K block (16 K-columns = 8 points).  Its operand blocks
+//     (1 KB each, already in MFMA lane order in memory) are copied straight
+//     into LDS with global_load_lds_dwordx4 (no register staging) into a ring
+//     of STAGES slots, STAGES stages ahead of the MFMAs; one barrier per
+//     stage, with per-wave vmcnt waits that let the later stages' copies stay
+//     in flight;
 //   - each wave reads its fragments with conflict-free ds_read_b128 (lane l
-//     reads bytes 16 l .. 16 l + 15 of a block) and issues, per K block,
-//     3 x (BM/64) x (BN/64) MFMAs, ordered product-major so that consecutive
-//     MFMAs never write the same accumulator.
+//     reads bytes 16 l .. 16 l + 15 of a block) and issues 3 x (BM/64) x
+//     (BN/64) MFMAs per stage, product-major, so consecutive MFMAs never write
+//     the same accumulator.  Fragments are double-buffered in registers: the
+//     barrier and the next stage's LDS reads sit in the middle of the current
+//     stage's MFMAs;
+//   - shapes with MINWG = 2 fit two workgroups per CU (<= 80 KB LDS and <= 256
+//     registers per lane each), so one workgroup's barrier and LDS waits are
+//     covered by the other's MFMAs.
 // Workgroup order: consecutive workgroup ids are dispatched round-robin over
 // the 8 XCDs, so ids are remapped to give each XCD a contiguous run of
 // (split, tile) work -- same K range, neighbouring tiles -- whose operands
@@ -33,7 +40,6 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int kXcds = 8;
 constexpr int kBlockBytes = 1024;   // one 32 x 16 operand block
-constexpr int kStageK = 2;          // K blocks per stage
 
 template <typename T>
 struct Frag;
@@ -63,32 +69,124 @@ __device__ __forceinline__ void copy_block_to_lds(const char *gsrc, char *lds_bl
         (__attribute__((address_space(3))) void *)lds_block, 16, 0, 0);
 }
 
-// LDS stage layout (blocks of 1 KB): [A hi: MB x kStageK][A lo][B hi: NB x kStageK][B lo]
+// Wait until at most N of this wave's vector-memory loads are outstanding
+// (s_waitcnt vmcnt(N), expcnt and lgkmcnt fields left at their maxima).
+template <int N>
+__device__ __forceinline__ void wait_vm()
+{
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+
+// `ahead` = later stages whose copies may stay in flight (0 .. 4).
+template <int LPS>
+__device__ __forceinline__ void wait_stages_ahead(int64_t ahead)
+{
+    if (ahead <= 0)
+        wait_vm<0>();
+    else if (ahead == 1)
+        wait_vm<LPS>();
+    else if (ahead == 2)
+        wait_vm<(2 * LPS < 64 ? 2 * LPS : 63)>();
+    else if (ahead == 3)
+        wait_vm<(3 * LPS < 64 ? 3 * LPS : 63)>();
+    else
+        wait_vm<(4 * LPS < 64 ? 4 * LPS : 63)>();
+}
+
+// Workgroup barrier for the copy ring.  It does not wait for this wave's
+// outstanding copies (a __syncthreads() fence would drain them all): the
+// caller has already waited for the stage it needs with wait_vm.  It does
+// wait for this wave's LDS reads, since other waves may overwrite the slot
+// they read once past the barrier.  The empty asm statements keep the
+// compiler from moving memory operations across it.
+__device__ __forceinline__ void ring_barrier()
+{
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0); vmcnt, expcnt at their maxima
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
+// LDS stage layout (blocks of 1 KB, one K block per stage):
+// [A hi: MB][A lo: MB][B hi: NB][B lo: NB]   (lo parts only with 3 products)
 template <int BM, int BN, int HL>
 struct StageLayout {
     static constexpr int MB = BM / 32;
     static constexpr int NB = BN / 32;
-    static constexpr int a_blocks = MB * kStageK;
-    static constexpr int b_blocks = NB * kStageK;
-    static constexpr int blocks = HL * (a_blocks + b_blocks);
+    static constexpr int blocks = HL * (MB + NB);
     static constexpr int bytes = blocks * kBlockBytes;
 };
 
-template <int BM, int BN, int PRODUCTS, typename T>
-__global__ __launch_bounds__(256, 1) void k_gemm(const char *__restrict__ Lh,
-                                                 const char *__restrict__ Ll,
-                                                 const char *__restrict__ Rh,
-                                                 const char *__restrict__ Rl, int64_t kblocks,
-                                                 int tiles_m, int tiles_n, int splits,
-                                                 int64_t stages_per_split, int M, int N,
-                                                 float *__restrict__ out, int64_t ldo,
-                                                 float *__restrict__ partials, int accumulate)
+// One stage's operand fragments of a wave: hi (and lo) parts of its FM
+// line blocks of L and FN line blocks of R.
+template <typename T, int HL, int FM, int FN>
+struct Frags {
+    typedef typename Frag<T>::type frag_t;
+    frag_t a[HL][FM], b[HL][FN];
+    // slot layout [A hi: MB][A lo: MB][B hi: NB][B lo: NB]
+    __device__ __forceinline__ void read(const char *slot, int MB, int NB, int wm, int wn, int lane)
+    {
+#pragma unroll
+        for (int r = 0; r < FM; ++r)
+            a[0][r] = *reinterpret_cast<const frag_t *>(slot + (wm * FM + r) * kBlockBytes + lane * 16);
+#pragma unroll
+        for (int c = 0; c < FN; ++c)
+            b[0][c] = *reinterpret_cast<const frag_t *>(slot + (HL * MB + wn * FN + c) * kBlockBytes +
+                                                        lane * 16);
+        if (HL == 2) {
+#pragma unroll
+            for (int c = 0; c < FN; ++c)
+                b[HL - 1][c] = *reinterpret_cast<const frag_t *>(
+                    slot + (HL * MB + NB + wn * FN + c) * kBlockBytes + lane * 16);
+#pragma unroll
+            for (int r = 0; r < FM; ++r)
+                a[HL - 1][r] = *reinterpret_cast<const frag_t *>(
+                    slot + (MB + wm * FM + r) * kBlockBytes + lane * 16);
+        }
+    }
+};
+
+// MFMAs [LO, HI) of a stage's list, ordered product-major -- hi*hi, hi*lo,
+// lo*hi -- then by line block, so consecutive MFMAs never write the same
+// accumulator.
+template <int LO, int HI, typename T, int HL, int FM, int FN>
+__device__ __forceinline__ void mfma_list(f32x16 (&acc)[FM][FN], const Frags<T, HL, FM, FN> &f)
+{
+#pragma unroll
+    for (int k = LO; k < HI; ++k) {
+        const int p = k / (FM * FN), r = (k / FN) % FM, c = k % FN;
+        const int ha = p == 2 ? HL - 1 : 0;   // lo * hi takes A's lo part
+        const int hb = p == 1 ? HL - 1 : 0;   // hi * lo takes B's lo part
+        acc[r][c] = Frag<T>::mfma(f.a[ha][r], f.b[hb][c], acc[r][c]);
+    }
+}
+
+template <int BM, int BN, int PRODUCTS, typename T, int STAGES, int MINWG>
+__global__ __launch_bounds__(256, MINWG) void k_gemm(const char *__restrict__ Lh,
+                                                     const char *__restrict__ Ll,
+                                                     const char *__restrict__ Rh,
+                                                     const char *__restrict__ Rl, int64_t kblocks,
+                                                     int tiles_m, int tiles_n, int splits,
+                                                     int64_t kb_per_split, int M, int N,
+                                                     float *__restrict__ out, int64_t ldo,
+                                                     float *__restrict__ partials, int accumulate)
 {
     constexpr int HL = PRODUCTS == 3 ? 2 : 1;
     typedef StageLayout<BM, BN, HL> SL;
     constexpr int FM = BM / 64;   // 32x32 blocks per wave along M
     constexpr int FN = BN / 64;   // ... along N
-    typedef typename Frag<T>::type frag_t;
+    constexpr int P = STAGES;     // ring slots = copy distance in stages
+    static_assert(P >= 2 && P <= 5, "ring depth");
+    // Copies per stage per wave: waves 0, 1 take L, waves 2, 3 take R -- the
+    // hi and lo parts with 3 products, else the two halves of the line blocks.
+    constexpr int LPS_A = HL == 2 ? SL::MB : SL::MB / 2;
+    constexpr int LPS_B = HL == 2 ? SL::NB : SL::NB / 2;
+    static_assert(HL == 2 || (SL::MB % 2 == 0 && SL::NB % 2 == 0), "even line blocks");
+    static_assert((P - 1) * (LPS_A > LPS_B ? LPS_A : LPS_B) < 64, "vmcnt range");
+    static_assert(P - 1 <= 4, "wait_stages_ahead covers up to 4 stages");
+    constexpr int kTotal = PRODUCTS * FM * FN;   // MFMAs per stage per wave
+    constexpr int kHalf = (kTotal + 1) / 2;
     extern __shared__ __attribute__((aligned(1024))) char lds[];
 
     // ---- which (split, tile) this workgroup computes
@@ -107,50 +205,38 @@ __global__ __launch_bounds__(256, 1) void k_gemm(const char *__restrict__ Lh,
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int wm = wave >> 1, wn = wave & 1;
 
-    const int64_t total_stages = kblocks / kStageK;
-    const int64_t s_begin = (int64_t)split * stages_per_split;
-    int64_t s_end = s_begin + stages_per_split;
-    if (s_end > total_stages)
-        s_end = total_stages;
+    const int64_t kb_begin = (int64_t)split * kb_per_split;
+    int64_t kb_end = kb_begin + kb_per_split;
+    if (kb_end > kblocks)
+        kb_end = kblocks;
+    const int64_t n_st = kb_end > kb_begin ? kb_end - kb_begin : 0;
 
-    // operand row-block bases (bytes) for this tile
+    // ---- this wave's copies: LPS line blocks from `src`, K block by K block
     const int64_t row_bytes = kblocks * kBlockBytes;   // one line block across all K
-    const char *a_src[2] = {Lh + (int64_t)tm * SL::MB * row_bytes,
-                            HL == 2 ? Ll + (int64_t)tm * SL::MB * row_bytes : nullptr};
-    const char *b_src[2] = {Rh + (int64_t)tn * SL::NB * row_bytes,
-                            HL == 2 ? Rl + (int64_t)tn * SL::NB * row_bytes : nullptr};
-
-    // Issue the copies of stage `st` into LDS buffer `buf`.  Waves 0, 1 copy
-    // L blocks, waves 2, 3 copy R blocks; with hi and lo factors, the odd wave
-    // takes the lo copy, otherwise the two waves split the line blocks.
     const int mat = wave >> 1, part = wave & 1;
-    auto issue = [&](int64_t st, int buf) {
-        char *base = lds + buf * SL::bytes;
-        const int64_t kofs = st * kStageK * (int64_t)kBlockBytes;
+    const char *src;
+    int dst_block0;
+    if (mat == 0) {
+        src = (HL == 2 && part ? Ll : Lh) +
+              ((int64_t)tm * SL::MB + (HL == 2 ? 0 : part * LPS_A)) * row_bytes;
+        dst_block0 = HL == 2 ? part * SL::MB : part * LPS_A;
+    } else {
+        src = (HL == 2 && part ? Rl : Rh) +
+              ((int64_t)tn * SL::NB + (HL == 2 ? 0 : part * LPS_B)) * row_bytes;
+        dst_block0 = HL * SL::MB + (HL == 2 ? part * SL::NB : part * LPS_B);
+    }
+    src += kb_begin * kBlockBytes;
+    auto issue = [&](int64_t i, int slot) {     // stage i (relative) into ring slot
+        char *dst = lds + slot * SL::bytes + dst_block0 * kBlockBytes;
+        const char *s0 = src + i * kBlockBytes;
         if (mat == 0) {
-            constexpr int n = HL == 2 ? SL::a_blocks : SL::a_blocks / 2;
-            const char *src = (HL == 2 ? a_src[part] : a_src[0]) + kofs;
-            char *dst = base + (HL == 2 ? part * SL::a_blocks : 0) * kBlockBytes;
-            const int first = HL == 2 ? 0 : part * n;
 #pragma unroll
-            for (int it = 0; it < n; ++it) {
-                const int i = first + it;             // i = rb * kStageK + kk
-                copy_block_to_lds(src + (int64_t)(i / kStageK) * row_bytes +
-                                      (i % kStageK) * kBlockBytes,
-                                  dst + i * kBlockBytes, lane);
-            }
+            for (int b = 0; b < LPS_A; ++b)
+                copy_block_to_lds(s0 + b * row_bytes, dst + b * kBlockBytes, lane);
         } else {
-            constexpr int n = HL == 2 ? SL::b_blocks : SL::b_blocks / 2;
-            const char *src = (HL == 2 ? b_src[part] : b_src[0]) + kofs;
-            char *dst = base + (HL * SL::a_blocks + (HL == 2 ? part * SL::b_blocks : 0)) * kBlockBytes;
-            const int first = HL == 2 ? 0 : part * n;
 #pragma unroll
-            for (int it = 0; it < n; ++it) {
-                const int i = first + it;
-                copy_block_to_lds(src + (int64_t)(i / kStageK) * row_bytes +
-                                      (i % kStageK) * kBlockBytes,
-                                  dst + i * kBlockBytes, lane);
-            }
+            for (int b = 0; b < LPS_B; ++b)
+                copy_block_to_lds(s0 + b * row_bytes, dst + b * kBlockBytes, lane);
         }
     };
 
@@ -163,54 +249,50 @@ __global__ __launch_bounds__(256, 1) void k_gemm(const char *__restrict__ Lh,
             for (int r = 0; r < 16; ++r)
                 acc[i][j][r] = 0.0f;
 
-    if (s_begin < s_end)
-        issue(s_begin, 0);
-    for (int64_t st = s_begin; st < s_end; ++st) {
-        const int buf = (int)((st - s_begin) & 1);
-        // own copies of this stage landed; then every wave's did, and every
-        // wave is done reading the other buffer
-        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-        __syncthreads();
-        if (st + 1 < s_end)
-            issue(st + 1, buf ^ 1);
-        const char *base = lds + buf * SL::bytes;
+    // Software pipeline.  Fragments of stage i sit in registers while stage
+    // i's MFMAs run; in the middle of them the workgroup passes the barrier
+    // for stage i+1, re-fills stage i's LDS slot with stage i+P's copies, and
+    // reads stage i+1's fragments into the other register set, so LDS latency
+    // hides behind the second half of stage i's MFMAs.
+    Frags<T, HL, FM, FN> f0, f1;
+    if (n_st > 0) {
 #pragma unroll
-        for (int kk = 0; kk < kStageK; ++kk) {
-            frag_t a[HL][FM], b[HL][FN];
-#pragma unroll
-            for (int h = 0; h < HL; ++h) {
-#pragma unroll
-                for (int i = 0; i < FM; ++i) {
-                    const int blk = h * SL::a_blocks + (wm * FM + i) * kStageK + kk;
-                    a[h][i] = *reinterpret_cast<const frag_t *>(base + blk * kBlockBytes + lane * 16);
-                }
-#pragma unroll
-                for (int j = 0; j < FN; ++j) {
-                    const int blk = HL * SL::a_blocks + h * SL::b_blocks + (wn * FN + j) * kStageK + kk;
-                    b[h][j] = *reinterpret_cast<const frag_t *>(base + blk * kBlockBytes + lane * 16);
-                }
-            }
-            // hi * hi
-#pragma unroll
-            for (int i = 0; i < FM; ++i)
-#pragma unroll
-                for (int j = 0; j < FN; ++j)
-                    acc[i][j] = Frag<T>::mfma(a[0][i], b[0][j], acc[i][j]);
-            if (PRODUCTS == 3) {
-                // hi * lo, then lo * hi
-#pragma unroll
-                for (int i = 0; i < FM; ++i)
-#pragma unroll
-                    for (int j = 0; j < FN; ++j)
-                        acc[i][j] = Frag<T>::mfma(a[0][i], b[HL - 1][j], acc[i][j]);
-#pragma unroll
-                for (int i = 0; i < FM; ++i)
-#pragma unroll
-                    for (int j = 0; j < FN; ++j)
-                        acc[i][j] = Frag<T>::mfma(a[HL - 1][i], b[0][j], acc[i][j]);
-            }
-        }
+        for (int i = 0; i < P; ++i)
+            if (i < n_st)
+                issue(i, i);
+        const int64_t ahead0 = (n_st - 1) < (P - 1) ? (n_st - 1) : (P - 1);
+        if (mat == 0)
+            wait_stages_ahead<LPS_A>(ahead0);
+        else
+            wait_stages_ahead<LPS_B>(ahead0);
+        ring_barrier();
+        f0.read(lds, SL::MB, SL::NB, wm, wn, lane);
     }
+    auto step = [&](int64_t i, Frags<T, HL, FM, FN> &cur, Frags<T, HL, FM, FN> &nxt) {
+        mfma_list<0, kHalf>(acc, cur);
+        if (i + 1 < n_st) {
+            // copies of stage i+1 landed (this wave's: stages i+2 .. i+P-1 may
+            // stay in flight); after the barrier every wave's did, and every
+            // wave has consumed its reads of stage i's slot
+            const int64_t ahead = (n_st - 2 - i) < (P - 2) ? (n_st - 2 - i) : (P - 2);
+            if (mat == 0)
+                wait_stages_ahead<LPS_A>(ahead);
+            else
+                wait_stages_ahead<LPS_B>(ahead);
+            ring_barrier();
+            if (i + P < n_st)
+                issue(i + P, (int)(i % P));
+            nxt.read(lds + (int)((i + 1) % P) * SL::bytes, SL::MB, SL::NB, wm, wn, lane);
+        }
+        mfma_list<kHalf, kTotal>(acc, cur);
+    };
+    int64_t i = 0;
+    for (; i + 1 < n_st; i += 2) {
+        step(i, f0, f1);
+        step(i + 1, f1, f0);
+    }
+    if (i < n_st)
+        step(i, f0, f1);
 
     // ---- epilogue: accumulator register r of a 32x32 block holds row
     // 8 (r / 4) + 4 (lane / 32) + (r mod 4), column lane mod 32.
@@ -220,18 +302,18 @@ __global__ __launch_bounds__(256, 1) void k_gemm(const char *__restrict__ Lh,
     const int64_t ld = splits == 1 ? ldo : (int64_t)N;
     const bool acc_old = splits == 1 && accumulate != 0;
 #pragma unroll
-    for (int i = 0; i < FM; ++i)
+    for (int r0 = 0; r0 < FM; ++r0)
 #pragma unroll
-        for (int j = 0; j < FN; ++j) {
-            const int col = col_base + j * 32 + (lane & 31);
+        for (int c0 = 0; c0 < FN; ++c0) {
+            const int col = col_base + c0 * 32 + (lane & 31);
             if (col >= N)
                 continue;
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
-                const int row = row_base + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                const int row = row_base + r0 * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
                 if (row < M) {
                     float *p = dst + (int64_t)row * ld + col;
-                    *p = acc_old ? *p + acc[i][j][r] : acc[i][j][r];
+                    *p = acc_old ? *p + acc[r0][c0][r] : acc[r0][c0][r];
                 }
             }
         }
@@ -255,22 +337,21 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(const float *__restrict__
     }
 }
 
-template <int BM, int BN, int PRODUCTS, typename T>
+template <int BM, int BN, int PRODUCTS, typename T, int STAGES, int MINWG>
 hipError_t launch_tile(const GemmPlan &plan, const void *Lh, const void *Ll, const void *Rh,
                        const void *Rl, int M, int N, float *out, int64_t ldo, float *partials,
                        bool accumulate, hipStream_t s)
 {
     constexpr int HL = PRODUCTS == 3 ? 2 : 1;
-    const int lds_bytes = 2 * StageLayout<BM, BN, HL>::bytes;
-    auto kern = k_gemm<BM, BN, PRODUCTS, T>;
+    const int lds_bytes = STAGES * StageLayout<BM, BN, HL>::bytes;
+    auto kern = k_gemm<BM, BN, PRODUCTS, T, STAGES, MINWG>;
     hipError_t e = hipFuncSetAttribute((const void *)kern,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
     if (e != hipSuccess)
         return e;
     const int tiles_m = plan.mblocks / (BM / 32);
     const int tiles_n = plan.nblocks / (BN / 32);
-    const int64_t total_stages = plan.kblocks / kStageK;
-    const int64_t per = (total_stages + plan.splits - 1) / plan.splits;
+    const int64_t per = (plan.kblocks + plan.splits - 1) / plan.splits;
     const int total = tiles_m * tiles_n * plan.splits;
     const int grid = (total + kXcds - 1) / kXcds * kXcds;
     hipLaunchKernelGGL(kern, dim3(grid), dim3(256), lds_bytes, s, (const char *)Lh,
@@ -280,31 +361,42 @@ hipError_t launch_tile(const GemmPlan &plan, const void *Lh, const void *Ll, con
     return hipGetLastError();
 }
 
+// Built shapes: (BM, BN, ring depth, workgroups per CU).
+#define CGH_GEMM_SHAPES(X)                                                                     \
+    X(192, 192, 3, 2)                                                                          \
+    X(192, 192, 5, 1)                                                                          \
+    X(256, 192, 4, 1)                                                                          \
+    X(192, 256, 4, 1)                                                                          \
+    X(256, 128, 5, 1)                                                                          \
+    X(128, 256, 5, 1)                                                                          \
+    X(128, 128, 4, 2)                                                                          \
+    X(128, 256, 3, 2)                                                                          \
+    X(256, 128, 3, 2)
+
 template <int PRODUCTS, typename T>
 hipError_t launch_products(const GemmPlan &plan, const void *Lh, const void *Ll, const void *Rh,
                            const void *Rl, int M, int N, float *out, int64_t ldo,
                            float *partials, bool accumulate, hipStream_t s)
 {
-#define CGH_TILE(TBM, TBN)                                                                    \
-    if (plan.bm == TBM && plan.bn == TBN)                                                     \
-        return launch_tile<TBM, TBN, PRODUCTS, T>(plan, Lh, Ll, Rh, Rl, M, N, out, ldo,         \
-                                                  partials, accumulate, s);
-    CGH_TILE(256, 192)
-    CGH_TILE(192, 256)
-    CGH_TILE(192, 192)
-    CGH_TILE(128, 256)
-    CGH_TILE(256, 128)
-    CGH_TILE(128, 128)
+#define CGH_TILE(TBM, TBN, TST, TWG)                                                          \
+    if (plan.bm == TBM && plan.bn == TBN && plan.stages == TST && plan.wg_per_cu == TWG)      \
+        return launch_tile<TBM, TBN, PRODUCTS, T, TST, TWG>(plan, Lh, Ll, Rh, Rl, M, N, out,  \
+                                                            ldo, partials, accumulate, s);
+    CGH_GEMM_SHAPES(CGH_TILE)
 #undef CGH_TILE
     return hipErrorInvalidValue;
 }
 
 }  // namespace
 
-bool gemm_tile_supported(int bm, int bn)
+bool gemm_tile_supported(int bm, int bn, int stages, int wg_per_cu)
 {
-    return (bm == 256 && (bn == 192 || bn == 128)) ||
-           (bm == 192 && (bn == 256 || bn == 192)) || (bm == 128 && (bn == 256 || bn == 128));
+#define CGH_TILE(TBM, TBN, TST, TWG)                                                          \
+    if (bm == TBM && bn == TBN && stages == TST && wg_per_cu == TWG)                          \
+        return true;
+    CGH_GEMM_SHAPES(CGH_TILE)
+#undef CGH_TILE
+    return false;
 }
 
 hipError_t launch_gemm(const GemmPlan &plan, FactorType ft, const void *Lh, const void *Ll,
