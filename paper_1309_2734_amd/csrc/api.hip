@@ -297,26 +297,27 @@ struct Plan {
 };
 
 // Tile shape and split count for an M x N output over `slots` points.
-// CGH_GEMM_PLAN="bm,bn,stages,wg_per_cu,splits" overrides the choice (used
-// to sweep shapes; an unsupported shape is ignored).
+// CGH_GEMM_PLAN="bm,bn,waves_m,waves_n,stages,splits" overrides the choice
+// (used to sweep shapes; an unsupported shape is ignored, splits 0 = auto).
 Plan plan_gemm(int M, int N, int64_t slots, int products)
 {
     struct Shape {
-        int bm, bn, stages, wg;
+        int bm, bn, wm, wn, stages;
     };
-    static const Shape cand[] = {{192, 192, 3, 2}, {256, 128, 3, 2}, {128, 256, 3, 2},
-                                 {128, 128, 4, 2}};
+    static const Shape cand[] = {{192, 384, 2, 4, 2}, {384, 192, 4, 2, 2}, {192, 256, 2, 4, 2},
+                                 {256, 256, 2, 4, 2}, {128, 256, 2, 4, 2}};
     Plan best;
     int forced_splits = 0;
+    Shape forced = {0, 0, 0, 0, 0};
     const char *env = std::getenv("CGH_GEMM_PLAN");
-    Shape forced = {0, 0, 0, 0};
-    if (env && std::sscanf(env, "%d,%d,%d,%d,%d", &forced.bm, &forced.bn, &forced.stages,
-                           &forced.wg, &forced_splits) >= 4 &&
-        gemm_tile_supported(forced.bm, forced.bn, forced.stages, forced.wg)) {
+    if (env && std::sscanf(env, "%d,%d,%d,%d,%d,%d", &forced.bm, &forced.bn, &forced.wm,
+                           &forced.wn, &forced.stages, &forced_splits) >= 5 &&
+        gemm_tile_supported(forced.bm, forced.bn, forced.wm, forced.wn, forced.stages)) {
         best.g.bm = forced.bm;
         best.g.bn = forced.bn;
+        best.g.waves_m = forced.wm;
+        best.g.waves_n = forced.wn;
         best.g.stages = forced.stages;
-        best.g.wg_per_cu = forced.wg;
     } else {
         forced_splits = 0;
         double best_cost = 1e300;
@@ -330,22 +331,23 @@ Plan plan_gemm(int M, int N, int64_t slots, int products)
                 best_cost = cost;
                 best.g.bm = t.bm;
                 best.g.bn = t.bn;
+                best.g.waves_m = t.wm;
+                best.g.waves_n = t.wn;
                 best.g.stages = t.stages;
-                best.g.wg_per_cu = t.wg;
             }
         }
     }
     best.tiles_m = (M + best.g.bm - 1) / best.g.bm;
     best.tiles_n = (N + best.g.bn - 1) / best.g.bn;
     const int tiles = best.tiles_m * best.tiles_n;
-    const int64_t kblocks = slots / 8;               // one K block = 8 points
-    // as many K splits as fit the device in one wave of workgroups
-    int splits = forced_splits > 0 ? forced_splits : std::max(1, 256 * best.g.wg_per_cu / tiles);
-    while (splits > 1 && kblocks / splits < 16)
+    const int64_t kblocks = slots / kFragPoints;
+    // as many K splits as fit the device (one workgroup per CU) in one wave
+    int splits = forced_splits > 0 ? forced_splits : std::max(1, 256 / tiles);
+    while (splits > 1 && kblocks / splits < 8)
         --splits;
     best.g.splits = splits;
-    best.g.mblocks = best.tiles_m * (best.g.bm / 32);
-    best.g.nblocks = best.tiles_n * (best.g.bn / 32);
+    best.g.mblocks = best.tiles_m * (best.g.bm / kFragLines);
+    best.g.nblocks = best.tiles_n * (best.g.bn / kFragLines);
     best.g.kblocks = kblocks;
     best.g.products = products;
     return best;
@@ -392,8 +394,9 @@ cgh_status run_gemm(cgh_ctx *c, int mode, int64_t slot0, int64_t slots, float *o
     const FactorType ft = mode == CGH_SPLIT_BF16 ? FactorType::BF16 : FactorType::FP16;
     const Plan p = plan_gemm(c->height, c->width, slots, split ? 3 : 1);
     const int hl = split ? 2 : 1;
-    const size_t lbytes = (size_t)p.g.mblocks * 32 * (size_t)slots * 2 * 2;
-    const size_t rbytes = (size_t)p.g.nblocks * 32 * (size_t)slots * 2 * 2;
+    // 2 K-columns (cos, sin) of 2 bytes per line and point
+    const size_t lbytes = (size_t)p.g.mblocks * kFragLines * (size_t)slots * 2 * 2;
+    const size_t rbytes = (size_t)p.g.nblocks * kFragLines * (size_t)slots * 2 * 2;
     CGH_HIP(ensure_ws(c, c->fac[0], lbytes), "factor allocation");
     CGH_HIP(ensure_ws(c, c->fac[2], rbytes), "factor allocation");
     if (hl == 2) {
@@ -437,7 +440,7 @@ size_t bytes_per_slot(cgh_ctx *c, int mode)
     if (mode == CGH_DIRECT_FP32)
         return (size_t)(c->wpad + c->hpad) * sizeof(float);
     const int hl = (mode == CGH_SPLIT_BF16 || mode == CGH_SPLIT_FP16) ? 2 : 1;
-    return (size_t)(round_up(c->width, 256) + round_up(c->height, 256)) * 2 * 2 * hl;
+    return (size_t)(round_up(c->width, 384) + round_up(c->height, 384)) * 2 * 2 * hl;
 }
 
 int64_t chunk_slots(cgh_ctx *c, int mode)

@@ -29,6 +29,10 @@ constexpr int kGroup = 16;
 constexpr int kSlotAlign = 32;
 // Line tables are padded to a multiple of this many columns / rows.
 constexpr int kLinePad = 64;
+// Matrix-core operand blocks (factors.hip, gemm.hip): 16 lines x 32
+// K-columns = 16 points, 1 KB in bf16/f16.
+constexpr int kFragLines = 16;
+constexpr int kFragPoints = 16;
 
 // Per-point constants of one evaluation segment, structure of arrays.
 struct PointConsts {
@@ -84,7 +88,9 @@ hipError_t launch_separable_fp32(const float *U, const float *V, const float *am
                                  hipStream_t s);
 
 // a4: factor build.  Writes the hi (and, if lo_* != nullptr, lo) factors of
-// L (rows) and R (columns) in the MFMA fragment order described in factors.hip.
+// L (rows) and R (columns) in the MFMA fragment order described in factors.hip:
+// mblocks / nblocks blocks of kFragLines lines, kblocks blocks of kFragPoints
+// points.
 enum class FactorType { BF16 = 0, FP16 = 1 };
 hipError_t launch_factors(PointConsts pc, int64_t slot0, int64_t n_slots, int width, int height,
                           int64_t kblocks, int mblocks, int nblocks, FactorType ft,
@@ -92,18 +98,18 @@ hipError_t launch_factors(PointConsts pc, int64_t slot0, int64_t n_slots, int wi
 
 // a5: split GEMM on MFMA.  See gemm.hip for the tiling.
 struct GemmPlan {
-    int bm, bn;          // macro tile (multiples of 64)
+    int bm, bn;          // macro tile (multiples of 32)
+    int waves_m, waves_n;// wave grid of a workgroup (4 or 8 waves)
     int stages;          // LDS ring depth (copies run stages-1 K blocks ahead)
-    int wg_per_cu;       // workgroups sharing a CU (occupancy target)
     int splits;          // K splits (1 = write the output directly)
-    int64_t kblocks;     // K / 16 (padded)
-    int mblocks, nblocks;// rows / 32, cols / 32 (padded)
+    int64_t kblocks;     // K blocks of kFragPoints points
+    int mblocks, nblocks;// line blocks of kFragLines (padded to whole tiles)
     int products;        // 3 = hi*hi + hi*lo + lo*hi, 1 = hi*hi only
 };
 hipError_t launch_gemm(const GemmPlan &plan, FactorType ft, const void *Lh, const void *Ll,
                        const void *Rh, const void *Rl, int M, int N, float *out, int64_t ldo,
                        float *partials, bool accumulate, hipStream_t s);
-bool gemm_tile_supported(int bm, int bn, int stages, int wg_per_cu);
+bool gemm_tile_supported(int bm, int bn, int waves_m, int waves_n, int stages);
 hipError_t launch_splitk_reduce(const float *partials, int splits, int M, int N, float *out,
                                 int64_t ldo, bool accumulate, hipStream_t s);
 

@@ -9,10 +9,10 @@
 // Each value v is stored as hi = round(v) and lo = round(v - hi) in the
 // 16-bit type (round to nearest even; v - hi is exact in FP32).
 //
-// Storage order = the operand order of v_mfma_f32_32x32x16_{bf16,f16}: the
-// matrix is cut into blocks of 32 lines x 16 K-columns (8 points); a block
-// is 64 lanes x 8 values = 1 KB, lane l holding line (l mod 32) and
-// K-columns 8 (l / 32) .. 8 (l / 32) + 7 of the block, i.e. 4 points'
+// Storage order = the operand order of v_mfma_f32_16x16x32_{bf16,f16}: the
+// matrix is cut into blocks of 16 lines x 32 K-columns (16 points); a block
+// is 64 lanes x 8 values = 1 KB, lane l holding line (l mod 16) and
+// K-columns 8 (l / 16) .. 8 (l / 16) + 7 of the block, i.e. 4 points'
 // (cos, sin) pairs.  Blocks are ordered [line block][K block], so a GEMM
 // stage copies whole 1 KB blocks straight into LDS.  Lines past the
 // hologram are written as zeros.
@@ -47,9 +47,9 @@ __global__ __launch_bounds__(256) void k_factors(PointConsts pc, int64_t slot0, 
     const int64_t kb = t >> 6;
     const bool is_l = (int)blockIdx.y < mblocks;
     const int rb = is_l ? (int)blockIdx.y : (int)blockIdx.y - mblocks;
-    const int line = rb * 32 + (lane & 31);
+    const int line = rb * kFragLines + (lane & (kFragLines - 1));
     const int lines = is_l ? height : width;
-    const int64_t j0 = slot0 + kb * 8 + 4 * (lane >> 5);
+    const int64_t j0 = slot0 + kb * kFragPoints + 4 * (lane / kFragLines);
 
     Vec8<T> hi, lo;
 #pragma unroll

@@ -3,26 +3,28 @@
 // I[iy, ix] = sum_k L[iy, k] R[ix, k] (K = 2N, see factors.hip), evaluated as
 //     Lh Rh^T + Lh Rl^T + Ll Rh^T        (3 products; Ll Rl^T is below FP32 noise)
 // or Lh Rh^T alone, in BF16 or FP16 with FP32 accumulation, using
-// v_mfma_f32_32x32x16_{bf16,f16}.
+// v_mfma_f32_16x16x32_{bf16,f16} (the 16x16 shape keeps the matrix pipe
+// busier than the 32x32 one on gfx950).
 //
-// Tiling (256 threads = 4 waves as 2 x 2):
-//   - a workgroup computes a BM x BN output tile over one K range (split-K);
-//     each wave owns a (BM/2) x (BN/2) sub-tile of 32 x 32 MFMA blocks;
-//   - one stage = one K block (16 K-columns = 8 points).  Its operand blocks
-//     (1 KB each, already in MFMA lane order in memory) are copied straight
-//     into LDS with global_load_lds_dwordx4 (no register staging) into a ring
-//     of STAGES slots, STAGES stages ahead of the MFMAs; one barrier per
-//     stage, with per-wave vmcnt waits that let the later stages' copies stay
-//     in flight;
+// Tiling:
+//   - a workgroup of WM x WN waves computes a BM x BN output tile over one
+//     K range (split-K); each wave owns a (BM/WM) x (BN/WN) sub-tile of
+//     16 x 16 MFMA blocks, its accumulators in registers;
+//   - one stage = one K block (32 K-columns = 16 points).  Its operand
+//     blocks (1 KB each, already in MFMA lane order in memory) are copied
+//     straight into LDS with global_load_lds_dwordx4 (no register staging)
+//     into a ring of STAGES slots, STAGES-1 stages ahead of the MFMAs.  The
+//     copies of a stage are dealt evenly to all waves.  One barrier per
+//     stage; its per-wave vmcnt wait lets later stages' copies stay in flight
+//     (a __syncthreads() fence would drain them);
 //   - each wave reads its fragments with conflict-free ds_read_b128 (lane l
-//     reads bytes 16 l .. 16 l + 15 of a block) and issues 3 x (BM/64) x
-//     (BN/64) MFMAs per stage, product-major, so consecutive MFMAs never write
-//     the same accumulator.  Fragments are double-buffered in registers: the
-//     barrier and the next stage's LDS reads sit in the middle of the current
-//     stage's MFMAs;
-//   - shapes with MINWG = 2 fit two workgroups per CU (<= 80 KB LDS and <= 256
-//     registers per lane each), so one workgroup's barrier and LDS waits are
-//     covered by the other's MFMAs.
+//     reads bytes 16 l .. 16 l + 15 of a block) in product order -- A hi and
+//     B hi for hi*hi, then B lo for hi*lo, then A lo for lo*hi -- so reads
+//     overlap the MFMAs of the previous product, and issues the MFMAs of each
+//     product over all its blocks before the next, so consecutive MFMAs never
+//     write the same accumulator.
+// Eight-wave shapes put two waves on each SIMD; one wave's waits are covered
+// by the other's MFMAs.
 // Workgroup order: consecutive workgroup ids are dispatched round-robin over
 // the 8 XCDs, so ids are remapped to give each XCD a contiguous run of
 // (split, tile) work -- same K range, neighbouring tiles -- whose operands
@@ -36,27 +38,27 @@ namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
-typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kXcds = 8;
-constexpr int kBlockBytes = 1024;   // one 32 x 16 operand block
+constexpr int kBlockBytes = 1024;   // one 16-line x 32-K operand block
 
 template <typename T>
 struct Frag;
 template <>
 struct Frag<__bf16> {
     typedef bf16x8 type;
-    static __device__ __forceinline__ f32x16 mfma(type a, type b, f32x16 c)
+    static __device__ __forceinline__ f32x4 mfma(type a, type b, f32x4 c)
     {
-        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
     }
 };
 template <>
 struct Frag<_Float16> {
     typedef f16x8 type;
-    static __device__ __forceinline__ f32x16 mfma(type a, type b, f32x16 c)
+    static __device__ __forceinline__ f32x4 mfma(type a, type b, f32x4 c)
     {
-        return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
     }
 };
 
@@ -78,25 +80,22 @@ __device__ __forceinline__ void wait_vm()
     __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
 }
 
-// `ahead` = later stages whose copies may stay in flight (0 .. 4).
+// `ahead` = later stages whose copies may stay in flight (0 .. 3).
 template <int LPS>
 __device__ __forceinline__ void wait_stages_ahead(int64_t ahead)
 {
     if (ahead <= 0)
         wait_vm<0>();
     else if (ahead == 1)
-        wait_vm<LPS>();
+        wait_vm<(LPS < 64 ? LPS : 63)>();
     else if (ahead == 2)
         wait_vm<(2 * LPS < 64 ? 2 * LPS : 63)>();
-    else if (ahead == 3)
-        wait_vm<(3 * LPS < 64 ? 3 * LPS : 63)>();
     else
-        wait_vm<(4 * LPS < 64 ? 4 * LPS : 63)>();
+        wait_vm<(3 * LPS < 64 ? 3 * LPS : 63)>();
 }
 
 // Workgroup barrier for the copy ring.  It does not wait for this wave's
-// outstanding copies (a __syncthreads() fence would drain them all): the
-// caller has already waited for the stage it needs with wait_vm.  It does
+// outstanding copies (the caller has waited for the stage it needs); it does
 // wait for this wave's LDS reads, since other waves may overwrite the slot
 // they read once past the barrier.  The empty asm statements keep the
 // compiler from moving memory operations across it.
@@ -108,85 +107,30 @@ __device__ __forceinline__ void ring_barrier()
     asm volatile("" ::: "memory");
 }
 
-// LDS stage layout (blocks of 1 KB, one K block per stage):
-// [A hi: MB][A lo: MB][B hi: NB][B lo: NB]   (lo parts only with 3 products)
-template <int BM, int BN, int HL>
-struct StageLayout {
-    static constexpr int MB = BM / 32;
-    static constexpr int NB = BN / 32;
-    static constexpr int blocks = HL * (MB + NB);
-    static constexpr int bytes = blocks * kBlockBytes;
-};
-
-// One stage's operand fragments of a wave: hi (and lo) parts of its FM
-// line blocks of L and FN line blocks of R.
-template <typename T, int HL, int FM, int FN>
-struct Frags {
-    typedef typename Frag<T>::type frag_t;
-    frag_t a[HL][FM], b[HL][FN];
-    // slot layout [A hi: MB][A lo: MB][B hi: NB][B lo: NB]
-    __device__ __forceinline__ void read(const char *slot, int MB, int NB, int wm, int wn, int lane)
-    {
-#pragma unroll
-        for (int r = 0; r < FM; ++r)
-            a[0][r] = *reinterpret_cast<const frag_t *>(slot + (wm * FM + r) * kBlockBytes + lane * 16);
-#pragma unroll
-        for (int c = 0; c < FN; ++c)
-            b[0][c] = *reinterpret_cast<const frag_t *>(slot + (HL * MB + wn * FN + c) * kBlockBytes +
-                                                        lane * 16);
-        if (HL == 2) {
-#pragma unroll
-            for (int c = 0; c < FN; ++c)
-                b[HL - 1][c] = *reinterpret_cast<const frag_t *>(
-                    slot + (HL * MB + NB + wn * FN + c) * kBlockBytes + lane * 16);
-#pragma unroll
-            for (int r = 0; r < FM; ++r)
-                a[HL - 1][r] = *reinterpret_cast<const frag_t *>(
-                    slot + (MB + wm * FM + r) * kBlockBytes + lane * 16);
-        }
-    }
-};
-
-// MFMAs [LO, HI) of a stage's list, ordered product-major -- hi*hi, hi*lo,
-// lo*hi -- then by line block, so consecutive MFMAs never write the same
-// accumulator.
-template <int LO, int HI, typename T, int HL, int FM, int FN>
-__device__ __forceinline__ void mfma_list(f32x16 (&acc)[FM][FN], const Frags<T, HL, FM, FN> &f)
+template <int BM, int BN, int WM, int WN, int PRODUCTS, typename T, int STAGES>
+__global__ __launch_bounds__(64 * WM * WN, 1) void k_gemm(
+    const char *__restrict__ Lh, const char *__restrict__ Ll, const char *__restrict__ Rh,
+    const char *__restrict__ Rl, int64_t kblocks, int tiles_m, int tiles_n, int splits,
+    int64_t kb_per_split, int M, int N, float *__restrict__ out, int64_t ldo,
+    float *__restrict__ partials, int accumulate)
 {
-#pragma unroll
-    for (int k = LO; k < HI; ++k) {
-        const int p = k / (FM * FN), r = (k / FN) % FM, c = k % FN;
-        const int ha = p == 2 ? HL - 1 : 0;   // lo * hi takes A's lo part
-        const int hb = p == 1 ? HL - 1 : 0;   // hi * lo takes B's lo part
-        acc[r][c] = Frag<T>::mfma(f.a[ha][r], f.b[hb][c], acc[r][c]);
-    }
-}
-
-template <int BM, int BN, int PRODUCTS, typename T, int STAGES, int MINWG>
-__global__ __launch_bounds__(256, MINWG) void k_gemm(const char *__restrict__ Lh,
-                                                     const char *__restrict__ Ll,
-                                                     const char *__restrict__ Rh,
-                                                     const char *__restrict__ Rl, int64_t kblocks,
-                                                     int tiles_m, int tiles_n, int splits,
-                                                     int64_t kb_per_split, int M, int N,
-                                                     float *__restrict__ out, int64_t ldo,
-                                                     float *__restrict__ partials, int accumulate)
-{
+    constexpr int NW = WM * WN;
     constexpr int HL = PRODUCTS == 3 ? 2 : 1;
-    typedef StageLayout<BM, BN, HL> SL;
-    constexpr int FM = BM / 64;   // 32x32 blocks per wave along M
-    constexpr int FN = BN / 64;   // ... along N
-    constexpr int P = STAGES;     // ring slots = copy distance in stages
-    static_assert(P >= 2 && P <= 5, "ring depth");
-    // Copies per stage per wave: waves 0, 1 take L, waves 2, 3 take R -- the
-    // hi and lo parts with 3 products, else the two halves of the line blocks.
-    constexpr int LPS_A = HL == 2 ? SL::MB : SL::MB / 2;
-    constexpr int LPS_B = HL == 2 ? SL::NB : SL::NB / 2;
-    static_assert(HL == 2 || (SL::MB % 2 == 0 && SL::NB % 2 == 0), "even line blocks");
-    static_assert((P - 1) * (LPS_A > LPS_B ? LPS_A : LPS_B) < 64, "vmcnt range");
-    static_assert(P - 1 <= 4, "wait_stages_ahead covers up to 4 stages");
-    constexpr int kTotal = PRODUCTS * FM * FN;   // MFMAs per stage per wave
-    constexpr int kHalf = (kTotal + 1) / 2;
+    constexpr int MB = BM / kFragLines;          // line blocks per tile
+    constexpr int NB = BN / kFragLines;
+    constexpr int FM = MB / WM;                  // MFMA blocks per wave along M
+    constexpr int FN = NB / WN;                  // ... along N
+    static_assert(MB % WM == 0 && NB % WN == 0, "tile splits evenly over waves");
+    constexpr int SLOT_BLOCKS = HL * (MB + NB);  // [A hi: MB][A lo: MB][B hi: NB][B lo: NB]
+    constexpr int SLOT_BYTES = SLOT_BLOCKS * kBlockBytes;
+    constexpr int P = STAGES - 1;                // copy distance in stages
+    static_assert(P >= 1 && P <= 4, "ring depth");
+    // copies per stage per wave (at most); with copies more than one stage
+    // ahead every wave must issue the same number, for its vmcnt waits
+    constexpr int LPS = (SLOT_BLOCKS + NW - 1) / NW;
+    static_assert(SLOT_BLOCKS % NW == 0 || P == 1, "stage copies deal evenly");
+    static_assert((P - 1) * LPS < 64, "vmcnt range");
+    typedef typename Frag<T>::type frag_t;
     extern __shared__ __attribute__((aligned(1024))) char lds[];
 
     // ---- which (split, tile) this workgroup computes
@@ -203,7 +147,7 @@ __global__ __launch_bounds__(256, MINWG) void k_gemm(const char *__restrict__ Lh
 
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int wm = wave >> 1, wn = wave & 1;
+    const int wm = wave / WN, wn = wave % WN;
 
     const int64_t kb_begin = (int64_t)split * kb_per_split;
     int64_t kb_end = kb_begin + kb_per_split;
@@ -211,93 +155,98 @@ __global__ __launch_bounds__(256, MINWG) void k_gemm(const char *__restrict__ Lh
         kb_end = kblocks;
     const int64_t n_st = kb_end > kb_begin ? kb_end - kb_begin : 0;
 
-    // ---- this wave's copies: LPS line blocks from `src`, K block by K block
+    // ---- this wave's copies: slot blocks wave, wave + NW, ...
     const int64_t row_bytes = kblocks * kBlockBytes;   // one line block across all K
-    const int mat = wave >> 1, part = wave & 1;
-    const char *src;
-    int dst_block0;
-    if (mat == 0) {
-        src = (HL == 2 && part ? Ll : Lh) +
-              ((int64_t)tm * SL::MB + (HL == 2 ? 0 : part * LPS_A)) * row_bytes;
-        dst_block0 = HL == 2 ? part * SL::MB : part * LPS_A;
-    } else {
-        src = (HL == 2 && part ? Rl : Rh) +
-              ((int64_t)tn * SL::NB + (HL == 2 ? 0 : part * LPS_B)) * row_bytes;
-        dst_block0 = HL * SL::MB + (HL == 2 ? part * SL::NB : part * LPS_B);
-    }
-    src += kb_begin * kBlockBytes;
-    auto issue = [&](int64_t i, int slot) {     // stage i (relative) into ring slot
-        char *dst = lds + slot * SL::bytes + dst_block0 * kBlockBytes;
-        const char *s0 = src + i * kBlockBytes;
-        if (mat == 0) {
+    const char *csrc[LPS];
 #pragma unroll
-            for (int b = 0; b < LPS_A; ++b)
-                copy_block_to_lds(s0 + b * row_bytes, dst + b * kBlockBytes, lane);
+    for (int c = 0; c < LPS; ++c) {
+        const int b = (wave + NW * c) % SLOT_BLOCKS;   // wrapped entries are not copied
+        const char *base;
+        int64_t line_block;
+        if (b < HL * MB) {
+            base = (HL == 2 && b >= MB) ? Ll : Lh;
+            line_block = (int64_t)tm * MB + (b % MB);
         } else {
-#pragma unroll
-            for (int b = 0; b < LPS_B; ++b)
-                copy_block_to_lds(s0 + b * row_bytes, dst + b * kBlockBytes, lane);
+            const int bb = b - HL * MB;
+            base = (HL == 2 && bb >= NB) ? Rl : Rh;
+            line_block = (int64_t)tn * NB + (bb % NB);
         }
+        csrc[c] = base + line_block * row_bytes + kb_begin * kBlockBytes;
+    }
+    auto issue = [&](int64_t i, int slot) {     // stage i (relative) into ring slot
+        char *dst = lds + slot * SLOT_BYTES;
+#pragma unroll
+        for (int c = 0; c < LPS; ++c)
+            if (SLOT_BLOCKS % NW == 0 || wave + NW * c < SLOT_BLOCKS)
+                copy_block_to_lds(csrc[c] + i * kBlockBytes,
+                                  dst + (wave + NW * c) * kBlockBytes, lane);
     };
 
-    f32x16 acc[FM][FN];
+    f32x4 acc[FM][FN];
 #pragma unroll
     for (int i = 0; i < FM; ++i)
 #pragma unroll
         for (int j = 0; j < FN; ++j)
-#pragma unroll
-            for (int r = 0; r < 16; ++r)
-                acc[i][j][r] = 0.0f;
+            acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 
-    // Software pipeline.  Fragments of stage i sit in registers while stage
-    // i's MFMAs run; in the middle of them the workgroup passes the barrier
-    // for stage i+1, re-fills stage i's LDS slot with stage i+P's copies, and
-    // reads stage i+1's fragments into the other register set, so LDS latency
-    // hides behind the second half of stage i's MFMAs.
-    Frags<T, HL, FM, FN> f0, f1;
-    if (n_st > 0) {
 #pragma unroll
-        for (int i = 0; i < P; ++i)
-            if (i < n_st)
-                issue(i, i);
-        const int64_t ahead0 = (n_st - 1) < (P - 1) ? (n_st - 1) : (P - 1);
-        if (mat == 0)
-            wait_stages_ahead<LPS_A>(ahead0);
-        else
-            wait_stages_ahead<LPS_B>(ahead0);
+    for (int i = 0; i < P; ++i)
+        if (i < n_st)
+            issue(i, i);
+    int slot = 0;
+    for (int64_t i = 0; i < n_st; ++i) {
+        // this wave's copies of stage i landed; later stages may stay in flight
+        const int64_t ahead = (n_st - 1 - i) < (P - 1) ? (n_st - 1 - i) : (P - 1);
+        wait_stages_ahead<LPS>(ahead);
+        // every wave's copies of stage i landed, and every wave is done with
+        // stage i-1's slot, which the next copy overwrites
         ring_barrier();
-        f0.read(lds, SL::MB, SL::NB, wm, wn, lane);
-    }
-    auto step = [&](int64_t i, Frags<T, HL, FM, FN> &cur, Frags<T, HL, FM, FN> &nxt) {
-        mfma_list<0, kHalf>(acc, cur);
-        if (i + 1 < n_st) {
-            // copies of stage i+1 landed (this wave's: stages i+2 .. i+P-1 may
-            // stay in flight); after the barrier every wave's did, and every
-            // wave has consumed its reads of stage i's slot
-            const int64_t ahead = (n_st - 2 - i) < (P - 2) ? (n_st - 2 - i) : (P - 2);
-            if (mat == 0)
-                wait_stages_ahead<LPS_A>(ahead);
-            else
-                wait_stages_ahead<LPS_B>(ahead);
-            ring_barrier();
-            if (i + P < n_st)
-                issue(i + P, (int)(i % P));
-            nxt.read(lds + (int)((i + 1) % P) * SL::bytes, SL::MB, SL::NB, wm, wn, lane);
+        if (i + P < n_st)
+            issue(i + P, slot == 0 ? P : slot - 1);
+        const char *sb = lds + slot * SLOT_BYTES + lane * 16;
+        auto blk = [&](int b) { return *reinterpret_cast<const frag_t *>(sb + b * kBlockBytes); };
+        frag_t ah[FM], bh[FN];
+#pragma unroll
+        for (int r = 0; r < FM; ++r)
+            ah[r] = blk(wm * FM + r);
+#pragma unroll
+        for (int c = 0; c < FN; ++c)
+            bh[c] = blk(HL * MB + wn * FN + c);
+        // hi * hi
+#pragma unroll
+        for (int r = 0; r < FM; ++r)
+#pragma unroll
+            for (int c = 0; c < FN; ++c)
+                acc[r][c] = Frag<T>::mfma(ah[r], bh[c], acc[r][c]);
+        if (PRODUCTS == 3) {
+            frag_t bl[FN];
+#pragma unroll
+            for (int c = 0; c < FN; ++c)
+                bl[c] = blk(HL * MB + NB + wn * FN + c);
+            // hi * lo
+#pragma unroll
+            for (int r = 0; r < FM; ++r)
+#pragma unroll
+                for (int c = 0; c < FN; ++c)
+                    acc[r][c] = Frag<T>::mfma(ah[r], bl[c], acc[r][c]);
+            frag_t al[FM];
+#pragma unroll
+            for (int r = 0; r < FM; ++r)
+                al[r] = blk(MB + wm * FM + r);
+            // lo * hi
+#pragma unroll
+            for (int r = 0; r < FM; ++r)
+#pragma unroll
+                for (int c = 0; c < FN; ++c)
+                    acc[r][c] = Frag<T>::mfma(al[r], bh[c], acc[r][c]);
         }
-        mfma_list<kHalf, kTotal>(acc, cur);
-    };
-    int64_t i = 0;
-    for (; i + 1 < n_st; i += 2) {
-        step(i, f0, f1);
-        step(i + 1, f1, f0);
+        slot = slot == P ? 0 : slot + 1;
     }
-    if (i < n_st)
-        step(i, f0, f1);
 
-    // ---- epilogue: accumulator register r of a 32x32 block holds row
-    // 8 (r / 4) + 4 (lane / 32) + (r mod 4), column lane mod 32.
-    const int row_base = tm * BM + wm * (BM / 2);
-    const int col_base = tn * BN + wn * (BN / 2);
+    // ---- epilogue: accumulator register r of a 16x16 block holds row
+    // 4 (lane / 16) + r, column lane mod 16.
+    const int row_base = tm * BM + wm * FM * kFragLines;
+    const int col_base = tn * BN + wn * FN * kFragLines;
     float *dst = splits == 1 ? out : partials + (int64_t)split * M * N;
     const int64_t ld = splits == 1 ? ldo : (int64_t)N;
     const bool acc_old = splits == 1 && accumulate != 0;
@@ -305,12 +254,12 @@ __global__ __launch_bounds__(256, MINWG) void k_gemm(const char *__restrict__ Lh
     for (int r0 = 0; r0 < FM; ++r0)
 #pragma unroll
         for (int c0 = 0; c0 < FN; ++c0) {
-            const int col = col_base + c0 * 32 + (lane & 31);
+            const int col = col_base + c0 * kFragLines + (lane & 15);
             if (col >= N)
                 continue;
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int row = row_base + r0 * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+            for (int r = 0; r < 4; ++r) {
+                const int row = row_base + r0 * kFragLines + 4 * (lane >> 4) + r;
                 if (row < M) {
                     float *p = dst + (int64_t)row * ld + col;
                     *p = acc_old ? *p + acc[r0][c0][r] : acc[r0][c0][r];
@@ -319,14 +268,36 @@ __global__ __launch_bounds__(256, MINWG) void k_gemm(const char *__restrict__ Lh
         }
 }
 
-// out[i] = (accumulate ? out[i] : 0) + partials[0][i] + ... + partials[S-1][i], in that order.
+// out[i] = (accumulate ? out[i] : 0) + partials[0][i] + ... + partials[S-1][i], in that
+// order; four consecutive elements per thread when N allows.
 __global__ __launch_bounds__(256) void k_splitk_reduce(const float *__restrict__ partials,
                                                        int splits, int M, int N,
                                                        float *__restrict__ out, int64_t ldo,
-                                                       int accumulate)
+                                                       int accumulate, int vec4)
 {
     const int64_t total = (int64_t)M * N;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    if (vec4) {
+        const int64_t q = total / 4;
+        for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < q; e += stride) {
+            float4 s = reinterpret_cast<const float4 *>(partials)[e];
+            for (int k = 1; k < splits; ++k) {
+                const float4 v = reinterpret_cast<const float4 *>(partials + (int64_t)k * total)[e];
+                s.x += v.x;
+                s.y += v.y;
+                s.z += v.z;
+                s.w += v.w;
+            }
+            const int64_t row = (4 * e) / N, col = (4 * e) % N;
+            float4 *p = reinterpret_cast<float4 *>(out + row * ldo + col);
+            if (accumulate) {
+                const float4 o = *p;
+                s = float4{o.x + s.x, o.y + s.y, o.z + s.z, o.w + s.w};
+            }
+            *p = s;
+        }
+        return;
+    }
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
         const int64_t row = e / N, col = e % N;
         float s = partials[e];
@@ -337,51 +308,53 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(const float *__restrict__
     }
 }
 
-template <int BM, int BN, int PRODUCTS, typename T, int STAGES, int MINWG>
+template <int BM, int BN, int WM, int WN, int PRODUCTS, typename T, int STAGES>
 hipError_t launch_tile(const GemmPlan &plan, const void *Lh, const void *Ll, const void *Rh,
                        const void *Rl, int M, int N, float *out, int64_t ldo, float *partials,
                        bool accumulate, hipStream_t s)
 {
     constexpr int HL = PRODUCTS == 3 ? 2 : 1;
-    const int lds_bytes = STAGES * StageLayout<BM, BN, HL>::bytes;
-    auto kern = k_gemm<BM, BN, PRODUCTS, T, STAGES, MINWG>;
+    const int lds_bytes = STAGES * HL * (BM + BN) / kFragLines * kBlockBytes;
+    auto kern = k_gemm<BM, BN, WM, WN, PRODUCTS, T, STAGES>;
     hipError_t e = hipFuncSetAttribute((const void *)kern,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
     if (e != hipSuccess)
         return e;
-    const int tiles_m = plan.mblocks / (BM / 32);
-    const int tiles_n = plan.nblocks / (BN / 32);
+    const int tiles_m = plan.mblocks / (BM / kFragLines);
+    const int tiles_n = plan.nblocks / (BN / kFragLines);
     const int64_t per = (plan.kblocks + plan.splits - 1) / plan.splits;
     const int total = tiles_m * tiles_n * plan.splits;
     const int grid = (total + kXcds - 1) / kXcds * kXcds;
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(256), lds_bytes, s, (const char *)Lh,
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * WM * WN), lds_bytes, s, (const char *)Lh,
                        (const char *)Ll, (const char *)Rh, (const char *)Rl, plan.kblocks,
                        tiles_m, tiles_n, plan.splits, per, M, N, out, ldo, partials,
                        accumulate ? 1 : 0);
     return hipGetLastError();
 }
 
-// Built shapes: (BM, BN, ring depth, workgroups per CU).
+// Built shapes: (BM, BN, waves along M, waves along N, LDS ring depth).  The
+// ring holds STAGES x 2 (hi, lo) x (BM + BN) / 16 KB with three products
+// (half of that with one) and must fit the 160 KB of LDS.
 #define CGH_GEMM_SHAPES(X)                                                                     \
-    X(192, 192, 3, 2)                                                                          \
-    X(192, 192, 5, 1)                                                                          \
-    X(256, 192, 4, 1)                                                                          \
-    X(192, 256, 4, 1)                                                                          \
-    X(256, 128, 5, 1)                                                                          \
-    X(128, 256, 5, 1)                                                                          \
-    X(128, 128, 4, 2)                                                                          \
-    X(128, 256, 3, 2)                                                                          \
-    X(256, 128, 3, 2)
+    X(192, 384, 2, 4, 2)                                                                       \
+    X(384, 192, 4, 2, 2)                                                                       \
+    X(192, 256, 2, 4, 2)                                                                       \
+    X(256, 256, 2, 4, 2)                                                                       \
+    X(192, 192, 2, 2, 3)                                                                       \
+    X(192, 192, 2, 4, 3)                                                                       \
+    X(128, 256, 2, 4, 2)
 
 template <int PRODUCTS, typename T>
 hipError_t launch_products(const GemmPlan &plan, const void *Lh, const void *Ll, const void *Rh,
                            const void *Rl, int M, int N, float *out, int64_t ldo,
                            float *partials, bool accumulate, hipStream_t s)
 {
-#define CGH_TILE(TBM, TBN, TST, TWG)                                                          \
-    if (plan.bm == TBM && plan.bn == TBN && plan.stages == TST && plan.wg_per_cu == TWG)      \
-        return launch_tile<TBM, TBN, PRODUCTS, T, TST, TWG>(plan, Lh, Ll, Rh, Rl, M, N, out,  \
-                                                            ldo, partials, accumulate, s);
+#define CGH_TILE(TBM, TBN, TWM, TWN, TST)                                                     \
+    if (plan.bm == TBM && plan.bn == TBN && plan.waves_m == TWM && plan.waves_n == TWN &&     \
+        plan.stages == TST)                                                                   \
+        return launch_tile<TBM, TBN, TWM, TWN, PRODUCTS, T, TST>(plan, Lh, Ll, Rh, Rl, M, N,  \
+                                                                 out, ldo, partials,          \
+                                                                 accumulate, s);
     CGH_GEMM_SHAPES(CGH_TILE)
 #undef CGH_TILE
     return hipErrorInvalidValue;
@@ -389,10 +362,10 @@ hipError_t launch_products(const GemmPlan &plan, const void *Lh, const void *Ll,
 
 }  // namespace
 
-bool gemm_tile_supported(int bm, int bn, int stages, int wg_per_cu)
+bool gemm_tile_supported(int bm, int bn, int waves_m, int waves_n, int stages)
 {
-#define CGH_TILE(TBM, TBN, TST, TWG)                                                          \
-    if (bm == TBM && bn == TBN && stages == TST && wg_per_cu == TWG)                          \
+#define CGH_TILE(TBM, TBN, TWM, TWN, TST)                                                     \
+    if (bm == TBM && bn == TBN && waves_m == TWM && waves_n == TWN && stages == TST)          \
         return true;
     CGH_GEMM_SHAPES(CGH_TILE)
 #undef CGH_TILE
@@ -423,11 +396,16 @@ hipError_t launch_splitk_reduce(const float *partials, int splits, int M, int N,
     const int64_t total = (int64_t)M * N;
     if (total <= 0)
         return hipSuccess;
-    int64_t blocks = (total + 255) / 256;
+    int64_t blocks = (total / 4 + 255) / 256;
     if (blocks > 8192)
         blocks = 8192;
+    if (blocks < 1)
+        blocks = 1;
+    // float4 path: rows of whole float4s, 16-byte aligned buffers
+    const int vec4 = (N % 4 == 0) && (ldo % 4 == 0) && ((uintptr_t)out % 16 == 0) &&
+                     ((uintptr_t)partials % 16 == 0);
     hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)blocks), dim3(256), 0, s, partials, splits,
-                       M, N, out, ldo, accumulate ? 1 : 0);
+                       M, N, out, ldo, accumulate ? 1 : 0, vec4);
     return hipGetLastError();
 }
 
