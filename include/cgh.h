@@ -145,6 +145,22 @@ CGH_API cgh_status cgh_compute(cgh_ctx *c, cgh_mode mode, float *out_dev, void *
 CGH_API cgh_status cgh_batch_compute(cgh_ctx *c, const cgh_frame *frames, int32_t n_frames,
                              cgh_mode mode, float *out_dev, void *stream);
 
+/* Autotune the launch shape of `mode` for this context's hologram size:
+ * times every candidate (matrix-core modes: each built GEMM tile shape with a
+ * few split-K counts, the time of the GEMM plus its split-K reduce; direct
+ * mode: 4, 8 or 16 rows per lane) `repeats` times on the uploaded cloud (its
+ * first point chunk) with HIP events on `stream`, and keeps the fastest for
+ * later evaluations of this size and mode whose K size falls in the same
+ * power-of-two bucket.  With the environment variable CGH_TUNE_CACHE set to
+ * a file path, the choice is appended to that file (JSON lines) and every
+ * later cgh_create reads the file back.  `report` (optional, report_len
+ * bytes) receives a one-line description of the choice.  Blocks the host
+ * until the timing finishes.
+ * Errors: CGH_EINVAL (repeats outside [1, 1000], bad buffer, unknown mode),
+ * CGH_ESTATE (no upload), CGH_ENOTSUP (CGH_SEPARABLE_FP32), CGH_EDEVICE. */
+CGH_API cgh_status cgh_tune(cgh_ctx *c, cgh_mode mode, int32_t repeats, char *report,
+                            int32_t report_len, void *stream);
+
 /* Free the context and all its device memory (synchronises the device it
  * used first).  NULL-safe. */
 CGH_API void cgh_destroy(cgh_ctx *c);

@@ -43,7 +43,7 @@ MEM_DEVICE = 1
 
 # every symbol include/cgh.h declares
 EXPORTS = ("cgh_create", "cgh_points_upload", "cgh_compute", "cgh_batch_compute",
-           "cgh_destroy", "cgh_strerror", "cgh_last_error", "cgh_profile_enable",
+           "cgh_tune", "cgh_destroy", "cgh_strerror", "cgh_last_error", "cgh_profile_enable",
            "cgh_profile_reset", "cgh_profile_read", "cgh_version")
 
 
@@ -82,6 +82,8 @@ def lib() -> ctypes.CDLL:
     L.cgh_compute.restype = st
     L.cgh_batch_compute.argtypes = [vp, ctypes.POINTER(Frame), i32, ctypes.c_int, vp, vp]
     L.cgh_batch_compute.restype = st
+    L.cgh_tune.argtypes = [vp, ctypes.c_int, i32, ctypes.c_char_p, i32, vp]
+    L.cgh_tune.restype = st
     L.cgh_destroy.argtypes = [vp]
     L.cgh_destroy.restype = None
     L.cgh_strerror.argtypes = [ctypes.c_int]
@@ -209,6 +211,14 @@ class Context:
         _check(lib().cgh_batch_compute(self._h, arr, F, int(mode), self._out_ptr(out, F),
                                        _stream_handle(stream, [out])), "cgh_batch_compute")
         return out
+
+    def tune(self, mode: int, repeats: int = 5, stream=None) -> str:
+        """Autotune `mode`'s launch shape on the uploaded cloud (cgh_tune);
+        returns the library's one-line report of the choice."""
+        buf = ctypes.create_string_buffer(512)
+        _check(lib().cgh_tune(self._h, int(mode), int(repeats), buf, 512,
+                              _stream_handle(stream)), "cgh_tune")
+        return buf.value.decode()
 
     # -- measurement
     def profile(self, on: bool = True) -> None:

@@ -123,7 +123,7 @@ size_t workspace_budget()
         if (end && *end == '\0' && v >= (1ull << 20))
             return (size_t)v;
     }
-    return (size_t)4 << 30;
+    return (size_t)16 << 30;
 }
 
 struct ProfRecord {
@@ -139,6 +139,15 @@ struct ProfTotal {
 }  // namespace
 
 // ------------------------------------------------------------------ context
+// One autotuned choice: a GEMM shape + split count, or (direct mode) the rows
+// each lane owns.  Keyed by device arch, hologram size, mode and the K-size
+// bucket (ceil(log2(K blocks))).
+struct TuneEntry {
+    std::string key;
+    int bm = 0, bn = 0, wm = 0, wn = 0, stages = 0, splits = 0, rows = 0;
+    double us = 0.0;
+};
+
 struct cgh_ctx {
     int width = 0, height = 0, device = 0;
     double pitch = 0.0, wavelength = 0.0;
@@ -156,6 +165,8 @@ struct cgh_ctx {
     DevBuf fac[4];                    // Lh, Ll, Rh, Rl
     DevBuf partials;                  // split-K partial tiles
     DevBuf segs, frames;              // small device tables
+    DevBuf tune_out;                  // scratch hologram for cgh_tune
+    DevBuf items, counter;            // batched GEMM work list and its queue counter
     uint64_t ws_generation = 0;       // bumps when a buffer moves
 
     // batch graph cache
@@ -167,6 +178,10 @@ struct cgh_ctx {
     uint64_t graph_generation = 0;
     uint64_t points_generation = 0;
     uint64_t graph_points_generation = 0;
+
+    // autotuned plans (from cgh_tune or the cache file), see plan lookup
+    std::string arch;
+    std::vector<struct TuneEntry> tuned;
 
     // profiling
     bool profiling = false;
@@ -299,7 +314,29 @@ struct Plan {
 // Tile shape and split count for an M x N output over `slots` points.
 // CGH_GEMM_PLAN="bm,bn,waves_m,waves_n,stages,splits" overrides the choice
 // (used to sweep shapes; an unsupported shape is ignored, splits 0 = auto).
-Plan plan_gemm(int M, int N, int64_t slots, int products)
+int kblock_bucket(int64_t kblocks)
+{
+    int b = 0;
+    while (((int64_t)1 << b) < kblocks)
+        ++b;
+    return b;
+}
+
+std::string tune_key(const cgh_ctx *c, int mode, int64_t kblocks)
+{
+    return c->arch + "/" + std::to_string(c->width) + "x" + std::to_string(c->height) + "/mode" +
+           std::to_string(mode) + "/kb" + std::to_string(kblock_bucket(kblocks));
+}
+
+const TuneEntry *find_tuned(const cgh_ctx *c, const std::string &key)
+{
+    for (auto &t : c->tuned)
+        if (t.key == key)
+            return &t;
+    return nullptr;
+}
+
+Plan plan_gemm(int M, int N, int64_t slots, int products, const TuneEntry *tuned = nullptr)
 {
     struct Shape {
         int bm, bn, wm, wn, stages;
@@ -310,9 +347,14 @@ Plan plan_gemm(int M, int N, int64_t slots, int products)
     int forced_splits = 0;
     Shape forced = {0, 0, 0, 0, 0};
     const char *env = std::getenv("CGH_GEMM_PLAN");
-    if (env && std::sscanf(env, "%d,%d,%d,%d,%d,%d", &forced.bm, &forced.bn, &forced.wm,
-                           &forced.wn, &forced.stages, &forced_splits) >= 5 &&
-        gemm_tile_supported(forced.bm, forced.bn, forced.wm, forced.wn, forced.stages)) {
+    if (tuned && gemm_tile_supported(tuned->bm, tuned->bn, tuned->wm, tuned->wn, tuned->stages)) {
+        forced = {tuned->bm, tuned->bn, tuned->wm, tuned->wn, tuned->stages};
+        forced_splits = tuned->splits;
+    }
+    if ((tuned && forced.bm) ||
+        (env && std::sscanf(env, "%d,%d,%d,%d,%d,%d", &forced.bm, &forced.bn, &forced.wm,
+                            &forced.wn, &forced.stages, &forced_splits) >= 5 &&
+         gemm_tile_supported(forced.bm, forced.bn, forced.wm, forced.wn, forced.stages))) {
         best.g.bm = forced.bm;
         best.g.bn = forced.bn;
         best.g.waves_m = forced.wm;
@@ -348,6 +390,8 @@ Plan plan_gemm(int M, int N, int64_t slots, int products)
     best.g.splits = splits;
     best.g.mblocks = best.tiles_m * (best.g.bm / kFragLines);
     best.g.nblocks = best.tiles_n * (best.g.bn / kFragLines);
+    best.g.alloc_mblocks = best.g.mblocks;   // the caller sizes the factors from these
+    best.g.alloc_nblocks = best.g.nblocks;
     best.g.kblocks = kblocks;
     best.g.products = products;
     return best;
@@ -377,10 +421,12 @@ cgh_status run_direct(cgh_ctx *c, const FrameDesc *fd_dev, int n_frames, int64_t
                 "phase_tables launch");
         br.done();
     }
+    const TuneEntry *t = find_tuned(c, tune_key(c, CGH_DIRECT_FP32, 0));
+    const int rows = t && (t->rows == 4 || t->rows == 8 || t->rows == 16) ? t->rows : 16;
     Bracket br(c, "direct_fp32", s);
     CGH_HIP(launch_direct((const float *)c->tab_u.p, (const float *)c->tab_v.p,
                           consts_view(c, c->consts_cap).amp, fd_dev, n_frames, c->width,
-                          c->height, c->wpad, c->hpad, 16, out, accumulate, s),
+                          c->height, c->wpad, c->hpad, rows, out, accumulate, s),
             "direct launch");
     br.done();
     return CGH_OK;
@@ -392,7 +438,8 @@ cgh_status run_gemm(cgh_ctx *c, int mode, int64_t slot0, int64_t slots, float *o
 {
     const bool split = mode == CGH_SPLIT_BF16 || mode == CGH_SPLIT_FP16;
     const FactorType ft = mode == CGH_SPLIT_BF16 ? FactorType::BF16 : FactorType::FP16;
-    const Plan p = plan_gemm(c->height, c->width, slots, split ? 3 : 1);
+    const Plan p = plan_gemm(c->height, c->width, slots, split ? 3 : 1,
+                             find_tuned(c, tune_key(c, mode, slots / kFragPoints)));
     const int hl = split ? 2 : 1;
     // 2 K-columns (cos, sin) of 2 bytes per line and point
     const size_t lbytes = (size_t)p.g.mblocks * kFragLines * (size_t)slots * 2 * 2;
@@ -440,7 +487,9 @@ size_t bytes_per_slot(cgh_ctx *c, int mode)
     if (mode == CGH_DIRECT_FP32)
         return (size_t)(c->wpad + c->hpad) * sizeof(float);
     const int hl = (mode == CGH_SPLIT_BF16 || mode == CGH_SPLIT_FP16) ? 2 : 1;
-    return (size_t)(round_up(c->width, 384) + round_up(c->height, 384)) * 2 * 2 * hl;
+    const int64_t w = std::max(round_up(c->width, 384), round_up(c->width, 256));
+    const int64_t h = std::max(round_up(c->height, 384), round_up(c->height, 256));
+    return (size_t)(w + h) * 2 * 2 * hl;
 }
 
 int64_t chunk_slots(cgh_ctx *c, int mode)
@@ -534,6 +583,233 @@ cgh_status eval_batch_direct(cgh_ctx *c, const cgh_frame *frames, int n_frames, 
     return run_direct(c, (const FrameDesc *)c->frames.p, n_frames, slot, out, false, s);
 }
 
+
+// Matrix-core modes over many frames: frames are grouped so that each
+// group's factors fit the workspace budget; per group one constants launch,
+// one factor launch (all frames side by side along K) and one persistent
+// GEMM launch over (frame, tile) items, largest K first.
+cgh_status eval_batch_gemm(cgh_ctx *c, int mode, const cgh_frame *frames, int n_frames,
+                           float *out, hipStream_t s)
+{
+    const bool split = mode == CGH_SPLIT_BF16 || mode == CGH_SPLIT_FP16;
+    const FactorType ft = mode == CGH_SPLIT_BF16 ? FactorType::BF16 : FactorType::FP16;
+    const int hl = split ? 2 : 1;
+    const int64_t plane = (int64_t)c->width * c->height;
+    // tile shape: the tuned (or default) shape for the largest frame
+    int64_t max_count = 0;
+    for (int f = 0; f < n_frames; ++f)
+        max_count = std::max(max_count, frames[f].point_count);
+    const int64_t max_slots = std::max<int64_t>(round_up(max_count, kSlotAlign), kSlotAlign);
+    Plan p = plan_gemm(c->height, c->width, max_slots, split ? 3 : 1,
+                       find_tuned(c, tune_key(c, mode, max_slots / kFragPoints)));
+    const size_t per_slot = (size_t)(p.g.mblocks + p.g.nblocks) * kFragLines * 2 * 2 * hl;
+    const int64_t budget = std::max<int64_t>((int64_t)(workspace_budget() / per_slot), kSlotAlign);
+
+    // Groups of frames [f0, f1) whose padded slots fit the budget (at least
+    // one frame each).  All groups' segments and work items go to the device
+    // in one table each, so a repeated call (and its graph capture) copies
+    // nothing.
+    struct Group {
+        int seg0, nseg;
+        int item0, nitem;
+        int64_t slots, max_count;
+    };
+    std::vector<Group> groups;
+    std::vector<Segment> segs;
+    std::vector<BatchItem> items;
+    for (int f0 = 0; f0 < n_frames;) {
+        Group gr{(int)segs.size(), 0, (int)items.size(), 0, 0, 0};
+        int f1 = f0;
+        while (f1 < n_frames) {
+            const int64_t ps = round_up(frames[f1].point_count, kSlotAlign);
+            if (f1 > f0 && gr.slots + ps > budget)
+                break;
+            segs.push_back({frames[f1].point_offset, frames[f1].point_count, gr.slots,
+                            frames[f1].wavelength});
+            for (int tm = 0; tm < p.tiles_m; ++tm)
+                for (int tn = 0; tn < p.tiles_n; ++tn)
+                    items.push_back({gr.slots / kFragPoints, ps / kFragPoints, f1 * plane, tm, tn});
+            gr.slots += ps;
+            gr.max_count = std::max(gr.max_count, frames[f1].point_count);
+            ++f1;
+        }
+        gr.nseg = (int)segs.size() - gr.seg0;
+        gr.nitem = (int)items.size() - gr.item0;
+        std::stable_sort(items.begin() + gr.item0, items.end(),
+                         [](const BatchItem &x, const BatchItem &y) { return x.kblocks > y.kblocks; });
+        groups.push_back(gr);
+        f0 = f1;
+    }
+    CGH_HIP(upload_small(c, c->segs, segs.data(), segs.size() * sizeof(Segment), s),
+            "segment table upload");
+    CGH_HIP(upload_small(c, c->items, items.data(), items.size() * sizeof(BatchItem), s),
+            "work list upload");
+    CGH_HIP(ensure_ws(c, c->counter, sizeof(int)), "counter allocation");
+    int64_t max_group_slots = kSlotAlign;
+    for (auto &gr : groups)
+        max_group_slots = std::max(max_group_slots, gr.slots);
+    const size_t lbytes = (size_t)p.g.mblocks * kFragLines * (size_t)max_group_slots * 4;
+    const size_t rbytes = (size_t)p.g.nblocks * kFragLines * (size_t)max_group_slots * 4;
+    CGH_HIP(ensure_ws(c, c->fac[0], lbytes), "factor allocation");
+    CGH_HIP(ensure_ws(c, c->fac[2], rbytes), "factor allocation");
+    if (hl == 2) {
+        CGH_HIP(ensure_ws(c, c->fac[1], lbytes), "factor allocation");
+        CGH_HIP(ensure_ws(c, c->fac[3], rbytes), "factor allocation");
+    }
+    CGH_HIP(ensure_consts(c, max_group_slots), "constant allocation");
+    for (auto &gr : groups) {
+        const int64_t total = std::max<int64_t>(gr.slots, kSlotAlign);
+        cgh_status st = point_consts(c, gr.seg0, gr.nseg, gr.max_count, total, s);
+        if (st != CGH_OK)
+            return st;
+        GemmPlan g = p.g;
+        g.kblocks = total / kFragPoints;
+        {
+            Bracket br(c, split ? "factors_split" : "factors", s);
+            CGH_HIP(launch_factors(consts_view(c, c->consts_cap), 0, total, c->width, c->height,
+                                   g.kblocks, g.mblocks, g.nblocks, ft, c->fac[0].p,
+                                   hl == 2 ? c->fac[1].p : nullptr, c->fac[2].p,
+                                   hl == 2 ? c->fac[3].p : nullptr, s),
+                    "factor launch");
+            br.done();
+        }
+        {
+            Bracket br(c, split ? "gemm_split_mfma_batch" : "gemm_mfma_batch", s);
+            CGH_HIP(launch_gemm_batch(g, ft, c->fac[0].p, hl == 2 ? c->fac[1].p : nullptr,
+                                      c->fac[2].p, hl == 2 ? c->fac[3].p : nullptr,
+                                      (const BatchItem *)c->items.p + gr.item0, gr.nitem,
+                                      (int *)c->counter.p, c->height, c->width, out,
+                                      std::min(256, gr.nitem), s),
+                    "batched gemm launch");
+            br.done();
+        }
+    }
+    return CGH_OK;
+}
+
+// The kernel sequence of one batch call, without graph handling.
+cgh_status batch_sequence(cgh_ctx *c, const cgh_frame *frames, int n_frames, int mode, float *out,
+                          hipStream_t s)
+{
+    const int64_t plane = (int64_t)c->width * c->height;
+    if (mode == CGH_DIRECT_FP32) {
+        int64_t total = 0;
+        for (int f = 0; f < n_frames; ++f)
+            total += round_up(frames[f].point_count, kSlotAlign);
+        if (total <= chunk_slots(c, mode))
+            return eval_batch_direct(c, frames, n_frames, out, s);
+        for (int f = 0; f < n_frames; ++f) {
+            cgh_status st = eval_one(c, mode, frames[f].point_offset, frames[f].point_count,
+                                     frames[f].wavelength, out + f * plane, s);
+            if (st != CGH_OK)
+                return st;
+        }
+        return CGH_OK;
+    }
+    return eval_batch_gemm(c, mode, frames, n_frames, out, s);
+}
+
+bool same_frames(const std::vector<cgh_frame> &a, const cgh_frame *b, int n)
+{
+    if ((int)a.size() != n)
+        return false;
+    for (int i = 0; i < n; ++i)
+        if (a[i].point_offset != b[i].point_offset || a[i].point_count != b[i].point_count ||
+            a[i].wavelength != b[i].wavelength)
+            return false;
+    return true;
+}
+
+// ------------------------------------------------------------ tune cache
+// JSON lines, one choice per line:
+// {"key": "gfx950/1920x1080/mode1/kb10", "bm": 192, "bn": 384, "wm": 2, "wn": 4,
+//  "stages": 2, "splits": 8, "rows": 0, "us": 220.3}
+const char *tune_cache_path()
+{
+    const char *p = std::getenv("CGH_TUNE_CACHE");
+    return p && *p ? p : nullptr;
+}
+
+void put_tuned(cgh_ctx *c, const TuneEntry &e)
+{
+    for (auto &t : c->tuned)
+        if (t.key == e.key) {
+            t = e;
+            return;
+        }
+    c->tuned.push_back(e);
+}
+
+void load_tune_cache(cgh_ctx *c)
+{
+    const char *path = tune_cache_path();
+    if (!path)
+        return;
+    FILE *f = std::fopen(path, "r");
+    if (!f)
+        return;
+    char line[512];
+    while (std::fgets(line, sizeof line, f)) {
+        char key[256];
+        TuneEntry e;
+        if (std::sscanf(line,
+                        " {\"key\": \"%255[^\"]\", \"bm\": %d, \"bn\": %d, \"wm\": %d, \"wn\": %d, "
+                        "\"stages\": %d, \"splits\": %d, \"rows\": %d, \"us\": %lf",
+                        key, &e.bm, &e.bn, &e.wm, &e.wn, &e.stages, &e.splits, &e.rows,
+                        &e.us) == 9) {
+            e.key = key;
+            put_tuned(c, e);   // later lines win
+        }
+    }
+    std::fclose(f);
+}
+
+void append_tune_cache(const TuneEntry &e)
+{
+    const char *path = tune_cache_path();
+    if (!path)
+        return;
+    FILE *f = std::fopen(path, "a");
+    if (!f)
+        return;
+    std::fprintf(f,
+                 "{\"key\": \"%s\", \"bm\": %d, \"bn\": %d, \"wm\": %d, \"wn\": %d, "
+                 "\"stages\": %d, \"splits\": %d, \"rows\": %d, \"us\": %.3f}\n",
+                 e.key.c_str(), e.bm, e.bn, e.wm, e.wn, e.stages, e.splits, e.rows, e.us);
+    std::fclose(f);
+}
+
+// Average duration (us) of `reps` launches of fn on stream s, after one warm-up.
+template <typename F>
+cgh_status time_launches(F fn, int reps, hipStream_t s, double *us)
+{
+    hipEvent_t a = nullptr, b = nullptr;
+    CGH_HIP(hipEventCreate(&a), "hipEventCreate");
+    hipError_t e = hipEventCreate(&b);
+    if (e != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return hip_fail(e, "hipEventCreate");
+    }
+    e = fn();
+    if (e == hipSuccess)
+        e = hipEventRecord(a, s);
+    for (int r = 0; r < reps && e == hipSuccess; ++r)
+        e = fn();
+    if (e == hipSuccess)
+        e = hipEventRecord(b, s);
+    if (e == hipSuccess)
+        e = hipEventSynchronize(b);
+    float ms = 0.0f;
+    if (e == hipSuccess)
+        e = hipEventElapsedTime(&ms, a, b);
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (e != hipSuccess)
+        return hip_fail(e, "tuning launch");
+    *us = 1e3 * ms / reps;
+    return CGH_OK;
+}
+
 }  // namespace
 
 // ====================================================================== ABI
@@ -597,6 +873,9 @@ cgh_status cgh_create(cgh_ctx **out, int32_t width, int32_t height, double pitch
     c->device = device;
     c->wpad = (int)round_up(width, kLinePad);
     c->hpad = (int)round_up(height, kLinePad);
+    c->arch = prop.gcnArchName;
+    c->arch = c->arch.substr(0, c->arch.find(':'));
+    load_tune_cache(c);
     *out = c;
     return CGH_OK;
 }
@@ -624,6 +903,9 @@ void cgh_destroy(cgh_ctx *c)
     c->partials.release();
     c->segs.release();
     c->frames.release();
+    c->tune_out.release();
+    c->items.release();
+    c->counter.release();
     delete c;
 }
 
@@ -734,20 +1016,208 @@ cgh_status cgh_batch_compute(cgh_ctx *c, const cgh_frame *frames, int32_t n_fram
     DeviceGuard g;
     CGH_HIP(g.set(c->device), "hipSetDevice");
     hipStream_t s = (hipStream_t)stream;
-    const int64_t plane = (int64_t)c->width * c->height;
+    // Replay: same mode, frames and output as the captured call, and no
+    // workspace buffer moved since (a move drops the graph).
+    if (c->graph_exec && !c->profiling && c->graph_mode == (int)mode && c->graph_out == out_dev &&
+        c->graph_generation == c->ws_generation && same_frames(c->graph_frames, frames, n_frames)) {
+        CGH_HIP(hipGraphLaunch(c->graph_exec, s), "hipGraphLaunch");
+        return CGH_OK;
+    }
+    drop_graph(c);
+    st = batch_sequence(c, frames, n_frames, (int)mode, out_dev, s);
+    if (st != CGH_OK || c->profiling || s == nullptr)
+        return st;
+    // Capture the same sequence for replay.  Its small tables and workspace
+    // are now in place, so the captured pass issues kernel launches only; if
+    // anything else would be recorded, the capture is abandoned and later
+    // calls run eagerly.
+    const uint64_t gen = c->ws_generation;
+    hipGraph_t graph = nullptr;
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipGetLastError();
+        return CGH_OK;
+    }
+    const cgh_status cst = batch_sequence(c, frames, n_frames, (int)mode, out_dev, s);
+    const hipError_t ce = hipStreamEndCapture(s, &graph);
+    hipGraphExec_t exec = nullptr;
+    if (cst == CGH_OK && ce == hipSuccess && graph && c->ws_generation == gen &&
+        hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess) {
+        c->graph_exec = exec;
+        c->graph_mode = (int)mode;
+        c->graph_out = out_dev;
+        c->graph_generation = c->ws_generation;
+        c->graph_frames.assign(frames, frames + n_frames);
+    }
+    if (graph)
+        (void)hipGraphDestroy(graph);
+    (void)hipGetLastError();
+    g_last_error.clear();
+    return CGH_OK;
+}
+
+cgh_status cgh_tune(cgh_ctx *c, cgh_mode mode, int32_t repeats, char *report, int32_t report_len,
+                    void *stream)
+{
+    g_last_error.clear();
+    if (!c)
+        return fail(CGH_EINVAL, "context is NULL");
+    cgh_status st = check_mode(mode);
+    if (st != CGH_OK)
+        return st;
+    if (repeats < 1 || repeats > 1000)
+        return fail(CGH_EINVAL, "repeats must be in [1, 1000]");
+    if (report_len < 0 || (report_len > 0 && !report))
+        return fail(CGH_EINVAL, "bad report buffer");
+    if (!c->uploaded)
+        return fail(CGH_ESTATE, "no points uploaded");
+    if (mode == CGH_SEPARABLE_FP32)
+        return fail(CGH_ENOTSUP, "CGH_SEPARABLE_FP32 has no tunable choice");
+    DeviceGuard g;
+    CGH_HIP(g.set(c->device), "hipSetDevice");
+    hipStream_t s = (hipStream_t)stream;
+    CGH_HIP(ensure_ws(c, c->tune_out, (size_t)c->width * c->height * sizeof(float)),
+            "tuning output allocation");
+    float *out = (float *)c->tune_out.p;
+
+    // the first point chunk of the cloud (at least one slot group)
+    const int64_t count = std::min(c->n, chunk_slots(c, mode));
+    std::vector<Segment> segs{{0, count, 0, c->wavelength}};
+    const int64_t slots = std::max<int64_t>(round_up(count, kSlotAlign), kSlotAlign);
+    std::vector<FrameDesc> fds{{0, slots / kGroup, 0}};
+    CGH_HIP(upload_small(c, c->segs, segs.data(), sizeof(Segment), s), "segment table upload");
+    CGH_HIP(upload_small(c, c->frames, fds.data(), sizeof(FrameDesc), s), "frame table upload");
+    st = point_consts(c, 0, 1, count, slots, s);
+    if (st != CGH_OK)
+        return st;
+
+    TuneEntry best;
+    int tried = 0;
     if (mode == CGH_DIRECT_FP32) {
-        int64_t total = 0;
-        for (int f = 0; f < n_frames; ++f)
-            total += round_up(frames[f].point_count, kSlotAlign);
-        if (total <= chunk_slots(c, mode))
-            return eval_batch_direct(c, frames, n_frames, out_dev, s);
+        best.key = tune_key(c, mode, 0);
+        const int64_t tu = slots * c->wpad * (int64_t)sizeof(float);
+        const int64_t tv = slots * c->hpad * (int64_t)sizeof(float);
+        CGH_HIP(ensure_ws(c, c->tab_u, (size_t)tu), "table allocation");
+        CGH_HIP(ensure_ws(c, c->tab_v, (size_t)tv), "table allocation");
+        CGH_HIP(launch_phase_tables(consts_view(c, c->consts_cap), slots, c->wpad, c->hpad,
+                                    (float *)c->tab_u.p, (float *)c->tab_v.p, s),
+                "phase_tables launch");
+        for (int rows : {4, 8, 16}) {
+            double us = 0;
+            st = time_launches(
+                [&] {
+                    return launch_direct((const float *)c->tab_u.p, (const float *)c->tab_v.p,
+                                         consts_view(c, c->consts_cap).amp,
+                                         (const FrameDesc *)c->frames.p, 1, c->width, c->height,
+                                         c->wpad, c->hpad, rows, out, false, s);
+                },
+                repeats, s, &us);
+            if (st != CGH_OK)
+                return st;
+            ++tried;
+            if (best.rows == 0 || us < best.us) {
+                best.rows = rows;
+                best.us = us;
+            }
+        }
+    } else {
+        const bool split = mode == CGH_SPLIT_BF16 || mode == CGH_SPLIT_FP16;
+        const FactorType ft = mode == CGH_SPLIT_BF16 ? FactorType::BF16 : FactorType::FP16;
+        const int hl = split ? 2 : 1;
+        const int64_t kblocks = slots / kFragPoints;
+        best.key = tune_key(c, mode, kblocks);
+        static const int shapes[][5] = {{192, 384, 2, 4, 2}, {384, 192, 4, 2, 2},
+                                        {192, 256, 2, 4, 2}, {256, 256, 2, 4, 2},
+                                        {192, 192, 2, 2, 3}, {192, 192, 2, 4, 3},
+                                        {128, 256, 2, 4, 2}};
+        // factors padded to whole tiles of every candidate shape
+        int mb = 0, nb = 0;
+        for (auto &sh : shapes) {
+            mb = std::max(mb, (int)(round_up(c->height, sh[0]) / kFragLines));
+            nb = std::max(nb, (int)(round_up(c->width, sh[1]) / kFragLines));
+        }
+        const size_t lbytes = (size_t)mb * kFragLines * slots * 4;
+        const size_t rbytes = (size_t)nb * kFragLines * slots * 4;
+        CGH_HIP(ensure_ws(c, c->fac[0], lbytes), "factor allocation");
+        CGH_HIP(ensure_ws(c, c->fac[2], rbytes), "factor allocation");
+        if (hl == 2) {
+            CGH_HIP(ensure_ws(c, c->fac[1], lbytes), "factor allocation");
+            CGH_HIP(ensure_ws(c, c->fac[3], rbytes), "factor allocation");
+        }
+        CGH_HIP(launch_factors(consts_view(c, c->consts_cap), 0, slots, c->width, c->height,
+                               kblocks, mb, nb, ft, c->fac[0].p, hl == 2 ? c->fac[1].p : nullptr,
+                               c->fac[2].p, hl == 2 ? c->fac[3].p : nullptr, s),
+                "factor launch");
+        for (auto &sh : shapes) {
+            if (!gemm_tile_supported(sh[0], sh[1], sh[2], sh[3], sh[4]))
+                continue;
+            const int tiles = (int)((c->height + sh[0] - 1) / sh[0] * ((c->width + sh[1] - 1) / sh[1]));
+            // split counts around "one workgroup per CU", each split >= 8 K blocks
+            const int smax = (int)std::max<int64_t>(1, kblocks / 8);
+            const int s0 = std::min(std::max(1, 256 / tiles), smax);
+            std::vector<int> cands{s0};
+            if (s0 / 2 >= 1 && s0 / 2 != s0)
+                cands.push_back(s0 / 2);
+            if (2 * s0 <= smax && 2 * s0 * tiles <= 512)
+                cands.push_back(2 * s0);
+            if (s0 != 1 && s0 / 2 != 1)
+                cands.push_back(1);
+            for (int sp : cands) {
+                GemmPlan gp;
+                gp.bm = sh[0];
+                gp.bn = sh[1];
+                gp.waves_m = sh[2];
+                gp.waves_n = sh[3];
+                gp.stages = sh[4];
+                gp.splits = sp;
+                gp.mblocks = (c->height + sh[0] - 1) / sh[0] * (sh[0] / kFragLines);
+                gp.nblocks = (c->width + sh[1] - 1) / sh[1] * (sh[1] / kFragLines);
+                gp.kblocks = kblocks;
+                gp.products = split ? 3 : 1;
+                gp.alloc_mblocks = mb;
+                gp.alloc_nblocks = nb;
+                if (sp > 1)
+                    CGH_HIP(ensure_ws(c, c->partials,
+                                      (size_t)sp * c->height * (size_t)c->width * sizeof(float)),
+                            "split-K workspace allocation");
+                double us = 0;
+                st = time_launches(
+                    [&] {
+                        hipError_t e = launch_gemm(gp, ft, c->fac[0].p,
+                                                   hl == 2 ? c->fac[1].p : nullptr, c->fac[2].p,
+                                                   hl == 2 ? c->fac[3].p : nullptr, c->height,
+                                                   c->width, out, c->width,
+                                                   (float *)c->partials.p, false, s);
+                        if (e == hipSuccess && sp > 1)
+                            e = launch_splitk_reduce((const float *)c->partials.p, sp, c->height,
+                                                     c->width, out, c->width, false, s);
+                        return e;
+                    },
+                    repeats, s, &us);
+                if (st != CGH_OK)
+                    return st;
+                ++tried;
+                if (best.bm == 0 || us < best.us) {
+                    best.bm = sh[0];
+                    best.bn = sh[1];
+                    best.wm = sh[2];
+                    best.wn = sh[3];
+                    best.stages = sh[4];
+                    best.splits = sp;
+                    best.us = us;
+                }
+            }
+        }
     }
-    for (int f = 0; f < n_frames; ++f) {
-        st = eval_one(c, mode, frames[f].point_offset, frames[f].point_count,
-                      frames[f].wavelength, out_dev + f * plane, s);
-        if (st != CGH_OK)
-            return st;
-    }
+    if (tried == 0)
+        return fail(CGH_ENOTSUP, "no launch shape fits this hologram");
+    put_tuned(c, best);
+    append_tune_cache(best);
+    if (report_len > 0)
+        std::snprintf(report, (size_t)report_len,
+                      "%s: bm=%d bn=%d waves=%dx%d stages=%d splits=%d rows=%d %.1f us "
+                      "(%d candidates)",
+                      best.key.c_str(), best.bm, best.bn, best.wm, best.wn, best.stages,
+                      best.splits, best.rows, best.us, tried);
     return CGH_OK;
 }
 

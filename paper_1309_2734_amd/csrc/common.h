@@ -104,12 +104,29 @@ struct GemmPlan {
     int splits;          // K splits (1 = write the output directly)
     int64_t kblocks;     // K blocks of kFragPoints points
     int mblocks, nblocks;// line blocks of kFragLines (padded to whole tiles)
+    int alloc_mblocks;   // line blocks the L / R factor arrays hold; a launch whose
+    int alloc_nblocks;   // tiles would read beyond them is refused
     int products;        // 3 = hi*hi + hi*lo + lo*hi, 1 = hi*hi only
 };
 hipError_t launch_gemm(const GemmPlan &plan, FactorType ft, const void *Lh, const void *Ll,
                        const void *Rh, const void *Rl, int M, int N, float *out, int64_t ldo,
                        float *partials, bool accumulate, hipStream_t s);
 bool gemm_tile_supported(int bm, int bn, int waves_m, int waves_n, int stages);
+
+// a6: one (frame, tile) work item of the persistent batched GEMM.  The
+// factors of all frames sit side by side along K (one [line block][K block]
+// array per factor); an item's K blocks are [kb_begin, kb_begin + kblocks).
+struct BatchItem {
+    int64_t kb_begin;
+    int64_t kblocks;
+    int64_t out_off;   // floats: frame index * height * width
+    int32_t tm, tn;    // tile indices
+};
+// plan.kblocks = total K blocks of the factor arrays; grid = persistent
+// workgroups; counter = one int of device memory (reset by the launch).
+hipError_t launch_gemm_batch(const GemmPlan &plan, FactorType ft, const void *Lh, const void *Ll,
+                             const void *Rh, const void *Rl, const BatchItem *items, int n_items,
+                             int *counter, int M, int N, float *out, int grid, hipStream_t s);
 hipError_t launch_splitk_reduce(const float *partials, int splits, int M, int N, float *out,
                                 int64_t ldo, bool accumulate, hipStream_t s);
 

@@ -107,12 +107,17 @@ __device__ __forceinline__ void ring_barrier()
     asm volatile("" ::: "memory");
 }
 
+// One output tile: line blocks tm (of L) and tn (of R), K blocks
+// [kb_begin, kb_begin + n_st) of matrices whose line blocks are row_bytes
+// apart; the result goes to dst[row * ld + col] for row < M, col < N (added
+// to what is there when acc_old).  All threads of the workgroup call it.
 template <int BM, int BN, int WM, int WN, int PRODUCTS, typename T, int STAGES>
-__global__ __launch_bounds__(64 * WM * WN, 1) void k_gemm(
-    const char *__restrict__ Lh, const char *__restrict__ Ll, const char *__restrict__ Rh,
-    const char *__restrict__ Rl, int64_t kblocks, int tiles_m, int tiles_n, int splits,
-    int64_t kb_per_split, int M, int N, float *__restrict__ out, int64_t ldo,
-    float *__restrict__ partials, int accumulate)
+__device__ __forceinline__ void gemm_tile(const char *__restrict__ Lh, const char *__restrict__ Ll,
+                                          const char *__restrict__ Rh,
+                                          const char *__restrict__ Rl, int64_t row_bytes,
+                                          int64_t kb_begin, int64_t n_st, int tm, int tn, int M,
+                                          int N, float *__restrict__ dst, int64_t ld,
+                                          bool acc_old, char *lds)
 {
     constexpr int NW = WM * WN;
     constexpr int HL = PRODUCTS == 3 ? 2 : 1;
@@ -131,32 +136,12 @@ __global__ __launch_bounds__(64 * WM * WN, 1) void k_gemm(
     static_assert(SLOT_BLOCKS % NW == 0 || P == 1, "stage copies deal evenly");
     static_assert((P - 1) * LPS < 64, "vmcnt range");
     typedef typename Frag<T>::type frag_t;
-    extern __shared__ __attribute__((aligned(1024))) char lds[];
-
-    // ---- which (split, tile) this workgroup computes
-    const int total = tiles_m * tiles_n * splits;
-    const int per_xcd = gridDim.x / kXcds;
-    const int work = (blockIdx.x % kXcds) * per_xcd + blockIdx.x / kXcds;
-    if (work >= total)
-        return;
-    const int tiles = tiles_m * tiles_n;
-    const int split = work / tiles;
-    const int tile = work % tiles;
-    const int tm = tile / tiles_n;
-    const int tn = tile % tiles_n;
 
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int wm = wave / WN, wn = wave % WN;
 
-    const int64_t kb_begin = (int64_t)split * kb_per_split;
-    int64_t kb_end = kb_begin + kb_per_split;
-    if (kb_end > kblocks)
-        kb_end = kblocks;
-    const int64_t n_st = kb_end > kb_begin ? kb_end - kb_begin : 0;
-
     // ---- this wave's copies: slot blocks wave, wave + NW, ...
-    const int64_t row_bytes = kblocks * kBlockBytes;   // one line block across all K
     const char *csrc[LPS];
 #pragma unroll
     for (int c = 0; c < LPS; ++c) {
@@ -174,12 +159,12 @@ __global__ __launch_bounds__(64 * WM * WN, 1) void k_gemm(
         csrc[c] = base + line_block * row_bytes + kb_begin * kBlockBytes;
     }
     auto issue = [&](int64_t i, int slot) {     // stage i (relative) into ring slot
-        char *dst = lds + slot * SLOT_BYTES;
+        char *dst_slot = lds + slot * SLOT_BYTES;
 #pragma unroll
         for (int c = 0; c < LPS; ++c)
             if (SLOT_BLOCKS % NW == 0 || wave + NW * c < SLOT_BLOCKS)
                 copy_block_to_lds(csrc[c] + i * kBlockBytes,
-                                  dst + (wave + NW * c) * kBlockBytes, lane);
+                                  dst_slot + (wave + NW * c) * kBlockBytes, lane);
     };
 
     f32x4 acc[FM][FN];
@@ -247,9 +232,6 @@ __global__ __launch_bounds__(64 * WM * WN, 1) void k_gemm(
     // 4 (lane / 16) + r, column lane mod 16.
     const int row_base = tm * BM + wm * FM * kFragLines;
     const int col_base = tn * BN + wn * FN * kFragLines;
-    float *dst = splits == 1 ? out : partials + (int64_t)split * M * N;
-    const int64_t ld = splits == 1 ? ldo : (int64_t)N;
-    const bool acc_old = splits == 1 && accumulate != 0;
 #pragma unroll
     for (int r0 = 0; r0 < FM; ++r0)
 #pragma unroll
@@ -267,6 +249,64 @@ __global__ __launch_bounds__(64 * WM * WN, 1) void k_gemm(
             }
         }
 }
+
+// One hologram, split-K: workgroup -> (split, tile).
+template <int BM, int BN, int WM, int WN, int PRODUCTS, typename T, int STAGES>
+__global__ __launch_bounds__(64 * WM * WN, 1) void k_gemm(
+    const char *__restrict__ Lh, const char *__restrict__ Ll, const char *__restrict__ Rh,
+    const char *__restrict__ Rl, int64_t kblocks, int tiles_m, int tiles_n, int splits,
+    int64_t kb_per_split, int M, int N, float *__restrict__ out, int64_t ldo,
+    float *__restrict__ partials, int accumulate)
+{
+    extern __shared__ __attribute__((aligned(1024))) char lds[];
+    const int total = tiles_m * tiles_n * splits;
+    const int per_xcd = gridDim.x / kXcds;
+    const int work = (blockIdx.x % kXcds) * per_xcd + blockIdx.x / kXcds;
+    if (work >= total)
+        return;
+    const int tiles = tiles_m * tiles_n;
+    const int split = work / tiles;
+    const int tile = work % tiles;
+    const int64_t kb_begin = (int64_t)split * kb_per_split;
+    int64_t kb_end = kb_begin + kb_per_split;
+    if (kb_end > kblocks)
+        kb_end = kblocks;
+    const int64_t n_st = kb_end > kb_begin ? kb_end - kb_begin : 0;
+    float *dst = splits == 1 ? out : partials + (int64_t)split * M * N;
+    const int64_t ld = splits == 1 ? ldo : (int64_t)N;
+    gemm_tile<BM, BN, WM, WN, PRODUCTS, T, STAGES>(
+        Lh, Ll, Rh, Rl, kblocks * kBlockBytes, kb_begin, n_st, tile / tiles_n, tile % tiles_n, M,
+        N, dst, ld, splits == 1 && accumulate != 0, lds);
+}
+
+// Many holograms, persistent: every workgroup takes (frame, tile) items from
+// a shared counter until none is left; an item covers its frame's whole K
+// range and writes its tile of that frame's output.  Items are ordered
+// largest K first.  The counter starts at 0 (k_reset_counter).
+template <int BM, int BN, int WM, int WN, int PRODUCTS, typename T, int STAGES>
+__global__ __launch_bounds__(64 * WM * WN, 1) void k_gemm_batch(
+    const char *__restrict__ Lh, const char *__restrict__ Ll, const char *__restrict__ Rh,
+    const char *__restrict__ Rl, int64_t total_kblocks, const BatchItem *__restrict__ items,
+    int n_items, int *__restrict__ counter, int M, int N, float *__restrict__ out)
+{
+    extern __shared__ __attribute__((aligned(1024))) char lds[];
+    __shared__ int next;
+    for (;;) {
+        if (threadIdx.x == 0)
+            next = atomicAdd(counter, 1);
+        __syncthreads();            // next is visible; the previous tile's LDS use is over
+        const int it = next;
+        __syncthreads();            // everyone has read next before thread 0 rewrites it
+        if (it >= n_items)
+            break;
+        const BatchItem w = items[it];
+        gemm_tile<BM, BN, WM, WN, PRODUCTS, T, STAGES>(
+            Lh, Ll, Rh, Rl, total_kblocks * kBlockBytes, w.kb_begin, w.kblocks, w.tm, w.tn, M, N,
+            out + w.out_off, N, false, lds);
+    }
+}
+
+__global__ void k_reset_counter(int *counter) { *counter = 0; }
 
 // out[i] = (accumulate ? out[i] : 0) + partials[0][i] + ... + partials[S-1][i], in that
 // order; four consecutive elements per thread when N allows.
@@ -313,13 +353,21 @@ hipError_t launch_tile(const GemmPlan &plan, const void *Lh, const void *Ll, con
                        const void *Rl, int M, int N, float *out, int64_t ldo, float *partials,
                        bool accumulate, hipStream_t s)
 {
+    if (plan.mblocks % (BM / kFragLines) != 0 || plan.nblocks % (BN / kFragLines) != 0 ||
+        plan.mblocks > plan.alloc_mblocks || plan.nblocks > plan.alloc_nblocks ||
+        (int64_t)plan.mblocks * kFragLines < M || (int64_t)plan.nblocks * kFragLines < N)
+        return hipErrorInvalidValue;     // tiles would read past the factor arrays
     constexpr int HL = PRODUCTS == 3 ? 2 : 1;
     const int lds_bytes = STAGES * HL * (BM + BN) / kFragLines * kBlockBytes;
     auto kern = k_gemm<BM, BN, WM, WN, PRODUCTS, T, STAGES>;
-    hipError_t e = hipFuncSetAttribute((const void *)kern,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
-    if (e != hipSuccess)
-        return e;
+    static bool attr = false;      // set once, outside any graph capture
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void *)kern,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+        if (e != hipSuccess)
+            return e;
+        attr = true;
+    }
     const int tiles_m = plan.mblocks / (BM / kFragLines);
     const int tiles_n = plan.nblocks / (BN / kFragLines);
     const int64_t per = (plan.kblocks + plan.splits - 1) / plan.splits;
@@ -329,6 +377,33 @@ hipError_t launch_tile(const GemmPlan &plan, const void *Lh, const void *Ll, con
                        (const char *)Ll, (const char *)Rh, (const char *)Rl, plan.kblocks,
                        tiles_m, tiles_n, plan.splits, per, M, N, out, ldo, partials,
                        accumulate ? 1 : 0);
+    return hipGetLastError();
+}
+
+template <int BM, int BN, int WM, int WN, int PRODUCTS, typename T, int STAGES>
+hipError_t launch_tile_batch(const GemmPlan &plan, const void *Lh, const void *Ll, const void *Rh,
+                             const void *Rl, const BatchItem *items, int n_items, int *counter,
+                             int M, int N, float *out, int grid, hipStream_t s)
+{
+    if (plan.mblocks % (BM / kFragLines) != 0 || plan.nblocks % (BN / kFragLines) != 0 ||
+        plan.mblocks > plan.alloc_mblocks || plan.nblocks > plan.alloc_nblocks ||
+        (int64_t)plan.mblocks * kFragLines < M || (int64_t)plan.nblocks * kFragLines < N)
+        return hipErrorInvalidValue;     // tiles would read past the factor arrays
+    constexpr int HL = PRODUCTS == 3 ? 2 : 1;
+    const int lds_bytes = STAGES * HL * (BM + BN) / kFragLines * kBlockBytes;
+    auto kern = k_gemm_batch<BM, BN, WM, WN, PRODUCTS, T, STAGES>;
+    static bool attr = false;      // set once, outside any graph capture
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void *)kern,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+        if (e != hipSuccess)
+            return e;
+        attr = true;
+    }
+    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, s, counter);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * WM * WN), lds_bytes, s, (const char *)Lh,
+                       (const char *)Ll, (const char *)Rh, (const char *)Rl, plan.kblocks, items,
+                       n_items, counter, M, N, out);
     return hipGetLastError();
 }
 
@@ -360,7 +435,41 @@ hipError_t launch_products(const GemmPlan &plan, const void *Lh, const void *Ll,
     return hipErrorInvalidValue;
 }
 
+template <int PRODUCTS, typename T>
+hipError_t launch_products_batch(const GemmPlan &plan, const void *Lh, const void *Ll,
+                                 const void *Rh, const void *Rl, const BatchItem *items,
+                                 int n_items, int *counter, int M, int N, float *out, int grid,
+                                 hipStream_t s)
+{
+#define CGH_TILE(TBM, TBN, TWM, TWN, TST)                                                     \
+    if (plan.bm == TBM && plan.bn == TBN && plan.waves_m == TWM && plan.waves_n == TWN &&     \
+        plan.stages == TST)                                                                   \
+        return launch_tile_batch<TBM, TBN, TWM, TWN, PRODUCTS, T, TST>(                       \
+            plan, Lh, Ll, Rh, Rl, items, n_items, counter, M, N, out, grid, s);
+    CGH_GEMM_SHAPES(CGH_TILE)
+#undef CGH_TILE
+    return hipErrorInvalidValue;
+}
+
 }  // namespace
+
+hipError_t launch_gemm_batch(const GemmPlan &plan, FactorType ft, const void *Lh, const void *Ll,
+                             const void *Rh, const void *Rl, const BatchItem *items, int n_items,
+                             int *counter, int M, int N, float *out, int grid, hipStream_t s)
+{
+    if (plan.products == 3) {
+        if (ft == FactorType::BF16)
+            return launch_products_batch<3, __bf16>(plan, Lh, Ll, Rh, Rl, items, n_items, counter,
+                                                    M, N, out, grid, s);
+        return launch_products_batch<3, _Float16>(plan, Lh, Ll, Rh, Rl, items, n_items, counter,
+                                                  M, N, out, grid, s);
+    }
+    if (ft == FactorType::BF16)
+        return launch_products_batch<1, __bf16>(plan, Lh, Ll, Rh, Rl, items, n_items, counter, M,
+                                                N, out, grid, s);
+    return launch_products_batch<1, _Float16>(plan, Lh, Ll, Rh, Rl, items, n_items, counter, M,
+                                              N, out, grid, s);
+}
 
 bool gemm_tile_supported(int bm, int bn, int waves_m, int waves_n, int stages)
 {
