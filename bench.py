@@ -42,6 +42,39 @@ GEMM_KERNEL = {"split_bf16": "gemm_split_mfma", "split_fp16": "gemm_split_mfma",
                "fp16": "gemm_mfma"}
 MODE_DTYPE = {"split_bf16": "bf16", "split_fp16": "f16", "fp16": "f16", "direct_fp32": "f32"}
 
+# HBM bytes per launch from two rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE)
+# on this workload, each scaled by what the counter reads for a plain device
+# copy of 256 MiB (FETCH_SIZE reads 128 MiB: x2.0; WRITE_SIZE 256 MiB: x1.0);
+# see profiles/.  Valid only for the kernel source they were taken on (the
+# sha256 prefix of the file) and that launch shape; otherwise reported null.
+TRAFFIC = {
+    "gemm_split_mfma": {"src": "paper_1309_2734_amd/csrc/gemm.hip", "sha": "04513c51f4aeeff7",
+                        "plan": "384,192,4,2,2,8", "bytes": (117.5 * 2.0 + 63.3) * 2 ** 20},
+    "direct_fp32": {"src": "paper_1309_2734_amd/csrc/direct.hip", "sha": "c3651537e2728bc9",
+                    "plan": "rows=16", "bytes": (463.2 * 2.0 + 7.9) * 2 ** 20},
+}
+
+
+def traffic_bytes(kernel: str, tuned):
+    """Measured HBM bytes per launch, or None if the kernel or shape changed."""
+    import hashlib
+    t = TRAFFIC.get(kernel)
+    if t is None:
+        return None
+    with open(os.path.join(ROOT, t["src"]), "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest()[:16] != t["sha"]:
+            return None
+    if t["plan"].startswith("rows="):
+        want = t["plan"] + " "                  # direct kernel: rows per lane
+        if not (tuned is None and t["plan"] == "rows=16") and (not tuned or want not in tuned):
+            return None
+    else:
+        bm, bn, wm, wn, st, sp = t["plan"].split(",")
+        want = f"bm={bm} bn={bn} waves={wm}x{wn} stages={st} splits={sp}"
+        if not tuned or want not in tuned:
+            return None
+    return t["bytes"]
+
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
@@ -91,6 +124,29 @@ def bench_batch(args, torch, cghgen, cgh):
             "launch": "hipGraph replay", "nrms_sampled_frames": errs}
 
 
+def traffic_driver(torch, cghgen, cgh) -> int:
+    """Kernel sequence for `rocprofv3 --pmc FETCH_SIZE|WRITE_SIZE -- python bench.py
+    --traffic-driver`: the per-launch counters of the GEMM and direct kernels, and of a
+    plain 256 MiB device copy whose true byte counts calibrate them."""
+    os.environ["CGH_GEMM_PLAN"] = TRAFFIC["gemm_split_mfma"]["plan"]
+    c = cghgen.make_config(2)
+    ctx = cgh.Context(c.width, c.height, c.pitch, c.wavelength)
+    ctx.upload_cloud(c)
+    out = torch.empty((c.height, c.width), device="cuda:0")
+    for _ in range(3):
+        ctx.compute(out, cgh.SPLIT_BF16)
+    for _ in range(2):
+        ctx.compute(out, cgh.DIRECT_FP32)
+    src = torch.ones(64 << 20, device="cuda:0")       # 256 MiB of float32
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    ctx.close()
+    log("traffic driver done")
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -104,6 +160,10 @@ def main() -> int:
     ap.add_argument("--no-tune", action="store_true", help="use the default launch shapes")
     ap.add_argument("--batch-frames", type=int, default=64,
                     help="frames of the batched-workload side measurement (0 = skip)")
+    ap.add_argument("--traffic-driver", action="store_true",
+                    help="run only the fixed kernel sequence the HBM-traffic counter passes "
+                         "read (3 split-BF16 computes with the recorded GEMM shape, 2 direct "
+                         "computes, 3 device copies of 256 MiB for calibration), then exit")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -114,6 +174,9 @@ def main() -> int:
 
     import cghgen
     import paper_1309_2734_amd as cgh
+
+    if args.traffic_driver:
+        return traffic_driver(torch, cghgen, cgh)
 
     modes = [m.strip() for m in args.modes.split(",") if m.strip()]
     head = modes[0]
@@ -170,8 +233,8 @@ def main() -> int:
                 ach = pp / (t * 1e-3)
                 r["roofline"] = {"bound": "alu", "achieved": ach, "peak": PEAK_DIRECT_PPS,
                                  "unit": "point*pixel/s", "frac": ach / PEAK_DIRECT_PPS,
-                                 "traffic": None, "kernel": "direct_fp32",
-                                 "kernel_ms": t}
+                                 "traffic": traffic_bytes("direct_fp32", tuned),
+                                 "kernel": "direct_fp32", "kernel_ms": t}
         else:
             kname = GEMM_KERNEL[m]
             t = r["kernels_ms"].get(kname)
@@ -180,8 +243,9 @@ def main() -> int:
                 ach = flops / (t * 1e-3) / 1e12
                 peak = PEAK_MFMA_BF16_TFLOPS if m == "split_bf16" else PEAK_MFMA_FP16_TFLOPS
                 r["roofline"] = {"bound": "mfma", "achieved": ach, "peak": peak,
-                                 "unit": "TFLOP/s", "frac": ach / peak, "traffic": None,
-                                 "kernel": kname, "kernel_ms": t}
+                                 "unit": "TFLOP/s", "frac": ach / peak,
+                                 "traffic": traffic_bytes(kname, tuned) if m == "split_bf16"
+                                 else None, "kernel": kname, "kernel_ms": t}
         log(f"mode {m}: {wall_ms:.4f} ms/step, {r['pp_per_s']:.3e} pp/s, kernels {r['kernels_ms']}")
         results[m] = r
     ctx.close()
