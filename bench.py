@@ -31,16 +31,20 @@ if ROOT not in sys.path:
 # Published MI355X peaks (dense) and the issue-rate roofline of the direct kernel.
 PEAK_MFMA_BF16_TFLOPS = 2500.0
 PEAK_MFMA_FP16_TFLOPS = 2500.0
+PEAK_MFMA_FP32_TFLOPS = 157.3
 CUS, CLOCK_HZ, LANES = 256, 2.4e9, 64
 # direct kernel: v_add_f32 (1 slot) + v_cos_f32 (2 slots, half rate) + v_fmac_f32 (1 slot)
 DIRECT_SLOTS_PER_PP = 4
 PEAK_DIRECT_PPS = CUS * CLOCK_HZ * LANES / DIRECT_SLOTS_PER_PP      # 9.83e12 point*pixel/s
 
 # executed matrix flops per point*pixel: K = 2N columns, 2 flop per MAC, x products
-FLOP_PER_PP = {"split_bf16": 12, "split_fp16": 12, "fp16": 4}
+FLOP_PER_PP = {"split_bf16": 12, "split_fp16": 12, "fp16": 4, "separable_fp32": 4}
 GEMM_KERNEL = {"split_bf16": "gemm_split_mfma", "split_fp16": "gemm_split_mfma",
-               "fp16": "gemm_mfma"}
-MODE_DTYPE = {"split_bf16": "bf16", "split_fp16": "f16", "fp16": "f16", "direct_fp32": "f32"}
+               "fp16": "gemm_mfma", "separable_fp32": "gemm_fp32_mfma"}
+GEMM_PEAK = {"split_bf16": PEAK_MFMA_BF16_TFLOPS, "split_fp16": PEAK_MFMA_FP16_TFLOPS,
+             "fp16": PEAK_MFMA_FP16_TFLOPS, "separable_fp32": PEAK_MFMA_FP32_TFLOPS}
+MODE_DTYPE = {"split_bf16": "bf16", "split_fp16": "f16", "fp16": "f16", "direct_fp32": "f32",
+              "separable_fp32": "f32"}
 
 # HBM bytes per launch from two rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE)
 # on this workload, each scaled by what the counter reads for a plain device
@@ -152,7 +156,7 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--modes", default="split_bf16,direct_fp32,split_fp16,fp16",
+    ap.add_argument("--modes", default="split_bf16,direct_fp32,separable_fp32,split_fp16,fp16",
                     help="comma list; the first is the headline mode")
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the oracle (profiling runs)")
@@ -194,7 +198,7 @@ def main() -> int:
     for m in modes:
         mode = cgh.MODES[m]
         tuned = None
-        if not args.no_tune and mode != cgh.SEPARABLE_FP32:
+        if not args.no_tune:
             tuned = ctx.tune(mode, repeats=3, stream=stream)
             log(f"mode {m}: tuned {tuned}")
         log(f"mode {m}: warmup {args.warmup}")
@@ -241,7 +245,7 @@ def main() -> int:
             if t:
                 flops = FLOP_PER_PP[m] * pp
                 ach = flops / (t * 1e-3) / 1e12
-                peak = PEAK_MFMA_BF16_TFLOPS if m == "split_bf16" else PEAK_MFMA_FP16_TFLOPS
+                peak = GEMM_PEAK[m]
                 r["roofline"] = {"bound": "mfma", "achieved": ach, "peak": peak,
                                  "unit": "TFLOP/s", "frac": ach / peak,
                                  "traffic": traffic_bytes(kname, tuned) if m == "split_bf16"

@@ -82,8 +82,11 @@ typedef enum {
  *                   (hi*hi + hi*lo + lo*hi) win back the precision.
  * CGH_SPLIT_FP16    As CGH_SPLIT_BF16 with FP16 hi + lo factors.
  * CGH_FP16          One FP16 product (no lo part): a third of the matrix work.
- * CGH_SEPARABLE_FP32  The factor product evaluated in FP32 on the vector
- *                   units (no per-pixel cosine, no reduced-precision operand).
+ * CGH_SEPARABLE_FP32  The same factor product with FP32 factors on the
+ *                   FP32 matrix instructions (no per-pixel cosine, no
+ *                   reduced-precision operand): the accuracy of
+ *                   CGH_DIRECT_FP32 at a quarter of the matrix rate of the
+ *                   16-bit products.
  */
 typedef enum {
     CGH_DIRECT_FP32 = 0,
@@ -139,8 +142,16 @@ CGH_API cgh_status cgh_compute(cgh_ctx *c, cgh_mode mode, float *out_dev, void *
  * overlap, repeat, or be empty (a zero hologram).  Work of all frames is
  * balanced across the device by one persistent kernel launch per stage, and
  * a repeated call with the same frame table replays a captured HIP graph.
- *   n_frames in [1, 65536]; each frame's points lie within the upload and
- *   its wavelength is finite and > 0.
+ *   n_frames in [1, 65535]; each frame's points lie within the upload and
+ *   its wavelength is finite and > 0.  The matrix-core modes process the
+ *   frames in groups whose factors fit the workspace budget (one constants,
+ *   one factor and one persistent GEMM launch per group; each (frame, tile)
+ *   item runs its frame's whole K range in one workgroup, so a frame's sums
+ *   are ordered differently from cgh_compute's split-K).  A call on a
+ *   non-NULL stream runs eagerly and then records its kernel sequence in a
+ *   HIP graph; a later call with the same mode, frame table and output
+ *   replays that graph.  A call that changes any of them, or that must grow
+ *   a workspace buffer, runs eagerly and replaces the graph.
  * Modes: all of cgh_mode.  Errors as cgh_compute. */
 CGH_API cgh_status cgh_batch_compute(cgh_ctx *c, const cgh_frame *frames, int32_t n_frames,
                              cgh_mode mode, float *out_dev, void *stream);
@@ -157,7 +168,8 @@ CGH_API cgh_status cgh_batch_compute(cgh_ctx *c, const cgh_frame *frames, int32_
  * bytes) receives a one-line description of the choice.  Blocks the host
  * until the timing finishes.
  * Errors: CGH_EINVAL (repeats outside [1, 1000], bad buffer, unknown mode),
- * CGH_ESTATE (no upload), CGH_ENOTSUP (CGH_SEPARABLE_FP32), CGH_EDEVICE. */
+ * CGH_ESTATE (no upload), CGH_ENOTSUP (no candidate fits the hologram),
+ * CGH_EDEVICE. */
 CGH_API cgh_status cgh_tune(cgh_ctx *c, cgh_mode mode, int32_t repeats, char *report,
                             int32_t report_len, void *stream);
 

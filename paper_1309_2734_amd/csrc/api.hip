@@ -305,6 +305,43 @@ const float *pts_y(cgh_ctx *c) { return pts_x(c) + c->n_cap; }
 const float *pts_z(cgh_ctx *c) { return pts_x(c) + 2 * c->n_cap; }
 const float *pts_a(cgh_ctx *c) { return pts_x(c) + 3 * c->n_cap; }
 
+cgh_status check_mode(int mode)
+{
+    if (mode < CGH_DIRECT_FP32 || mode > CGH_SEPARABLE_FP32)
+        return fail(CGH_EINVAL, "unknown mode");
+    return CGH_OK;
+}
+
+// How a matrix-core mode stores and multiplies its factors.
+struct ModeInfo {
+    FactorType ft;
+    int products;        // 3 = hi*hi + hi*lo + lo*hi, 1 = one product
+    int hl;              // factor arrays per side (hi, lo)
+    int elem;            // bytes per factor value
+    int kbp;             // points per K block
+    const char *fac_name, *gemm_name, *batch_name;   // profiling labels
+    // bytes of factors per line (row or column) and point
+    int line_bytes() const { return 2 * elem * hl; }
+};
+
+ModeInfo mode_info(int mode)
+{
+    switch (mode) {
+    case CGH_SPLIT_BF16:
+        return {FactorType::BF16, 3, 2, 2, kblock_points(FactorType::BF16), "factors_split",
+                "gemm_split_mfma", "gemm_split_mfma_batch"};
+    case CGH_SPLIT_FP16:
+        return {FactorType::FP16, 3, 2, 2, kblock_points(FactorType::FP16), "factors_split",
+                "gemm_split_mfma", "gemm_split_mfma_batch"};
+    case CGH_SEPARABLE_FP32:
+        return {FactorType::FP32, 1, 1, 4, kblock_points(FactorType::FP32), "factors_fp32",
+                "gemm_fp32_mfma", "gemm_fp32_mfma_batch"};
+    default:   // CGH_FP16
+        return {FactorType::FP16, 1, 1, 2, kblock_points(FactorType::FP16), "factors",
+                "gemm_mfma", "gemm_mfma_batch"};
+    }
+}
+
 // ---------------------------------------------------------------- planning
 struct Plan {
     GemmPlan g;
@@ -336,7 +373,7 @@ const TuneEntry *find_tuned(const cgh_ctx *c, const std::string &key)
     return nullptr;
 }
 
-Plan plan_gemm(int M, int N, int64_t slots, int products, const TuneEntry *tuned = nullptr)
+Plan plan_gemm(int M, int N, int64_t slots, const ModeInfo &mi, const TuneEntry *tuned = nullptr)
 {
     struct Shape {
         int bm, bn, wm, wn, stages;
@@ -382,7 +419,7 @@ Plan plan_gemm(int M, int N, int64_t slots, int products, const TuneEntry *tuned
     best.tiles_m = (M + best.g.bm - 1) / best.g.bm;
     best.tiles_n = (N + best.g.bn - 1) / best.g.bn;
     const int tiles = best.tiles_m * best.tiles_n;
-    const int64_t kblocks = slots / kFragPoints;
+    const int64_t kblocks = slots / mi.kbp;
     // as many K splits as fit the device (one workgroup per CU) in one wave
     int splits = forced_splits > 0 ? forced_splits : std::max(1, 256 / tiles);
     while (splits > 1 && kblocks / splits < 8)
@@ -393,15 +430,8 @@ Plan plan_gemm(int M, int N, int64_t slots, int products, const TuneEntry *tuned
     best.g.alloc_mblocks = best.g.mblocks;   // the caller sizes the factors from these
     best.g.alloc_nblocks = best.g.nblocks;
     best.g.kblocks = kblocks;
-    best.g.products = products;
+    best.g.products = mi.products;
     return best;
-}
-
-cgh_status check_mode(int mode)
-{
-    if (mode < CGH_DIRECT_FP32 || mode > CGH_SEPARABLE_FP32)
-        return fail(CGH_EINVAL, "unknown mode");
-    return CGH_OK;
 }
 
 // ------------------------------------------------------- one set of frames
@@ -436,14 +466,14 @@ cgh_status run_direct(cgh_ctx *c, const FrameDesc *fd_dev, int n_frames, int64_t
 cgh_status run_gemm(cgh_ctx *c, int mode, int64_t slot0, int64_t slots, float *out,
                     bool accumulate, hipStream_t s)
 {
-    const bool split = mode == CGH_SPLIT_BF16 || mode == CGH_SPLIT_FP16;
-    const FactorType ft = mode == CGH_SPLIT_BF16 ? FactorType::BF16 : FactorType::FP16;
-    const Plan p = plan_gemm(c->height, c->width, slots, split ? 3 : 1,
-                             find_tuned(c, tune_key(c, mode, slots / kFragPoints)));
-    const int hl = split ? 2 : 1;
-    // 2 K-columns (cos, sin) of 2 bytes per line and point
-    const size_t lbytes = (size_t)p.g.mblocks * kFragLines * (size_t)slots * 2 * 2;
-    const size_t rbytes = (size_t)p.g.nblocks * kFragLines * (size_t)slots * 2 * 2;
+    const ModeInfo mi = mode_info(mode);
+    const FactorType ft = mi.ft;
+    const Plan p = plan_gemm(c->height, c->width, slots, mi,
+                             find_tuned(c, tune_key(c, mode, slots / mi.kbp)));
+    const int hl = mi.hl;
+    // 2 K-columns (cos, sin) per line and point
+    const size_t lbytes = (size_t)p.g.mblocks * kFragLines * (size_t)slots * 2 * mi.elem;
+    const size_t rbytes = (size_t)p.g.nblocks * kFragLines * (size_t)slots * 2 * mi.elem;
     CGH_HIP(ensure_ws(c, c->fac[0], lbytes), "factor allocation");
     CGH_HIP(ensure_ws(c, c->fac[2], rbytes), "factor allocation");
     if (hl == 2) {
@@ -456,7 +486,7 @@ cgh_status run_gemm(cgh_ctx *c, int mode, int64_t slot0, int64_t slots, float *o
                 "split-K workspace allocation");
     PointConsts pc = consts_view(c, c->consts_cap);
     {
-        Bracket br(c, split ? "factors_split" : "factors", s);
+        Bracket br(c, mi.fac_name, s);
         CGH_HIP(launch_factors(pc, slot0, slots, c->width, c->height, p.g.kblocks, p.g.mblocks,
                                p.g.nblocks, ft, c->fac[0].p, hl == 2 ? c->fac[1].p : nullptr,
                                c->fac[2].p, hl == 2 ? c->fac[3].p : nullptr, s),
@@ -464,7 +494,7 @@ cgh_status run_gemm(cgh_ctx *c, int mode, int64_t slot0, int64_t slots, float *o
         br.done();
     }
     {
-        Bracket br(c, split ? "gemm_split_mfma" : "gemm_mfma", s);
+        Bracket br(c, mi.gemm_name, s);
         CGH_HIP(launch_gemm(p.g, ft, c->fac[0].p, hl == 2 ? c->fac[1].p : nullptr, c->fac[2].p,
                             hl == 2 ? c->fac[3].p : nullptr, c->height, c->width, out, c->width,
                             (float *)c->partials.p, accumulate, s),
@@ -486,10 +516,9 @@ size_t bytes_per_slot(cgh_ctx *c, int mode)
 {
     if (mode == CGH_DIRECT_FP32)
         return (size_t)(c->wpad + c->hpad) * sizeof(float);
-    const int hl = (mode == CGH_SPLIT_BF16 || mode == CGH_SPLIT_FP16) ? 2 : 1;
     const int64_t w = std::max(round_up(c->width, 384), round_up(c->width, 256));
     const int64_t h = std::max(round_up(c->height, 384), round_up(c->height, 256));
-    return (size_t)(w + h) * 2 * 2 * hl;
+    return (size_t)(w + h) * mode_info(mode).line_bytes();
 }
 
 int64_t chunk_slots(cgh_ctx *c, int mode)
@@ -591,18 +620,18 @@ cgh_status eval_batch_direct(cgh_ctx *c, const cgh_frame *frames, int n_frames, 
 cgh_status eval_batch_gemm(cgh_ctx *c, int mode, const cgh_frame *frames, int n_frames,
                            float *out, hipStream_t s)
 {
-    const bool split = mode == CGH_SPLIT_BF16 || mode == CGH_SPLIT_FP16;
-    const FactorType ft = mode == CGH_SPLIT_BF16 ? FactorType::BF16 : FactorType::FP16;
-    const int hl = split ? 2 : 1;
+    const ModeInfo mi = mode_info(mode);
+    const FactorType ft = mi.ft;
+    const int hl = mi.hl;
     const int64_t plane = (int64_t)c->width * c->height;
     // tile shape: the tuned (or default) shape for the largest frame
     int64_t max_count = 0;
     for (int f = 0; f < n_frames; ++f)
         max_count = std::max(max_count, frames[f].point_count);
     const int64_t max_slots = std::max<int64_t>(round_up(max_count, kSlotAlign), kSlotAlign);
-    Plan p = plan_gemm(c->height, c->width, max_slots, split ? 3 : 1,
-                       find_tuned(c, tune_key(c, mode, max_slots / kFragPoints)));
-    const size_t per_slot = (size_t)(p.g.mblocks + p.g.nblocks) * kFragLines * 2 * 2 * hl;
+    Plan p = plan_gemm(c->height, c->width, max_slots, mi,
+                       find_tuned(c, tune_key(c, mode, max_slots / mi.kbp)));
+    const size_t per_slot = (size_t)(p.g.mblocks + p.g.nblocks) * kFragLines * mi.line_bytes();
     const int64_t budget = std::max<int64_t>((int64_t)(workspace_budget() / per_slot), kSlotAlign);
 
     // Groups of frames [f0, f1) whose padded slots fit the budget (at least
@@ -628,7 +657,7 @@ cgh_status eval_batch_gemm(cgh_ctx *c, int mode, const cgh_frame *frames, int n_
                             frames[f1].wavelength});
             for (int tm = 0; tm < p.tiles_m; ++tm)
                 for (int tn = 0; tn < p.tiles_n; ++tn)
-                    items.push_back({gr.slots / kFragPoints, ps / kFragPoints, f1 * plane, tm, tn});
+                    items.push_back({gr.slots / mi.kbp, ps / mi.kbp, f1 * plane, tm, tn});
             gr.slots += ps;
             gr.max_count = std::max(gr.max_count, frames[f1].point_count);
             ++f1;
@@ -648,8 +677,8 @@ cgh_status eval_batch_gemm(cgh_ctx *c, int mode, const cgh_frame *frames, int n_
     int64_t max_group_slots = kSlotAlign;
     for (auto &gr : groups)
         max_group_slots = std::max(max_group_slots, gr.slots);
-    const size_t lbytes = (size_t)p.g.mblocks * kFragLines * (size_t)max_group_slots * 4;
-    const size_t rbytes = (size_t)p.g.nblocks * kFragLines * (size_t)max_group_slots * 4;
+    const size_t lbytes = (size_t)p.g.mblocks * kFragLines * (size_t)max_group_slots * 2 * mi.elem;
+    const size_t rbytes = (size_t)p.g.nblocks * kFragLines * (size_t)max_group_slots * 2 * mi.elem;
     CGH_HIP(ensure_ws(c, c->fac[0], lbytes), "factor allocation");
     CGH_HIP(ensure_ws(c, c->fac[2], rbytes), "factor allocation");
     if (hl == 2) {
@@ -663,9 +692,9 @@ cgh_status eval_batch_gemm(cgh_ctx *c, int mode, const cgh_frame *frames, int n_
         if (st != CGH_OK)
             return st;
         GemmPlan g = p.g;
-        g.kblocks = total / kFragPoints;
+        g.kblocks = total / mi.kbp;
         {
-            Bracket br(c, split ? "factors_split" : "factors", s);
+            Bracket br(c, mi.fac_name, s);
             CGH_HIP(launch_factors(consts_view(c, c->consts_cap), 0, total, c->width, c->height,
                                    g.kblocks, g.mblocks, g.nblocks, ft, c->fac[0].p,
                                    hl == 2 ? c->fac[1].p : nullptr, c->fac[2].p,
@@ -674,7 +703,7 @@ cgh_status eval_batch_gemm(cgh_ctx *c, int mode, const cgh_frame *frames, int n_
             br.done();
         }
         {
-            Bracket br(c, split ? "gemm_split_mfma_batch" : "gemm_mfma_batch", s);
+            Bracket br(c, mi.batch_name, s);
             CGH_HIP(launch_gemm_batch(g, ft, c->fac[0].p, hl == 2 ? c->fac[1].p : nullptr,
                                       c->fac[2].p, hl == 2 ? c->fac[3].p : nullptr,
                                       (const BatchItem *)c->items.p + gr.item0, gr.nitem,
@@ -979,8 +1008,6 @@ cgh_status cgh_compute(cgh_ctx *c, cgh_mode mode, float *out_dev, void *stream)
         return st;
     if (!c->uploaded)
         return fail(CGH_ESTATE, "no points uploaded");
-    if (mode == CGH_SEPARABLE_FP32)
-        return fail(CGH_ENOTSUP, "CGH_SEPARABLE_FP32 is not built yet");
     DeviceGuard g;
     CGH_HIP(g.set(c->device), "hipSetDevice");
     return eval_one(c, mode, 0, c->n, c->wavelength, out_dev, (hipStream_t)stream);
@@ -1011,8 +1038,6 @@ cgh_status cgh_batch_compute(cgh_ctx *c, const cgh_frame *frames, int32_t n_fram
         if (!finite_pos(fr.wavelength))
             return fail(CGH_EINVAL, "frame " + std::to_string(f) + " has a bad wavelength");
     }
-    if (mode == CGH_SEPARABLE_FP32)
-        return fail(CGH_ENOTSUP, "CGH_SEPARABLE_FP32 is not built yet");
     DeviceGuard g;
     CGH_HIP(g.set(c->device), "hipSetDevice");
     hipStream_t s = (hipStream_t)stream;
@@ -1070,8 +1095,6 @@ cgh_status cgh_tune(cgh_ctx *c, cgh_mode mode, int32_t repeats, char *report, in
         return fail(CGH_EINVAL, "bad report buffer");
     if (!c->uploaded)
         return fail(CGH_ESTATE, "no points uploaded");
-    if (mode == CGH_SEPARABLE_FP32)
-        return fail(CGH_ENOTSUP, "CGH_SEPARABLE_FP32 has no tunable choice");
     DeviceGuard g;
     CGH_HIP(g.set(c->device), "hipSetDevice");
     hipStream_t s = (hipStream_t)stream;
@@ -1120,10 +1143,10 @@ cgh_status cgh_tune(cgh_ctx *c, cgh_mode mode, int32_t repeats, char *report, in
             }
         }
     } else {
-        const bool split = mode == CGH_SPLIT_BF16 || mode == CGH_SPLIT_FP16;
-        const FactorType ft = mode == CGH_SPLIT_BF16 ? FactorType::BF16 : FactorType::FP16;
-        const int hl = split ? 2 : 1;
-        const int64_t kblocks = slots / kFragPoints;
+        const ModeInfo mi = mode_info(mode);
+        const FactorType ft = mi.ft;
+        const int hl = mi.hl;
+        const int64_t kblocks = slots / mi.kbp;
         best.key = tune_key(c, mode, kblocks);
         static const int shapes[][5] = {{192, 384, 2, 4, 2}, {384, 192, 4, 2, 2},
                                         {192, 256, 2, 4, 2}, {256, 256, 2, 4, 2},
@@ -1135,8 +1158,8 @@ cgh_status cgh_tune(cgh_ctx *c, cgh_mode mode, int32_t repeats, char *report, in
             mb = std::max(mb, (int)(round_up(c->height, sh[0]) / kFragLines));
             nb = std::max(nb, (int)(round_up(c->width, sh[1]) / kFragLines));
         }
-        const size_t lbytes = (size_t)mb * kFragLines * slots * 4;
-        const size_t rbytes = (size_t)nb * kFragLines * slots * 4;
+        const size_t lbytes = (size_t)mb * kFragLines * slots * 2 * mi.elem;
+        const size_t rbytes = (size_t)nb * kFragLines * slots * 2 * mi.elem;
         CGH_HIP(ensure_ws(c, c->fac[0], lbytes), "factor allocation");
         CGH_HIP(ensure_ws(c, c->fac[2], rbytes), "factor allocation");
         if (hl == 2) {
@@ -1172,7 +1195,7 @@ cgh_status cgh_tune(cgh_ctx *c, cgh_mode mode, int32_t repeats, char *report, in
                 gp.mblocks = (c->height + sh[0] - 1) / sh[0] * (sh[0] / kFragLines);
                 gp.nblocks = (c->width + sh[1] - 1) / sh[1] * (sh[1] / kFragLines);
                 gp.kblocks = kblocks;
-                gp.products = split ? 3 : 1;
+                gp.products = mi.products;
                 gp.alloc_mblocks = mb;
                 gp.alloc_nblocks = nb;
                 if (sp > 1)

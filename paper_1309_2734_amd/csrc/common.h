@@ -29,10 +29,9 @@ constexpr int kGroup = 16;
 constexpr int kSlotAlign = 32;
 // Line tables are padded to a multiple of this many columns / rows.
 constexpr int kLinePad = 64;
-// Matrix-core operand blocks (factors.hip, gemm.hip): 16 lines x 32
-// K-columns = 16 points, 1 KB in bf16/f16.
+// Matrix-core operand blocks (factors.hip, gemm.hip) are 1 KB of 16 lines:
+// 32 K-columns = 16 points in bf16/f16, 16 K-columns = 8 points in FP32.
 constexpr int kFragLines = 16;
-constexpr int kFragPoints = 16;
 
 // Per-point constants of one evaluation segment, structure of arrays.
 struct PointConsts {
@@ -81,17 +80,12 @@ hipError_t launch_direct(const float *U, const float *V, const float *amp,
                          int wpad, int hpad, int rows_per_wave, float *out, bool accumulate,
                          hipStream_t s);
 
-// F2: FP32 separable product on the vector units, same tables plus factors.
-hipError_t launch_separable_fp32(const float *U, const float *V, const float *amp,
-                                 int64_t n_slots, const FrameDesc *frames_dev, int n_frames,
-                                 int64_t max_groups, int width, int height, float *out,
-                                 hipStream_t s);
-
 // a4: factor build.  Writes the hi (and, if lo_* != nullptr, lo) factors of
 // L (rows) and R (columns) in the MFMA fragment order described in factors.hip:
-// mblocks / nblocks blocks of kFragLines lines, kblocks blocks of kFragPoints
-// points.
-enum class FactorType { BF16 = 0, FP16 = 1 };
+// mblocks / nblocks blocks of kFragLines lines, kblocks blocks of
+// kblock_points(ft) points.  FP32 factors have no lo half.
+enum class FactorType { BF16 = 0, FP16 = 1, FP32 = 2 };
+constexpr int kblock_points(FactorType ft) { return ft == FactorType::FP32 ? 8 : 16; }
 hipError_t launch_factors(PointConsts pc, int64_t slot0, int64_t n_slots, int width, int height,
                           int64_t kblocks, int mblocks, int nblocks, FactorType ft,
                           void *Lh, void *Ll, void *Rh, void *Rl, hipStream_t s);
@@ -102,7 +96,7 @@ struct GemmPlan {
     int waves_m, waves_n;// wave grid of a workgroup (4 or 8 waves)
     int stages;          // LDS ring depth (copies run stages-1 K blocks ahead)
     int splits;          // K splits (1 = write the output directly)
-    int64_t kblocks;     // K blocks of kFragPoints points
+    int64_t kblocks;     // K blocks of kblock_points(factor type) points
     int mblocks, nblocks;// line blocks of kFragLines (padded to whole tiles)
     int alloc_mblocks;   // line blocks the L / R factor arrays hold; a launch whose
     int alloc_nblocks;   // tiles would read beyond them is refused

@@ -6,40 +6,51 @@
 // K = 2N interleaved columns:
 //     L[iy, 2j] =  A_j cos(2 pi V[iy, j]),   L[iy, 2j+1] = -A_j sin(2 pi V[iy, j]),
 //     R[ix, 2j] =      cos(2 pi U[ix, j]),   R[ix, 2j+1] =      sin(2 pi U[ix, j]).
-// Each value v is stored as hi = round(v) and lo = round(v - hi) in the
-// 16-bit type (round to nearest even; v - hi is exact in FP32).
+// In the 16-bit types each value v is stored as hi = round(v) and
+// lo = round(v - hi) (round to nearest even; v - hi is exact in FP32), or as
+// hi alone; FP32 factors are stored as computed.
 //
-// Storage order = the operand order of v_mfma_f32_16x16x32_{bf16,f16}: the
-// matrix is cut into blocks of 16 lines x 32 K-columns (16 points); a block
-// is 64 lanes x 8 values = 1 KB, lane l holding line (l mod 16) and
-// K-columns 8 (l / 16) .. 8 (l / 16) + 7 of the block, i.e. 4 points'
-// (cos, sin) pairs.  Blocks are ordered [line block][K block], so a GEMM
-// stage copies whole 1 KB blocks straight into LDS.  Lines past the
-// hologram are written as zeros.
+// Storage order = the operand order of the matrix instructions: the matrix
+// is cut into 1 KB blocks of 16 lines, a block being 64 lanes x 16 bytes;
+// lane l holds line (l mod 16) and the next 16 bytes of K-columns of group
+// l / 16.  In bf16/f16 (v_mfma_f32_16x16x32_*) that is K-columns
+// 8 (l / 16) .. + 7, 4 points' (cos, sin) pairs, 16 points a block; in FP32
+// (four v_mfma_f32_16x16x4_f32 per block, see gemm.hip) K-columns
+// 4 (l / 16) .. + 3, 2 points, 8 points a block.  Blocks are ordered
+// [line block][K block], so a GEMM stage copies whole 1 KB blocks straight
+// into LDS.  Lines past the hologram are written as zeros.
 #include "common.h"
 
 namespace cgh {
 namespace {
 
 template <typename T>
-__device__ __forceinline__ T to16(float v);
+__device__ __forceinline__ T to_t(float v);
 template <>
-__device__ __forceinline__ __bf16 to16<__bf16>(float v) { return (__bf16)v; }
+__device__ __forceinline__ __bf16 to_t<__bf16>(float v) { return (__bf16)v; }
 template <>
-__device__ __forceinline__ _Float16 to16<_Float16>(float v) { return (_Float16)v; }
+__device__ __forceinline__ _Float16 to_t<_Float16>(float v) { return (_Float16)v; }
+template <>
+__device__ __forceinline__ float to_t<float>(float v) { return v; }
 
+// one lane's 16 bytes of a block
 template <typename T>
-struct alignas(16) Vec8 {
-    T v[8];
+struct alignas(16) Vec16B {
+    static constexpr int kValues = 16 / sizeof(T);
+    T v[kValues];
 };
 
 // Grid: x = K block * 64 + lane, y = line block (L blocks first, then R).
 template <typename T, bool SPLIT>
 __global__ __launch_bounds__(256) void k_factors(PointConsts pc, int64_t slot0, int64_t kblocks,
                                                  int height, int width, int mblocks,
-                                                 Vec8<T> *__restrict__ Lh, Vec8<T> *__restrict__ Ll,
-                                                 Vec8<T> *__restrict__ Rh, Vec8<T> *__restrict__ Rl)
+                                                 Vec16B<T> *__restrict__ Lh,
+                                                 Vec16B<T> *__restrict__ Ll,
+                                                 Vec16B<T> *__restrict__ Rh,
+                                                 Vec16B<T> *__restrict__ Rl)
 {
+    constexpr int kLanePoints = Vec16B<T>::kValues / 2;      // (cos, sin) pairs per lane
+    constexpr int kBlockPoints = 4 * kLanePoints;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= kblocks * 64)
         return;
@@ -49,11 +60,11 @@ __global__ __launch_bounds__(256) void k_factors(PointConsts pc, int64_t slot0, 
     const int rb = is_l ? (int)blockIdx.y : (int)blockIdx.y - mblocks;
     const int line = rb * kFragLines + (lane & (kFragLines - 1));
     const int lines = is_l ? height : width;
-    const int64_t j0 = slot0 + kb * kFragPoints + 4 * (lane / kFragLines);
+    const int64_t j0 = slot0 + kb * kBlockPoints + kLanePoints * (lane / kFragLines);
 
-    Vec8<T> hi, lo;
+    Vec16B<T> hi, lo;
 #pragma unroll
-    for (int p = 0; p < 4; ++p) {
+    for (int p = 0; p < kLanePoints; ++p) {
         float c = 0.0f, s = 0.0f;
         if (line < lines) {
             const int64_t j = j0 + p;
@@ -68,12 +79,12 @@ __global__ __launch_bounds__(256) void k_factors(PointConsts pc, int64_t slot0, 
                 s = -a * s;
             }
         }
-        const T ch = to16<T>(c), sh = to16<T>(s);
+        const T ch = to_t<T>(c), sh = to_t<T>(s);
         hi.v[2 * p] = ch;
         hi.v[2 * p + 1] = sh;
         if (SPLIT) {
-            lo.v[2 * p] = to16<T>(c - (float)ch);
-            lo.v[2 * p + 1] = to16<T>(s - (float)sh);
+            lo.v[2 * p] = to_t<T>(c - (float)ch);
+            lo.v[2 * p + 1] = to_t<T>(s - (float)sh);
         }
     }
     const int64_t idx = ((int64_t)rb * kblocks + kb) * 64 + lane;
@@ -95,14 +106,13 @@ hipError_t launch_t(PointConsts pc, int64_t slot0, int64_t n_slots, int width, i
 {
     (void)n_slots;
     dim3 grid((unsigned)((kblocks * 64 + 255) / 256), (unsigned)(mblocks + nblocks));
-    if (Ll != nullptr)
-        hipLaunchKernelGGL((k_factors<T, true>), grid, dim3(256), 0, s, pc, slot0, kblocks, height,
-                           width, mblocks, (Vec8<T> *)Lh, (Vec8<T> *)Ll, (Vec8<T> *)Rh,
-                           (Vec8<T> *)Rl);
+    typedef Vec16B<T> V;
+    if (Ll != nullptr && sizeof(T) == 2)
+        hipLaunchKernelGGL((k_factors<T, sizeof(T) == 2>), grid, dim3(256), 0, s, pc, slot0,
+                           kblocks, height, width, mblocks, (V *)Lh, (V *)Ll, (V *)Rh, (V *)Rl);
     else
         hipLaunchKernelGGL((k_factors<T, false>), grid, dim3(256), 0, s, pc, slot0, kblocks,
-                           height, width, mblocks, (Vec8<T> *)Lh, (Vec8<T> *)nullptr,
-                           (Vec8<T> *)Rh, (Vec8<T> *)nullptr);
+                           height, width, mblocks, (V *)Lh, (V *)nullptr, (V *)Rh, (V *)nullptr);
     return hipGetLastError();
 }
 
@@ -117,6 +127,12 @@ hipError_t launch_factors(PointConsts pc, int64_t slot0, int64_t n_slots, int wi
     if (ft == FactorType::BF16)
         return launch_t<__bf16>(pc, slot0, n_slots, width, height, kblocks, mblocks, nblocks, Lh,
                                 Ll, Rh, Rl, s);
+    if (ft == FactorType::FP32) {
+        if (Ll != nullptr || Rl != nullptr)
+            return hipErrorInvalidValue;    // FP32 factors have no lo half
+        return launch_t<float>(pc, slot0, n_slots, width, height, kblocks, mblocks, nblocks, Lh,
+                               nullptr, Rh, nullptr, s);
+    }
     return launch_t<_Float16>(pc, slot0, n_slots, width, height, kblocks, mblocks, nblocks, Lh,
                               Ll, Rh, Rl, s);
 }

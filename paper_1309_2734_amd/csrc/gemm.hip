@@ -4,13 +4,17 @@
 //     Lh Rh^T + Lh Rl^T + Ll Rh^T        (3 products; Ll Rl^T is below FP32 noise)
 // or Lh Rh^T alone, in BF16 or FP16 with FP32 accumulation, using
 // v_mfma_f32_16x16x32_{bf16,f16} (the 16x16 shape keeps the matrix pipe
-// busier than the 32x32 one on gfx950).
+// busier than the 32x32 one on gfx950); or L R^T in FP32 with
+// v_mfma_f32_16x16x4_f32, four per 1 KB block.  In FP32 lane l holds K-columns
+// 4 (l / 16) .. + 3 of a block and the m-th instruction takes its m-th value,
+// so instruction m sums K-columns m, 4 + m, 8 + m, 12 + m: the four together
+// cover the block's 16 K-columns once, in an order both operands share.
 //
 // Tiling:
 //   - a workgroup of WM x WN waves computes a BM x BN output tile over one
 //     K range (split-K); each wave owns a (BM/WM) x (BN/WN) sub-tile of
 //     16 x 16 MFMA blocks, its accumulators in registers;
-//   - one stage = one K block (32 K-columns = 16 points).  Its operand
+//   - one stage = one K block (16 points in bf16/f16, 8 in FP32).  Its operand
 //     blocks (1 KB each, already in MFMA lane order in memory) are copied
 //     straight into LDS with global_load_lds_dwordx4 (no register staging)
 //     into a ring of STAGES slots, STAGES-1 stages ahead of the MFMAs.  The
@@ -48,7 +52,8 @@ struct Frag;
 template <>
 struct Frag<__bf16> {
     typedef bf16x8 type;
-    static __device__ __forceinline__ f32x4 mfma(type a, type b, f32x4 c)
+    static constexpr int kSub = 1;
+    static __device__ __forceinline__ f32x4 mfma(type a, type b, f32x4 c, int)
     {
         return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
     }
@@ -56,9 +61,19 @@ struct Frag<__bf16> {
 template <>
 struct Frag<_Float16> {
     typedef f16x8 type;
-    static __device__ __forceinline__ f32x4 mfma(type a, type b, f32x4 c)
+    static constexpr int kSub = 1;
+    static __device__ __forceinline__ f32x4 mfma(type a, type b, f32x4 c, int)
     {
         return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+    }
+};
+template <>
+struct Frag<float> {
+    typedef f32x4 type;
+    static constexpr int kSub = 4;    // instructions per block (m = 0 .. 3)
+    static __device__ __forceinline__ f32x4 mfma(type a, type b, f32x4 c, int m)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a[m], b[m], c, 0, 0, 0);
     }
 };
 
@@ -135,6 +150,7 @@ __device__ __forceinline__ void gemm_tile(const char *__restrict__ Lh, const cha
     constexpr int LPS = (SLOT_BLOCKS + NW - 1) / NW;
     static_assert(SLOT_BLOCKS % NW == 0 || P == 1, "stage copies deal evenly");
     static_assert((P - 1) * LPS < 64, "vmcnt range");
+    static_assert(PRODUCTS == 1 || Frag<T>::kSub == 1, "split products are 16-bit only");
     typedef typename Frag<T>::type frag_t;
 
     const int lane = threadIdx.x & 63;
@@ -199,10 +215,12 @@ __device__ __forceinline__ void gemm_tile(const char *__restrict__ Lh, const cha
             bh[c] = blk(HL * MB + wn * FN + c);
         // hi * hi
 #pragma unroll
-        for (int r = 0; r < FM; ++r)
+        for (int m = 0; m < Frag<T>::kSub; ++m)
 #pragma unroll
-            for (int c = 0; c < FN; ++c)
-                acc[r][c] = Frag<T>::mfma(ah[r], bh[c], acc[r][c]);
+            for (int r = 0; r < FM; ++r)
+#pragma unroll
+                for (int c = 0; c < FN; ++c)
+                    acc[r][c] = Frag<T>::mfma(ah[r], bh[c], acc[r][c], m);
         if (PRODUCTS == 3) {
             frag_t bl[FN];
 #pragma unroll
@@ -213,7 +231,7 @@ __device__ __forceinline__ void gemm_tile(const char *__restrict__ Lh, const cha
             for (int r = 0; r < FM; ++r)
 #pragma unroll
                 for (int c = 0; c < FN; ++c)
-                    acc[r][c] = Frag<T>::mfma(ah[r], bl[c], acc[r][c]);
+                    acc[r][c] = Frag<T>::mfma(ah[r], bl[c], acc[r][c], 0);
             frag_t al[FM];
 #pragma unroll
             for (int r = 0; r < FM; ++r)
@@ -223,7 +241,7 @@ __device__ __forceinline__ void gemm_tile(const char *__restrict__ Lh, const cha
             for (int r = 0; r < FM; ++r)
 #pragma unroll
                 for (int c = 0; c < FN; ++c)
-                    acc[r][c] = Frag<T>::mfma(al[r], bh[c], acc[r][c]);
+                    acc[r][c] = Frag<T>::mfma(al[r], bh[c], acc[r][c], 0);
         }
         slot = slot == P ? 0 : slot + 1;
     }
@@ -457,6 +475,11 @@ hipError_t launch_gemm_batch(const GemmPlan &plan, FactorType ft, const void *Lh
                              const void *Rh, const void *Rl, const BatchItem *items, int n_items,
                              int *counter, int M, int N, float *out, int grid, hipStream_t s)
 {
+    if (ft == FactorType::FP32)
+        return plan.products == 1 ? launch_products_batch<1, float>(plan, Lh, nullptr, Rh,
+                                                                    nullptr, items, n_items,
+                                                                    counter, M, N, out, grid, s)
+                                  : hipErrorInvalidValue;
     if (plan.products == 3) {
         if (ft == FactorType::BF16)
             return launch_products_batch<3, __bf16>(plan, Lh, Ll, Rh, Rl, items, n_items, counter,
@@ -485,6 +508,11 @@ hipError_t launch_gemm(const GemmPlan &plan, FactorType ft, const void *Lh, cons
                        const void *Rh, const void *Rl, int M, int N, float *out, int64_t ldo,
                        float *partials, bool accumulate, hipStream_t s)
 {
+    if (ft == FactorType::FP32)
+        return plan.products == 1 ? launch_products<1, float>(plan, Lh, nullptr, Rh, nullptr, M,
+                                                              N, out, ldo, partials, accumulate,
+                                                              s)
+                                  : hipErrorInvalidValue;
     if (plan.products == 3) {
         if (ft == FactorType::BF16)
             return launch_products<3, __bf16>(plan, Lh, Ll, Rh, Rl, M, N, out, ldo, partials,

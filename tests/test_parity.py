@@ -2,10 +2,11 @@
 
 Tolerances (normalised RMS error vs the FP64 oracle, over the evaluation set):
   direct FP32 .............. 1e-5
+  separable FP32 (MFMA) .... 1e-5
   BF16 / FP16 hi+lo split .. 1e-3
   FP16 single product ...... 1e-3
-The first two are the target accuracies of the two forms; the single-product
-FP16 form is held to the split forms' bound.
+The FP32 forms and the split forms are held to their target accuracies; the
+single-product FP16 form is held to the split forms' bound.
 Full-size workloads are compared on strided pixel subsets the oracle
 evaluates pixel by pixel; small ones on the full grid.
 """
@@ -20,9 +21,10 @@ import paper_1309_2734_amd as cgh
 
 pytestmark = pytest.mark.gpu
 
-TOL = {cgh.DIRECT_FP32: 1e-5, cgh.SPLIT_BF16: 1e-3, cgh.SPLIT_FP16: 1e-3, cgh.FP16: 1e-3}
+TOL = {cgh.DIRECT_FP32: 1e-5, cgh.SEPARABLE_FP32: 1e-5, cgh.SPLIT_BF16: 1e-3,
+       cgh.SPLIT_FP16: 1e-3, cgh.FP16: 1e-3}
 NAMES = {v: k for k, v in cgh.MODES.items()}
-GEMM_MODES = (cgh.SPLIT_BF16, cgh.SPLIT_FP16, cgh.FP16)
+GEMM_MODES = (cgh.SPLIT_BF16, cgh.SPLIT_FP16, cgh.FP16, cgh.SEPARABLE_FP32)
 ALL_MODES = (cgh.DIRECT_FP32,) + GEMM_MODES
 
 
@@ -108,8 +110,8 @@ def test_c2_full_size_strided(mode):
     check("C2", got, ref, mode)
 
 
-@pytest.mark.parametrize("mode", (cgh.DIRECT_FP32, cgh.SPLIT_BF16),
-                         ids=["direct_fp32", "split_bf16"])
+@pytest.mark.parametrize("mode", (cgh.DIRECT_FP32, cgh.SPLIT_BF16, cgh.SEPARABLE_FP32),
+                         ids=["direct_fp32", "split_bf16", "separable_fp32"])
 def test_c3_full_size_strided(mode):
     c = cghgen.make_config(3)
     cols, rows = _strided(c, 64)
@@ -285,8 +287,9 @@ def test_batch_graph_replays_match_eager(mode):
     octx.close()
 
 
-@pytest.mark.parametrize("mode", (cgh.SPLIT_FP16, cgh.SPLIT_BF16, cgh.DIRECT_FP32),
-                         ids=["split_fp16", "split_bf16", "direct_fp32"])
+@pytest.mark.parametrize("mode", (cgh.SPLIT_FP16, cgh.SPLIT_BF16, cgh.DIRECT_FP32,
+                                  cgh.SEPARABLE_FP32),
+                         ids=["split_fp16", "split_bf16", "direct_fp32", "separable_fp32"])
 def test_batch_full_size_frames(mode):
     """Frames of the batch workload (1920 x 1080, RGB wavelengths, log-uniform
     point counts), the first six, checked on strided pixels of every frame."""
