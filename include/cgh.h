@@ -136,6 +136,28 @@ CGH_API cgh_status cgh_points_upload(cgh_ctx *c, const float *x, const float *y,
  * yet), CGH_ENOMEM (workspace), CGH_EDEVICE (launch failure). */
 CGH_API cgh_status cgh_compute(cgh_ctx *c, cgh_mode mode, float *out_dev, void *stream);
 
+/* Complex object wave O of Eq. (2) (Section 2.1, Fresnel form, without the
+ * per-point constant phase, as for cgh_compute) of the whole cloud:
+ *   Re O = sum_j A_j cos(pi r_j^2 / (lambda z_j)),
+ *   Im O = sum_j A_j sin(pi r_j^2 / (lambda z_j)),
+ * into `out_dev`, a caller-owned device buffer of 2*height*width floats:
+ * plane 0 (the first height*width floats) = Re O, which equals cgh_compute's
+ * output up to rounding, plane 1 = Im O; each plane row-major, x fastest.
+ * Modes: all of cgh_mode; the direct mode evaluates a sine beside each
+ * cosine, the matrix-core modes multiply a stacked [real; imaginary] row
+ * factor (2*height rows) by the same column factor.
+ * Errors as cgh_compute. */
+CGH_API cgh_status cgh_compute_complex(cgh_ctx *c, cgh_mode mode, float *out_dev, void *stream);
+
+/* Phase-only hologram (kinoform) of Eq. (3): for every pixel the argument
+ * theta = atan2(Im O, Re O) of the object wave above, moved to [0, 2 pi) by
+ * adding 2 pi when negative, quantised to floor(theta * 255 / (2 pi)) in
+ * FP32 (codes 0 .. 254; 255 only when rounding carries theta up to 2 pi).
+ * `out_dev`: caller-owned device buffer of height*width bytes, row-major.
+ * The complex field is kept in a library-owned workspace (8 bytes per
+ * pixel).  Errors as cgh_compute. */
+CGH_API cgh_status cgh_kinoform(cgh_ctx *c, cgh_mode mode, uint8_t *out_dev, void *stream);
+
 /* Compute n_frames holograms in one go: frame f covers the points and the
  * wavelength of frames[f] (a host array) and lands in
  * out_dev[f*height*width ...] (device, caller-owned).  The frames may

@@ -42,8 +42,8 @@ MEM_HOST = 0
 MEM_DEVICE = 1
 
 # every symbol include/cgh.h declares
-EXPORTS = ("cgh_create", "cgh_points_upload", "cgh_compute", "cgh_batch_compute",
-           "cgh_tune", "cgh_destroy", "cgh_strerror", "cgh_last_error", "cgh_profile_enable",
+EXPORTS = ("cgh_create", "cgh_points_upload", "cgh_compute", "cgh_compute_complex",
+           "cgh_kinoform", "cgh_batch_compute", "cgh_tune", "cgh_destroy", "cgh_strerror", "cgh_last_error", "cgh_profile_enable",
            "cgh_profile_reset", "cgh_profile_read", "cgh_version")
 
 
@@ -80,6 +80,10 @@ def lib() -> ctypes.CDLL:
     L.cgh_points_upload.restype = st
     L.cgh_compute.argtypes = [vp, ctypes.c_int, vp, vp]
     L.cgh_compute.restype = st
+    L.cgh_compute_complex.argtypes = [vp, ctypes.c_int, vp, vp]
+    L.cgh_compute_complex.restype = st
+    L.cgh_kinoform.argtypes = [vp, ctypes.c_int, vp, vp]
+    L.cgh_kinoform.restype = st
     L.cgh_batch_compute.argtypes = [vp, ctypes.POINTER(Frame), i32, ctypes.c_int, vp, vp]
     L.cgh_batch_compute.restype = st
     L.cgh_tune.argtypes = [vp, ctypes.c_int, i32, ctypes.c_char_p, i32, vp]
@@ -185,20 +189,33 @@ class Context:
         self.upload(cloud.x, cloud.y, cloud.z, cloud.amp, stream)
 
     # -- evaluation
-    def _out_ptr(self, out, planes: int) -> int:
+    def _out_ptr(self, out, planes: int, dtype: str = "float32") -> int:
         if not (_is_torch(out) and out.is_cuda):
-            raise TypeError("out must be a CUDA float32 torch tensor")
+            raise TypeError(f"out must be a CUDA {dtype} torch tensor")
         import torch
-        if out.dtype != torch.float32 or not out.is_contiguous():
-            raise TypeError("out must be contiguous float32")
+        if out.dtype != getattr(torch, dtype) or not out.is_contiguous():
+            raise TypeError(f"out must be contiguous {dtype}")
         if out.numel() != planes * self.width * self.height:
-            raise ValueError(f"out must hold {planes} x {self.height} x {self.width} floats")
+            raise ValueError(f"out must hold {planes} x {self.height} x {self.width} values")
         return out.data_ptr()
 
     def compute(self, out, mode: int = DIRECT_FP32, stream=None):
         """Hologram of the uploaded cloud into `out` ([H, W] float32, device)."""
         _check(lib().cgh_compute(self._h, int(mode), self._out_ptr(out, 1),
                                  _stream_handle(stream, [out])), "cgh_compute")
+        return out
+
+    def compute_complex(self, out, mode: int = DIRECT_FP32, stream=None):
+        """Complex object wave into `out` ([2, H, W] float32, device): plane 0
+        the real part (the hologram of compute()), plane 1 the imaginary part."""
+        _check(lib().cgh_compute_complex(self._h, int(mode), self._out_ptr(out, 2),
+                                         _stream_handle(stream, [out])), "cgh_compute_complex")
+        return out
+
+    def kinoform(self, out, mode: int = DIRECT_FP32, stream=None):
+        """Phase-only hologram into `out` ([H, W] uint8, device)."""
+        _check(lib().cgh_kinoform(self._h, int(mode), self._out_ptr(out, 1, "uint8"),
+                                  _stream_handle(stream, [out])), "cgh_kinoform")
         return out
 
     def batch_compute(self, frames: Sequence[Tuple[int, int, float]], out,

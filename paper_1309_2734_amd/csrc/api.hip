@@ -166,6 +166,7 @@ struct cgh_ctx {
     DevBuf partials;                  // split-K partial tiles
     DevBuf segs, frames;              // small device tables
     DevBuf tune_out;                  // scratch hologram for cgh_tune
+    DevBuf field;                     // complex object wave for cgh_kinoform
     DevBuf items, counter;            // batched GEMM work list and its queue counter
     uint64_t ws_generation = 0;       // bumps when a buffer moves
 
@@ -359,9 +360,11 @@ int kblock_bucket(int64_t kblocks)
     return b;
 }
 
-std::string tune_key(const cgh_ctx *c, int mode, int64_t kblocks)
+// `m_lines` = output rows of the product: the height, or twice it for a
+// complex evaluation (real and imaginary planes stacked).
+std::string tune_key(const cgh_ctx *c, int mode, int64_t kblocks, int m_lines)
 {
-    return c->arch + "/" + std::to_string(c->width) + "x" + std::to_string(c->height) + "/mode" +
+    return c->arch + "/" + std::to_string(c->width) + "x" + std::to_string(m_lines) + "/mode" +
            std::to_string(mode) + "/kb" + std::to_string(kblock_bucket(kblocks));
 }
 
@@ -438,7 +441,7 @@ Plan plan_gemm(int M, int N, int64_t slots, const ModeInfo &mi, const TuneEntry 
 // Direct kernel over frames whose constants occupy slots [0, total_slots)
 // (tables built here).  `fd_dev` points at the device copy of the frames.
 cgh_status run_direct(cgh_ctx *c, const FrameDesc *fd_dev, int n_frames, int64_t total_slots,
-                      float *out, bool accumulate, hipStream_t s)
+                      float *out, float *out_im, bool accumulate, hipStream_t s)
 {
     const size_t tu = (size_t)std::max<int64_t>(total_slots, 1) * c->wpad * sizeof(float);
     const size_t tv = (size_t)std::max<int64_t>(total_slots, 1) * c->hpad * sizeof(float);
@@ -451,25 +454,28 @@ cgh_status run_direct(cgh_ctx *c, const FrameDesc *fd_dev, int n_frames, int64_t
                 "phase_tables launch");
         br.done();
     }
-    const TuneEntry *t = find_tuned(c, tune_key(c, CGH_DIRECT_FP32, 0));
+    const TuneEntry *t = find_tuned(c, tune_key(c, CGH_DIRECT_FP32, 0, c->height));
     const int rows = t && (t->rows == 4 || t->rows == 8 || t->rows == 16) ? t->rows : 16;
-    Bracket br(c, "direct_fp32", s);
+    Bracket br(c, out_im ? "direct_fp32_complex" : "direct_fp32", s);
     CGH_HIP(launch_direct((const float *)c->tab_u.p, (const float *)c->tab_v.p,
                           consts_view(c, c->consts_cap).amp, fd_dev, n_frames, c->width,
-                          c->height, c->wpad, c->hpad, rows, out, accumulate, s),
+                          c->height, c->wpad, c->hpad, rows, out, out_im, accumulate, s),
             "direct launch");
     br.done();
     return CGH_OK;
 }
 
 // Matrix-core modes for one frame whose constants are slots [slot0, slot0 + slots).
-cgh_status run_gemm(cgh_ctx *c, int mode, int64_t slot0, int64_t slots, float *out,
+// With `cplx`, L holds the real- and imaginary-part rows stacked (M = 2H) and
+// `out` receives [Re; Im] as two consecutive H x W planes.
+cgh_status run_gemm(cgh_ctx *c, int mode, int64_t slot0, int64_t slots, float *out, bool cplx,
                     bool accumulate, hipStream_t s)
 {
     const ModeInfo mi = mode_info(mode);
     const FactorType ft = mi.ft;
-    const Plan p = plan_gemm(c->height, c->width, slots, mi,
-                             find_tuned(c, tune_key(c, mode, slots / mi.kbp)));
+    const int M = cplx ? 2 * c->height : c->height;
+    const Plan p = plan_gemm(M, c->width, slots, mi,
+                             find_tuned(c, tune_key(c, mode, slots / mi.kbp, M)));
     const int hl = mi.hl;
     // 2 K-columns (cos, sin) per line and point
     const size_t lbytes = (size_t)p.g.mblocks * kFragLines * (size_t)slots * 2 * mi.elem;
@@ -482,13 +488,13 @@ cgh_status run_gemm(cgh_ctx *c, int mode, int64_t slot0, int64_t slots, float *o
     }
     if (p.g.splits > 1)
         CGH_HIP(ensure_ws(c, c->partials,
-                          (size_t)p.g.splits * c->height * (size_t)c->width * sizeof(float)),
+                          (size_t)p.g.splits * M * (size_t)c->width * sizeof(float)),
                 "split-K workspace allocation");
     PointConsts pc = consts_view(c, c->consts_cap);
     {
         Bracket br(c, mi.fac_name, s);
-        CGH_HIP(launch_factors(pc, slot0, slots, c->width, c->height, p.g.kblocks, p.g.mblocks,
-                               p.g.nblocks, ft, c->fac[0].p, hl == 2 ? c->fac[1].p : nullptr,
+        CGH_HIP(launch_factors(pc, slot0, slots, c->width, c->height, cplx, p.g.kblocks,
+                               p.g.mblocks, p.g.nblocks, ft, c->fac[0].p, hl == 2 ? c->fac[1].p : nullptr,
                                c->fac[2].p, hl == 2 ? c->fac[3].p : nullptr, s),
                 "factor launch");
         br.done();
@@ -496,15 +502,15 @@ cgh_status run_gemm(cgh_ctx *c, int mode, int64_t slot0, int64_t slots, float *o
     {
         Bracket br(c, mi.gemm_name, s);
         CGH_HIP(launch_gemm(p.g, ft, c->fac[0].p, hl == 2 ? c->fac[1].p : nullptr, c->fac[2].p,
-                            hl == 2 ? c->fac[3].p : nullptr, c->height, c->width, out, c->width,
+                            hl == 2 ? c->fac[3].p : nullptr, M, c->width, out, c->width,
                             (float *)c->partials.p, accumulate, s),
                 "gemm launch");
         br.done();
     }
     if (p.g.splits > 1) {
         Bracket br(c, "splitk_reduce", s);
-        CGH_HIP(launch_splitk_reduce((const float *)c->partials.p, p.g.splits, c->height,
-                                     c->width, out, c->width, accumulate, s),
+        CGH_HIP(launch_splitk_reduce((const float *)c->partials.p, p.g.splits, M, c->width, out,
+                                     c->width, accumulate, s),
                 "split-K reduce launch");
         br.done();
     }
@@ -512,18 +518,19 @@ cgh_status run_gemm(cgh_ctx *c, int mode, int64_t slot0, int64_t slots, float *o
 }
 
 // Bytes of workspace per constant slot for a mode (tables or factors).
-size_t bytes_per_slot(cgh_ctx *c, int mode)
+size_t bytes_per_slot(cgh_ctx *c, int mode, bool cplx)
 {
     if (mode == CGH_DIRECT_FP32)
         return (size_t)(c->wpad + c->hpad) * sizeof(float);
+    const int64_t m = cplx ? 2 * (int64_t)c->height : c->height;
     const int64_t w = std::max(round_up(c->width, 384), round_up(c->width, 256));
-    const int64_t h = std::max(round_up(c->height, 384), round_up(c->height, 256));
+    const int64_t h = std::max(round_up(m, 384), round_up(m, 256));
     return (size_t)(w + h) * mode_info(mode).line_bytes();
 }
 
-int64_t chunk_slots(cgh_ctx *c, int mode)
+int64_t chunk_slots(cgh_ctx *c, int mode, bool cplx = false)
 {
-    int64_t chunk = (int64_t)(workspace_budget() / bytes_per_slot(c, mode));
+    int64_t chunk = (int64_t)(workspace_budget() / bytes_per_slot(c, mode, cplx));
     return std::max<int64_t>(kSlotAlign, chunk / kSlotAlign * kSlotAlign);
 }
 
@@ -546,9 +553,10 @@ cgh_status point_consts(cgh_ctx *c, int seg_index, int n_segs, int64_t max_count
 // cut into point chunks that fit the workspace budget.  Chunk i's segment
 // and frame descriptors are entry i of the two small tables.
 cgh_status eval_one(cgh_ctx *c, int mode, int64_t p0, int64_t count, double lam, float *out,
-                    hipStream_t s)
+                    bool cplx, hipStream_t s)
 {
-    const int64_t chunk = chunk_slots(c, mode);
+    const int64_t chunk = chunk_slots(c, mode, cplx);
+    float *out_im = cplx ? out + (int64_t)c->width * c->height : nullptr;
     std::vector<Segment> segs;
     std::vector<FrameDesc> fds;
     for (int64_t off = 0; off < count || segs.empty(); off += chunk) {
@@ -568,9 +576,9 @@ cgh_status eval_one(cgh_ctx *c, int mode, int64_t p0, int64_t count, double lam,
         const bool acc = i > 0;
         if (mode == CGH_DIRECT_FP32 || segs[i].count == 0)
             st = run_direct(c, (const FrameDesc *)c->frames.p + i, 1,
-                            round_up(segs[i].count, kSlotAlign), out, acc, s);
+                            round_up(segs[i].count, kSlotAlign), out, out_im, acc, s);
         else
-            st = run_gemm(c, mode, 0, slots, out, acc, s);
+            st = run_gemm(c, mode, 0, slots, out, cplx, acc, s);
         if (st != CGH_OK)
             return st;
     }
@@ -609,7 +617,7 @@ cgh_status eval_batch_direct(cgh_ctx *c, const cgh_frame *frames, int n_frames, 
     cgh_status st = point_consts(c, 0, n_frames, max_count, slots, s);
     if (st != CGH_OK)
         return st;
-    return run_direct(c, (const FrameDesc *)c->frames.p, n_frames, slot, out, false, s);
+    return run_direct(c, (const FrameDesc *)c->frames.p, n_frames, slot, out, nullptr, false, s);
 }
 
 
@@ -630,7 +638,7 @@ cgh_status eval_batch_gemm(cgh_ctx *c, int mode, const cgh_frame *frames, int n_
         max_count = std::max(max_count, frames[f].point_count);
     const int64_t max_slots = std::max<int64_t>(round_up(max_count, kSlotAlign), kSlotAlign);
     Plan p = plan_gemm(c->height, c->width, max_slots, mi,
-                       find_tuned(c, tune_key(c, mode, max_slots / mi.kbp)));
+                       find_tuned(c, tune_key(c, mode, max_slots / mi.kbp, c->height)));
     const size_t per_slot = (size_t)(p.g.mblocks + p.g.nblocks) * kFragLines * mi.line_bytes();
     const int64_t budget = std::max<int64_t>((int64_t)(workspace_budget() / per_slot), kSlotAlign);
 
@@ -696,7 +704,7 @@ cgh_status eval_batch_gemm(cgh_ctx *c, int mode, const cgh_frame *frames, int n_
         {
             Bracket br(c, mi.fac_name, s);
             CGH_HIP(launch_factors(consts_view(c, c->consts_cap), 0, total, c->width, c->height,
-                                   g.kblocks, g.mblocks, g.nblocks, ft, c->fac[0].p,
+                                   false, g.kblocks, g.mblocks, g.nblocks, ft, c->fac[0].p,
                                    hl == 2 ? c->fac[1].p : nullptr, c->fac[2].p,
                                    hl == 2 ? c->fac[3].p : nullptr, s),
                     "factor launch");
@@ -729,7 +737,7 @@ cgh_status batch_sequence(cgh_ctx *c, const cgh_frame *frames, int n_frames, int
             return eval_batch_direct(c, frames, n_frames, out, s);
         for (int f = 0; f < n_frames; ++f) {
             cgh_status st = eval_one(c, mode, frames[f].point_offset, frames[f].point_count,
-                                     frames[f].wavelength, out + f * plane, s);
+                                     frames[f].wavelength, out + f * plane, false, s);
             if (st != CGH_OK)
                 return st;
         }
@@ -933,6 +941,7 @@ void cgh_destroy(cgh_ctx *c)
     c->segs.release();
     c->frames.release();
     c->tune_out.release();
+    c->field.release();
     c->items.release();
     c->counter.release();
     delete c;
@@ -1010,7 +1019,51 @@ cgh_status cgh_compute(cgh_ctx *c, cgh_mode mode, float *out_dev, void *stream)
         return fail(CGH_ESTATE, "no points uploaded");
     DeviceGuard g;
     CGH_HIP(g.set(c->device), "hipSetDevice");
-    return eval_one(c, mode, 0, c->n, c->wavelength, out_dev, (hipStream_t)stream);
+    return eval_one(c, mode, 0, c->n, c->wavelength, out_dev, false, (hipStream_t)stream);
+}
+
+cgh_status cgh_compute_complex(cgh_ctx *c, cgh_mode mode, float *out_dev, void *stream)
+{
+    g_last_error.clear();
+    if (!c)
+        return fail(CGH_EINVAL, "context is NULL");
+    if (!out_dev)
+        return fail(CGH_EINVAL, "output is NULL");
+    cgh_status st = check_mode(mode);
+    if (st != CGH_OK)
+        return st;
+    if (!c->uploaded)
+        return fail(CGH_ESTATE, "no points uploaded");
+    DeviceGuard g;
+    CGH_HIP(g.set(c->device), "hipSetDevice");
+    return eval_one(c, mode, 0, c->n, c->wavelength, out_dev, true, (hipStream_t)stream);
+}
+
+cgh_status cgh_kinoform(cgh_ctx *c, cgh_mode mode, uint8_t *out_dev, void *stream)
+{
+    g_last_error.clear();
+    if (!c)
+        return fail(CGH_EINVAL, "context is NULL");
+    if (!out_dev)
+        return fail(CGH_EINVAL, "output is NULL");
+    cgh_status st = check_mode(mode);
+    if (st != CGH_OK)
+        return st;
+    if (!c->uploaded)
+        return fail(CGH_ESTATE, "no points uploaded");
+    DeviceGuard g;
+    CGH_HIP(g.set(c->device), "hipSetDevice");
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t plane = (int64_t)c->width * c->height;
+    CGH_HIP(ensure_ws(c, c->field, (size_t)plane * 2 * sizeof(float)), "field allocation");
+    float *field = (float *)c->field.p;
+    st = eval_one(c, mode, 0, c->n, c->wavelength, field, true, s);
+    if (st != CGH_OK)
+        return st;
+    Bracket br(c, "kinoform", s);
+    CGH_HIP(launch_kinoform(field, field + plane, plane, out_dev, s), "kinoform launch");
+    br.done();
+    return CGH_OK;
 }
 
 cgh_status cgh_batch_compute(cgh_ctx *c, const cgh_frame *frames, int32_t n_frames,
@@ -1116,7 +1169,7 @@ cgh_status cgh_tune(cgh_ctx *c, cgh_mode mode, int32_t repeats, char *report, in
     TuneEntry best;
     int tried = 0;
     if (mode == CGH_DIRECT_FP32) {
-        best.key = tune_key(c, mode, 0);
+        best.key = tune_key(c, mode, 0, c->height);
         const int64_t tu = slots * c->wpad * (int64_t)sizeof(float);
         const int64_t tv = slots * c->hpad * (int64_t)sizeof(float);
         CGH_HIP(ensure_ws(c, c->tab_u, (size_t)tu), "table allocation");
@@ -1131,7 +1184,7 @@ cgh_status cgh_tune(cgh_ctx *c, cgh_mode mode, int32_t repeats, char *report, in
                     return launch_direct((const float *)c->tab_u.p, (const float *)c->tab_v.p,
                                          consts_view(c, c->consts_cap).amp,
                                          (const FrameDesc *)c->frames.p, 1, c->width, c->height,
-                                         c->wpad, c->hpad, rows, out, false, s);
+                                         c->wpad, c->hpad, rows, out, nullptr, false, s);
                 },
                 repeats, s, &us);
             if (st != CGH_OK)
@@ -1147,7 +1200,7 @@ cgh_status cgh_tune(cgh_ctx *c, cgh_mode mode, int32_t repeats, char *report, in
         const FactorType ft = mi.ft;
         const int hl = mi.hl;
         const int64_t kblocks = slots / mi.kbp;
-        best.key = tune_key(c, mode, kblocks);
+        best.key = tune_key(c, mode, kblocks, c->height);
         static const int shapes[][5] = {{192, 384, 2, 4, 2}, {384, 192, 4, 2, 2},
                                         {192, 256, 2, 4, 2}, {256, 256, 2, 4, 2},
                                         {192, 192, 2, 2, 3}, {192, 192, 2, 4, 3},
@@ -1167,7 +1220,7 @@ cgh_status cgh_tune(cgh_ctx *c, cgh_mode mode, int32_t repeats, char *report, in
             CGH_HIP(ensure_ws(c, c->fac[3], rbytes), "factor allocation");
         }
         CGH_HIP(launch_factors(consts_view(c, c->consts_cap), 0, slots, c->width, c->height,
-                               kblocks, mb, nb, ft, c->fac[0].p, hl == 2 ? c->fac[1].p : nullptr,
+                               false, kblocks, mb, nb, ft, c->fac[0].p, hl == 2 ? c->fac[1].p : nullptr,
                                c->fac[2].p, hl == 2 ? c->fac[3].p : nullptr, s),
                 "factor launch");
         for (auto &sh : shapes) {

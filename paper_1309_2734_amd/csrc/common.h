@@ -74,20 +74,23 @@ hipError_t launch_phase_tables(PointConsts pc, int64_t n_slots, int wpad, int hp
                                float *U, float *V, hipStream_t s);
 
 // a3: direct FP32 accumulation for frames[0 .. n_frames) (tables from a2,
-// padded to wpad columns and hpad rows, multiples of kLinePad).
+// padded to wpad columns and hpad rows, multiples of kLinePad).  With out_im
+// != nullptr the imaginary part of the object wave goes there as well.
 hipError_t launch_direct(const float *U, const float *V, const float *amp,
                          const FrameDesc *frames_dev, int n_frames, int width, int height,
-                         int wpad, int hpad, int rows_per_wave, float *out, bool accumulate,
-                         hipStream_t s);
+                         int wpad, int hpad, int rows_per_wave, float *out, float *out_im,
+                         bool accumulate, hipStream_t s);
 
 // a4: factor build.  Writes the hi (and, if lo_* != nullptr, lo) factors of
 // L (rows) and R (columns) in the MFMA fragment order described in factors.hip:
 // mblocks / nblocks blocks of kFragLines lines, kblocks blocks of
-// kblock_points(ft) points.  FP32 factors have no lo half.
+// kblock_points(ft) points.  FP32 factors have no lo half.  With `cplx`, L
+// has 2 * height lines: the real-part factors of rows 0 .. height-1, then the
+// imaginary-part factors of the same rows, so that L R^T is [Re O; Im O].
 enum class FactorType { BF16 = 0, FP16 = 1, FP32 = 2 };
 constexpr int kblock_points(FactorType ft) { return ft == FactorType::FP32 ? 8 : 16; }
 hipError_t launch_factors(PointConsts pc, int64_t slot0, int64_t n_slots, int width, int height,
-                          int64_t kblocks, int mblocks, int nblocks, FactorType ft,
+                          bool cplx, int64_t kblocks, int mblocks, int nblocks, FactorType ft,
                           void *Lh, void *Ll, void *Rh, void *Rl, hipStream_t s);
 
 // a5: split GEMM on MFMA.  See gemm.hip for the tiling.
@@ -121,6 +124,9 @@ struct BatchItem {
 hipError_t launch_gemm_batch(const GemmPlan &plan, FactorType ft, const void *Lh, const void *Ll,
                              const void *Rh, const void *Rl, const BatchItem *items, int n_items,
                              int *counter, int M, int N, float *out, int grid, hipStream_t s);
+// a8: phase-only hologram (Eq. (3)) from the real and imaginary planes.
+hipError_t launch_kinoform(const float *re, const float *im, int64_t n, uint8_t *out,
+                           hipStream_t s);
 hipError_t launch_splitk_reduce(const float *partials, int splits, int M, int N, float *out,
                                 int64_t ldo, bool accumulate, hipStream_t s);
 

@@ -19,7 +19,10 @@
 //     the hardware cosine's domain and keeps its absolute error ~1e-7.
 // No LDS, no barrier: the four waves of a workgroup take the same 64 columns
 // and consecutive row bands, so their column-table loads hit in L1.
-// Accumulation: a fresh FP32 partial per 64 points, added to the running sum.
+// Accumulation: a fresh FP32 partial per 32 points, added to the running sum.
+// The complex variant (CPLX) also accumulates the imaginary part of the
+// object wave of Eq. (2), A_k sin(2 pi t) with v_sin_f32, for the phase-only
+// hologram of Eq. (3).
 #include "common.h"
 
 namespace cgh {
@@ -62,8 +65,8 @@ __device__ __forceinline__ void load_group(GroupRegs<R> &G, const float *__restr
         G.a[k] = Ag[k];
 }
 
-template <int K, int R>
-__device__ __forceinline__ void point_step(const GroupRegs<R> &G, float *part)
+template <int K, int R, bool CPLX>
+__device__ __forceinline__ void point_step(const GroupRegs<R> &G, float *part, float *part_im)
 {
     const float uk = reinterpret_cast<const float *>(G.u)[K];
     const float ak = G.a[K];
@@ -71,32 +74,36 @@ __device__ __forceinline__ void point_step(const GroupRegs<R> &G, float *part)
     for (int r = 0; r < R; ++r) {
         const float t = row_bcast<K>(G.v[r]) + uk;
         part[r] = __builtin_fmaf(ak, __builtin_amdgcn_cosf(t), part[r]);
+        if (CPLX)
+            part_im[r] = __builtin_fmaf(ak, __builtin_amdgcn_sinf(t), part_im[r]);
     }
 }
 
-template <int R>
-__device__ __forceinline__ void group_step(const GroupRegs<R> &G, float *part)
+template <int R, bool CPLX>
+__device__ __forceinline__ void group_step(const GroupRegs<R> &G, float *p, float *q)
 {
-    point_step<0, R>(G, part);   point_step<1, R>(G, part);
-    point_step<2, R>(G, part);   point_step<3, R>(G, part);
-    point_step<4, R>(G, part);   point_step<5, R>(G, part);
-    point_step<6, R>(G, part);   point_step<7, R>(G, part);
-    point_step<8, R>(G, part);   point_step<9, R>(G, part);
-    point_step<10, R>(G, part);  point_step<11, R>(G, part);
-    point_step<12, R>(G, part);  point_step<13, R>(G, part);
-    point_step<14, R>(G, part);  point_step<15, R>(G, part);
+    point_step<0, R, CPLX>(G, p, q);   point_step<1, R, CPLX>(G, p, q);
+    point_step<2, R, CPLX>(G, p, q);   point_step<3, R, CPLX>(G, p, q);
+    point_step<4, R, CPLX>(G, p, q);   point_step<5, R, CPLX>(G, p, q);
+    point_step<6, R, CPLX>(G, p, q);   point_step<7, R, CPLX>(G, p, q);
+    point_step<8, R, CPLX>(G, p, q);   point_step<9, R, CPLX>(G, p, q);
+    point_step<10, R, CPLX>(G, p, q);  point_step<11, R, CPLX>(G, p, q);
+    point_step<12, R, CPLX>(G, p, q);  point_step<13, R, CPLX>(G, p, q);
+    point_step<14, R, CPLX>(G, p, q);  point_step<15, R, CPLX>(G, p, q);
 }
 
 // Grid: x = column blocks of 64, y = row bands of kWaves * R rows, z = frame.
 // Tables: U [groups][wpad][16], V [groups][hpad][16]; wpad, hpad multiples of
-// 64; every frame's group count is even.
-template <int R>
+// 64; every frame's group count is even.  CPLX: the imaginary part goes to
+// out_im (same layout and offsets as out).
+template <int R, bool CPLX>
 __global__ __launch_bounds__(256) void k_direct(const float *__restrict__ U,
                                                 const float *__restrict__ V,
                                                 const float *__restrict__ amp,
                                                 const FrameDesc *__restrict__ frames, int width,
                                                 int height, int wpad, int hpad,
-                                                float *__restrict__ out, int accumulate)
+                                                float *__restrict__ out,
+                                                float *__restrict__ out_im, int accumulate)
 {
     const FrameDesc fd = frames[blockIdx.z];
     const int lane = threadIdx.x & 63;
@@ -111,12 +118,16 @@ __global__ __launch_bounds__(256) void k_direct(const float *__restrict__ U,
     const float *Vg = V + fd.first * hpad + (int64_t)row0 * kGroup + (lane & (kGroup - 1));
     const float *Ag = amp + fd.first;
 
-    float acc[R];
-    float part[R];
+    float acc[R], part[R];
+    float acc_im[CPLX ? R : 1], part_im[CPLX ? R : 1];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         acc[r] = 0.0f;
         part[r] = 0.0f;
+        if (CPLX) {
+            acc_im[r] = 0.0f;
+            part_im[r] = 0.0f;
+        }
     }
     // Two register sets in ping-pong: the loads of the next group are in
     // flight while the current one is evaluated.  The last prefetch re-reads
@@ -130,16 +141,20 @@ __global__ __launch_bounds__(256) void k_direct(const float *__restrict__ U,
     for (int64_t g = 0; g < G; g += 2) {
         const int64_t g1 = g + 1 < G ? g + 1 : G - 1;
         load_group<R>(gb, Ug + g1 * ustep, Vg + g1 * vstep, Ag + g1 * kGroup);
-        group_step<R>(ga, part);
+        group_step<R, CPLX>(ga, part, part_im);
         const int64_t gn = g + 2 < G ? g + 2 : G - 1;
         load_group<R>(ga, Ug + gn * ustep, Vg + gn * vstep, Ag + gn * kGroup);
-        group_step<R>(gb, part);
-        // a fresh partial every 64 points keeps the FP32 running sum's
+        group_step<R, CPLX>(gb, part, part_im);
+        // a fresh partial every 32 points keeps the FP32 running sum's
         // rounding error small
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             acc[r] += part[r];
             part[r] = 0.0f;
+            if (CPLX) {
+                acc_im[r] += part_im[r];
+                part_im[r] = 0.0f;
+            }
         }
     }
     if (col < width) {
@@ -150,40 +165,52 @@ __global__ __launch_bounds__(256) void k_direct(const float *__restrict__ U,
                 float *p = o + (int64_t)(row0 + r) * width + col;
                 *p = accumulate ? *p + acc[r] : acc[r];
             }
+        if (CPLX) {
+            float *oi = out_im + fd.out_off;
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                if (row0 + r < height) {
+                    float *p = oi + (int64_t)(row0 + r) * width + col;
+                    *p = accumulate ? *p + acc_im[r] : acc_im[r];
+                }
+        }
     }
+}
+
+template <int R>
+void launch_rows(const float *U, const float *V, const float *amp, const FrameDesc *frames_dev,
+                 int n_frames, int width, int height, int wpad, int hpad, float *out,
+                 float *out_im, int acc, hipStream_t s)
+{
+    const dim3 grid((unsigned)((width + 63) / 64),
+                    (unsigned)((height + kWaves * R - 1) / (kWaves * R)), (unsigned)n_frames);
+    if (out_im != nullptr)
+        hipLaunchKernelGGL((k_direct<R, true>), grid, dim3(256), 0, s, U, V, amp, frames_dev,
+                           width, height, wpad, hpad, out, out_im, acc);
+    else
+        hipLaunchKernelGGL((k_direct<R, false>), grid, dim3(256), 0, s, U, V, amp, frames_dev,
+                           width, height, wpad, hpad, out, (float *)nullptr, acc);
 }
 
 }  // namespace
 
 hipError_t launch_direct(const float *U, const float *V, const float *amp,
                          const FrameDesc *frames_dev, int n_frames, int width, int height,
-                         int wpad, int hpad, int rows_per_wave, float *out, bool accumulate,
-                         hipStream_t s)
+                         int wpad, int hpad, int rows_per_wave, float *out, float *out_im,
+                         bool accumulate, hipStream_t s)
 {
     const int acc = accumulate ? 1 : 0;
     if (n_frames <= 0)
         return hipSuccess;
-    const unsigned bx = (unsigned)((width + 63) / 64);
-    switch (rows_per_wave) {
-    case 8: {
-        const unsigned by = (unsigned)((height + kWaves * 8 - 1) / (kWaves * 8));
-        hipLaunchKernelGGL(k_direct<8>, dim3(bx, by, (unsigned)n_frames), dim3(256), 0, s, U, V,
-                           amp, frames_dev, width, height, wpad, hpad, out, acc);
-        break;
-    }
-    case 16: {
-        const unsigned by = (unsigned)((height + kWaves * 16 - 1) / (kWaves * 16));
-        hipLaunchKernelGGL(k_direct<16>, dim3(bx, by, (unsigned)n_frames), dim3(256), 0, s, U,
-                           V, amp, frames_dev, width, height, wpad, hpad, out, acc);
-        break;
-    }
-    default: {
-        const unsigned by = (unsigned)((height + kWaves * 4 - 1) / (kWaves * 4));
-        hipLaunchKernelGGL(k_direct<4>, dim3(bx, by, (unsigned)n_frames), dim3(256), 0, s, U, V,
-                           amp, frames_dev, width, height, wpad, hpad, out, acc);
-        break;
-    }
-    }
+    if (rows_per_wave == 8)
+        launch_rows<8>(U, V, amp, frames_dev, n_frames, width, height, wpad, hpad, out, out_im,
+                       acc, s);
+    else if (rows_per_wave == 16)
+        launch_rows<16>(U, V, amp, frames_dev, n_frames, width, height, wpad, hpad, out, out_im,
+                        acc, s);
+    else
+        launch_rows<4>(U, V, amp, frames_dev, n_frames, width, height, wpad, hpad, out, out_im,
+                       acc, s);
     return hipGetLastError();
 }
 

@@ -6,6 +6,11 @@
 // K = 2N interleaved columns:
 //     L[iy, 2j] =  A_j cos(2 pi V[iy, j]),   L[iy, 2j+1] = -A_j sin(2 pi V[iy, j]),
 //     R[ix, 2j] =      cos(2 pi U[ix, j]),   R[ix, 2j+1] =      sin(2 pi U[ix, j]).
+// The imaginary part of the object wave of Eq. (2),
+//     A_j sin(2 pi (U + V)) = A_j sin(2 pi V) cos(2 pi U) + A_j cos(2 pi V) sin(2 pi U),
+// uses the same R with the rows
+//     L'[iy, 2j] = A_j sin(2 pi V[iy, j]),   L'[iy, 2j+1] =  A_j cos(2 pi V[iy, j]);
+// for a complex evaluation L' is stacked under L (lines H .. 2H-1).
 // In the 16-bit types each value v is stored as hi = round(v) and
 // lo = round(v - hi) (round to nearest even; v - hi is exact in FP32), or as
 // hi alone; FP32 factors are stored as computed.
@@ -43,7 +48,7 @@ struct alignas(16) Vec16B {
 // Grid: x = K block * 64 + lane, y = line block (L blocks first, then R).
 template <typename T, bool SPLIT>
 __global__ __launch_bounds__(256) void k_factors(PointConsts pc, int64_t slot0, int64_t kblocks,
-                                                 int height, int width, int mblocks,
+                                                 int height, int width, int cplx, int mblocks,
                                                  Vec16B<T> *__restrict__ Lh,
                                                  Vec16B<T> *__restrict__ Ll,
                                                  Vec16B<T> *__restrict__ Rh,
@@ -59,7 +64,9 @@ __global__ __launch_bounds__(256) void k_factors(PointConsts pc, int64_t slot0, 
     const bool is_l = (int)blockIdx.y < mblocks;
     const int rb = is_l ? (int)blockIdx.y : (int)blockIdx.y - mblocks;
     const int line = rb * kFragLines + (lane & (kFragLines - 1));
-    const int lines = is_l ? height : width;
+    const int lines = is_l ? (cplx ? 2 * height : height) : width;
+    const bool im_part = is_l && line >= height;           // rows of L' (complex only)
+    const int src_line = im_part ? line - height : line;
     const int64_t j0 = slot0 + kb * kBlockPoints + kLanePoints * (lane / kFragLines);
 
     Vec16B<T> hi, lo;
@@ -69,11 +76,16 @@ __global__ __launch_bounds__(256) void k_factors(PointConsts pc, int64_t slot0, 
         if (line < lines) {
             const int64_t j = j0 + p;
             const double ctr = is_l ? pc.cy[j] : pc.cx[j];
-            const double d = (double)line - ctr;
+            const double d = (double)src_line - ctr;
             const float ph = (float)__builtin_amdgcn_fract(pc.beta[j] * (d * d));
             c = __builtin_amdgcn_cosf(ph);     // cos(2 pi ph)
             s = __builtin_amdgcn_sinf(ph);     // sin(2 pi ph)
-            if (is_l) {
+            if (im_part) {
+                const float a = pc.amp[j];
+                const float ac = a * c;
+                c = a * s;
+                s = ac;
+            } else if (is_l) {
                 const float a = pc.amp[j];
                 c = a * c;
                 s = -a * s;
@@ -100,41 +112,44 @@ __global__ __launch_bounds__(256) void k_factors(PointConsts pc, int64_t slot0, 
 }
 
 template <typename T>
-hipError_t launch_t(PointConsts pc, int64_t slot0, int64_t n_slots, int width, int height,
+hipError_t launch_t(PointConsts pc, int64_t slot0, int width, int height, int cplx,
                     int64_t kblocks, int mblocks, int nblocks, void *Lh, void *Ll, void *Rh,
                     void *Rl, hipStream_t s)
 {
-    (void)n_slots;
-    dim3 grid((unsigned)((kblocks * 64 + 255) / 256), (unsigned)(mblocks + nblocks));
+    const dim3 grid((unsigned)((kblocks * 64 + 255) / 256), (unsigned)(mblocks + nblocks));
     typedef Vec16B<T> V;
     if (Ll != nullptr && sizeof(T) == 2)
         hipLaunchKernelGGL((k_factors<T, sizeof(T) == 2>), grid, dim3(256), 0, s, pc, slot0,
-                           kblocks, height, width, mblocks, (V *)Lh, (V *)Ll, (V *)Rh, (V *)Rl);
+                           kblocks, height, width, cplx, mblocks, (V *)Lh, (V *)Ll, (V *)Rh,
+                           (V *)Rl);
     else
         hipLaunchKernelGGL((k_factors<T, false>), grid, dim3(256), 0, s, pc, slot0, kblocks,
-                           height, width, mblocks, (V *)Lh, (V *)nullptr, (V *)Rh, (V *)nullptr);
+                           height, width, cplx, mblocks, (V *)Lh, (V *)nullptr, (V *)Rh,
+                           (V *)nullptr);
     return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t launch_factors(PointConsts pc, int64_t slot0, int64_t n_slots, int width, int height,
-                          int64_t kblocks, int mblocks, int nblocks, FactorType ft, void *Lh,
-                          void *Ll, void *Rh, void *Rl, hipStream_t s)
+                          bool cplx, int64_t kblocks, int mblocks, int nblocks, FactorType ft,
+                          void *Lh, void *Ll, void *Rh, void *Rl, hipStream_t s)
 {
+    (void)n_slots;
     if (kblocks <= 0)
         return hipSuccess;
+    const int cx = cplx ? 1 : 0;
     if (ft == FactorType::BF16)
-        return launch_t<__bf16>(pc, slot0, n_slots, width, height, kblocks, mblocks, nblocks, Lh,
-                                Ll, Rh, Rl, s);
+        return launch_t<__bf16>(pc, slot0, width, height, cx, kblocks, mblocks, nblocks, Lh, Ll,
+                                Rh, Rl, s);
     if (ft == FactorType::FP32) {
         if (Ll != nullptr || Rl != nullptr)
             return hipErrorInvalidValue;    // FP32 factors have no lo half
-        return launch_t<float>(pc, slot0, n_slots, width, height, kblocks, mblocks, nblocks, Lh,
+        return launch_t<float>(pc, slot0, width, height, cx, kblocks, mblocks, nblocks, Lh,
                                nullptr, Rh, nullptr, s);
     }
-    return launch_t<_Float16>(pc, slot0, n_slots, width, height, kblocks, mblocks, nblocks, Lh,
-                              Ll, Rh, Rl, s);
+    return launch_t<_Float16>(pc, slot0, width, height, cx, kblocks, mblocks, nblocks, Lh, Ll, Rh,
+                              Rl, s);
 }
 
 }  // namespace cgh

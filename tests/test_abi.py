@@ -80,6 +80,9 @@ def test_null_context_is_rejected_everywhere(L):
     f = (cgh.Frame * 1)()
     assert L.cgh_points_upload(None, None, None, None, None, 0, 0, None) == cgh.EINVAL
     assert L.cgh_compute(None, 0, ctypes.c_void_p(16), None) == cgh.EINVAL
+    assert L.cgh_compute_complex(None, 0, ctypes.c_void_p(16), None) == cgh.EINVAL
+    assert L.cgh_kinoform(None, 0, ctypes.c_void_p(16), None) == cgh.EINVAL
+    assert L.cgh_tune(None, 0, 1, None, 0, None) == cgh.EINVAL
     assert L.cgh_batch_compute(None, f, 1, 0, ctypes.c_void_p(16), None) == cgh.EINVAL
     assert L.cgh_profile_enable(None, 1) == cgh.EINVAL
     assert L.cgh_profile_reset(None) == cgh.EINVAL
