@@ -30,8 +30,9 @@ SPLIT_BF16 = 1
 SPLIT_FP16 = 2
 FP16 = 3
 SEPARABLE_FP32 = 4
+SPHERICAL_FP32 = 5      # the exact spherical wave (Eq. (1)), not the Fresnel sum
 MODES = {"direct_fp32": DIRECT_FP32, "split_bf16": SPLIT_BF16, "split_fp16": SPLIT_FP16,
-         "fp16": FP16, "separable_fp32": SEPARABLE_FP32}
+         "fp16": FP16, "separable_fp32": SEPARABLE_FP32, "spherical_fp32": SPHERICAL_FP32}
 
 # cgh_status
 OK, EINVAL, ENOMEM, EDEVICE, ENOTSUP, ESTATE = range(6)

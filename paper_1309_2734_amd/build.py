@@ -21,7 +21,8 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libcgh.so")
 
-SOURCES = ["api.hip", "points.hip", "direct.hip", "factors.hip", "gemm.hip", "phase.hip"]
+SOURCES = ["api.hip", "points.hip", "direct.hip", "spherical.hip", "factors.hip", "gemm.hip",
+           "phase.hip"]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

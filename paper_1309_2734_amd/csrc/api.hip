@@ -159,9 +159,10 @@ struct cgh_ctx {
     bool uploaded = false;
 
     // workspace
-    DevBuf consts;                    // beta | cx | cy (double) | amp (float)
+    DevBuf consts;                    // beta | cx | cy | zlam (double) | amp | zhalf (float)
     int64_t consts_cap = 0;           // slots
     DevBuf tab_u, tab_v;              // a2 tables
+    DevBuf tab_x, tab_y;              // a2s offset tables (exact spherical wave)
     DevBuf fac[4];                    // Lh, Ll, Rh, Rl
     DevBuf partials;                  // split-K partial tiles
     DevBuf segs, frames;              // small device tables
@@ -265,14 +266,16 @@ PointConsts consts_view(cgh_ctx *c, int64_t slots)
     pc.beta = (double *)base;
     pc.cx = (double *)(base + 8 * slots);
     pc.cy = (double *)(base + 16 * slots);
-    pc.amp = (float *)(base + 24 * slots);
+    pc.zlam = (double *)(base + 24 * slots);
+    pc.amp = (float *)(base + 32 * slots);
+    pc.zhalf = (float *)(base + 36 * slots);
     return pc;
 }
 
 hipError_t ensure_consts(cgh_ctx *c, int64_t slots)
 {
-    // 8 + 8 + 8 + 4 bytes per slot; the view is laid out for `slots`
-    hipError_t e = ensure_ws(c, c->consts, (size_t)slots * 28 + 256);
+    // 4 x 8 + 2 x 4 bytes per slot; the view is laid out for `slots`
+    hipError_t e = ensure_ws(c, c->consts, (size_t)slots * 40 + 256);
     if (e == hipSuccess)
         c->consts_cap = slots;
     return e;
@@ -308,10 +311,13 @@ const float *pts_a(cgh_ctx *c) { return pts_x(c) + 3 * c->n_cap; }
 
 cgh_status check_mode(int mode)
 {
-    if (mode < CGH_DIRECT_FP32 || mode > CGH_SEPARABLE_FP32)
+    if (mode < CGH_DIRECT_FP32 || mode > CGH_SPHERICAL_FP32)
         return fail(CGH_EINVAL, "unknown mode");
     return CGH_OK;
 }
+
+// Modes evaluated by the direct kernels (a cosine per point and pixel).
+bool is_direct(int mode) { return mode == CGH_DIRECT_FP32 || mode == CGH_SPHERICAL_FP32; }
 
 // How a matrix-core mode stores and multiplies its factors.
 struct ModeInfo {
@@ -438,28 +444,74 @@ Plan plan_gemm(int M, int N, int64_t slots, const ModeInfo &mi, const TuneEntry 
 }
 
 // ------------------------------------------------------- one set of frames
-// Direct kernel over frames whose constants occupy slots [0, total_slots)
-// (tables built here).  `fd_dev` points at the device copy of the frames.
-cgh_status run_direct(cgh_ctx *c, const FrameDesc *fd_dev, int n_frames, int64_t total_slots,
-                      float *out, float *out_im, bool accumulate, hipStream_t s)
+// Tables of a direct mode for constant slots [0, slots): a2 (Eq. (2)) or
+// a2s (Eq. (1)).
+cgh_status direct_tables(cgh_ctx *c, int mode, int64_t slots, hipStream_t s)
 {
-    const size_t tu = (size_t)std::max<int64_t>(total_slots, 1) * c->wpad * sizeof(float);
-    const size_t tv = (size_t)std::max<int64_t>(total_slots, 1) * c->hpad * sizeof(float);
+    const bool sph = mode == CGH_SPHERICAL_FP32;
+    const size_t tu = (size_t)std::max<int64_t>(slots, 1) * c->wpad * sizeof(float);
+    const size_t tv = (size_t)std::max<int64_t>(slots, 1) * c->hpad * sizeof(float);
     CGH_HIP(ensure_ws(c, c->tab_u, tu), "table allocation");
     CGH_HIP(ensure_ws(c, c->tab_v, tv), "table allocation");
-    if (total_slots > 0) {
-        Bracket br(c, "phase_tables", s);
-        CGH_HIP(launch_phase_tables(consts_view(c, c->consts_cap), total_slots, c->wpad, c->hpad,
-                                    (float *)c->tab_u.p, (float *)c->tab_v.p, s),
-                "phase_tables launch");
-        br.done();
+    if (sph) {
+        CGH_HIP(ensure_ws(c, c->tab_x, tu), "table allocation");
+        CGH_HIP(ensure_ws(c, c->tab_y, tv), "table allocation");
     }
-    const TuneEntry *t = find_tuned(c, tune_key(c, CGH_DIRECT_FP32, 0, c->height));
-    const int rows = t && (t->rows == 4 || t->rows == 8 || t->rows == 16) ? t->rows : 16;
-    Bracket br(c, out_im ? "direct_fp32_complex" : "direct_fp32", s);
-    CGH_HIP(launch_direct((const float *)c->tab_u.p, (const float *)c->tab_v.p,
-                          consts_view(c, c->consts_cap).amp, fd_dev, n_frames, c->width,
-                          c->height, c->wpad, c->hpad, rows, out, out_im, accumulate, s),
+    if (slots <= 0)
+        return CGH_OK;
+    const PointConsts pc = consts_view(c, c->consts_cap);
+    Bracket br(c, sph ? "sphere_tables" : "phase_tables", s);
+    if (sph)
+        CGH_HIP(launch_sphere_tables(pc, slots, c->wpad, c->hpad, (float *)c->tab_u.p,
+                                     (float *)c->tab_v.p, (float *)c->tab_x.p,
+                                     (float *)c->tab_y.p, s),
+                "sphere_tables launch");
+    else
+        CGH_HIP(launch_phase_tables(pc, slots, c->wpad, c->hpad, (float *)c->tab_u.p,
+                                    (float *)c->tab_v.p, s),
+                "phase_tables launch");
+    br.done();
+    return CGH_OK;
+}
+
+// Row counts per lane the direct kernels are built for.
+bool direct_rows_ok(int mode, int rows)
+{
+    if (mode == CGH_SPHERICAL_FP32)
+        return rows == 4 || rows == 8;
+    return rows == 4 || rows == 8 || rows == 16;
+}
+
+hipError_t launch_direct_mode(cgh_ctx *c, int mode, const FrameDesc *fd_dev, int n_frames,
+                              int rows, float *out, float *out_im, bool accumulate, hipStream_t s)
+{
+    const PointConsts pc = consts_view(c, c->consts_cap);
+    if (mode == CGH_SPHERICAL_FP32)
+        return launch_direct_sphere((const float *)c->tab_u.p, (const float *)c->tab_v.p,
+                                    (const float *)c->tab_x.p, (const float *)c->tab_y.p, pc.amp,
+                                    pc.zhalf, fd_dev, n_frames, c->width, c->height, c->wpad,
+                                    c->hpad, rows, out, out_im, accumulate, s);
+    return launch_direct((const float *)c->tab_u.p, (const float *)c->tab_v.p, pc.amp, fd_dev,
+                         n_frames, c->width, c->height, c->wpad, c->hpad, rows, out, out_im,
+                         accumulate, s);
+}
+
+// Direct kernel over frames whose constants occupy slots [0, total_slots)
+// (tables built here).  `fd_dev` points at the device copy of the frames.
+cgh_status run_direct(cgh_ctx *c, int mode, const FrameDesc *fd_dev, int n_frames,
+                      int64_t total_slots, float *out, float *out_im, bool accumulate,
+                      hipStream_t s)
+{
+    cgh_status st = direct_tables(c, mode, total_slots, s);
+    if (st != CGH_OK)
+        return st;
+    const bool sph = mode == CGH_SPHERICAL_FP32;
+    const TuneEntry *t = find_tuned(c, tune_key(c, mode, 0, c->height));
+    const int rows = t && direct_rows_ok(mode, t->rows) ? t->rows : (sph ? 8 : 16);
+    const char *name = sph ? (out_im ? "direct_sphere_complex" : "direct_sphere")
+                           : (out_im ? "direct_fp32_complex" : "direct_fp32");
+    Bracket br(c, name, s);
+    CGH_HIP(launch_direct_mode(c, mode, fd_dev, n_frames, rows, out, out_im, accumulate, s),
             "direct launch");
     br.done();
     return CGH_OK;
@@ -520,8 +572,8 @@ cgh_status run_gemm(cgh_ctx *c, int mode, int64_t slot0, int64_t slots, float *o
 // Bytes of workspace per constant slot for a mode (tables or factors).
 size_t bytes_per_slot(cgh_ctx *c, int mode, bool cplx)
 {
-    if (mode == CGH_DIRECT_FP32)
-        return (size_t)(c->wpad + c->hpad) * sizeof(float);
+    if (is_direct(mode))
+        return (size_t)(c->wpad + c->hpad) * sizeof(float) * (mode == CGH_SPHERICAL_FP32 ? 2 : 1);
     const int64_t m = cplx ? 2 * (int64_t)c->height : c->height;
     const int64_t w = std::max(round_up(c->width, 384), round_up(c->width, 256));
     const int64_t h = std::max(round_up(m, 384), round_up(m, 256));
@@ -574,8 +626,9 @@ cgh_status eval_one(cgh_ctx *c, int mode, int64_t p0, int64_t count, double lam,
         if (st != CGH_OK)
             return st;
         const bool acc = i > 0;
-        if (mode == CGH_DIRECT_FP32 || segs[i].count == 0)
-            st = run_direct(c, (const FrameDesc *)c->frames.p + i, 1,
+        if (is_direct(mode) || segs[i].count == 0)
+            st = run_direct(c, is_direct(mode) ? mode : CGH_DIRECT_FP32,
+                            (const FrameDesc *)c->frames.p + i, 1,
                             round_up(segs[i].count, kSlotAlign), out, out_im, acc, s);
         else
             st = run_gemm(c, mode, 0, slots, out, cplx, acc, s);
@@ -588,8 +641,8 @@ cgh_status eval_one(cgh_ctx *c, int mode, int64_t p0, int64_t count, double lam,
 // Direct mode over many frames with one launch per stage: all frames'
 // constants and tables side by side, the direct kernel's grid covering every
 // frame (largest first, so the longest workgroups start first).
-cgh_status eval_batch_direct(cgh_ctx *c, const cgh_frame *frames, int n_frames, float *out,
-                             hipStream_t s)
+cgh_status eval_batch_direct(cgh_ctx *c, int mode, const cgh_frame *frames, int n_frames,
+                             float *out, hipStream_t s)
 {
     const int64_t plane = (int64_t)c->width * c->height;
     std::vector<int> order(n_frames);
@@ -617,7 +670,8 @@ cgh_status eval_batch_direct(cgh_ctx *c, const cgh_frame *frames, int n_frames, 
     cgh_status st = point_consts(c, 0, n_frames, max_count, slots, s);
     if (st != CGH_OK)
         return st;
-    return run_direct(c, (const FrameDesc *)c->frames.p, n_frames, slot, out, nullptr, false, s);
+    return run_direct(c, mode, (const FrameDesc *)c->frames.p, n_frames, slot, out, nullptr,
+                      false, s);
 }
 
 
@@ -729,12 +783,12 @@ cgh_status batch_sequence(cgh_ctx *c, const cgh_frame *frames, int n_frames, int
                           hipStream_t s)
 {
     const int64_t plane = (int64_t)c->width * c->height;
-    if (mode == CGH_DIRECT_FP32) {
+    if (is_direct(mode)) {
         int64_t total = 0;
         for (int f = 0; f < n_frames; ++f)
             total += round_up(frames[f].point_count, kSlotAlign);
         if (total <= chunk_slots(c, mode))
-            return eval_batch_direct(c, frames, n_frames, out, s);
+            return eval_batch_direct(c, mode, frames, n_frames, out, s);
         for (int f = 0; f < n_frames; ++f) {
             cgh_status st = eval_one(c, mode, frames[f].point_offset, frames[f].point_count,
                                      frames[f].wavelength, out + f * plane, false, s);
@@ -935,6 +989,8 @@ void cgh_destroy(cgh_ctx *c)
     c->consts.release();
     c->tab_u.release();
     c->tab_v.release();
+    c->tab_x.release();
+    c->tab_y.release();
     for (auto &f : c->fac)
         f.release();
     c->partials.release();
@@ -1168,23 +1224,19 @@ cgh_status cgh_tune(cgh_ctx *c, cgh_mode mode, int32_t repeats, char *report, in
 
     TuneEntry best;
     int tried = 0;
-    if (mode == CGH_DIRECT_FP32) {
+    if (is_direct(mode)) {
         best.key = tune_key(c, mode, 0, c->height);
-        const int64_t tu = slots * c->wpad * (int64_t)sizeof(float);
-        const int64_t tv = slots * c->hpad * (int64_t)sizeof(float);
-        CGH_HIP(ensure_ws(c, c->tab_u, (size_t)tu), "table allocation");
-        CGH_HIP(ensure_ws(c, c->tab_v, (size_t)tv), "table allocation");
-        CGH_HIP(launch_phase_tables(consts_view(c, c->consts_cap), slots, c->wpad, c->hpad,
-                                    (float *)c->tab_u.p, (float *)c->tab_v.p, s),
-                "phase_tables launch");
+        st = direct_tables(c, mode, slots, s);
+        if (st != CGH_OK)
+            return st;
         for (int rows : {4, 8, 16}) {
+            if (!direct_rows_ok(mode, rows))
+                continue;
             double us = 0;
             st = time_launches(
                 [&] {
-                    return launch_direct((const float *)c->tab_u.p, (const float *)c->tab_v.p,
-                                         consts_view(c, c->consts_cap).amp,
-                                         (const FrameDesc *)c->frames.p, 1, c->width, c->height,
-                                         c->wpad, c->hpad, rows, out, nullptr, false, s);
+                    return launch_direct_mode(c, mode, (const FrameDesc *)c->frames.p, 1, rows,
+                                              out, nullptr, false, s);
                 },
                 repeats, s, &us);
             if (st != CGH_OK)

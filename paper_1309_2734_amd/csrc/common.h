@@ -38,8 +38,19 @@ struct PointConsts {
     double *beta;  // revolutions per pixel^2
     double *cx;    // point position in pixel units along x
     double *cy;    // ... along y
+    double *zlam;  // z_j / lambda: the on-axis distance in revolutions
     float *amp;    // A_j
+    float *zhalf;  // z_j / (2 lambda), rounded to float
 };
+
+// DPP row_newbcast:K -- every lane of a 16-lane row reads lane K of that row.
+// The compiler folds the move into a consuming VOP2 instruction (v_add_f32).
+template <int K>
+__device__ __forceinline__ float row_bcast(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
+                                                                 0x150 + K, 0xF, 0xF, false));
+}
 
 // A run of points to prepare: source points [src, src + count) of the
 // uploaded cloud, seen at wavelength `wavelength`, written to constant slots
@@ -72,6 +83,20 @@ hipError_t launch_point_consts(const float *x, const float *y, const float *z, c
 // evaluated like the others and never stored), for slots [0, n_slots).
 hipError_t launch_phase_tables(PointConsts pc, int64_t n_slots, int wpad, int hpad,
                                float *U, float *V, hipStream_t s);
+
+// a2s: tables of the exact spherical wave (Eq. (1)), blocked like a2's:
+// U, V as a2's with z_j / lambda added to V before the reduction, and the
+// squared offsets in units of z_j, X = ((ix - cx_j) p / z_j)^2 and
+// Y = ((iy - cy_j) p / z_j)^2.
+hipError_t launch_sphere_tables(PointConsts pc, int64_t n_slots, int wpad, int hpad, float *U,
+                                float *V, float *X, float *Y, hipStream_t s);
+
+// a3s: direct FP32 accumulation of the exact spherical wave (tables from a2s).
+hipError_t launch_direct_sphere(const float *U, const float *V, const float *X, const float *Y,
+                                const float *amp, const float *zhalf,
+                                const FrameDesc *frames_dev, int n_frames, int width, int height,
+                                int wpad, int hpad, int rows_per_wave, float *out,
+                                float *out_im, bool accumulate, hipStream_t s);
 
 // a3: direct FP32 accumulation for frames[0 .. n_frames) (tables from a2,
 // padded to wpad columns and hpad rows, multiples of kLinePad).  With out_im

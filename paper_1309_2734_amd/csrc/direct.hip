@@ -30,15 +30,6 @@ namespace {
 
 constexpr int kWaves = 4;
 
-template <int K>
-__device__ __forceinline__ float row_bcast(float v)
-{
-    // DPP row_newbcast:K -- every lane of a 16-lane row reads lane K of that
-    // row.  The compiler folds this move into the consuming v_add_f32.
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
-                                                                 0x150 + K, 0xF, 0xF, false));
-}
-
 template <int R>
 struct GroupRegs {
     float4 u[4];      // U[col, 16g + 0..15]

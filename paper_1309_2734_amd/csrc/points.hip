@@ -31,13 +31,17 @@ __global__ __launch_bounds__(256) void k_point_consts(const float *__restrict__ 
         pc.beta[d] = pitch * pitch / (2.0 * sg.wavelength * (double)z[s]);
         pc.cx[d] = half_w + (double)x[s] / pitch;
         pc.cy[d] = half_h + (double)y[s] / pitch;
+        pc.zlam[d] = (double)z[s] / sg.wavelength;
         pc.amp[d] = amp[s];
+        pc.zhalf[d] = (float)(0.5 * (double)z[s] / sg.wavelength);
     } else {
         // padding slot: zero amplitude, zero phase
         pc.beta[d] = 0.0;
         pc.cx[d] = 0.0;
         pc.cy[d] = 0.0;
+        pc.zlam[d] = 0.0;
         pc.amp[d] = 0.0f;
+        pc.zhalf[d] = 0.0f;
     }
 }
 

@@ -1,0 +1,183 @@
+"""GPU parity of the exact spherical wave (Eq. (1), mode SPHERICAL_FP32)
+against the FP64 oracle, which evaluates 2 pi d / lambda with
+d = sqrt(dx^2 + dy^2 + z^2) directly.
+
+Tolerance: NRMS <= 1e-5, the FP32 target.  Each case also checks that the
+Fresnel form of Eq. (2) (with its on-axis phase z_j / lambda) is far from the
+reference, so the comparison would see a dropped remainder term.
+"""
+import numpy as np
+import pytest
+
+import cghgen
+import oracle
+import paper_1309_2734_amd as cgh
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+MODE = cgh.SPHERICAL_FP32
+
+
+def say(*a):
+    print("[spherical]", *a, flush=True)
+
+
+def sph_ref(c, cols=None, rows=None):
+    return oracle.spherical_complex(c.width, c.height, c.pitch, c.wavelength, c.x, c.y, c.z,
+                                    c.amp, cols=cols, rows=rows)
+
+
+def fresnel_with_depth_term(c, cols=None, rows=None):
+    """Eq. (2) including the per-point phase 2 pi z_j / lambda (the
+    approximation Eq. (1) is compared with), from the oracle's Fresnel sum
+    of each point: O = sum_j exp(i 2 pi z_j / lambda) O_j."""
+    re = 0.0
+    for j in range(c.n):
+        r, i = oracle.fresnel_complex(c.width, c.height, c.pitch, c.wavelength, c.x[j:j + 1],
+                                      c.y[j:j + 1], c.z[j:j + 1], c.amp[j:j + 1],
+                                      cols=cols, rows=rows, threads=1)
+        ph = 2.0 * np.pi * float(np.float64(c.z[j])) / c.wavelength
+        re = re + r * np.cos(ph) - i * np.sin(ph)
+    return re
+
+
+def gpu(c, ctx=None, planes=1):
+    import torch
+    own = ctx is None
+    if own:
+        ctx = cgh.Context(c.width, c.height, c.pitch, c.wavelength)
+        ctx.upload_cloud(c)
+    if planes == 1:
+        out = torch.empty((c.height, c.width), device="cuda")
+        ctx.compute(out, MODE)
+    else:
+        out = torch.empty((2, c.height, c.width), device="cuda")
+        ctx.compute_complex(out, MODE)
+    torch.cuda.synchronize()
+    res = out.cpu().numpy().astype(np.float64)
+    if own:
+        ctx.close()
+    return res
+
+
+def check(name, got, ref):
+    e = oracle.nrms(got, ref)
+    say(f"{name}: nrms={e:.3e} max={oracle.max_err(got, ref):.3e}")
+    assert np.all(np.isfinite(got))
+    assert e <= TOL, f"{name}: nrms {e:.3e}"
+
+
+def test_c1_full_grid_real_complex_kinoform():
+    import torch
+    c = cghgen.make_config(1)
+    re, im = sph_ref(c)
+    got = gpu(c)
+    check("C1 spherical", got, re)
+    fr = fresnel_with_depth_term(c)
+    say(f"C1 Fresnel vs exact: nrms {oracle.nrms(fr, re):.3e}")
+    assert oracle.nrms(fr, re) > 100 * TOL
+    ctx = cgh.Context(c.width, c.height, c.pitch, c.wavelength)
+    ctx.upload_cloud(c)
+    both = gpu(c, ctx, planes=2)
+    check("C1 spherical Re", both[0], re)
+    check("C1 spherical Im", both[1], im)
+    assert np.array_equal(both[0], got)
+    codes = torch.empty((c.height, c.width), dtype=torch.uint8, device="cuda")
+    ctx.kinoform(codes, MODE)
+    torch.cuda.synchronize()
+    codes = codes.cpu().numpy()
+    own = oracle.kinoform(both[0], both[1])
+    t = np.arctan2(both[1], both[0])
+    t = np.where(t < 0, t + 2 * np.pi, t) * 255.0 / (2 * np.pi)
+    far = np.abs(t - np.round(t)) > 1e-3
+    assert np.array_equal(codes[far], own[far])
+    ctx.close()
+
+
+@pytest.mark.parametrize("k, step", [(2, 48), (3, 96)])
+def test_full_size_strided(k, step):
+    c = cghgen.make_config(k)
+    cols, rows = np.arange(0, c.width, step), np.arange(3, c.height, step)
+    say(f"C{k} {c.width}x{c.height} N={c.n} sample {len(rows)}x{len(cols)}")
+    re, _ = sph_ref(c, cols=cols, rows=rows)
+    got = gpu(c)[np.ix_(rows, cols)]
+    check(f"C{k} spherical", got, re)
+
+
+@pytest.mark.parametrize("n", [1, 31, 33])
+def test_ragged_point_counts(n):
+    c = cghgen.make_config(1, n=n)
+    re, _ = sph_ref(c)
+    check(f"N={n}", gpu(c), re)
+
+
+@pytest.mark.parametrize("wh", [(1, 1), (65, 33), (7, 300)])
+def test_ragged_sizes(wh):
+    w, h = wh
+    c0 = cghgen.make_config(1, n=77)
+    c = cghgen.Cloud("ragged", w, h, c0.pitch, c0.wavelength, c0.x, c0.y, c0.z, c0.amp)
+    re, _ = sph_ref(c)
+    got = gpu(c)
+    if w * h == 1:
+        assert abs(got[0, 0] - re[0, 0]) <= 10 * TOL * max(1.0, abs(re[0, 0]))
+    else:
+        check(f"{w}x{h}", got, re)
+
+
+def test_wide_angle_point():
+    """A point 2 mm in front of a 2 mm hologram, seen at up to ~36 degrees:
+    the remainder (d - z)^2 / (2 z lambda) reaches ~90 revolutions, and its
+    FP32 evaluation (a few roundings of 6e-8 each, < 2e-6 relative in all)
+    bounds the phase error by 2 pi * 2e-6 * remainder."""
+    W = H = 129
+    p, lam = 16e-6, 633e-9
+    x = np.array([0.0], np.float32)
+    y = np.array([0.0], np.float32)
+    z = np.array([2e-3], np.float32)
+    a = np.array([1.0], np.float32)
+    c = cghgen.Cloud("wide", W, H, p, lam, x, y, z, a)
+    re, _ = sph_ref(c)
+    got = gpu(c)
+    e = oracle.nrms(got, re)
+    r_max = np.hypot(64 * p, 64 * p)
+    d_max = np.hypot(r_max, 2e-3)
+    rem = (d_max - 2e-3) ** 2 / (2 * 2e-3 * lam)
+    bound = 2 * np.pi * 2e-6 * rem
+    say(f"wide angle: remainder up to {rem:.1f} rev, nrms {e:.3e}, bound {bound:.3e}")
+    assert rem > 50
+    assert e <= bound
+
+
+def test_batch_frames_with_wavelengths():
+    import torch
+    counts = [0, 5, 200, 33]
+    b = cghgen.make_batch(n_frames=len(counts), width=160, height=96, counts=counts)
+    frames = cgh.batch_frames(b)
+    ctx = cgh.Context(b.width, b.height, b.pitch, 532e-9)
+    ctx.upload_cloud(b)
+    out = torch.empty((len(frames), b.height, b.width), device="cuda")
+    ctx.batch_compute(frames, out, MODE)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().astype(np.float64)
+    for f, (o, n, lam) in enumerate(frames):
+        sl = slice(o, o + n)
+        if n == 0:
+            assert np.all(got[f] == 0.0)
+            continue
+        re, _ = oracle.spherical_complex(b.width, b.height, b.pitch, lam, b.x[sl], b.y[sl],
+                                         b.z[sl], b.amp[sl])
+        check(f"batch frame {f} N={n} lambda={lam:.3e}", got[f], re)
+    ctx.close()
+
+
+def test_tune_spherical():
+    c = cghgen.make_config(1, n=500)
+    re, _ = sph_ref(c)
+    ctx = cgh.Context(c.width, c.height, c.pitch, c.wavelength)
+    ctx.upload_cloud(c)
+    rep = ctx.tune(MODE, repeats=2)
+    say(rep)
+    assert "(2 candidates)" in rep
+    check("tuned", gpu(c, ctx), re)
+    ctx.close()
