@@ -8,8 +8,12 @@ cghgen config 2), points resident in HBM before timing.  One step = one
 cgh_compute of the whole cloud in the headline mode (BF16 hi/lo split on the
 matrix cores: per-point constants, factor build, split GEMM, split-K reduce).
 The direct FP32 kernel and the other modes are timed the same way and
-reported under "modes".  NRMS and max error of every mode are measured
-against the FP64 oracle on the CPU-baseline sample (every 4th row).
+reported under "modes" (spherical_fp32 evaluates the exact spherical wave of
+Eq. (1) instead of the Fresnel sum).  NRMS and max error of every mode are
+measured against the FP64 oracle on the CPU-baseline sample (every 4th row;
+every 16th for the spherical mode, against the oracle's Eq. (1)).  Side
+measurements: the 64-frame batched workload ("batch") and the phase-only
+hologram of Eq. (3) of the bench cloud ("kinoform").
 
 Prints one JSON line (rank 0).  --gpus N > 1 is refused: this build runs on
 one GPU.
@@ -28,14 +32,30 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# Published MI355X peaks (dense) and the issue-rate roofline of the direct kernel.
+# Published MI355X peaks (dense MFMA).
 PEAK_MFMA_BF16_TFLOPS = 2500.0
 PEAK_MFMA_FP16_TFLOPS = 2500.0
 PEAK_MFMA_FP32_TFLOPS = 157.3
-CUS, CLOCK_HZ, LANES = 256, 2.4e9, 64
-# direct kernel: v_add_f32 (1 slot) + v_cos_f32 (2 slots, half rate) + v_fmac_f32 (1 slot)
-DIRECT_SLOTS_PER_PP = 4
-PEAK_DIRECT_PPS = CUS * CLOCK_HZ * LANES / DIRECT_SLOTS_PER_PP      # 9.83e12 point*pixel/s
+CUS, CLOCK_HZ = 256, 2.4e9
+# ALU-bound kernels: an upper bound from two per-CU limits at the peak clock --
+# VALU issue of 64 lane-instructions per clock (4 SIMD16 units, one wave64
+# instruction per 4 clocks each; every instruction, transcendental or not,
+# takes one such slot) and transcendental results (v_cos/v_sin/v_sqrt/v_rcp)
+# at half that rate, 32 per clock.
+VALU_PER_CLK, TRANS_PER_CLK = 64, 32
+
+
+def alu_peak_pps(instr_per_pp: int, trans_per_pp: int) -> float:
+    return CUS * CLOCK_HZ * min(VALU_PER_CLK / instr_per_pp, TRANS_PER_CLK / trans_per_pp)
+
+
+# direct kernel: v_add_f32_dpp, v_cos_f32, v_fmac_f32 per point*pixel
+PEAK_DIRECT_PPS = alu_peak_pps(3, 1)          # 1.311e13 point*pixel/s
+# exact spherical wave: 2 v_add_f32_dpp, 2 v_add_f32, 2 v_mul_f32, v_fma_f32,
+# v_fmac_f32 and v_sqrt_f32, v_rcp_f32, v_cos_f32 per point*pixel
+PEAK_SPHERE_PPS = alu_peak_pps(11, 3)         # 3.575e12 point*pixel/s
+ALU_MODES = {"direct_fp32": ("direct_fp32", PEAK_DIRECT_PPS),
+             "spherical_fp32": ("direct_sphere", PEAK_SPHERE_PPS)}
 
 # executed matrix flops per point*pixel: K = 2N columns, 2 flop per MAC, x products
 FLOP_PER_PP = {"split_bf16": 12, "split_fp16": 12, "fp16": 4, "separable_fp32": 4}
@@ -44,7 +64,7 @@ GEMM_KERNEL = {"split_bf16": "gemm_split_mfma", "split_fp16": "gemm_split_mfma",
 GEMM_PEAK = {"split_bf16": PEAK_MFMA_BF16_TFLOPS, "split_fp16": PEAK_MFMA_FP16_TFLOPS,
              "fp16": PEAK_MFMA_FP16_TFLOPS, "separable_fp32": PEAK_MFMA_FP32_TFLOPS}
 MODE_DTYPE = {"split_bf16": "bf16", "split_fp16": "f16", "fp16": "f16", "direct_fp32": "f32",
-              "separable_fp32": "f32"}
+              "separable_fp32": "f32", "spherical_fp32": "f32"}
 
 # HBM bytes per launch from two rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE)
 # on this workload, each scaled by what the counter reads for a plain device
@@ -128,6 +148,69 @@ def bench_batch(args, torch, cghgen, cgh):
             "launch": "hipGraph replay", "nrms_sampled_frames": errs}
 
 
+def bench_kinoform(args, torch, cghgen, cgh, check: bool):
+    """Side measurement: the phase-only hologram of Eq. (3) (the paper's
+    timed workload) of the same 1920 x 1080, 10k-point cloud -- complex
+    field, then the 8-bit phase codes -- in three modes.  With `check`, the
+    codes on every 16th row are compared with the oracle's FP64 field where
+    the device field's error cannot move the phase across a code boundary."""
+    c = cghgen.make_config(2)
+    W, H, N = c.width, c.height, c.n
+    pp = W * H * N
+    ctx = cgh.Context(W, H, c.pitch, c.wavelength)
+    ctx.upload_cloud(c)
+    stream = torch.cuda.current_stream()
+    codes = torch.empty((H, W), dtype=torch.uint8, device="cuda:0")
+    field = torch.empty((2, H, W), device="cuda:0")
+    rows = np.arange(0, H, 16)
+    ref = None
+    if check:
+        import oracle
+        ref = oracle.fresnel_complex(W, H, c.pitch, c.wavelength, c.x, c.y, c.z, c.amp,
+                                     rows=rows, threads=oracle.host_threads())
+    res = {}
+    for m in ("split_bf16", "separable_fp32", "direct_fp32"):
+        mode = cgh.MODES[m]
+        for _ in range(2):
+            ctx.kinoform(codes, mode, stream)
+        torch.cuda.synchronize()
+        reps = max(1, args.steps)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            ctx.kinoform(codes, mode, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        r = {"ms_per_hologram": ms, "pp_per_s": pp / (ms * 1e-3)}
+        if ref is not None:
+            ctx.compute_complex(field, mode, stream)
+            torch.cuda.synchronize()
+            f = field.cpu().numpy().astype(np.float64)[:, rows]
+            got = codes.cpu().numpy()[rows]
+            import oracle
+            t = np.arctan2(ref[1], ref[0])
+            t = np.where(t < 0, t + 2 * np.pi, t) * 255.0 / (2 * np.pi)
+            mag = np.hypot(ref[0], ref[1])
+            e = float(np.max(np.hypot(f[0] - ref[0], f[1] - ref[1])))
+            ratio = np.where(mag > 0, e / np.maximum(mag, 1e-300), np.inf)
+            margin = np.where(ratio < 0.5, 2 * np.arcsin(np.minimum(ratio, 0.5)) * 255 / (2 * np.pi),
+                              np.inf) + 1e-3
+            sure = np.abs(t - np.round(t)) > margin
+            want = oracle.kinoform(ref[0], ref[1])
+            r["codes_checked"] = int(np.sum(sure))
+            r["codes_differing"] = int(np.sum(got[sure] != want[sure]))
+            r["codes_differing_any"] = int(np.sum(got != want))
+        log(f"kinoform {m}: {ms:.4f} ms, {r['pp_per_s']:.3e} pp/s {r}")
+        res[m] = r
+    ctx.close()
+    return {"workload": "phase-only hologram (Eq. 3) of the 1920x1080, 10000-point cloud: "
+                        "complex field + 8-bit phase codes", "modes": res,
+            "check": "codes on every 16th row vs the FP64 oracle field, where the device "
+                     "field's error cannot cross a code boundary" if check else None}
+
+
 def traffic_driver(torch, cghgen, cgh) -> int:
     """Kernel sequence for `rocprofv3 --pmc FETCH_SIZE|WRITE_SIZE -- python bench.py
     --traffic-driver`: the per-launch counters of the GEMM and direct kernels, and of a
@@ -156,12 +239,15 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--modes", default="split_bf16,direct_fp32,separable_fp32,split_fp16,fp16",
+    ap.add_argument("--modes", default="split_bf16,direct_fp32,separable_fp32,split_fp16,fp16,"
+                                       "spherical_fp32",
                     help="comma list; the first is the headline mode")
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the oracle (profiling runs)")
     ap.add_argument("--sample-row-step", type=int, default=4)
     ap.add_argument("--no-tune", action="store_true", help="use the default launch shapes")
+    ap.add_argument("--no-kinoform", action="store_true",
+                    help="skip the phase-only hologram side measurement")
     ap.add_argument("--batch-frames", type=int, default=64,
                     help="frames of the batched-workload side measurement (0 = skip)")
     ap.add_argument("--traffic-driver", action="store_true",
@@ -231,14 +317,15 @@ def main() -> int:
         r = {"ms_per_step": wall_ms, "ms_per_step_events": ev_ms, "pp_per_s": pp / (wall_ms * 1e-3),
              "kernels_ms": {k: v[1] / v[0] for k, v in kern.items()}, "sample": sample,
              "dtype": MODE_DTYPE[m], "tuned": tuned}
-        if m == "direct_fp32":
-            t = r["kernels_ms"].get("direct_fp32")
+        if m in ALU_MODES:
+            kname, peak = ALU_MODES[m]
+            t = r["kernels_ms"].get(kname)
             if t:
                 ach = pp / (t * 1e-3)
-                r["roofline"] = {"bound": "alu", "achieved": ach, "peak": PEAK_DIRECT_PPS,
-                                 "unit": "point*pixel/s", "frac": ach / PEAK_DIRECT_PPS,
-                                 "traffic": traffic_bytes("direct_fp32", tuned),
-                                 "kernel": "direct_fp32", "kernel_ms": t}
+                r["roofline"] = {"bound": "alu", "achieved": ach, "peak": peak,
+                                 "unit": "point*pixel/s", "frac": ach / peak,
+                                 "traffic": traffic_bytes(kname, tuned),
+                                 "kernel": kname, "kernel_ms": t}
         else:
             kname = GEMM_KERNEL[m]
             t = r["kernels_ms"].get(kname)
@@ -257,6 +344,9 @@ def main() -> int:
     batch = None
     if args.batch_frames > 0:
         batch = bench_batch(args, torch, cghgen, cgh)
+    kino = None
+    if not args.no_kinoform:
+        kino = bench_kinoform(args, torch, cghgen, cgh, check=not args.no_cpu_baseline)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -273,9 +363,18 @@ def main() -> int:
                          f"of the {W}x{H} hologram, all {N} points: {sample_pp:.3e} "
                          f"point*pixels in {dt:.1f} s (FP64, libm cos)"}
         import oracle as orc
+        sph_ref = None
         for m, r in results.items():
-            r["nrms"] = orc.nrms(r["sample"], ref)
-            r["max_err"] = orc.max_err(r["sample"], ref)
+            if m == "spherical_fp32":
+                # Eq. (1) has its own reference: every 4th sample row
+                srows = rows[::4]
+                sph_ref = orc.spherical_complex(W, H, c.pitch, c.wavelength, c.x, c.y, c.z,
+                                                c.amp, rows=srows, threads=threads)[0]
+                got, want = r["sample"][::4], sph_ref
+            else:
+                got, want = r["sample"], ref
+            r["nrms"] = orc.nrms(got, want)
+            r["max_err"] = orc.max_err(got, want)
             log(f"mode {m}: nrms {r['nrms']:.3e} max {r['max_err']:.3e}")
 
     h = results[head]
@@ -299,6 +398,7 @@ def main() -> int:
         "cpu_baseline": cpu,
         "modes": {m: {k: v for k, v in r.items() if k != "sample"} for m, r in results.items()},
         "batch": batch,
+        "kinoform": kino,
     }
     print(json.dumps(line), flush=True)
     return 0

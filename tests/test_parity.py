@@ -28,6 +28,9 @@ GEMM_MODES = (cgh.SPLIT_BF16, cgh.SPLIT_FP16, cgh.FP16, cgh.SEPARABLE_FP32)
 ALL_MODES = (cgh.DIRECT_FP32,) + GEMM_MODES
 
 
+_REFS = {}     # oracle references shared by parametrised cases
+
+
 def say(*a):
     print("[parity]", *a, flush=True)
 
@@ -119,6 +122,22 @@ def test_c3_full_size_strided(mode):
     ref = oracle.cloud_fresnel(c, cols=cols, rows=rows)
     got = gpu_hologram(c, mode)[np.ix_(rows, cols)]
     check("C3", got, ref, mode)
+
+
+@pytest.mark.parametrize("mode", (cgh.SPLIT_BF16, cgh.SEPARABLE_FP32, cgh.DIRECT_FP32),
+                         ids=["split_bf16", "separable_fp32", "direct_fp32"])
+def test_c5_large_scene_chunked(mode):
+    """4096 x 4096 at 4 um, 10^6 points on an ellipsoid surface: the factors
+    or tables of the whole cloud exceed the workspace budget, so the cloud
+    is evaluated in point chunks that accumulate into the output."""
+    c = cghgen.make_config(5)
+    cols, rows = np.arange(7, c.width, 160), np.arange(3, c.height, 160)
+    say(f"C5 {c.width}x{c.height} N={c.n} {NAMES[mode]} sample {len(rows)}x{len(cols)}")
+    if "c5" not in _REFS:
+        _REFS["c5"] = oracle.cloud_fresnel(c, cols=cols, rows=rows)
+    ref = _REFS["c5"]
+    got = gpu_hologram(c, mode)[np.ix_(rows, cols)]
+    check("C5", got, ref, mode)
 
 
 # ------------------------------------------------------------ edge cases
