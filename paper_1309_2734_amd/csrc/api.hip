@@ -163,7 +163,7 @@ struct cgh_ctx {
     int64_t consts_cap = 0;           // slots
     DevBuf tab_u, tab_v;              // a2 tables
     DevBuf tab_x, tab_y;              // a2s offset tables (exact spherical wave)
-    DevBuf fac[4];                    // Lh, Ll, Rh, Rl
+    DevBuf fac;                       // Lh | Ll | Rh | Rl in one allocation
     DevBuf partials;                  // split-K partial tiles
     DevBuf segs, frames;              // small device tables
     DevBuf tune_out;                  // scratch hologram for cgh_tune
@@ -279,6 +279,19 @@ hipError_t ensure_consts(cgh_ctx *c, int64_t slots)
     if (e == hipSuccess)
         c->consts_cap = slots;
     return e;
+}
+
+// Factor set of a matrix-core evaluation: amb / anb line blocks of L / R,
+// kblocks K blocks, hl halves (common.h has the layout).
+cgh_status ensure_factors(cgh_ctx *c, int amb, int anb, int64_t kblocks, int hl, FactorSet &f)
+{
+    f.hl = hl;
+    f.amb = amb;
+    f.anb = anb;
+    f.kblocks = kblocks;
+    CGH_HIP(ensure_ws(c, c->fac, (size_t)std::max<int64_t>(f.bytes(), 1)), "factor allocation");
+    f.base = (char *)c->fac.p;
+    return CGH_OK;
 }
 
 // Segment and frame tables (small) go to device memory with a synchronous
@@ -436,8 +449,6 @@ Plan plan_gemm(int M, int N, int64_t slots, const ModeInfo &mi, const TuneEntry 
     best.g.splits = splits;
     best.g.mblocks = best.tiles_m * (best.g.bm / kFragLines);
     best.g.nblocks = best.tiles_n * (best.g.bn / kFragLines);
-    best.g.alloc_mblocks = best.g.mblocks;   // the caller sizes the factors from these
-    best.g.alloc_nblocks = best.g.nblocks;
     best.g.kblocks = kblocks;
     best.g.products = mi.products;
     return best;
@@ -529,15 +540,10 @@ cgh_status run_gemm(cgh_ctx *c, int mode, int64_t slot0, int64_t slots, float *o
     const Plan p = plan_gemm(M, c->width, slots, mi,
                              find_tuned(c, tune_key(c, mode, slots / mi.kbp, M)));
     const int hl = mi.hl;
-    // 2 K-columns (cos, sin) per line and point
-    const size_t lbytes = (size_t)p.g.mblocks * kFragLines * (size_t)slots * 2 * mi.elem;
-    const size_t rbytes = (size_t)p.g.nblocks * kFragLines * (size_t)slots * 2 * mi.elem;
-    CGH_HIP(ensure_ws(c, c->fac[0], lbytes), "factor allocation");
-    CGH_HIP(ensure_ws(c, c->fac[2], rbytes), "factor allocation");
-    if (hl == 2) {
-        CGH_HIP(ensure_ws(c, c->fac[1], lbytes), "factor allocation");
-        CGH_HIP(ensure_ws(c, c->fac[3], rbytes), "factor allocation");
-    }
+    FactorSet fs;
+    cgh_status fst = ensure_factors(c, p.g.mblocks, p.g.nblocks, p.g.kblocks, hl, fs);
+    if (fst != CGH_OK)
+        return fst;
     if (p.g.splits > 1)
         CGH_HIP(ensure_ws(c, c->partials,
                           (size_t)p.g.splits * M * (size_t)c->width * sizeof(float)),
@@ -545,16 +551,14 @@ cgh_status run_gemm(cgh_ctx *c, int mode, int64_t slot0, int64_t slots, float *o
     PointConsts pc = consts_view(c, c->consts_cap);
     {
         Bracket br(c, mi.fac_name, s);
-        CGH_HIP(launch_factors(pc, slot0, slots, c->width, c->height, cplx, p.g.kblocks,
-                               p.g.mblocks, p.g.nblocks, ft, c->fac[0].p, hl == 2 ? c->fac[1].p : nullptr,
-                               c->fac[2].p, hl == 2 ? c->fac[3].p : nullptr, s),
+        CGH_HIP(launch_factors(pc, slot0, c->width, c->height, cplx, p.g.kblocks, p.g.mblocks,
+                               p.g.nblocks, ft, fs, s),
                 "factor launch");
         br.done();
     }
     {
         Bracket br(c, mi.gemm_name, s);
-        CGH_HIP(launch_gemm(p.g, ft, c->fac[0].p, hl == 2 ? c->fac[1].p : nullptr, c->fac[2].p,
-                            hl == 2 ? c->fac[3].p : nullptr, M, c->width, out, c->width,
+        CGH_HIP(launch_gemm(p.g, ft, fs, M, c->width, out, c->width,
                             (float *)c->partials.p, accumulate, s),
                 "gemm launch");
         br.done();
@@ -694,7 +698,8 @@ cgh_status eval_batch_gemm(cgh_ctx *c, int mode, const cgh_frame *frames, int n_
     Plan p = plan_gemm(c->height, c->width, max_slots, mi,
                        find_tuned(c, tune_key(c, mode, max_slots / mi.kbp, c->height)));
     const size_t per_slot = (size_t)(p.g.mblocks + p.g.nblocks) * kFragLines * mi.line_bytes();
-    const int64_t budget = std::max<int64_t>((int64_t)(workspace_budget() / per_slot), kSlotAlign);
+    const int64_t budget = std::max<int64_t>(
+        (int64_t)workspace_budget() / (int64_t)per_slot / kSlotAlign * kSlotAlign, kSlotAlign);
 
     // Groups of frames [f0, f1) whose padded slots fit the budget (at least
     // one frame each).  All groups' segments and work items go to the device
@@ -739,14 +744,11 @@ cgh_status eval_batch_gemm(cgh_ctx *c, int mode, const cgh_frame *frames, int n_
     int64_t max_group_slots = kSlotAlign;
     for (auto &gr : groups)
         max_group_slots = std::max(max_group_slots, gr.slots);
-    const size_t lbytes = (size_t)p.g.mblocks * kFragLines * (size_t)max_group_slots * 2 * mi.elem;
-    const size_t rbytes = (size_t)p.g.nblocks * kFragLines * (size_t)max_group_slots * 2 * mi.elem;
-    CGH_HIP(ensure_ws(c, c->fac[0], lbytes), "factor allocation");
-    CGH_HIP(ensure_ws(c, c->fac[2], rbytes), "factor allocation");
-    if (hl == 2) {
-        CGH_HIP(ensure_ws(c, c->fac[1], lbytes), "factor allocation");
-        CGH_HIP(ensure_ws(c, c->fac[3], rbytes), "factor allocation");
-    }
+    FactorSet fs;
+    cgh_status fst =
+        ensure_factors(c, p.g.mblocks, p.g.nblocks, max_group_slots / mi.kbp, hl, fs);
+    if (fst != CGH_OK)
+        return fst;
     CGH_HIP(ensure_consts(c, max_group_slots), "constant allocation");
     for (auto &gr : groups) {
         const int64_t total = std::max<int64_t>(gr.slots, kSlotAlign);
@@ -755,19 +757,18 @@ cgh_status eval_batch_gemm(cgh_ctx *c, int mode, const cgh_frame *frames, int n_
             return st;
         GemmPlan g = p.g;
         g.kblocks = total / mi.kbp;
+        FactorSet gfs = fs;            // this group's K extent
+        gfs.kblocks = g.kblocks;
         {
             Bracket br(c, mi.fac_name, s);
-            CGH_HIP(launch_factors(consts_view(c, c->consts_cap), 0, total, c->width, c->height,
-                                   false, g.kblocks, g.mblocks, g.nblocks, ft, c->fac[0].p,
-                                   hl == 2 ? c->fac[1].p : nullptr, c->fac[2].p,
-                                   hl == 2 ? c->fac[3].p : nullptr, s),
+            CGH_HIP(launch_factors(consts_view(c, c->consts_cap), 0, c->width, c->height, false,
+                                   g.kblocks, g.mblocks, g.nblocks, ft, gfs, s),
                     "factor launch");
             br.done();
         }
         {
             Bracket br(c, mi.batch_name, s);
-            CGH_HIP(launch_gemm_batch(g, ft, c->fac[0].p, hl == 2 ? c->fac[1].p : nullptr,
-                                      c->fac[2].p, hl == 2 ? c->fac[3].p : nullptr,
+            CGH_HIP(launch_gemm_batch(g, ft, gfs,
                                       (const BatchItem *)c->items.p + gr.item0, gr.nitem,
                                       (int *)c->counter.p, c->height, c->width, out,
                                       std::min(256, gr.nitem), s),
@@ -991,8 +992,7 @@ void cgh_destroy(cgh_ctx *c)
     c->tab_v.release();
     c->tab_x.release();
     c->tab_y.release();
-    for (auto &f : c->fac)
-        f.release();
+    c->fac.release();
     c->partials.release();
     c->segs.release();
     c->frames.release();
@@ -1263,17 +1263,12 @@ cgh_status cgh_tune(cgh_ctx *c, cgh_mode mode, int32_t repeats, char *report, in
             mb = std::max(mb, (int)(round_up(c->height, sh[0]) / kFragLines));
             nb = std::max(nb, (int)(round_up(c->width, sh[1]) / kFragLines));
         }
-        const size_t lbytes = (size_t)mb * kFragLines * slots * 2 * mi.elem;
-        const size_t rbytes = (size_t)nb * kFragLines * slots * 2 * mi.elem;
-        CGH_HIP(ensure_ws(c, c->fac[0], lbytes), "factor allocation");
-        CGH_HIP(ensure_ws(c, c->fac[2], rbytes), "factor allocation");
-        if (hl == 2) {
-            CGH_HIP(ensure_ws(c, c->fac[1], lbytes), "factor allocation");
-            CGH_HIP(ensure_ws(c, c->fac[3], rbytes), "factor allocation");
-        }
-        CGH_HIP(launch_factors(consts_view(c, c->consts_cap), 0, slots, c->width, c->height,
-                               false, kblocks, mb, nb, ft, c->fac[0].p, hl == 2 ? c->fac[1].p : nullptr,
-                               c->fac[2].p, hl == 2 ? c->fac[3].p : nullptr, s),
+        FactorSet fs;
+        st = ensure_factors(c, mb, nb, kblocks, hl, fs);
+        if (st != CGH_OK)
+            return st;
+        CGH_HIP(launch_factors(consts_view(c, c->consts_cap), 0, c->width, c->height, false,
+                               kblocks, mb, nb, ft, fs, s),
                 "factor launch");
         for (auto &sh : shapes) {
             if (!gemm_tile_supported(sh[0], sh[1], sh[2], sh[3], sh[4]))
@@ -1301,8 +1296,7 @@ cgh_status cgh_tune(cgh_ctx *c, cgh_mode mode, int32_t repeats, char *report, in
                 gp.nblocks = (c->width + sh[1] - 1) / sh[1] * (sh[1] / kFragLines);
                 gp.kblocks = kblocks;
                 gp.products = mi.products;
-                gp.alloc_mblocks = mb;
-                gp.alloc_nblocks = nb;
+
                 if (sp > 1)
                     CGH_HIP(ensure_ws(c, c->partials,
                                       (size_t)sp * c->height * (size_t)c->width * sizeof(float)),
@@ -1310,9 +1304,7 @@ cgh_status cgh_tune(cgh_ctx *c, cgh_mode mode, int32_t repeats, char *report, in
                 double us = 0;
                 st = time_launches(
                     [&] {
-                        hipError_t e = launch_gemm(gp, ft, c->fac[0].p,
-                                                   hl == 2 ? c->fac[1].p : nullptr, c->fac[2].p,
-                                                   hl == 2 ? c->fac[3].p : nullptr, c->height,
+                        hipError_t e = launch_gemm(gp, ft, fs, c->height,
                                                    c->width, out, c->width,
                                                    (float *)c->partials.p, false, s);
                         if (e == hipSuccess && sp > 1)

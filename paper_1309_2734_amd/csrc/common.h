@@ -106,17 +106,34 @@ hipError_t launch_direct(const float *U, const float *V, const float *amp,
                          int wpad, int hpad, int rows_per_wave, float *out, float *out_im,
                          bool accumulate, hipStream_t s);
 
-// a4: factor build.  Writes the hi (and, if lo_* != nullptr, lo) factors of
-// L (rows) and R (columns) in the MFMA fragment order described in factors.hip:
-// mblocks / nblocks blocks of kFragLines lines, kblocks blocks of
-// kblock_points(ft) points.  FP32 factors have no lo half.  With `cplx`, L
-// has 2 * height lines: the real-part factors of rows 0 .. height-1, then the
-// imaginary-part factors of the same rows, so that L R^T is [Re O; Im O].
+// a4/a5 factor set, K-major: for every K block kb one contiguous slab of
+// slab_blocks() 1 KB operand blocks -- the line blocks of Lh [0, amb), of Ll
+// [amb, 2 amb) (with lo halves), then those of Rh and Rl (anb each).  Block b
+// of an array sits at base + (kb * slab_blocks() + first + b) KB, so a GEMM
+// stage reads one slab and addresses it with small 32-bit offsets.
+struct FactorSet {
+    char *base = nullptr;
+    int hl = 1;            // 2: hi and lo halves
+    int amb = 0, anb = 0;  // L / R line blocks allocated
+    int64_t kblocks = 0;   // K blocks allocated
+    __host__ __device__ int slab_blocks() const { return hl * (amb + anb); }
+    __host__ __device__ int first_l(bool lo) const { return lo ? amb : 0; }
+    __host__ __device__ int first_r(bool lo) const { return hl * amb + (lo ? anb : 0); }
+    int64_t bytes() const { return kblocks * slab_blocks() * (int64_t)1024; }
+};
+
+// a4: factor build.  Writes K blocks [0, kblocks) of the hi (and, with
+// fs.hl == 2, lo) factors of L (rows; mblocks line blocks) and R (columns;
+// nblocks) in the MFMA fragment order described in factors.hip; a K block
+// holds kblock_points(ft) points starting at constant slot slot0.  FP32
+// factors have no lo half.  With `cplx`, L has 2 * height lines: the
+// real-part factors of rows 0 .. height-1, then the imaginary-part factors of
+// the same rows, so that L R^T is [Re O; Im O].
 enum class FactorType { BF16 = 0, FP16 = 1, FP32 = 2 };
 constexpr int kblock_points(FactorType ft) { return ft == FactorType::FP32 ? 8 : 16; }
-hipError_t launch_factors(PointConsts pc, int64_t slot0, int64_t n_slots, int width, int height,
-                          bool cplx, int64_t kblocks, int mblocks, int nblocks, FactorType ft,
-                          void *Lh, void *Ll, void *Rh, void *Rl, hipStream_t s);
+hipError_t launch_factors(PointConsts pc, int64_t slot0, int width, int height, bool cplx,
+                          int64_t kblocks, int mblocks, int nblocks, FactorType ft,
+                          const FactorSet &fs, hipStream_t s);
 
 // a5: split GEMM on MFMA.  See gemm.hip for the tiling.
 struct GemmPlan {
@@ -126,29 +143,28 @@ struct GemmPlan {
     int splits;          // K splits (1 = write the output directly)
     int64_t kblocks;     // K blocks of kblock_points(factor type) points
     int mblocks, nblocks;// line blocks of kFragLines (padded to whole tiles)
-    int alloc_mblocks;   // line blocks the L / R factor arrays hold; a launch whose
-    int alloc_nblocks;   // tiles would read beyond them is refused
     int products;        // 3 = hi*hi + hi*lo + lo*hi, 1 = hi*hi only
 };
-hipError_t launch_gemm(const GemmPlan &plan, FactorType ft, const void *Lh, const void *Ll,
-                       const void *Rh, const void *Rl, int M, int N, float *out, int64_t ldo,
-                       float *partials, bool accumulate, hipStream_t s);
+// Launches whose tiles or K range fall outside the factor set are refused
+// (hipErrorInvalidValue).
+hipError_t launch_gemm(const GemmPlan &plan, FactorType ft, const FactorSet &fs, int M, int N,
+                       float *out, int64_t ldo, float *partials, bool accumulate, hipStream_t s);
 bool gemm_tile_supported(int bm, int bn, int waves_m, int waves_n, int stages);
 
 // a6: one (frame, tile) work item of the persistent batched GEMM.  The
-// factors of all frames sit side by side along K (one [line block][K block]
-// array per factor); an item's K blocks are [kb_begin, kb_begin + kblocks).
+// factors of all frames sit side by side along K in one factor set; an
+// item's K blocks are [kb_begin, kb_begin + kblocks).
 struct BatchItem {
     int64_t kb_begin;
     int64_t kblocks;
     int64_t out_off;   // floats: frame index * height * width
     int32_t tm, tn;    // tile indices
 };
-// plan.kblocks = total K blocks of the factor arrays; grid = persistent
-// workgroups; counter = one int of device memory (reset by the launch).
-hipError_t launch_gemm_batch(const GemmPlan &plan, FactorType ft, const void *Lh, const void *Ll,
-                             const void *Rh, const void *Rl, const BatchItem *items, int n_items,
-                             int *counter, int M, int N, float *out, int grid, hipStream_t s);
+// plan.kblocks = the factor set's K blocks; grid = persistent workgroups;
+// counter = one int of device memory (reset by the launch).
+hipError_t launch_gemm_batch(const GemmPlan &plan, FactorType ft, const FactorSet &fs,
+                             const BatchItem *items, int n_items, int *counter, int M, int N,
+                             float *out, int grid, hipStream_t s);
 // a8: phase-only hologram (Eq. (3)) from the real and imaginary planes.
 hipError_t launch_kinoform(const float *re, const float *im, int64_t n, uint8_t *out,
                            hipStream_t s);

@@ -22,8 +22,10 @@
 // 8 (l / 16) .. + 7, 4 points' (cos, sin) pairs, 16 points a block; in FP32
 // (four v_mfma_f32_16x16x4_f32 per block, see gemm.hip) K-columns
 // 4 (l / 16) .. + 3, 2 points, 8 points a block.  Blocks are ordered
-// [line block][K block], so a GEMM stage copies whole 1 KB blocks straight
-// into LDS.  Lines past the hologram are written as zeros.
+// whole 1 KB units, so a GEMM stage copies whole 1 KB blocks straight
+// into LDS.  Blocks are stored K-major (one slab of every array's line
+// blocks per K block; FactorSet in common.h).  Lines past the hologram are
+// written as zeros.
 #include "common.h"
 
 namespace cgh {
@@ -49,10 +51,7 @@ struct alignas(16) Vec16B {
 template <typename T, bool SPLIT>
 __global__ __launch_bounds__(256) void k_factors(PointConsts pc, int64_t slot0, int64_t kblocks,
                                                  int height, int width, int cplx, int mblocks,
-                                                 Vec16B<T> *__restrict__ Lh,
-                                                 Vec16B<T> *__restrict__ Ll,
-                                                 Vec16B<T> *__restrict__ Rh,
-                                                 Vec16B<T> *__restrict__ Rl)
+                                                 FactorSet fs)
 {
     constexpr int kLanePoints = Vec16B<T>::kValues / 2;      // (cos, sin) pairs per lane
     constexpr int kBlockPoints = 4 * kLanePoints;
@@ -99,57 +98,49 @@ __global__ __launch_bounds__(256) void k_factors(PointConsts pc, int64_t slot0, 
             lo.v[2 * p + 1] = to_t<T>(s - (float)sh);
         }
     }
-    const int64_t idx = ((int64_t)rb * kblocks + kb) * 64 + lane;
-    if (is_l) {
-        Lh[idx] = hi;
-        if (SPLIT)
-            Ll[idx] = lo;
-    } else {
-        Rh[idx] = hi;
-        if (SPLIT)
-            Rl[idx] = lo;
+    Vec16B<T> *out = reinterpret_cast<Vec16B<T> *>(fs.base);
+    const int64_t slab = kb * fs.slab_blocks();
+    const int hi_blk = (is_l ? fs.first_l(false) : fs.first_r(false)) + rb;
+    out[(slab + hi_blk) * 64 + lane] = hi;
+    if (SPLIT) {
+        const int lo_blk = (is_l ? fs.first_l(true) : fs.first_r(true)) + rb;
+        out[(slab + lo_blk) * 64 + lane] = lo;
     }
 }
 
 template <typename T>
 hipError_t launch_t(PointConsts pc, int64_t slot0, int width, int height, int cplx,
-                    int64_t kblocks, int mblocks, int nblocks, void *Lh, void *Ll, void *Rh,
-                    void *Rl, hipStream_t s)
+                    int64_t kblocks, int mblocks, int nblocks, const FactorSet &fs,
+                    hipStream_t s)
 {
     const dim3 grid((unsigned)((kblocks * 64 + 255) / 256), (unsigned)(mblocks + nblocks));
-    typedef Vec16B<T> V;
-    if (Ll != nullptr && sizeof(T) == 2)
+    if (fs.hl == 2)
         hipLaunchKernelGGL((k_factors<T, sizeof(T) == 2>), grid, dim3(256), 0, s, pc, slot0,
-                           kblocks, height, width, cplx, mblocks, (V *)Lh, (V *)Ll, (V *)Rh,
-                           (V *)Rl);
+                           kblocks, height, width, cplx, mblocks, fs);
     else
         hipLaunchKernelGGL((k_factors<T, false>), grid, dim3(256), 0, s, pc, slot0, kblocks,
-                           height, width, cplx, mblocks, (V *)Lh, (V *)nullptr, (V *)Rh,
-                           (V *)nullptr);
+                           height, width, cplx, mblocks, fs);
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_factors(PointConsts pc, int64_t slot0, int64_t n_slots, int width, int height,
-                          bool cplx, int64_t kblocks, int mblocks, int nblocks, FactorType ft,
-                          void *Lh, void *Ll, void *Rh, void *Rl, hipStream_t s)
+hipError_t launch_factors(PointConsts pc, int64_t slot0, int width, int height, bool cplx,
+                          int64_t kblocks, int mblocks, int nblocks, FactorType ft,
+                          const FactorSet &fs, hipStream_t s)
 {
-    (void)n_slots;
     if (kblocks <= 0)
         return hipSuccess;
+    // the written blocks must lie in the set
+    if (fs.base == nullptr || kblocks > fs.kblocks || mblocks > fs.amb || nblocks > fs.anb ||
+        (fs.hl != 1 && fs.hl != 2) || (ft == FactorType::FP32 && fs.hl != 1))
+        return hipErrorInvalidValue;
     const int cx = cplx ? 1 : 0;
     if (ft == FactorType::BF16)
-        return launch_t<__bf16>(pc, slot0, width, height, cx, kblocks, mblocks, nblocks, Lh, Ll,
-                                Rh, Rl, s);
-    if (ft == FactorType::FP32) {
-        if (Ll != nullptr || Rl != nullptr)
-            return hipErrorInvalidValue;    // FP32 factors have no lo half
-        return launch_t<float>(pc, slot0, width, height, cx, kblocks, mblocks, nblocks, Lh,
-                               nullptr, Rh, nullptr, s);
-    }
-    return launch_t<_Float16>(pc, slot0, width, height, cx, kblocks, mblocks, nblocks, Lh, Ll, Rh,
-                              Rl, s);
+        return launch_t<__bf16>(pc, slot0, width, height, cx, kblocks, mblocks, nblocks, fs, s);
+    if (ft == FactorType::FP32)
+        return launch_t<float>(pc, slot0, width, height, cx, kblocks, mblocks, nblocks, fs, s);
+    return launch_t<_Float16>(pc, slot0, width, height, cx, kblocks, mblocks, nblocks, fs, s);
 }
 
 }  // namespace cgh

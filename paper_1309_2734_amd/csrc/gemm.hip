@@ -16,7 +16,9 @@
 //     16 x 16 MFMA blocks, its accumulators in registers;
 //   - one stage = one K block (16 points in bf16/f16, 8 in FP32).  Its operand
 //     blocks (1 KB each, already in MFMA lane order in memory) are copied
-//     straight into LDS with global_load_lds_dwordx4 (no register staging)
+//     straight into LDS with buffer_load_dwordx4 ... lds (no register staging;
+//     a buffer rather than a global load, so the compiler can count the LDS
+//     reads that follow precisely instead of waiting for all of them)
 //     into a ring of STAGES slots, STAGES-1 stages ahead of the MFMAs.  The
 //     copies of a stage are dealt evenly to all waves.  One barrier per
 //     stage; its per-wave vmcnt wait lets later stages' copies stay in flight
@@ -77,13 +79,21 @@ struct Frag<float> {
     }
 };
 
-__device__ __forceinline__ void copy_block_to_lds(const char *gsrc, char *lds_block, int lane)
+// Buffer resource over one K slab of the factor set (loads past it return
+// zeros), raw addressing (word 3 as for gfx9 raw buffers).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t slab_rsrc(const char *slab, int bytes)
 {
-    // Each lane copies its 16 bytes; the hardware writes lane l's data at
-    // lds_block + 16 l.
-    __builtin_amdgcn_global_load_lds(
-        (const __attribute__((address_space(1))) void *)(gsrc + lane * 16),
-        (__attribute__((address_space(3))) void *)lds_block, 16, 0, 0);
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<char *>(slab), (short)0, bytes,
+                                             0x00020000);
+}
+
+// One 1 KB block: lane l copies bytes voff .. voff + 15 (voff includes 16 l)
+// of the buffer to lds_block + 16 l.
+__device__ __forceinline__ void copy_block_to_lds(__amdgpu_buffer_rsrc_t rsrc, uint32_t voff,
+                                                  char *lds_block)
+{
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(
+        rsrc, (__attribute__((address_space(3))) void *)lds_block, 16, voff, 0, 0, 0);
 }
 
 // Wait until at most N of this wave's vector-memory loads are outstanding
@@ -123,16 +133,13 @@ __device__ __forceinline__ void ring_barrier()
 }
 
 // One output tile: line blocks tm (of L) and tn (of R), K blocks
-// [kb_begin, kb_begin + n_st) of matrices whose line blocks are row_bytes
-// apart; the result goes to dst[row * ld + col] for row < M, col < N (added
-// to what is there when acc_old).  All threads of the workgroup call it.
+// [kb_begin, kb_begin + n_st) of the factor set; the result goes to
+// dst[row * ld + col] for row < M, col < N (added to what is there when
+// acc_old).  All threads of the workgroup call it.
 template <int BM, int BN, int WM, int WN, int PRODUCTS, typename T, int STAGES>
-__device__ __forceinline__ void gemm_tile(const char *__restrict__ Lh, const char *__restrict__ Ll,
-                                          const char *__restrict__ Rh,
-                                          const char *__restrict__ Rl, int64_t row_bytes,
-                                          int64_t kb_begin, int64_t n_st, int tm, int tn, int M,
-                                          int N, float *__restrict__ dst, int64_t ld,
-                                          bool acc_old, char *lds)
+__device__ __forceinline__ void gemm_tile(const FactorSet &fs, int64_t kb_begin, int64_t n_st,
+                                          int tm, int tn, int M, int N, float *__restrict__ dst,
+                                          int64_t ld, bool acc_old, char *lds)
 {
     constexpr int NW = WM * WN;
     constexpr int HL = PRODUCTS == 3 ? 2 : 1;
@@ -157,30 +164,28 @@ __device__ __forceinline__ void gemm_tile(const char *__restrict__ Lh, const cha
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int wm = wave / WN, wn = wave % WN;
 
-    // ---- this wave's copies: slot blocks wave, wave + NW, ...
-    const char *csrc[LPS];
+    // ---- this wave's copies: slot blocks wave, wave + NW, ..., as byte
+    // offsets into a K slab of the factor set
+    const int slab_bytes = fs.slab_blocks() * kBlockBytes;
+    const char *slab0 = fs.base + kb_begin * (int64_t)slab_bytes;
+    uint32_t voff[LPS];
 #pragma unroll
     for (int c = 0; c < LPS; ++c) {
         const int b = (wave + NW * c) % SLOT_BLOCKS;   // wrapped entries are not copied
-        const char *base;
-        int64_t line_block;
-        if (b < HL * MB) {
-            base = (HL == 2 && b >= MB) ? Ll : Lh;
-            line_block = (int64_t)tm * MB + (b % MB);
-        } else {
-            const int bb = b - HL * MB;
-            base = (HL == 2 && bb >= NB) ? Rl : Rh;
-            line_block = (int64_t)tn * NB + (bb % NB);
-        }
-        csrc[c] = base + line_block * row_bytes + kb_begin * kBlockBytes;
+        int blk;
+        if (b < HL * MB)
+            blk = fs.first_l(HL == 2 && b >= MB) + tm * MB + b % MB;
+        else
+            blk = fs.first_r(HL == 2 && b - HL * MB >= NB) + tn * NB + (b - HL * MB) % NB;
+        voff[c] = (uint32_t)(blk * kBlockBytes + lane * 16);
     }
     auto issue = [&](int64_t i, int slot) {     // stage i (relative) into ring slot
         char *dst_slot = lds + slot * SLOT_BYTES;
+        const __amdgpu_buffer_rsrc_t rsrc = slab_rsrc(slab0 + i * slab_bytes, slab_bytes);
 #pragma unroll
         for (int c = 0; c < LPS; ++c)
             if (SLOT_BLOCKS % NW == 0 || wave + NW * c < SLOT_BLOCKS)
-                copy_block_to_lds(csrc[c] + i * kBlockBytes,
-                                  dst_slot + (wave + NW * c) * kBlockBytes, lane);
+                copy_block_to_lds(rsrc, voff[c], dst_slot + (wave + NW * c) * kBlockBytes);
     };
 
     f32x4 acc[FM][FN];
@@ -206,42 +211,55 @@ __device__ __forceinline__ void gemm_tile(const char *__restrict__ Lh, const cha
             issue(i + P, slot == 0 ? P : slot - 1);
         const char *sb = lds + slot * SLOT_BYTES + lane * 16;
         auto blk = [&](int b) { return *reinterpret_cast<const frag_t *>(sb + b * kBlockBytes); };
-        frag_t ah[FM], bh[FN];
-#pragma unroll
-        for (int r = 0; r < FM; ++r)
-            ah[r] = blk(wm * FM + r);
+        const int a_hi = wm * FM, a_lo = MB + wm * FM;          // this wave's A blocks
+        const int b_hi = HL * MB + wn * FN, b_lo = HL * MB + NB + wn * FN;
+        // B fragments for the whole stage; A fragments one row block at a
+        // time, the next one read while the current one's MFMAs issue
+        frag_t bh[FN];
+        frag_t a_cur = blk(a_hi);
 #pragma unroll
         for (int c = 0; c < FN; ++c)
-            bh[c] = blk(HL * MB + wn * FN + c);
-        // hi * hi
-#pragma unroll
-        for (int m = 0; m < Frag<T>::kSub; ++m)
-#pragma unroll
-            for (int r = 0; r < FM; ++r)
-#pragma unroll
-                for (int c = 0; c < FN; ++c)
-                    acc[r][c] = Frag<T>::mfma(ah[r], bh[c], acc[r][c], m);
+            bh[c] = blk(b_hi + c);
         if (PRODUCTS == 3) {
             frag_t bl[FN];
 #pragma unroll
             for (int c = 0; c < FN; ++c)
-                bl[c] = blk(HL * MB + NB + wn * FN + c);
-            // hi * lo
+                bl[c] = blk(b_lo + c);
+            // hi * hi and hi * lo, row block by row block
 #pragma unroll
-            for (int r = 0; r < FM; ++r)
+            for (int r = 0; r < FM; ++r) {
+                const frag_t a_nxt = blk(r + 1 < FM ? a_hi + r + 1 : a_lo);
 #pragma unroll
                 for (int c = 0; c < FN; ++c)
-                    acc[r][c] = Frag<T>::mfma(ah[r], bl[c], acc[r][c], 0);
-            frag_t al[FM];
+                    acc[r][c] = Frag<T>::mfma(a_cur, bh[c], acc[r][c], 0);
 #pragma unroll
-            for (int r = 0; r < FM; ++r)
-                al[r] = blk(MB + wm * FM + r);
+                for (int c = 0; c < FN; ++c)
+                    acc[r][c] = Frag<T>::mfma(a_cur, bl[c], acc[r][c], 0);
+                a_cur = a_nxt;
+                __builtin_amdgcn_sched_barrier(0);   // keep the next read ahead of these MFMAs
+            }
             // lo * hi
 #pragma unroll
-            for (int r = 0; r < FM; ++r)
+            for (int r = 0; r < FM; ++r) {
+                const frag_t a_nxt = blk(r + 1 < FM ? a_lo + r + 1 : a_lo);
 #pragma unroll
                 for (int c = 0; c < FN; ++c)
-                    acc[r][c] = Frag<T>::mfma(al[r], bh[c], acc[r][c], 0);
+                    acc[r][c] = Frag<T>::mfma(a_cur, bh[c], acc[r][c], 0);
+                a_cur = a_nxt;
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < FM; ++r) {
+                const frag_t a_nxt = blk(r + 1 < FM ? a_hi + r + 1 : a_hi);
+#pragma unroll
+                for (int m = 0; m < Frag<T>::kSub; ++m)
+#pragma unroll
+                    for (int c = 0; c < FN; ++c)
+                        acc[r][c] = Frag<T>::mfma(a_cur, bh[c], acc[r][c], m);
+                a_cur = a_nxt;
+                __builtin_amdgcn_sched_barrier(0);
+            }
         }
         slot = slot == P ? 0 : slot + 1;
     }
@@ -271,10 +289,9 @@ __device__ __forceinline__ void gemm_tile(const char *__restrict__ Lh, const cha
 // One hologram, split-K: workgroup -> (split, tile).
 template <int BM, int BN, int WM, int WN, int PRODUCTS, typename T, int STAGES>
 __global__ __launch_bounds__(64 * WM * WN, 1) void k_gemm(
-    const char *__restrict__ Lh, const char *__restrict__ Ll, const char *__restrict__ Rh,
-    const char *__restrict__ Rl, int64_t kblocks, int tiles_m, int tiles_n, int splits,
-    int64_t kb_per_split, int M, int N, float *__restrict__ out, int64_t ldo,
-    float *__restrict__ partials, int accumulate)
+    FactorSet fs, int64_t kblocks, int tiles_m, int tiles_n, int splits, int64_t kb_per_split,
+    int M, int N, float *__restrict__ out, int64_t ldo, float *__restrict__ partials,
+    int accumulate)
 {
     extern __shared__ __attribute__((aligned(1024))) char lds[];
     const int total = tiles_m * tiles_n * splits;
@@ -292,9 +309,9 @@ __global__ __launch_bounds__(64 * WM * WN, 1) void k_gemm(
     const int64_t n_st = kb_end > kb_begin ? kb_end - kb_begin : 0;
     float *dst = splits == 1 ? out : partials + (int64_t)split * M * N;
     const int64_t ld = splits == 1 ? ldo : (int64_t)N;
-    gemm_tile<BM, BN, WM, WN, PRODUCTS, T, STAGES>(
-        Lh, Ll, Rh, Rl, kblocks * kBlockBytes, kb_begin, n_st, tile / tiles_n, tile % tiles_n, M,
-        N, dst, ld, splits == 1 && accumulate != 0, lds);
+    gemm_tile<BM, BN, WM, WN, PRODUCTS, T, STAGES>(fs, kb_begin, n_st, tile / tiles_n,
+                                                   tile % tiles_n, M, N, dst, ld,
+                                                   splits == 1 && accumulate != 0, lds);
 }
 
 // Many holograms, persistent: every workgroup takes (frame, tile) items from
@@ -303,9 +320,8 @@ __global__ __launch_bounds__(64 * WM * WN, 1) void k_gemm(
 // largest K first.  The counter starts at 0 (k_reset_counter).
 template <int BM, int BN, int WM, int WN, int PRODUCTS, typename T, int STAGES>
 __global__ __launch_bounds__(64 * WM * WN, 1) void k_gemm_batch(
-    const char *__restrict__ Lh, const char *__restrict__ Ll, const char *__restrict__ Rh,
-    const char *__restrict__ Rl, int64_t total_kblocks, const BatchItem *__restrict__ items,
-    int n_items, int *__restrict__ counter, int M, int N, float *__restrict__ out)
+    FactorSet fs, const BatchItem *__restrict__ items, int n_items, int *__restrict__ counter,
+    int M, int N, float *__restrict__ out)
 {
     extern __shared__ __attribute__((aligned(1024))) char lds[];
     __shared__ int next;
@@ -318,9 +334,8 @@ __global__ __launch_bounds__(64 * WM * WN, 1) void k_gemm_batch(
         if (it >= n_items)
             break;
         const BatchItem w = items[it];
-        gemm_tile<BM, BN, WM, WN, PRODUCTS, T, STAGES>(
-            Lh, Ll, Rh, Rl, total_kblocks * kBlockBytes, w.kb_begin, w.kblocks, w.tm, w.tn, M, N,
-            out + w.out_off, N, false, lds);
+        gemm_tile<BM, BN, WM, WN, PRODUCTS, T, STAGES>(fs, w.kb_begin, w.kblocks, w.tm, w.tn, M,
+                                                       N, out + w.out_off, N, false, lds);
     }
 }
 
@@ -366,15 +381,24 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(const float *__restrict__
     }
 }
 
-template <int BM, int BN, int WM, int WN, int PRODUCTS, typename T, int STAGES>
-hipError_t launch_tile(const GemmPlan &plan, const void *Lh, const void *Ll, const void *Rh,
-                       const void *Rl, int M, int N, float *out, int64_t ldo, float *partials,
-                       bool accumulate, hipStream_t s)
+// The plan's tiles and K range stay inside the factor set, whose halves
+// match the product count.
+bool plan_fits(const GemmPlan &plan, int BM, int BN, int M, int N, const FactorSet &fs)
 {
-    if (plan.mblocks % (BM / kFragLines) != 0 || plan.nblocks % (BN / kFragLines) != 0 ||
-        plan.mblocks > plan.alloc_mblocks || plan.nblocks > plan.alloc_nblocks ||
-        (int64_t)plan.mblocks * kFragLines < M || (int64_t)plan.nblocks * kFragLines < N)
-        return hipErrorInvalidValue;     // tiles would read past the factor arrays
+    return plan.mblocks % (BM / kFragLines) == 0 && plan.nblocks % (BN / kFragLines) == 0 &&
+           plan.mblocks <= fs.amb && plan.nblocks <= fs.anb &&
+           (int64_t)plan.mblocks * kFragLines >= M && (int64_t)plan.nblocks * kFragLines >= N &&
+           plan.kblocks <= fs.kblocks && fs.base != nullptr &&
+           fs.hl == (plan.products == 3 ? 2 : 1) &&
+           (int64_t)fs.slab_blocks() * kBlockBytes < ((int64_t)1 << 31);
+}
+
+template <int BM, int BN, int WM, int WN, int PRODUCTS, typename T, int STAGES>
+hipError_t launch_tile(const GemmPlan &plan, const FactorSet &fs, int M, int N, float *out,
+                       int64_t ldo, float *partials, bool accumulate, hipStream_t s)
+{
+    if (!plan_fits(plan, BM, BN, M, N, fs))
+        return hipErrorInvalidValue;     // tiles would read past the factor set
     constexpr int HL = PRODUCTS == 3 ? 2 : 1;
     const int lds_bytes = STAGES * HL * (BM + BN) / kFragLines * kBlockBytes;
     auto kern = k_gemm<BM, BN, WM, WN, PRODUCTS, T, STAGES>;
@@ -391,22 +415,19 @@ hipError_t launch_tile(const GemmPlan &plan, const void *Lh, const void *Ll, con
     const int64_t per = (plan.kblocks + plan.splits - 1) / plan.splits;
     const int total = tiles_m * tiles_n * plan.splits;
     const int grid = (total + kXcds - 1) / kXcds * kXcds;
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * WM * WN), lds_bytes, s, (const char *)Lh,
-                       (const char *)Ll, (const char *)Rh, (const char *)Rl, plan.kblocks,
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * WM * WN), lds_bytes, s, fs, plan.kblocks,
                        tiles_m, tiles_n, plan.splits, per, M, N, out, ldo, partials,
                        accumulate ? 1 : 0);
     return hipGetLastError();
 }
 
 template <int BM, int BN, int WM, int WN, int PRODUCTS, typename T, int STAGES>
-hipError_t launch_tile_batch(const GemmPlan &plan, const void *Lh, const void *Ll, const void *Rh,
-                             const void *Rl, const BatchItem *items, int n_items, int *counter,
-                             int M, int N, float *out, int grid, hipStream_t s)
+hipError_t launch_tile_batch(const GemmPlan &plan, const FactorSet &fs, const BatchItem *items,
+                             int n_items, int *counter, int M, int N, float *out, int grid,
+                             hipStream_t s)
 {
-    if (plan.mblocks % (BM / kFragLines) != 0 || plan.nblocks % (BN / kFragLines) != 0 ||
-        plan.mblocks > plan.alloc_mblocks || plan.nblocks > plan.alloc_nblocks ||
-        (int64_t)plan.mblocks * kFragLines < M || (int64_t)plan.nblocks * kFragLines < N)
-        return hipErrorInvalidValue;     // tiles would read past the factor arrays
+    if (!plan_fits(plan, BM, BN, M, N, fs))
+        return hipErrorInvalidValue;     // tiles would read past the factor set
     constexpr int HL = PRODUCTS == 3 ? 2 : 1;
     const int lds_bytes = STAGES * HL * (BM + BN) / kFragLines * kBlockBytes;
     auto kern = k_gemm_batch<BM, BN, WM, WN, PRODUCTS, T, STAGES>;
@@ -419,9 +440,8 @@ hipError_t launch_tile_batch(const GemmPlan &plan, const void *Lh, const void *L
         attr = true;
     }
     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, s, counter);
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * WM * WN), lds_bytes, s, (const char *)Lh,
-                       (const char *)Ll, (const char *)Rh, (const char *)Rl, plan.kblocks, items,
-                       n_items, counter, M, N, out);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * WM * WN), lds_bytes, s, fs, items, n_items,
+                       counter, M, N, out);
     return hipGetLastError();
 }
 
@@ -438,32 +458,29 @@ hipError_t launch_tile_batch(const GemmPlan &plan, const void *Lh, const void *L
     X(128, 256, 2, 4, 2)
 
 template <int PRODUCTS, typename T>
-hipError_t launch_products(const GemmPlan &plan, const void *Lh, const void *Ll, const void *Rh,
-                           const void *Rl, int M, int N, float *out, int64_t ldo,
-                           float *partials, bool accumulate, hipStream_t s)
+hipError_t launch_products(const GemmPlan &plan, const FactorSet &fs, int M, int N, float *out,
+                           int64_t ldo, float *partials, bool accumulate, hipStream_t s)
 {
 #define CGH_TILE(TBM, TBN, TWM, TWN, TST)                                                     \
     if (plan.bm == TBM && plan.bn == TBN && plan.waves_m == TWM && plan.waves_n == TWN &&     \
         plan.stages == TST)                                                                   \
-        return launch_tile<TBM, TBN, TWM, TWN, PRODUCTS, T, TST>(plan, Lh, Ll, Rh, Rl, M, N,  \
-                                                                 out, ldo, partials,          \
-                                                                 accumulate, s);
+        return launch_tile<TBM, TBN, TWM, TWN, PRODUCTS, T, TST>(plan, fs, M, N, out, ldo,    \
+                                                                 partials, accumulate, s);
     CGH_GEMM_SHAPES(CGH_TILE)
 #undef CGH_TILE
     return hipErrorInvalidValue;
 }
 
 template <int PRODUCTS, typename T>
-hipError_t launch_products_batch(const GemmPlan &plan, const void *Lh, const void *Ll,
-                                 const void *Rh, const void *Rl, const BatchItem *items,
-                                 int n_items, int *counter, int M, int N, float *out, int grid,
-                                 hipStream_t s)
+hipError_t launch_products_batch(const GemmPlan &plan, const FactorSet &fs,
+                                 const BatchItem *items, int n_items, int *counter, int M, int N,
+                                 float *out, int grid, hipStream_t s)
 {
 #define CGH_TILE(TBM, TBN, TWM, TWN, TST)                                                     \
     if (plan.bm == TBM && plan.bn == TBN && plan.waves_m == TWM && plan.waves_n == TWN &&     \
         plan.stages == TST)                                                                   \
         return launch_tile_batch<TBM, TBN, TWM, TWN, PRODUCTS, T, TST>(                       \
-            plan, Lh, Ll, Rh, Rl, items, n_items, counter, M, N, out, grid, s);
+            plan, fs, items, n_items, counter, M, N, out, grid, s);
     CGH_GEMM_SHAPES(CGH_TILE)
 #undef CGH_TILE
     return hipErrorInvalidValue;
@@ -471,27 +488,26 @@ hipError_t launch_products_batch(const GemmPlan &plan, const void *Lh, const voi
 
 }  // namespace
 
-hipError_t launch_gemm_batch(const GemmPlan &plan, FactorType ft, const void *Lh, const void *Ll,
-                             const void *Rh, const void *Rl, const BatchItem *items, int n_items,
-                             int *counter, int M, int N, float *out, int grid, hipStream_t s)
+hipError_t launch_gemm_batch(const GemmPlan &plan, FactorType ft, const FactorSet &fs,
+                             const BatchItem *items, int n_items, int *counter, int M, int N,
+                             float *out, int grid, hipStream_t s)
 {
     if (ft == FactorType::FP32)
-        return plan.products == 1 ? launch_products_batch<1, float>(plan, Lh, nullptr, Rh,
-                                                                    nullptr, items, n_items,
+        return plan.products == 1 ? launch_products_batch<1, float>(plan, fs, items, n_items,
                                                                     counter, M, N, out, grid, s)
                                   : hipErrorInvalidValue;
     if (plan.products == 3) {
         if (ft == FactorType::BF16)
-            return launch_products_batch<3, __bf16>(plan, Lh, Ll, Rh, Rl, items, n_items, counter,
-                                                    M, N, out, grid, s);
-        return launch_products_batch<3, _Float16>(plan, Lh, Ll, Rh, Rl, items, n_items, counter,
-                                                  M, N, out, grid, s);
+            return launch_products_batch<3, __bf16>(plan, fs, items, n_items, counter, M, N, out,
+                                                    grid, s);
+        return launch_products_batch<3, _Float16>(plan, fs, items, n_items, counter, M, N, out,
+                                                  grid, s);
     }
     if (ft == FactorType::BF16)
-        return launch_products_batch<1, __bf16>(plan, Lh, Ll, Rh, Rl, items, n_items, counter, M,
-                                                N, out, grid, s);
-    return launch_products_batch<1, _Float16>(plan, Lh, Ll, Rh, Rl, items, n_items, counter, M,
-                                              N, out, grid, s);
+        return launch_products_batch<1, __bf16>(plan, fs, items, n_items, counter, M, N, out,
+                                                grid, s);
+    return launch_products_batch<1, _Float16>(plan, fs, items, n_items, counter, M, N, out, grid,
+                                              s);
 }
 
 bool gemm_tile_supported(int bm, int bn, int waves_m, int waves_n, int stages)
@@ -504,27 +520,21 @@ bool gemm_tile_supported(int bm, int bn, int waves_m, int waves_n, int stages)
     return false;
 }
 
-hipError_t launch_gemm(const GemmPlan &plan, FactorType ft, const void *Lh, const void *Ll,
-                       const void *Rh, const void *Rl, int M, int N, float *out, int64_t ldo,
-                       float *partials, bool accumulate, hipStream_t s)
+hipError_t launch_gemm(const GemmPlan &plan, FactorType ft, const FactorSet &fs, int M, int N,
+                       float *out, int64_t ldo, float *partials, bool accumulate, hipStream_t s)
 {
     if (ft == FactorType::FP32)
-        return plan.products == 1 ? launch_products<1, float>(plan, Lh, nullptr, Rh, nullptr, M,
-                                                              N, out, ldo, partials, accumulate,
-                                                              s)
+        return plan.products == 1 ? launch_products<1, float>(plan, fs, M, N, out, ldo, partials,
+                                                              accumulate, s)
                                   : hipErrorInvalidValue;
     if (plan.products == 3) {
         if (ft == FactorType::BF16)
-            return launch_products<3, __bf16>(plan, Lh, Ll, Rh, Rl, M, N, out, ldo, partials,
-                                              accumulate, s);
-        return launch_products<3, _Float16>(plan, Lh, Ll, Rh, Rl, M, N, out, ldo, partials,
-                                            accumulate, s);
+            return launch_products<3, __bf16>(plan, fs, M, N, out, ldo, partials, accumulate, s);
+        return launch_products<3, _Float16>(plan, fs, M, N, out, ldo, partials, accumulate, s);
     }
     if (ft == FactorType::BF16)
-        return launch_products<1, __bf16>(plan, Lh, Ll, Rh, Rl, M, N, out, ldo, partials,
-                                          accumulate, s);
-    return launch_products<1, _Float16>(plan, Lh, Ll, Rh, Rl, M, N, out, ldo, partials,
-                                        accumulate, s);
+        return launch_products<1, __bf16>(plan, fs, M, N, out, ldo, partials, accumulate, s);
+    return launch_products<1, _Float16>(plan, fs, M, N, out, ldo, partials, accumulate, s);
 }
 
 hipError_t launch_splitk_reduce(const float *partials, int splits, int M, int N, float *out,
