@@ -66,38 +66,38 @@ GEMM_PEAK = {"split_bf16": PEAK_MFMA_BF16_TFLOPS, "split_fp16": PEAK_MFMA_FP16_T
 MODE_DTYPE = {"split_bf16": "bf16", "split_fp16": "f16", "fp16": "f16", "direct_fp32": "f32",
               "separable_fp32": "f32", "spherical_fp32": "f32"}
 
-# HBM bytes per launch from two rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE)
-# on this workload, each scaled by what the counter reads for a plain device
-# copy of 256 MiB (FETCH_SIZE reads 128 MiB: x2.0; WRITE_SIZE 256 MiB: x1.0);
-# see profiles/.  Valid only for the kernel source they were taken on (the
-# sha256 prefix of the file) and that launch shape; otherwise reported null.
-TRAFFIC = {
-    "gemm_split_mfma": {"src": "paper_1309_2734_amd/csrc/gemm.hip", "sha": "04513c51f4aeeff7",
-                        "plan": "384,192,4,2,2,8", "bytes": (117.5 * 2.0 + 63.3) * 2 ** 20},
-    "direct_fp32": {"src": "paper_1309_2734_amd/csrc/direct.hip", "sha": "c3651537e2728bc9",
-                    "plan": "rows=16", "bytes": (463.2 * 2.0 + 7.9) * 2 ** 20},
-}
+# HBM bytes per launch from two rocprofv3 --pmc passes (FETCH_SIZE, then
+# WRITE_SIZE, KiB per dispatch) over `python bench.py --traffic-driver`, each
+# scaled by what the counter reads for a plain 256 MiB device copy (FETCH_SIZE
+# reads half the true bytes: x2.0; WRITE_SIZE the true bytes: x1.0); see
+# profiles/.  An entry holds for the kernel source it was taken on (sha256
+# prefix) and its launch shape; otherwise the bench reports traffic null.
+TRAFFIC_SCALE = {"fetch": 2.0, "write": 1.0}
+TRAFFIC = [
+]
+TRAFFIC_PLANS = {"gemm_split_mfma": ["384,192,4,2,2,8", "192,384,2,4,2,8"],
+                 "direct_fp32": ["8", "16"]}
+
+
+def _plan_in_tuned(kernel: str, plan: str, tuned) -> bool:
+    if kernel.startswith("direct"):
+        return (tuned is None and plan == "16") or bool(tuned and f"rows={plan} " in tuned)
+    bm, bn, wm, wn, st, sp = plan.split(",")
+    return bool(tuned and f"bm={bm} bn={bn} waves={wm}x{wn} stages={st} splits={sp}" in tuned)
 
 
 def traffic_bytes(kernel: str, tuned):
     """Measured HBM bytes per launch, or None if the kernel or shape changed."""
     import hashlib
-    t = TRAFFIC.get(kernel)
-    if t is None:
-        return None
-    with open(os.path.join(ROOT, t["src"]), "rb") as f:
-        if hashlib.sha256(f.read()).hexdigest()[:16] != t["sha"]:
-            return None
-    if t["plan"].startswith("rows="):
-        want = t["plan"] + " "                  # direct kernel: rows per lane
-        if not (tuned is None and t["plan"] == "rows=16") and (not tuned or want not in tuned):
-            return None
-    else:
-        bm, bn, wm, wn, st, sp = t["plan"].split(",")
-        want = f"bm={bm} bn={bn} waves={wm}x{wn} stages={st} splits={sp}"
-        if not tuned or want not in tuned:
-            return None
-    return t["bytes"]
+    for t in TRAFFIC:
+        if t["kernel"] != kernel or not _plan_in_tuned(kernel, t["plan"], tuned):
+            continue
+        with open(os.path.join(ROOT, t["src"]), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest()[:16] != t["sha"]:
+                return None
+        return (t["fetch_kib"] * TRAFFIC_SCALE["fetch"] +
+                t["write_kib"] * TRAFFIC_SCALE["write"]) * 1024.0
+    return None
 
 
 def log(*a):
@@ -213,17 +213,28 @@ def bench_kinoform(args, torch, cghgen, cgh, check: bool):
 
 def traffic_driver(torch, cghgen, cgh) -> int:
     """Kernel sequence for `rocprofv3 --pmc FETCH_SIZE|WRITE_SIZE -- python bench.py
-    --traffic-driver`: the per-launch counters of the GEMM and direct kernels, and of a
-    plain 256 MiB device copy whose true byte counts calibrate them."""
-    os.environ["CGH_GEMM_PLAN"] = TRAFFIC["gemm_split_mfma"]["plan"]
+    --traffic-driver`: the per-launch counters of the split-BF16 GEMM in each recorded
+    launch shape (3 computes each), of the direct kernel at each recorded row count
+    (2 computes each), and of a plain 256 MiB device copy (3 copies) whose true byte
+    counts calibrate them."""
     c = cghgen.make_config(2)
     ctx = cgh.Context(c.width, c.height, c.pitch, c.wavelength)
     ctx.upload_cloud(c)
     out = torch.empty((c.height, c.width), device="cuda:0")
-    for _ in range(3):
-        ctx.compute(out, cgh.SPLIT_BF16)
-    for _ in range(2):
-        ctx.compute(out, cgh.DIRECT_FP32)
+    for plan in TRAFFIC_PLANS["gemm_split_mfma"]:
+        os.environ["CGH_GEMM_PLAN"] = plan
+        for _ in range(3):
+            ctx.compute(out, cgh.SPLIT_BF16)
+        torch.cuda.synchronize()
+        log(f"traffic driver: split_bf16 plan {plan}")
+    os.environ.pop("CGH_GEMM_PLAN", None)
+    for rows in TRAFFIC_PLANS["direct_fp32"]:
+        os.environ["CGH_DIRECT_ROWS"] = rows
+        for _ in range(2):
+            ctx.compute(out, cgh.DIRECT_FP32)
+        torch.cuda.synchronize()
+        log(f"traffic driver: direct rows {rows}")
+    os.environ.pop("CGH_DIRECT_ROWS", None)
     src = torch.ones(64 << 20, device="cuda:0")       # 256 MiB of float32
     dst = torch.empty_like(src)
     for _ in range(3):
@@ -252,8 +263,9 @@ def main() -> int:
                     help="frames of the batched-workload side measurement (0 = skip)")
     ap.add_argument("--traffic-driver", action="store_true",
                     help="run only the fixed kernel sequence the HBM-traffic counter passes "
-                         "read (3 split-BF16 computes with the recorded GEMM shape, 2 direct "
-                         "computes, 3 device copies of 256 MiB for calibration), then exit")
+                         "read (split-BF16 computes in each recorded GEMM shape, direct "
+                         "computes at each recorded row count, 3 device copies of 256 MiB "
+                         "for calibration), then exit")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:

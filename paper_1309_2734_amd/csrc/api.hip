@@ -363,6 +363,21 @@ ModeInfo mode_info(int mode)
 }
 
 // ---------------------------------------------------------------- planning
+// GEMM launch shapes the tuner tries: (BM, BN, waves along M, waves along N,
+// LDS ring depth); each must be built in gemm.hip.
+const int kShapes[][5] = {{192, 384, 2, 4, 2}, {384, 192, 4, 2, 2}, {192, 256, 2, 4, 2},
+                          {256, 256, 2, 4, 2}, {192, 192, 2, 2, 3}, {192, 192, 2, 4, 3},
+                          {128, 256, 2, 4, 2}};
+
+// Lines padded to whole tiles of every shape (factor sets are sized for any
+// of them).
+int64_t pad_all_shapes(int64_t lines, bool rows)
+{
+    int64_t p = lines;
+    for (auto &sh : kShapes)
+        p = std::max(p, round_up(lines, rows ? sh[0] : sh[1]));
+    return p;
+}
 struct Plan {
     GemmPlan g;
     int tiles_m = 0, tiles_n = 0;
@@ -517,8 +532,15 @@ cgh_status run_direct(cgh_ctx *c, int mode, const FrameDesc *fd_dev, int n_frame
     if (st != CGH_OK)
         return st;
     const bool sph = mode == CGH_SPHERICAL_FP32;
+    // rows per lane: CGH_DIRECT_ROWS (4, 8 or 16; used to sweep), else the
+    // tuned choice, else the default
     const TuneEntry *t = find_tuned(c, tune_key(c, mode, 0, c->height));
-    const int rows = t && direct_rows_ok(mode, t->rows) ? t->rows : (sph ? 8 : 16);
+    int rows = t && direct_rows_ok(mode, t->rows) ? t->rows : (sph ? 8 : 16);
+    if (const char *env = std::getenv("CGH_DIRECT_ROWS")) {
+        const int r = std::atoi(env);
+        if (direct_rows_ok(mode, r))
+            rows = r;
+    }
     const char *name = sph ? (out_im ? "direct_sphere_complex" : "direct_sphere")
                            : (out_im ? "direct_fp32_complex" : "direct_fp32");
     Bracket br(c, name, s);
@@ -579,8 +601,8 @@ size_t bytes_per_slot(cgh_ctx *c, int mode, bool cplx)
     if (is_direct(mode))
         return (size_t)(c->wpad + c->hpad) * sizeof(float) * (mode == CGH_SPHERICAL_FP32 ? 2 : 1);
     const int64_t m = cplx ? 2 * (int64_t)c->height : c->height;
-    const int64_t w = std::max(round_up(c->width, 384), round_up(c->width, 256));
-    const int64_t h = std::max(round_up(m, 384), round_up(m, 256));
+    const int64_t w = pad_all_shapes(c->width, false);
+    const int64_t h = pad_all_shapes(m, true);
     return (size_t)(w + h) * mode_info(mode).line_bytes();
 }
 
@@ -1253,10 +1275,7 @@ cgh_status cgh_tune(cgh_ctx *c, cgh_mode mode, int32_t repeats, char *report, in
         const int hl = mi.hl;
         const int64_t kblocks = slots / mi.kbp;
         best.key = tune_key(c, mode, kblocks, c->height);
-        static const int shapes[][5] = {{192, 384, 2, 4, 2}, {384, 192, 4, 2, 2},
-                                        {192, 256, 2, 4, 2}, {256, 256, 2, 4, 2},
-                                        {192, 192, 2, 2, 3}, {192, 192, 2, 4, 3},
-                                        {128, 256, 2, 4, 2}};
+        const auto &shapes = kShapes;
         // factors padded to whole tiles of every candidate shape
         int mb = 0, nb = 0;
         for (auto &sh : shapes) {
