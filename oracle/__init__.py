@@ -3,7 +3,8 @@
 TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the benchmark's
 CPU-baseline leg use it; the GPU library never does, and this package never
 imports the GPU library.  See cgh_oracle.c for what is computed and which
-equations of the paper it follows (Section 2.1, Eq. (1), (2), (5)).
+equations of the paper it follows (Section 2.1, Eq. (1), (2), (5); Section
+2.3, Eq. (10) for the Fresnel diffraction of a sampled field).
 
 Inputs are the float32 values handed to the GPU library, widened exactly to
 float64, so input rounding is not counted as error.
@@ -49,6 +50,10 @@ def _load():
             fn.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
                            ctypes.c_int64, dp, dp, dp, dp, ctypes.c_int64, ip, ctypes.c_int64, ip,
                            dp, dp, ctypes.c_int32]
+        fn = lib.cgh_oracle_diffraction
+        fn.restype = ctypes.c_int
+        fn.argtypes = [ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_double, dp, dp,
+                       ctypes.c_int64, ip, dp, dp, ctypes.c_int32]
         _lib = lib
     return _lib
 
@@ -126,6 +131,51 @@ def cloud_fresnel(cloud, cols=None, rows=None, threads: Optional[int] = None) ->
     """fresnel() for a cghgen.Cloud."""
     return fresnel(cloud.width, cloud.height, cloud.pitch, cloud.wavelength,
                    cloud.x, cloud.y, cloud.z, cloud.amp, cols, rows, threads)
+
+
+def diffraction(u: np.ndarray, pitch: float, wavelength: float, z: float, rows=None,
+                threads: Optional[int] = None) -> np.ndarray:
+    """Eq. (10) by direct summation (cgh_oracle.c): the n x n complex field u
+    propagated by z, read on the same grid; complex128 [len(rows), n]."""
+    lib = _load()
+    u = np.asarray(u)
+    n = u.shape[0]
+    if u.shape != (n, n):
+        raise ValueError("u must be n x n")
+    ur = np.ascontiguousarray(u.real, dtype=np.float64)
+    ui = np.ascontiguousarray(u.imag, dtype=np.float64)
+    r32 = np.ascontiguousarray(np.arange(n, dtype=np.int32) if rows is None
+                               else np.asarray(rows, dtype=np.int32))
+    re = np.zeros((r32.shape[0], n), dtype=np.float64)
+    im = np.zeros_like(re)
+    rc = lib.cgh_oracle_diffraction(int(n), float(pitch), float(wavelength), float(z), _dp(ur),
+                                    _dp(ui), r32.shape[0], _ip(r32), _dp(re), _dp(im),
+                                    int(threads or host_threads()))
+    if rc != 0:
+        raise RuntimeError(f"cgh_oracle_diffraction failed with code {rc}")
+    return re + 1j * im
+
+
+def diffraction_fft(u: np.ndarray, pitch: float, wavelength: float, z: float) -> np.ndarray:
+    """Eq. (10) in its Fourier form: the field zero-padded to 2n x 2n, the
+    impulse response h = exp(i pi (x^2 + y^2) / (lambda z)) sampled at the
+    offsets -n .. n-1 in circular order, F^-1[F[u] F[h]] cropped to n x n, times
+    exp(i 2 pi z / lambda) / (i lambda z) and the sample area p^2.  numpy FFTs
+    in FP64 (Section 2.3)."""
+    u = np.asarray(u, dtype=np.complex128)
+    n = u.shape[0]
+    m = 2 * n
+    d = np.arange(m, dtype=np.float64)
+    d = np.where(d < n, d, d - m)                       # circular offsets
+    rev = np.fmod(d * d * (pitch * pitch / (2.0 * wavelength * z)), 1.0)
+    h1 = np.exp(2j * np.pi * rev)                       # separable: h = h1 (x) h1
+    up = np.zeros((m, m), dtype=np.complex128)
+    up[:n, :n] = u
+    spec = np.fft.fft2(up) * np.outer(np.fft.fft(h1), np.fft.fft(h1))
+    o = np.fft.ifft2(spec)[:n, :n]
+    zrev = np.fmod(z / wavelength, 1.0)
+    pref = np.exp(2j * np.pi * zrev) / (1j * wavelength * z) * pitch * pitch
+    return o * pref
 
 
 def kinoform(re: np.ndarray, im: np.ndarray) -> np.ndarray:

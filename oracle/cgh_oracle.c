@@ -161,3 +161,117 @@ int cgh_oracle_spherical(int32_t width, int32_t height, double pitch, double wav
     return run(width, height, pitch, wavelength, n_points, x, y, z, a, n_cols, cols, n_rows,
                rows, out_re, out_im, n_threads, 1);
 }
+
+
+/* ------------------------------------------------------------------------
+ * Fresnel diffraction of a sampled field, Eq. (10) (Section 2.3, the second
+ * step of the wavefront-recording method): the field u on an n x n grid of
+ * pitch p at distance z from the hologram plane propagates to
+ *
+ *   O(x_h, y_h) = exp(i 2 pi z / lambda) / (i lambda z)
+ *                 * integral u(x_w, y_w) exp(i pi / (lambda z) ((x_h - x_w)^2 + (y_h - y_w)^2)) dx_w dy_w,
+ *
+ * read on the same n x n grid, the integral taken as the sum over the samples
+ * times the sample area p^2:
+ *
+ *   O[m][c] = exp(i 2 pi z / lambda) / (i lambda z) * p^2
+ *             * sum_k sum_l u[k][l] exp(i pi p^2 ((m - k)^2 + (c - l)^2) / (lambda z)).
+ *
+ * A plain quadruple loop (output rows of the evaluation set x columns x
+ * input rows x input columns), FP64, libm cos/sin, sequential sums.  The
+ * phase is evaluated in revolutions, ((m-k)^2 + (c-l)^2) p^2 / (2 lambda z),
+ * and z / lambda likewise (one FP64 rounding each, relative 1e-16), and
+ * reduced with fmod (exact) before the trigonometric call.
+ */
+typedef struct {
+    int32_t n;
+    double pitch, wavelength, z;
+    const double *u_re, *u_im;
+    const int32_t *rows;
+    double *out_re, *out_im;
+    int64_t row_begin, row_end;
+} diff_job_t;
+
+static void *diff_worker(void *arg)
+{
+    const diff_job_t *jb = (const diff_job_t *)arg;
+    const double two_pi = 6.28318530717958647692;
+    const int32_t n = jb->n;
+    const double q = jb->pitch * jb->pitch / (2.0 * jb->wavelength * jb->z);   /* rev per px^2 */
+    for (int64_t r = jb->row_begin; r < jb->row_end; ++r) {
+        const int32_t m = jb->rows[r];
+        for (int32_t c = 0; c < n; ++c) {
+            double re = 0.0, im = 0.0;
+            for (int32_t k = 0; k < n; ++k) {
+                const double dm = (double)(m - k);
+                for (int32_t l = 0; l < n; ++l) {
+                    const double dc = (double)(c - l);
+                    const double rev = fmod(q * (dm * dm + dc * dc), 1.0);
+                    const double hr = cos(two_pi * rev), hi = sin(two_pi * rev);
+                    const double ur = jb->u_re[(int64_t)k * n + l];
+                    const double ui = jb->u_im[(int64_t)k * n + l];
+                    re += ur * hr - ui * hi;
+                    im += ur * hi + ui * hr;
+                }
+            }
+            /* prefactor exp(i 2 pi z / lambda) / (i lambda z) * p^2 */
+            const double zrev = fmod(jb->z / jb->wavelength, 1.0);
+            const double er = cos(two_pi * zrev), ei = sin(two_pi * zrev);
+            const double s = jb->pitch * jb->pitch / (jb->wavelength * jb->z);
+            /* (er + i ei) * (-i) * s = s (ei - i er) */
+            const double pr = s * ei, pi_ = -s * er;
+            jb->out_re[r * n + c] = re * pr - im * pi_;
+            jb->out_im[r * n + c] = re * pi_ + im * pr;
+        }
+    }
+    return NULL;
+}
+
+/* Eq. (10) by direct summation for output rows rows[0 .. n_rows) (all n
+ * columns each).  u_re, u_im: n x n row-major; out_re, out_im: n_rows x n.
+ * Returns 0 on success. */
+int cgh_oracle_diffraction(int32_t n, double pitch, double wavelength, double z,
+                           const double *u_re, const double *u_im, int64_t n_rows,
+                           const int32_t *rows, double *out_re, double *out_im,
+                           int32_t n_threads)
+{
+    if (n <= 0 || n_rows < 0 || !(pitch > 0.0) || !(wavelength > 0.0) || !(z != 0.0))
+        return 1;
+    if (!u_re || !u_im || !out_re || !out_im || (n_rows > 0 && !rows))
+        return 1;
+    if (n_threads < 1)
+        n_threads = 1;
+    if (n_threads > n_rows)
+        n_threads = n_rows > 0 ? (int32_t)n_rows : 1;
+    diff_job_t *jobs = (diff_job_t *)calloc((size_t)n_threads, sizeof(diff_job_t));
+    pthread_t *tids = (pthread_t *)calloc((size_t)n_threads, sizeof(pthread_t));
+    if (!jobs || !tids) {
+        free(jobs);
+        free(tids);
+        return 2;
+    }
+    for (int32_t t = 0; t < n_threads; ++t) {
+        diff_job_t *jb = &jobs[t];
+        jb->n = n; jb->pitch = pitch; jb->wavelength = wavelength; jb->z = z;
+        jb->u_re = u_re; jb->u_im = u_im; jb->rows = rows;
+        jb->out_re = out_re; jb->out_im = out_im;
+        jb->row_begin = n_rows * t / n_threads;
+        jb->row_end = n_rows * (t + 1) / n_threads;
+    }
+    int rc = 0;
+    int32_t started = 0;
+    for (int32_t t = 1; t < n_threads; ++t) {
+        if (pthread_create(&tids[t], NULL, diff_worker, &jobs[t]) != 0) {
+            rc = 3;
+            break;
+        }
+        started = t;
+    }
+    if (rc == 0)
+        diff_worker(&jobs[0]);
+    for (int32_t t = 1; t <= started; ++t)
+        pthread_join(tids[t], NULL);
+    free(jobs);
+    free(tids);
+    return rc;
+}

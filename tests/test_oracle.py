@@ -297,3 +297,67 @@ def test_nrms_and_max_err_definitions():
     assert oracle.nrms(ref, ref) == 0.0
     assert abs(oracle.nrms(ref + np.array([0.3, 0.4]), ref) - 0.1) < 1e-15
     assert abs(oracle.max_err(ref + np.array([0.0, 0.5]), ref) - 0.5 / math.sqrt(12.5)) < 1e-15
+
+
+# ---------------------------------------------------------------- Eq. (10)
+# Fresnel diffraction of a sampled field (Section 2.3): direct summation and
+# the Fourier form of the same equation.
+def _field(n, seed):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+
+
+def test_diffraction_of_one_sample_is_the_scaled_impulse_response():
+    """u = a at (k0, l0), zero elsewhere: Eq. (10) reduces to the prefactor
+    exp(i 2 pi z / lambda) / (i lambda z) p^2 times a exp(i pi p^2 ((m-k0)^2 +
+    (c-l0)^2) / (lambda z)) at every output sample."""
+    n, k0, l0, a = 12, 3, 8, 0.7 - 0.2j
+    p, lam, z = 10e-6, 633e-9, 0.03
+    u = np.zeros((n, n), dtype=np.complex128)
+    u[k0, l0] = a
+    got = oracle.diffraction(u, p, lam, z)
+    m = np.arange(n)[:, None]
+    c = np.arange(n)[None, :]
+    h = np.exp(1j * np.pi * p * p * ((m - k0) ** 2 + (c - l0) ** 2) / (lam * z))
+    # z / lambda is ~47,000 revolutions: its phase is taken to 40 digits
+    with mpmath.workdps(40):
+        ph = mpmath.mpf(2) * mpmath.pi * mpmath.mpf(z) / mpmath.mpf(lam)
+        e = complex(mpmath.cos(ph), mpmath.sin(ph))
+    pref = e / (1j * lam * z) * p * p
+    want = pref * a * h
+    # the oracle's FP64 z / lambda carries ~4e-12 revolution of rounding
+    tol = 1e-10 * np.max(np.abs(want))
+    assert np.max(np.abs(got - want)) <= tol
+    # and the Fourier form agrees
+    assert np.max(np.abs(oracle.diffraction_fft(u, p, lam, z) - want)) <= tol
+
+
+@pytest.mark.parametrize("n", [5, 8, 16, 33])
+def test_diffraction_direct_sum_equals_fourier_form(n):
+    """The two lines of Eq. (10): the direct sum and F^-1[F[u] F[h]] on the
+    2n-padded grid, cropped, agree to rounding for any field (odd n too)."""
+    u = _field(n, n)
+    for p, lam, z in ((8e-6, 532e-9, 0.02), (4e-6, 473e-9, -0.05)):
+        a = oracle.diffraction(u, p, lam, z)
+        b = oracle.diffraction_fft(u, p, lam, z)
+        assert np.max(np.abs(a - b)) <= 1e-12 * np.max(np.abs(a))
+
+
+def test_diffraction_conjugate_and_linearity():
+    """Propagating conj(u) by -z gives conj of propagating u by z (h and the
+    prefactor conjugate with z); the map is linear."""
+    n, p, lam, z = 10, 8e-6, 532e-9, 0.015
+    u, v = _field(n, 1), _field(n, 2)
+    a = oracle.diffraction(u, p, lam, z)
+    assert np.max(np.abs(oracle.diffraction(np.conj(u), p, lam, -z) - np.conj(a))) <= 1e-12 * np.max(np.abs(a))
+    b = oracle.diffraction(v, p, lam, z)
+    ab = oracle.diffraction(2.0 * u - 0.5j * v, p, lam, z)
+    assert np.max(np.abs(ab - (2.0 * a - 0.5j * b))) <= 1e-12 * np.max(np.abs(ab))
+
+
+def test_diffraction_row_subset_is_consistent():
+    n = 16
+    u = _field(n, 3)
+    full = oracle.diffraction(u, 8e-6, 532e-9, 0.02, threads=1)
+    sub = oracle.diffraction(u, 8e-6, 532e-9, 0.02, rows=[15, 0, 7], threads=3)
+    assert np.array_equal(sub, full[[15, 0, 7]])
