@@ -206,6 +206,40 @@ CGH_API cgh_status cgh_batch_compute(cgh_ctx *c, const cgh_frame *frames, int32_
 CGH_API cgh_status cgh_tune(cgh_ctx *c, cgh_mode mode, int32_t repeats, char *report,
                             int32_t report_len, void *stream);
 
+/* ---------------------------------------------------------------------
+ * Fresnel diffraction of a sampled field (Section 2.3, Eq. (10)): the second
+ * step of the wavefront-recording method, a field u on an n x n grid of pitch
+ * p at distance z from the hologram propagated to the hologram plane and read
+ * on the same grid,
+ *   O[m][c] = exp(i 2 pi z / lambda) / (i lambda z) p^2
+ *             sum_k sum_l u[k][l] exp(i pi p^2 ((m-k)^2 + (c-l)^2) / (lambda z)),
+ * the integral of Eq. (10) taken as a sum over the samples times the sample
+ * area.  Evaluated, as the equation's second line writes it, with FFTs on the
+ * grid zero-padded to 2n x 2n (no wrap-around) and cropped to n x n; FP32
+ * transforms with FP64-reduced chirp phases and twiddles.
+ * --------------------------------------------------------------------- */
+typedef struct cgh_fresnel cgh_fresnel;
+
+/* Plan for n x n fields: n a power of two in [16, 8192]; pitch_m and
+ * wavelength_m finite and > 0; z_m finite and non-zero (negative z
+ * propagates backwards); device as for cgh_create.  Allocates 32 n^2 + 16 n
+ * bytes of device workspace and computes the transform of the impulse
+ * response (blocks until done).
+ * Errors: CGH_EINVAL, CGH_EDEVICE, CGH_ENOMEM.  Free with cgh_fresnel_destroy. */
+CGH_API cgh_status cgh_fresnel_create(cgh_fresnel **out, int32_t n, double pitch_m,
+                                      double wavelength_m, double z_m, int32_t device);
+
+/* Propagate u_dev to out_dev, both device buffers of n*n complex values
+ * stored as interleaved float pairs (re, im), row-major; caller-owned; they
+ * may be the same buffer.  Ordered on `stream`.  Calls on one plan must not
+ * overlap (they share its workspace).
+ * Errors: CGH_EINVAL (NULL plan or buffer), CGH_EDEVICE (launch failure). */
+CGH_API cgh_status cgh_fresnel_run(cgh_fresnel *f, const float *u_dev, float *out_dev,
+                                   void *stream);
+
+/* Free the plan (synchronises its device first).  NULL-safe. */
+CGH_API void cgh_fresnel_destroy(cgh_fresnel *f);
+
 /* Free the context and all its device memory (synchronises the device it
  * used first).  NULL-safe. */
 CGH_API void cgh_destroy(cgh_ctx *c);

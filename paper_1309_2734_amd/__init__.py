@@ -44,7 +44,8 @@ MEM_DEVICE = 1
 
 # every symbol include/cgh.h declares
 EXPORTS = ("cgh_create", "cgh_points_upload", "cgh_compute", "cgh_compute_complex",
-           "cgh_kinoform", "cgh_batch_compute", "cgh_tune", "cgh_destroy", "cgh_strerror", "cgh_last_error", "cgh_profile_enable",
+           "cgh_kinoform", "cgh_batch_compute", "cgh_tune", "cgh_fresnel_create",
+           "cgh_fresnel_run", "cgh_fresnel_destroy", "cgh_destroy", "cgh_strerror", "cgh_last_error", "cgh_profile_enable",
            "cgh_profile_reset", "cgh_profile_read", "cgh_version")
 
 
@@ -104,6 +105,12 @@ def lib() -> ctypes.CDLL:
     L.cgh_profile_read.restype = st
     L.cgh_version.argtypes = []
     L.cgh_version.restype = i32
+    L.cgh_fresnel_create.argtypes = [ctypes.POINTER(vp), i32, dbl, dbl, dbl, i32]
+    L.cgh_fresnel_create.restype = st
+    L.cgh_fresnel_run.argtypes = [vp, vp, vp, vp]
+    L.cgh_fresnel_run.restype = st
+    L.cgh_fresnel_destroy.argtypes = [vp]
+    L.cgh_fresnel_destroy.restype = None
     _lib = L
     return L
 
@@ -255,6 +262,40 @@ class Context:
         _check(lib().cgh_profile_read(self._h, names, launches, ms, cap, ctypes.byref(cnt)),
                "cgh_profile_read")
         return {names[i].decode(): (int(launches[i]), float(ms[i])) for i in range(cnt.value)}
+
+
+class FresnelPlan:
+    """Fresnel diffraction of n x n sampled fields by z (cgh_fresnel_*)."""
+
+    def __init__(self, n: int, pitch: float, wavelength: float, z: float, device: int = 0):
+        h = ctypes.c_void_p()
+        _check(lib().cgh_fresnel_create(ctypes.byref(h), int(n), float(pitch), float(wavelength),
+                                        float(z), int(device)), "cgh_fresnel_create")
+        self._h = h
+        self.n, self.pitch, self.wavelength, self.z = int(n), float(pitch), float(wavelength), float(z)
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) and self._h.value:
+            lib().cgh_fresnel_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def run(self, u, out, stream=None):
+        """Propagate u into out: CUDA complex64 tensors of shape [n, n]."""
+        import torch
+        for t, name in ((u, "u"), (out, "out")):
+            if not (_is_torch(t) and t.is_cuda and t.dtype == torch.complex64 and t.is_contiguous()
+                    and tuple(t.shape) == (self.n, self.n)):
+                raise TypeError(f"{name} must be a contiguous CUDA complex64 tensor of shape "
+                                f"({self.n}, {self.n})")
+        _check(lib().cgh_fresnel_run(self._h, u.data_ptr(), out.data_ptr(),
+                                     _stream_handle(stream, [out])), "cgh_fresnel_run")
+        return out
 
 
 def version() -> int:

@@ -22,7 +22,7 @@ BUILD_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libcgh.so")
 
 SOURCES = ["api.hip", "points.hip", "direct.hip", "spherical.hip", "factors.hip", "gemm.hip",
-           "phase.hip"]
+           "phase.hip", "fresnel.hip"]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -927,6 +927,31 @@ cgh_status time_launches(F fn, int reps, hipStream_t s, double *us)
 }  // namespace
 
 // ====================================================================== ABI
+namespace {
+// The device exists and is a gfx950; `arch` receives its name.
+cgh_status check_device(int32_t device, std::string &arch)
+{
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || count == 0)
+        return fail(CGH_EDEVICE, std::string("no HIP device: ") +
+                                     (e != hipSuccess ? hipGetErrorString(e) : "none visible"));
+    if (device >= count)
+        return fail(CGH_EDEVICE, "device index out of range");
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, device);
+    if (e != hipSuccess)
+        return hip_fail(e, "hipGetDeviceProperties");
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(CGH_EDEVICE, std::string("device is ") + prop.gcnArchName +
+                                     ", this library is built for gfx950");
+    arch = prop.gcnArchName;
+    arch = arch.substr(0, arch.find(':'));
+    return CGH_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char *cgh_strerror(cgh_status s)
@@ -946,6 +971,108 @@ const char *cgh_last_error(void) { return g_last_error.c_str(); }
 
 int32_t cgh_version(void) { return 10000; }
 
+// ------------------------------------------------------ Fresnel diffraction
+struct cgh_fresnel {
+    int device = 0;
+    int n = 0, m = 0;              // field size, log2 of the padded size 2n
+    float2 scale{0.0f, 0.0f};      // exp(i 2 pi z / lambda) / (i lambda z) p^2 / (2n)^2
+    DevBuf tw, hc, x, y;
+};
+
+cgh_status cgh_fresnel_create(cgh_fresnel **out, int32_t n, double pitch_m, double wavelength_m,
+                              double z_m, int32_t device)
+{
+    g_last_error.clear();
+    if (!out)
+        return fail(CGH_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n < 16 || n > 8192 || (n & (n - 1)) != 0)
+        return fail(CGH_EINVAL, "n must be a power of two in [16, 8192]");
+    if (!finite_pos(pitch_m))
+        return fail(CGH_EINVAL, "pitch must be finite and > 0");
+    if (!finite_pos(wavelength_m))
+        return fail(CGH_EINVAL, "wavelength must be finite and > 0");
+    if (!std::isfinite(z_m) || z_m == 0.0)
+        return fail(CGH_EINVAL, "z must be finite and non-zero");
+    if (device < 0)
+        return fail(CGH_EINVAL, "device index must be >= 0");
+    std::string arch;
+    cgh_status st = check_device(device, arch);
+    if (st != CGH_OK)
+        return st;
+    DeviceGuard g;
+    CGH_HIP(g.set(device), "hipSetDevice");
+    cgh_fresnel *f = new (std::nothrow) cgh_fresnel();
+    if (!f)
+        return fail(CGH_ENOMEM, "plan allocation");
+    f->device = device;
+    f->n = n;
+    int m = 0;
+    while ((1 << m) < 2 * n)
+        ++m;
+    f->m = m;
+    const int64_t L = (int64_t)1 << m;
+    // exp(i 2 pi frac(z / lambda)) (-i) p^2 / (lambda z L^2), in FP64
+    const double two_pi = 6.28318530717958647692;
+    const double zr = z_m / wavelength_m - std::floor(z_m / wavelength_m);
+    const double mag = pitch_m * pitch_m / (wavelength_m * z_m) / ((double)L * (double)L);
+    f->scale = float2{(float)(mag * std::sin(two_pi * zr)), (float)(-mag * std::cos(two_pi * zr))};
+    hipError_t e = fresnel_prepare_kernels();
+    if (e == hipSuccess)
+        e = f->tw.ensure((size_t)L * sizeof(float2));
+    if (e == hipSuccess)
+        e = f->hc.ensure((size_t)L * sizeof(float2));
+    if (e == hipSuccess)
+        e = f->x.ensure((size_t)n * L * sizeof(float2));
+    if (e == hipSuccess)
+        e = f->y.ensure((size_t)n * L * sizeof(float2));
+    if (e == hipSuccess)
+        e = fresnel_tables(n, m, pitch_m * pitch_m / (2.0 * wavelength_m * z_m),
+                           (float2 *)f->tw.p, (float2 *)f->hc.p, nullptr);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(nullptr);
+    if (e != hipSuccess) {
+        f->tw.release();
+        f->hc.release();
+        f->x.release();
+        f->y.release();
+        delete f;
+        return hip_fail(e, "Fresnel plan set-up");
+    }
+    *out = f;
+    return CGH_OK;
+}
+
+cgh_status cgh_fresnel_run(cgh_fresnel *f, const float *u_dev, float *out_dev, void *stream)
+{
+    g_last_error.clear();
+    if (!f)
+        return fail(CGH_EINVAL, "plan is NULL");
+    if (!u_dev || !out_dev)
+        return fail(CGH_EINVAL, "field or output is NULL");
+    DeviceGuard g;
+    CGH_HIP(g.set(f->device), "hipSetDevice");
+    CGH_HIP(fresnel_run(f->n, f->m, (const float2 *)f->tw.p, (const float2 *)f->hc.p, f->scale,
+                        (const float2 *)u_dev, (float2 *)out_dev, (float2 *)f->x.p,
+                        (float2 *)f->y.p, (hipStream_t)stream),
+            "Fresnel diffraction launch");
+    return CGH_OK;
+}
+
+void cgh_fresnel_destroy(cgh_fresnel *f)
+{
+    if (!f)
+        return;
+    DeviceGuard g;
+    if (g.set(f->device) == hipSuccess)
+        (void)hipDeviceSynchronize();
+    f->tw.release();
+    f->hc.release();
+    f->x.release();
+    f->y.release();
+    delete f;
+}
+
 cgh_status cgh_create(cgh_ctx **out, int32_t width, int32_t height, double pitch_m,
                       double wavelength_m, int32_t device)
 {
@@ -962,20 +1089,10 @@ cgh_status cgh_create(cgh_ctx **out, int32_t width, int32_t height, double pitch
     if (device < 0)
         return fail(CGH_EINVAL, "device index must be >= 0");
 
-    int count = 0;
-    hipError_t e = hipGetDeviceCount(&count);
-    if (e != hipSuccess || count == 0)
-        return fail(CGH_EDEVICE, std::string("no HIP device: ") +
-                                     (e != hipSuccess ? hipGetErrorString(e) : "none visible"));
-    if (device >= count)
-        return fail(CGH_EDEVICE, "device index out of range");
-    hipDeviceProp_t prop;
-    e = hipGetDeviceProperties(&prop, device);
-    if (e != hipSuccess)
-        return hip_fail(e, "hipGetDeviceProperties");
-    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
-        return fail(CGH_EDEVICE, std::string("device is ") + prop.gcnArchName +
-                                     ", this library is built for gfx950");
+    std::string arch;
+    cgh_status dst = check_device(device, arch);
+    if (dst != CGH_OK)
+        return dst;
 
     cgh_ctx *c = new (std::nothrow) cgh_ctx();
     if (!c)
@@ -987,8 +1104,7 @@ cgh_status cgh_create(cgh_ctx **out, int32_t width, int32_t height, double pitch
     c->device = device;
     c->wpad = (int)round_up(width, kLinePad);
     c->hpad = (int)round_up(height, kLinePad);
-    c->arch = prop.gcnArchName;
-    c->arch = c->arch.substr(0, c->arch.find(':'));
+    c->arch = arch;
     load_tune_cache(c);
     *out = c;
     return CGH_OK;

@@ -83,6 +83,8 @@ def test_null_context_is_rejected_everywhere(L):
     assert L.cgh_compute_complex(None, 0, ctypes.c_void_p(16), None) == cgh.EINVAL
     assert L.cgh_kinoform(None, 0, ctypes.c_void_p(16), None) == cgh.EINVAL
     assert L.cgh_tune(None, 0, 1, None, 0, None) == cgh.EINVAL
+    assert L.cgh_fresnel_run(None, ctypes.c_void_p(16), ctypes.c_void_p(16), None) == cgh.EINVAL
+    L.cgh_fresnel_destroy(None)
     assert L.cgh_batch_compute(None, f, 1, 0, ctypes.c_void_p(16), None) == cgh.EINVAL
     assert L.cgh_profile_enable(None, 1) == cgh.EINVAL
     assert L.cgh_profile_reset(None) == cgh.EINVAL
@@ -96,3 +98,24 @@ def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(cgh, "_lib", None)
     with pytest.raises(RuntimeError, match="no fallback"):
         cgh.lib()
+
+
+@pytest.mark.parametrize("n, p, lam, z, dev", [
+    (0, 8e-6, 5e-7, 0.1, 0), (48, 8e-6, 5e-7, 0.1, 0), (8, 8e-6, 5e-7, 0.1, 0),
+    (16384, 8e-6, 5e-7, 0.1, 0), (64, 0.0, 5e-7, 0.1, 0), (64, 8e-6, float("nan"), 0.1, 0),
+    (64, 8e-6, 5e-7, 0.0, 0), (64, 8e-6, 5e-7, float("inf"), 0), (64, 8e-6, 5e-7, 0.1, -1),
+])
+def test_fresnel_create_rejects_bad_arguments(L, n, p, lam, z, dev):
+    out = ctypes.c_void_p(123)
+    assert L.cgh_fresnel_create(ctypes.byref(out), n, p, lam, z, dev) == cgh.EINVAL
+    assert out.value is None
+    assert L.cgh_fresnel_create(None, 64, 8e-6, 5e-7, 0.1, 0) == cgh.EINVAL
+
+
+def test_fresnel_create_without_gpu_reports_device_error(L):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    out = ctypes.c_void_p(123)
+    assert L.cgh_fresnel_create(ctypes.byref(out), 64, 8e-6, 5e-7, 0.1, 0) == cgh.EDEVICE
+    assert out.value is None
