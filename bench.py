@@ -12,8 +12,9 @@ reported under "modes" (spherical_fp32 evaluates the exact spherical wave of
 Eq. (1) instead of the Fresnel sum).  NRMS and max error of every mode are
 measured against the FP64 oracle on the CPU-baseline sample (every 4th row;
 every 16th for the spherical mode, against the oracle's Eq. (1)).  Side
-measurements: the 64-frame batched workload ("batch") and the phase-only
-hologram of Eq. (3) of the bench cloud ("kinoform").
+measurements: the 64-frame batched workload ("batch"), the phase-only
+hologram of Eq. (3) of the bench cloud ("kinoform"), and the Fresnel
+diffraction of Eq. (10) at the paper's plane sizes ("fresnel_diffraction").
 
 Prints one JSON line (rank 0).  --gpus N > 1 is refused: this build runs on
 one GPU.
@@ -219,6 +220,49 @@ def bench_kinoform(args, torch, cghgen, cgh, check: bool):
                      "field's error cannot cross a code boundary" if check else None}
 
 
+def bench_fresnel(args, torch, cgh, check: bool):
+    """Side measurement: Fresnel diffraction of a sampled n x n field (Eq. (10),
+    the second step of the wavefront-recording method) at the paper's plane sizes
+    (Table 7: n = 1024 .. 8192), random complex fields, z = 0.05 m, 8 um, 532 nm.
+    Reports ms per diffraction and the effective HBM rate of the pruned pipeline
+    (18 n^2 complex values moved); with `check`, the NRMS of n = 1024 against the
+    oracle's FP64 Fourier form."""
+    p, lam, z = 8e-6, 532e-9, 0.05
+    res = {}
+    for n in (1024, 2048, 4096, 8192):
+        g = torch.Generator(device="cuda:0").manual_seed(n)
+        u = torch.randn((n, n), dtype=torch.complex64, device="cuda:0", generator=g)
+        out = torch.empty_like(u)
+        plan = cgh.FresnelPlan(n, p, lam, z)
+        stream = torch.cuda.current_stream()
+        for _ in range(2):
+            plan.run(u, out, stream)
+        torch.cuda.synchronize()
+        reps = max(3, min(args.steps, 10))
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            plan.run(u, out, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        r = {"ms": ms, "hbm_gb_per_s": 18.0 * n * n * 8 / (ms * 1e-3) / 1e9}
+        if check and n == 1024:
+            import oracle
+            ref = oracle.diffraction_fft(u.cpu().numpy().astype(np.complex128), p, lam, z)
+            got = out.cpu().numpy().astype(np.complex128)
+            r["nrms"] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        plan.close()
+        log(f"fresnel n={n}: {ms:.3f} ms {r}")
+        res[str(n)] = r
+    return {"workload": "Fresnel diffraction (Eq. 10) of a random complex n x n field, "
+                        "zero-padded FFTs on the 2n grid, 8 um, 532 nm, z = 0.05 m",
+            "n": res,
+            "paper_table7_gpu_s": {"1024": 0.011, "2048": 0.027, "4096": 0.125, "8192": None},
+            "paper_hardware": "NVIDIA Tesla K20, CUFFT (context only)"}
+
+
 def traffic_driver(torch, cghgen, cgh) -> int:
     """Kernel sequence for `rocprofv3 --pmc FETCH_SIZE|WRITE_SIZE -- python bench.py
     --traffic-driver`: the per-launch counters of the split-BF16 GEMM in each recorded
@@ -267,6 +311,8 @@ def main() -> int:
     ap.add_argument("--no-tune", action="store_true", help="use the default launch shapes")
     ap.add_argument("--no-kinoform", action="store_true",
                     help="skip the phase-only hologram side measurement")
+    ap.add_argument("--no-fresnel", action="store_true",
+                    help="skip the Fresnel-diffraction side measurement")
     ap.add_argument("--batch-frames", type=int, default=64,
                     help="frames of the batched-workload side measurement (0 = skip)")
     ap.add_argument("--traffic-driver", action="store_true",
@@ -367,6 +413,9 @@ def main() -> int:
     kino = None
     if not args.no_kinoform:
         kino = bench_kinoform(args, torch, cghgen, cgh, check=not args.no_cpu_baseline)
+    fres = None
+    if not args.no_fresnel:
+        fres = bench_fresnel(args, torch, cgh, check=not args.no_cpu_baseline)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -419,6 +468,7 @@ def main() -> int:
         "modes": {m: {k: v for k, v in r.items() if k != "sample"} for m, r in results.items()},
         "batch": batch,
         "kinoform": kino,
+        "fresnel_diffraction": fres,
     }
     print(json.dumps(line), flush=True)
     return 0
