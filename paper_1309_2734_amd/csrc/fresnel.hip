@@ -15,8 +15,10 @@
 //   - 2-D transforms are row transforms with transposes between them; every
 //     row transform runs in LDS (a whole row, up to L = 16384 complex = 128 KB,
 //     in one workgroup) as a Stockham autosort FFT of radix-16 passes (plus one
-//     radix-2/4/8 pass), the small DFTs in registers, twiddles from an FP64-
-//     computed table.  Inverse transforms are conj(F[conj(x)]).
+//     radix-2/4/8 pass), the small DFTs in registers.  Twiddles come from an
+//     FP64-computed table, kept in LDS as two factors, w^t = w^(64 t_hi)
+//     w^t_lo (64 + L/64 entries), so a pass reads none from global memory.
+//     Inverse transforms are conj(F[conj(x)]).
 //   - Zero padding and cropping are pruned: rows that are all zero are never
 //     transformed, zeros are never loaded, and outputs outside the crop are
 //     never stored.  The forward column transform, the spectrum product and
@@ -27,7 +29,11 @@
 namespace cgh {
 namespace {
 
-constexpr int kFftThreads = 512;
+// threads per row transform: 1024 for long rows (one or two rows fill a CU's
+// LDS, so the waves of one row must hide the LDS latency), 256 otherwise
+constexpr int kFftThreadsLong = 1024;
+constexpr int kFftThreadsShort = 256;
+constexpr int kLongLog2 = 13;
 constexpr int kMaxLog2 = 14;               // L <= 16384: a row is 128 KB of LDS
 constexpr int kMaxL = 1 << kMaxLog2;
 
@@ -79,32 +85,40 @@ __device__ __forceinline__ void dft(float2 *v)
 // input r by w_L^(r k L/(ns R)) (w_L = exp(-2 pi i / L), table tw), applies
 // the size-R DFT and writes output q to s[(j - k) R + k + q ns].  In place:
 // every thread reads all its inputs before the barrier, writes after it.
-template <int R, int LR>
-__device__ __forceinline__ void stockham_pass(float2 *s, int m, int lns,
-                                              const float2 *__restrict__ tw)
+// Twiddle w_L^t from the two LDS factor tables (t < L).
+__device__ __forceinline__ float2 twiddle(const float2 *tw_hi, const float2 *tw_lo, int t)
 {
-    constexpr int BMAX = (kMaxL / R + kFftThreads - 1) / kFftThreads;
+    return cmul(tw_hi[t >> 6], tw_lo[t & 63]);
+}
+
+template <int R, int LR, int T>
+__device__ __forceinline__ void stockham_pass(float2 *s, int m, int lns, const float2 *tw_hi,
+                                              const float2 *tw_lo)
+{
+    // the long-row launch covers L >= 2^kLongLog2, the short one L below it
+    constexpr int LMAX = T == kFftThreadsLong ? kMaxL : (1 << (kLongLog2 - 1));
+    constexpr int BMAX = (LMAX / R + T - 1) / T;
     const int nb = (1 << m) / R;                 // butterflies
     const int ns = 1 << lns;
     const int tshift = m - lns - LR;             // log2(L / (ns R))
     float2 v[BMAX][R];
 #pragma unroll
     for (int b = 0; b < BMAX; ++b) {
-        const int j = threadIdx.x + b * kFftThreads;
+        const int j = threadIdx.x + b * T;
         if (j < nb) {
             const int k = j & (ns - 1);
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 v[b][r] = s[j + r * nb];
                 if (r > 0 && k > 0)
-                    v[b][r] = cmul(v[b][r], tw[(r * k) << tshift]);
+                    v[b][r] = cmul(v[b][r], twiddle(tw_hi, tw_lo, (r * k) << tshift));
             }
         }
     }
     __syncthreads();
 #pragma unroll
     for (int b = 0; b < BMAX; ++b) {
-        const int j = threadIdx.x + b * kFftThreads;
+        const int j = threadIdx.x + b * T;
         if (j < nb) {
             const int k = j & (ns - 1);
             dft<R>(v[b]);
@@ -119,27 +133,36 @@ __device__ __forceinline__ void stockham_pass(float2 *s, int m, int lns,
 
 // Forward FFT of s[0 .. 2^m) in LDS, natural order in and out.  The caller
 // has synchronised after filling s.
-__device__ __forceinline__ void fft_lds(float2 *s, int m, const float2 *__restrict__ tw)
+template <int T>
+__device__ __forceinline__ void fft_lds(float2 *s, int m, const float2 *tw_hi,
+                                        const float2 *tw_lo)
 {
     int lns = 0;
     switch (m & 3) {
     case 1:
-        stockham_pass<2, 1>(s, m, 0, tw);
+        stockham_pass<2, 1, T>(s, m, 0, tw_hi, tw_lo);
         lns = 1;
         break;
     case 2:
-        stockham_pass<4, 2>(s, m, 0, tw);
+        stockham_pass<4, 2, T>(s, m, 0, tw_hi, tw_lo);
         lns = 2;
         break;
     case 3:
-        stockham_pass<8, 3>(s, m, 0, tw);
+        stockham_pass<8, 3, T>(s, m, 0, tw_hi, tw_lo);
         lns = 3;
         break;
     default:
         break;
     }
     for (; lns < m; lns += 4)
-        stockham_pass<16, 4>(s, m, lns, tw);
+        stockham_pass<16, 4, T>(s, m, lns, tw_hi, tw_lo);
+}
+
+// LDS of a row transform: the row (L values), then the twiddle factors w^t
+// (t < 64) and w^(64 t) (t < L / 64).
+constexpr size_t row_lds_bytes(int m)
+{
+    return sizeof(float2) * ((size_t(1) << m) + 64 + ((size_t(1) << m) / 64 + 1));
 }
 
 enum class RowOp { Forward, Fresnel, Inverse };
@@ -151,8 +174,8 @@ enum class RowOp { Forward, Fresnel, Inverse };
 //            conj F conj;
 // and stores the first out_len outputs to out[row].  in and out may be the
 // same rows (the row is in LDS before anything is stored).
-template <RowOp OP>
-__global__ __launch_bounds__(kFftThreads) void k_fft_rows(const float2 *in, int64_t in_ld,
+template <RowOp OP, int T>
+__global__ __launch_bounds__(T) void k_fft_rows(const float2 *in, int64_t in_ld,
                                                           int in_len, float2 *out, int64_t out_ld,
                                                           int out_len, int m,
                                                           const float2 *__restrict__ tw,
@@ -161,23 +184,29 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_rows(const float2 *in, int6
 {
     extern __shared__ float2 s[];
     const int L = 1 << m;
+    float2 *tw_lo = s + L;
+    float2 *tw_hi = tw_lo + 64;
+    for (int t = threadIdx.x; t < 64; t += T)
+        tw_lo[t] = tw[t & (L - 1)];
+    for (int t = threadIdx.x; t * 64 < L; t += T)
+        tw_hi[t] = tw[t * 64];
     const int64_t row = blockIdx.x;
     const float2 *src = in + row * in_ld;
-    for (int i = threadIdx.x; i < L; i += kFftThreads) {
+    for (int i = threadIdx.x; i < L; i += T) {
         const float2 x = i < in_len ? src[i] : float2{0.0f, 0.0f};
         s[i] = OP == RowOp::Inverse ? conjf2(x) : x;
     }
     __syncthreads();
-    fft_lds(s, m, tw);
+    fft_lds<T>(s, m, tw_hi, tw_lo);
     if (OP == RowOp::Fresnel) {
         const float2 hr = cmul(hc[row], scale);
-        for (int i = threadIdx.x; i < L; i += kFftThreads)
+        for (int i = threadIdx.x; i < L; i += T)
             s[i] = conjf2(cmul(s[i], cmul(hc[i], hr)));
         __syncthreads();
-        fft_lds(s, m, tw);
+        fft_lds<T>(s, m, tw_hi, tw_lo);
     }
     float2 *dst = out + row * out_ld;
-    for (int i = threadIdx.x; i < out_len; i += kFftThreads)
+    for (int i = threadIdx.x; i < out_len; i += T)
         dst[i] = OP == RowOp::Forward ? s[i] : conjf2(s[i]);
 }
 
@@ -236,9 +265,15 @@ hipError_t rows(const float2 *in, int64_t in_ld, int in_len, float2 *out, int64_
                 int out_len, int n_rows, int m, const float2 *tw, const float2 *hc, float2 scale,
                 hipStream_t s)
 {
-    const size_t lds = sizeof(float2) << m;
-    hipLaunchKernelGGL(k_fft_rows<OP>, dim3((unsigned)n_rows), dim3(kFftThreads), lds, s, in,
-                       in_ld, in_len, out, out_ld, out_len, m, tw, hc, scale);
+    const size_t lds = row_lds_bytes(m);
+    if (m >= kLongLog2)
+        hipLaunchKernelGGL((k_fft_rows<OP, kFftThreadsLong>), dim3((unsigned)n_rows),
+                           dim3(kFftThreadsLong), lds, s, in, in_ld, in_len, out, out_ld, out_len,
+                           m, tw, hc, scale);
+    else
+        hipLaunchKernelGGL((k_fft_rows<OP, kFftThreadsShort>), dim3((unsigned)n_rows),
+                           dim3(kFftThreadsShort), lds, s, in, in_ld, in_len, out, out_ld,
+                           out_len, m, tw, hc, scale);
     return hipGetLastError();
 }
 
@@ -254,16 +289,20 @@ hipError_t transpose(const float2 *in, int64_t in_ld, float2 *out, int64_t out_l
 
 hipError_t fresnel_prepare_kernels()
 {
-    const int lds = (int)(sizeof(float2) << kMaxLog2);
-    hipError_t e = hipFuncSetAttribute((const void *)k_fft_rows<RowOp::Forward>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void *)k_fft_rows<RowOp::Fresnel>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void *)k_fft_rows<RowOp::Inverse>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    return e;
+    const int lds = (int)row_lds_bytes(kMaxLog2);
+    const void *kernels[] = {
+        (const void *)k_fft_rows<RowOp::Forward, kFftThreadsLong>,
+        (const void *)k_fft_rows<RowOp::Fresnel, kFftThreadsLong>,
+        (const void *)k_fft_rows<RowOp::Inverse, kFftThreadsLong>,
+        (const void *)k_fft_rows<RowOp::Forward, kFftThreadsShort>,
+        (const void *)k_fft_rows<RowOp::Fresnel, kFftThreadsShort>,
+        (const void *)k_fft_rows<RowOp::Inverse, kFftThreadsShort>};
+    for (const void *k : kernels) {
+        hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        if (e != hipSuccess)
+            return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t fresnel_tables(int n, int m, double q, float2 *tw, float2 *hc, hipStream_t s)
