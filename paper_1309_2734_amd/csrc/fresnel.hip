@@ -57,6 +57,43 @@ __device__ __forceinline__ float2 root16(int q)
     return float2{c[q & 15], -c[(q + 12) & 15]};   // sin(x) = cos(x - pi/2)
 }
 
+// x * exp(-2 pi i Q / 16) with the exact forms of the multiples of pi / 2
+// (a swap and a sign) and pi / 4 (two products) spelled out.
+template <int Q>
+__device__ __forceinline__ float2 mul_root16(float2 x)
+{
+    constexpr int q = Q & 15;
+    if constexpr (q == 0)
+        return x;
+    else if constexpr (q == 4)
+        return float2{x.y, -x.x};                           // * (-i)
+    else if constexpr (q == 8)
+        return float2{-x.x, -x.y};                          // * (-1)
+    else if constexpr (q == 12)
+        return float2{-x.y, x.x};                           // * i
+    else if constexpr (q == 2)
+        return float2{kR2 * (x.x + x.y), kR2 * (x.y - x.x)};   // * (1 - i) / sqrt 2
+    else if constexpr (q == 6)
+        return float2{kR2 * (x.y - x.x), -kR2 * (x.x + x.y)};  // * (-1 - i) / sqrt 2
+    else if constexpr (q == 10)
+        return float2{-kR2 * (x.x + x.y), kR2 * (x.x - x.y)};  // * (-1 + i) / sqrt 2
+    else if constexpr (q == 14)
+        return float2{kR2 * (x.x - x.y), kR2 * (x.x + x.y)};   // * (1 + i) / sqrt 2
+    else
+        return cmul(x, root16(q));
+}
+
+template <int R, int Q>
+__device__ __forceinline__ void dft_combine(float2 *v, const float2 *e, const float2 *o)
+{
+    if constexpr (Q < R / 2) {
+        const float2 t = mul_root16<Q *(16 / R)>(o[Q]);
+        v[Q] = cadd(e[Q], t);
+        v[Q + R / 2] = csub(e[Q], t);
+        dft_combine<R, Q + 1>(v, e, o);
+    }
+}
+
 // In-register forward DFT of size R (R = 1, 2, 4, 8, 16): v[q] <- sum_r v[r]
 // exp(-2 pi i r q / R), by radix-2 decimation in time.
 template <int R>
@@ -71,12 +108,7 @@ __device__ __forceinline__ void dft(float2 *v)
         }
         dft<R / 2>(e);
         dft<R / 2>(o);
-#pragma unroll
-        for (int q = 0; q < R / 2; ++q) {
-            const float2 t = q == 0 ? o[q] : cmul(o[q], root16(q * (16 / R)));
-            v[q] = cadd(e[q], t);
-            v[q + R / 2] = csub(e[q], t);
-        }
+        dft_combine<R, 0>(v, e, o);
     }
 }
 
@@ -89,6 +121,31 @@ __device__ __forceinline__ void dft(float2 *v)
 __device__ __forceinline__ float2 twiddle(const float2 *tw_hi, const float2 *tw_lo, int t)
 {
     return cmul(tw_hi[t >> 6], tw_lo[t & 63]);
+}
+
+// The twiddles w^(r e), r = 1 .. R-1, of one butterfly: table lookups for
+// r = 1, 2, 4, 8 and products of those (at most three) for the rest, so each
+// carries at most a few roundings; e (R - 1) < L.
+template <int R>
+__device__ __forceinline__ void butterfly_twiddles(const float2 *tw_hi, const float2 *tw_lo,
+                                                   int e, int lmask, float2 *w)
+{
+    float2 p[4];
+#pragma unroll
+    for (int b = 0; (1 << b) < R; ++b)
+        p[b] = twiddle(tw_hi, tw_lo, (e << b) & lmask);
+#pragma unroll
+    for (int r = 1; r < R; ++r) {
+        float2 acc{1.0f, 0.0f};
+        bool first = true;
+#pragma unroll
+        for (int b = 0; (1 << b) < R; ++b)
+            if (r & (1 << b)) {
+                acc = first ? p[b] : cmul(acc, p[b]);
+                first = false;
+            }
+        w[r] = acc;
+    }
 }
 
 template <int R, int LR, int T>
@@ -108,10 +165,14 @@ __device__ __forceinline__ void stockham_pass(float2 *s, int m, int lns, const f
         if (j < nb) {
             const int k = j & (ns - 1);
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
+            for (int r = 0; r < R; ++r)
                 v[b][r] = s[j + r * nb];
-                if (r > 0 && k > 0)
-                    v[b][r] = cmul(v[b][r], twiddle(tw_hi, tw_lo, (r * k) << tshift));
+            if (k > 0) {
+                float2 w[R];
+                butterfly_twiddles<R>(tw_hi, tw_lo, k << tshift, (1 << m) - 1, w);
+#pragma unroll
+                for (int r = 1; r < R; ++r)
+                    v[b][r] = cmul(v[b][r], w[r]);
             }
         }
     }
