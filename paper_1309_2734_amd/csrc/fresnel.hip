@@ -29,13 +29,8 @@
 namespace cgh {
 namespace {
 
-// threads per row transform: 1024 for long rows (one or two rows fill a CU's
-// LDS, so the waves of one row must hide the LDS latency), 256 otherwise
-constexpr int kFftThreadsLong = 1024;
-constexpr int kFftThreadsShort = 256;
-constexpr int kLongLog2 = 13;
-constexpr int kMaxLog2 = 14;               // L <= 16384: a row is 128 KB of LDS
-constexpr int kMaxL = 1 << kMaxLog2;
+constexpr int kMinLog2 = 5;                // L >= 32 (n >= 16)
+constexpr int kMaxLog2 = 14;               // L <= 16384: a row is 136 KB of LDS, 1024 threads
 
 __device__ __forceinline__ float2 cmul(float2 a, float2 b)
 {
@@ -112,11 +107,6 @@ __device__ __forceinline__ void dft(float2 *v)
     }
 }
 
-// One Stockham pass of radix R over s[0 .. L) (L = 2^m) with sub-transform
-// size ns (2^lns): butterfly j (k = j mod ns) takes s[j + r L/R], multiplies
-// input r by w_L^(r k L/(ns R)) (w_L = exp(-2 pi i / L), table tw), applies
-// the size-R DFT and writes output q to s[(j - k) R + k + q ns].  In place:
-// every thread reads all its inputs before the barrier, writes after it.
 // Twiddle w_L^t from the two LDS factor tables (t < L).
 __device__ __forceinline__ float2 twiddle(const float2 *tw_hi, const float2 *tw_lo, int t)
 {
@@ -148,127 +138,173 @@ __device__ __forceinline__ void butterfly_twiddles(const float2 *tw_hi, const fl
     }
 }
 
-template <int R, int LR, int T>
-__device__ __forceinline__ void stockham_pass(float2 *s, int m, int lns, const float2 *tw_hi,
-                                              const float2 *tw_lo)
+// Shape of a row transform of length L = 2^M.  Every thread holds 16
+// values of its row in registers, so a row takes TR = L / 16 threads and a
+// workgroup takes ROWS rows (at least one wave).  The transform is a Stockham
+// autosort FFT: one radix-R0 pass (R0 = 2^(M mod 4), or 16), then radix-16
+// passes.  Pass with sub-transform size ns and radix R: butterfly b
+// (k = b mod ns) takes X[b + r L/R], multiplies input r by w^(r k L/(ns R))
+// (w = exp(-2 pi i / L)), applies the size-R DFT and puts output q at
+// (b - k) R + k + q ns.  Thread j's values are X[j + r TR] (r < 16): exactly
+// the inputs of its butterflies in every pass, and, after the last pass
+// (ns = TR), the outputs X[j + q TR] in natural order.  So the first pass
+// runs on the values as loaded, the last one leaves results in registers,
+// and LDS only carries the exchange between two passes.
+template <int M>
+struct Fft {
+    static_assert(M >= kMinLog2 && M <= kMaxLog2, "row length");
+    static constexpr int L = 1 << M;
+    static constexpr int TR = L / 16;                        // threads per row
+    static constexpr int ROWS = TR >= 64 ? 1 : 64 / TR;      // rows per workgroup
+    static constexpr int T = TR * ROWS;                      // threads per workgroup
+    static constexpr int LR0 = M % 4 == 0 ? 4 : M % 4;       // log2 of the first radix
+    static constexpr int R0 = 1 << LR0;
+    static constexpr int NB0 = 16 / R0;                      // first-pass butterflies per thread
+    static constexpr int PASSES = 1 + (M - LR0) / 4;
+    static constexpr int ROW_SLOTS = L + L / 16;             // padded row in LDS
+    // LDS: the rows, then the twiddle factors w^t (t < 64) and w^(64 t) (t < L / 64)
+    static constexpr size_t lds_bytes = sizeof(float2) * (ROWS * ROW_SLOTS + 64 + L / 64 + 1);
+};
+
+// LDS slot of row position i: one spare slot after every 16 values spreads
+// the strided stores of the early passes over the banks.
+__device__ __forceinline__ int slot(int i) { return i + (i >> 4); }
+
+// Row position of thread j's value idx once pass p (p = 0: the first pass)
+// has produced it.
+template <int M>
+__device__ __forceinline__ int out_pos(int p, int j, int idx)
 {
-    // the long-row launch covers L >= 2^kLongLog2, the short one L below it
-    constexpr int LMAX = T == kFftThreadsLong ? kMaxL : (1 << (kLongLog2 - 1));
-    constexpr int BMAX = (LMAX / R + T - 1) / T;
-    const int nb = (1 << m) / R;                 // butterflies
-    const int ns = 1 << lns;
-    const int tshift = m - lns - LR;             // log2(L / (ns R))
-    float2 v[BMAX][R];
-#pragma unroll
-    for (int b = 0; b < BMAX; ++b) {
-        const int j = threadIdx.x + b * T;
-        if (j < nb) {
-            const int k = j & (ns - 1);
-#pragma unroll
-            for (int r = 0; r < R; ++r)
-                v[b][r] = s[j + r * nb];
-            if (k > 0) {
-                float2 w[R];
-                butterfly_twiddles<R>(tw_hi, tw_lo, k << tshift, (1 << m) - 1, w);
-#pragma unroll
-                for (int r = 1; r < R; ++r)
-                    v[b][r] = cmul(v[b][r], w[r]);
-            }
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int b = 0; b < BMAX; ++b) {
-        const int j = threadIdx.x + b * T;
-        if (j < nb) {
-            const int k = j & (ns - 1);
-            dft<R>(v[b]);
-            const int base = ((j - k) << LR) + k;
-#pragma unroll
-            for (int q = 0; q < R; ++q)
-                s[base + q * ns] = v[b][q];
-        }
-    }
-    __syncthreads();
+    using F = Fft<M>;
+    if (p == 0)   // butterfly j + b TR, output q, held in x[b + q NB0]
+        return (j + (idx % F::NB0) * F::TR) * F::R0 + idx / F::NB0;
+    const int ns = 1 << (F::LR0 + 4 * (p - 1));
+    const int k = j & (ns - 1);
+    return ((j - k) << 4) + k + idx * ns;
 }
 
-// Forward FFT of s[0 .. 2^m) in LDS, natural order in and out.  The caller
-// has synchronised after filling s.
-template <int T>
-__device__ __forceinline__ void fft_lds(float2 *s, int m, const float2 *tw_hi,
-                                        const float2 *tw_lo)
+// Forward transform of one row; x[r] = X[j + r TR] in, x[q] = F[X][j + q TR]
+// out.  s is the row's LDS.  Every thread of the workgroup calls it (it
+// holds barriers).  The twiddle tables must be in LDS by the first barrier.
+template <int M>
+__device__ __forceinline__ void fft_row(float2 (&x)[16], float2 *s, int j,
+                                        const float2 *tw_hi, const float2 *tw_lo)
 {
-    int lns = 0;
-    switch (m & 3) {
-    case 1:
-        stockham_pass<2, 1, T>(s, m, 0, tw_hi, tw_lo);
-        lns = 1;
-        break;
-    case 2:
-        stockham_pass<4, 2, T>(s, m, 0, tw_hi, tw_lo);
-        lns = 2;
-        break;
-    case 3:
-        stockham_pass<8, 3, T>(s, m, 0, tw_hi, tw_lo);
-        lns = 3;
-        break;
-    default:
-        break;
+    using F = Fft<M>;
+    // Opaque copy of j: the LDS addresses of two transforms in one kernel
+    // are then computed twice instead of being held through both.
+    asm volatile("" : "+v"(j));
+#pragma unroll
+    for (int b = 0; b < F::NB0; ++b) {
+        float2 v[F::R0];
+#pragma unroll
+        for (int a = 0; a < F::R0; ++a)
+            v[a] = x[b + a * F::NB0];
+        dft<F::R0>(v);
+#pragma unroll
+        for (int q = 0; q < F::R0; ++q)
+            x[b + q * F::NB0] = v[q];
     }
-    for (; lns < m; lns += 4)
-        stockham_pass<16, 4, T>(s, m, lns, tw_hi, tw_lo);
-}
-
-// LDS of a row transform: the row (L values), then the twiddle factors w^t
-// (t < 64) and w^(64 t) (t < L / 64).
-constexpr size_t row_lds_bytes(int m)
-{
-    return sizeof(float2) * ((size_t(1) << m) + 64 + ((size_t(1) << m) / 64 + 1));
+#pragma unroll
+    for (int p = 1; p < F::PASSES; ++p) {
+        __syncthreads();   // the previous exchange's reads are done
+#pragma unroll
+        for (int idx = 0; idx < 16; ++idx)
+            s[slot(out_pos<M>(p - 1, j, idx))] = x[idx];
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+            x[r] = s[slot(j + r * F::TR)];
+        const int lns = F::LR0 + 4 * (p - 1);
+        const int k = j & ((1 << lns) - 1);
+        float2 w[16];
+        butterfly_twiddles<16>(tw_hi, tw_lo, k << (M - lns - 4), F::L - 1, w);
+#pragma unroll
+        for (int r = 1; r < 16; ++r)
+            x[r] = cmul(x[r], w[r]);
+        dft<16>(x);
+    }
 }
 
 enum class RowOp { Forward, Fresnel, Inverse };
 
-// One row per workgroup.  Loads in[row][0 .. in_len) (zeros beyond), then
+// ROWS rows per workgroup.  Loads in[row][0 .. in_len) (zeros beyond), then
 //   Forward: F;   Inverse: conj F conj;
 //   Fresnel: F, times hc[i] hc[row] scale (the spectrum of the separable
 //            impulse response at frequency (row, i), and the constant), then
 //            conj F conj;
-// and stores the first out_len outputs to out[row].  in and out may be the
-// same rows (the row is in LDS before anything is stored).
-template <RowOp OP, int T>
-__global__ __launch_bounds__(T) void k_fft_rows(const float2 *in, int64_t in_ld,
-                                                          int in_len, float2 *out, int64_t out_ld,
-                                                          int out_len, int m,
-                                                          const float2 *__restrict__ tw,
-                                                          const float2 *__restrict__ hc,
-                                                          float2 scale)
+// and stores the first out_len outputs to out[row], rows < n_rows.  in and
+// out may be the same rows (a thread's loads precede its stores, and a row
+// is read by its own threads only).
+template <RowOp OP, int M>
+__global__ __launch_bounds__(Fft<M>::T) __attribute__((amdgpu_waves_per_eu(4))) void k_fft_rows(const float2 *in, int64_t in_ld,
+                                                        int in_len, float2 *out, int64_t out_ld,
+                                                        int out_len, int n_rows,
+                                                        const float2 *__restrict__ tw,
+                                                        const float2 *__restrict__ hc,
+                                                        float2 scale)
 {
-    extern __shared__ float2 s[];
-    const int L = 1 << m;
-    float2 *tw_lo = s + L;
+    using F = Fft<M>;
+    extern __shared__ float2 lds[];
+    float2 *tw_lo = lds + F::ROWS * F::ROW_SLOTS;
     float2 *tw_hi = tw_lo + 64;
-    for (int t = threadIdx.x; t < 64; t += T)
-        tw_lo[t] = tw[t & (L - 1)];
-    for (int t = threadIdx.x; t * 64 < L; t += T)
+    for (int t = threadIdx.x; t < 64; t += F::T)
+        tw_lo[t] = tw[t & (F::L - 1)];
+    for (int t = threadIdx.x; t * 64 < F::L; t += F::T)
         tw_hi[t] = tw[t * 64];
-    const int64_t row = blockIdx.x;
-    const float2 *src = in + row * in_ld;
-    for (int i = threadIdx.x; i < L; i += T) {
-        const float2 x = i < in_len ? src[i] : float2{0.0f, 0.0f};
-        s[i] = OP == RowOp::Inverse ? conjf2(x) : x;
+    const int rl = threadIdx.x / F::TR;
+    const int j = threadIdx.x % F::TR;
+    const int64_t row = (int64_t)blockIdx.x * F::ROWS + rl;
+    const bool live = row < n_rows;
+    float2 *s = lds + rl * F::ROW_SLOTS;
+
+    float2 x[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r)
+        x[r] = float2{0.0f, 0.0f};
+    if (live) {
+        const float2 *src = in + row * in_ld;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int i = j + r * F::TR;
+            if (i < in_len)
+                x[r] = OP == RowOp::Inverse ? conjf2(src[i]) : src[i];
+        }
     }
-    __syncthreads();
-    fft_lds<T>(s, m, tw_hi, tw_lo);
+    fft_row<M>(x, s, j, tw_hi, tw_lo);
     if (OP == RowOp::Fresnel) {
-        const float2 hr = cmul(hc[row], scale);
-        for (int i = threadIdx.x; i < L; i += T)
-            s[i] = conjf2(cmul(s[i], cmul(hc[i], hr)));
-        __syncthreads();
-        fft_lds<T>(s, m, tw_hi, tw_lo);
+        if (live) {
+            // All 17 spectrum loads in flight at once, then the products.
+            // The empty asm hides the index from the compiler, so the loads
+            // cannot be hoisted into the transform, where they would hold
+            // 32 more registers.
+            int jj = j;
+            asm volatile("" : "+v"(jj));
+            float2 h[16];
+            const float2 hrow = hc[row];
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                h[r] = hc[jj + r * F::TR];
+            __builtin_amdgcn_sched_barrier(0);
+            const float2 hr = cmul(hrow, scale);
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                x[r] = conjf2(cmul(x[r], cmul(h[r], hr)));
+        }
+        fft_row<M>(x, s, j, tw_hi, tw_lo);
     }
-    float2 *dst = out + row * out_ld;
-    for (int i = threadIdx.x; i < out_len; i += T)
-        dst[i] = OP == RowOp::Forward ? s[i] : conjf2(s[i]);
+    if (live) {
+        // store addresses from here on (hoisted, they would hold 32 registers)
+        int jo = j;
+        asm volatile("" : "+v"(jo));
+        float2 *dst = out + row * out_ld;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int i = jo + q * F::TR;
+            if (i < out_len)
+                dst[i] = OP == RowOp::Forward ? x[q] : conjf2(x[q]);
+        }
+    }
 }
 
 // out[c][r] = in[r][c] for r < rows, c < cols; 32 x 32 tiles through LDS.
@@ -321,21 +357,44 @@ __global__ void k_chirp(int m, int n, double q, float2 *h)
     }
 }
 
-template <RowOp OP>
+template <RowOp OP, int M = kMinLog2>
 hipError_t rows(const float2 *in, int64_t in_ld, int in_len, float2 *out, int64_t out_ld,
                 int out_len, int n_rows, int m, const float2 *tw, const float2 *hc, float2 scale,
                 hipStream_t s)
 {
-    const size_t lds = row_lds_bytes(m);
-    if (m >= kLongLog2)
-        hipLaunchKernelGGL((k_fft_rows<OP, kFftThreadsLong>), dim3((unsigned)n_rows),
-                           dim3(kFftThreadsLong), lds, s, in, in_ld, in_len, out, out_ld, out_len,
-                           m, tw, hc, scale);
-    else
-        hipLaunchKernelGGL((k_fft_rows<OP, kFftThreadsShort>), dim3((unsigned)n_rows),
-                           dim3(kFftThreadsShort), lds, s, in, in_ld, in_len, out, out_ld,
-                           out_len, m, tw, hc, scale);
-    return hipGetLastError();
+    if constexpr (M > kMaxLog2) {
+        return hipErrorInvalidValue;
+    } else {
+        if (m != M)
+            return rows<OP, M + 1>(in, in_ld, in_len, out, out_ld, out_len, n_rows, m, tw, hc,
+                                   scale, s);
+        using F = Fft<M>;
+        if (n_rows <= 0)
+            return hipSuccess;
+        hipLaunchKernelGGL((k_fft_rows<OP, M>), dim3((unsigned)((n_rows + F::ROWS - 1) / F::ROWS)),
+                           dim3(F::T), F::lds_bytes, s, in, in_ld, in_len, out, out_ld, out_len,
+                           n_rows, tw, hc, scale);
+        return hipGetLastError();
+    }
+}
+
+template <int M = kMinLog2>
+hipError_t prepare_rows()
+{
+    if constexpr (M > kMaxLog2) {
+        return hipSuccess;
+    } else {
+        const int lds = (int)Fft<M>::lds_bytes;
+        const void *kernels[] = {(const void *)k_fft_rows<RowOp::Forward, M>,
+                                 (const void *)k_fft_rows<RowOp::Fresnel, M>,
+                                 (const void *)k_fft_rows<RowOp::Inverse, M>};
+        for (const void *k : kernels) {
+            hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+            if (e != hipSuccess)
+                return e;
+        }
+        return prepare_rows<M + 1>();
+    }
 }
 
 hipError_t transpose(const float2 *in, int64_t in_ld, float2 *out, int64_t out_ld, int r, int c,
@@ -348,27 +407,11 @@ hipError_t transpose(const float2 *in, int64_t in_ld, float2 *out, int64_t out_l
 
 }  // namespace
 
-hipError_t fresnel_prepare_kernels()
-{
-    const int lds = (int)row_lds_bytes(kMaxLog2);
-    const void *kernels[] = {
-        (const void *)k_fft_rows<RowOp::Forward, kFftThreadsLong>,
-        (const void *)k_fft_rows<RowOp::Fresnel, kFftThreadsLong>,
-        (const void *)k_fft_rows<RowOp::Inverse, kFftThreadsLong>,
-        (const void *)k_fft_rows<RowOp::Forward, kFftThreadsShort>,
-        (const void *)k_fft_rows<RowOp::Fresnel, kFftThreadsShort>,
-        (const void *)k_fft_rows<RowOp::Inverse, kFftThreadsShort>};
-    for (const void *k : kernels) {
-        hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-        if (e != hipSuccess)
-            return e;
-    }
-    return hipSuccess;
-}
+hipError_t fresnel_prepare_kernels() { return prepare_rows(); }
 
 hipError_t fresnel_tables(int n, int m, double q, float2 *tw, float2 *hc, hipStream_t s)
 {
-    if (n < 1 || m < 1 || m > kMaxLog2 || (2 * n) != (1 << m))
+    if (n < 1 || m < kMinLog2 || m > kMaxLog2 || (2 * n) != (1 << m))
         return hipErrorInvalidValue;
     const int L = 1 << m;
     const unsigned blocks = (unsigned)((L + 255) / 256);
@@ -384,7 +427,7 @@ hipError_t fresnel_tables(int n, int m, double q, float2 *tw, float2 *hc, hipStr
 hipError_t fresnel_run(int n, int m, const float2 *tw, const float2 *hc, float2 scale,
                        const float2 *u, float2 *out, float2 *x, float2 *y, hipStream_t s)
 {
-    if (n < 1 || m < 1 || m > kMaxLog2 || (2 * n) != (1 << m))
+    if (n < 1 || m < kMinLog2 || m > kMaxLog2 || (2 * n) != (1 << m))
         return hipErrorInvalidValue;
     const int L = 1 << m;
     const float2 none{0.0f, 0.0f};
