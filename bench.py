@@ -33,10 +33,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# Published MI355X peaks (dense MFMA).
+# Published MI355X peaks (dense MFMA; HBM).
 PEAK_MFMA_BF16_TFLOPS = 2500.0
 PEAK_MFMA_FP16_TFLOPS = 2500.0
 PEAK_MFMA_FP32_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
 CUS, CLOCK_HZ = 256, 2.4e9
 # ALU-bound kernels: an upper bound from two per-CU limits at the peak clock --
 # VALU issue of 64 lane-instructions per clock (4 SIMD16 units, one wave64
@@ -247,7 +248,12 @@ def bench_fresnel(args, torch, cgh, check: bool):
         e1.record(stream)
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / reps
-        r = {"ms": ms, "hbm_gb_per_s": 18.0 * n * n * 8 / (ms * 1e-3) / 1e9}
+        gbs = 18.0 * n * n * 8 / (ms * 1e-3) / 1e9
+        r = {"ms": ms, "hbm_gb_per_s": gbs,
+             "roofline": {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                          "frac": gbs / PEAK_HBM_GBS, "traffic": None,
+                          "note": "achieved = the five-kernel pipeline's 18 n^2 x 8 B over the "
+                                  "whole diffraction time"}}
         if check and n == 1024:
             import oracle
             ref = oracle.diffraction_fft(u.cpu().numpy().astype(np.complex128), p, lam, z)

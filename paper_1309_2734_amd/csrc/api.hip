@@ -1019,7 +1019,7 @@ cgh_status cgh_fresnel_create(cgh_fresnel **out, int32_t n, double pitch_m, doub
     f->scale = float2{(float)(mag * std::sin(two_pi * zr)), (float)(-mag * std::cos(two_pi * zr))};
     hipError_t e = fresnel_prepare_kernels();
     if (e == hipSuccess)
-        e = f->tw.ensure((size_t)L * sizeof(float2));
+        e = f->tw.ensure(fresnel_twiddle_bytes(m));
     if (e == hipSuccess)
         e = f->hc.ensure((size_t)L * sizeof(float2));
     if (e == hipSuccess)
@@ -1028,7 +1028,7 @@ cgh_status cgh_fresnel_create(cgh_fresnel **out, int32_t n, double pitch_m, doub
         e = f->y.ensure((size_t)n * L * sizeof(float2));
     if (e == hipSuccess)
         e = fresnel_tables(n, m, pitch_m * pitch_m / (2.0 * wavelength_m * z_m),
-                           (float2 *)f->tw.p, (float2 *)f->hc.p, nullptr);
+                           (float4 *)f->tw.p, (float2 *)f->hc.p, nullptr);
     if (e == hipSuccess)
         e = hipStreamSynchronize(nullptr);
     if (e != hipSuccess) {
@@ -1052,7 +1052,7 @@ cgh_status cgh_fresnel_run(cgh_fresnel *f, const float *u_dev, float *out_dev, v
         return fail(CGH_EINVAL, "field or output is NULL");
     DeviceGuard g;
     CGH_HIP(g.set(f->device), "hipSetDevice");
-    CGH_HIP(fresnel_run(f->n, f->m, (const float2 *)f->tw.p, (const float2 *)f->hc.p, f->scale,
+    CGH_HIP(fresnel_run(f->n, f->m, (const float4 *)f->tw.p, (const float2 *)f->hc.p, f->scale,
                         (const float2 *)u_dev, (float2 *)out_dev, (float2 *)f->x.p,
                         (float2 *)f->y.p, (hipStream_t)stream),
             "Fresnel diffraction launch");

@@ -169,15 +169,17 @@ hipError_t launch_gemm_batch(const GemmPlan &plan, FactorType ft, const FactorSe
 hipError_t launch_kinoform(const float *re, const float *im, int64_t n, uint8_t *out,
                            hipStream_t s);
 // F4: Fresnel diffraction of a sampled n x n field (Eq. (10)), n a power of
-// two, L = 2n <= 16384 (m = log2 L).  fresnel_tables fills the twiddle table
-// tw[L] and the transform hc[L] of the 1-D chirp for q = p^2 / (2 lambda z)
-// revolutions per pixel^2; fresnel_run propagates u (n x n complex) to out
-// (n x n), scale = exp(i 2 pi z / lambda) / (i lambda z) p^2 / L^2, with
-// workspaces x and y of n * L complex each.  fresnel_prepare_kernels raises
-// the kernels' LDS limit (once, before any capture).
+// two, L = 2n <= 16384 (m = log2 L).  fresnel_tables fills the transforms'
+// twiddle table tw (fresnel_twiddle_bytes(m) bytes) and the transform hc[L]
+// of the 1-D chirp for q = p^2 / (2 lambda z) revolutions per pixel^2;
+// fresnel_run propagates u (n x n complex) to out (n x n), scale =
+// exp(i 2 pi z / lambda) / (i lambda z) p^2 / L^2, with workspaces x and y of
+// n * L complex each.  fresnel_prepare_kernels raises the kernels' LDS limit
+// (once, before any capture).
 hipError_t fresnel_prepare_kernels();
-hipError_t fresnel_tables(int n, int m, double q, float2 *tw, float2 *hc, hipStream_t s);
-hipError_t fresnel_run(int n, int m, const float2 *tw, const float2 *hc, float2 scale,
+size_t fresnel_twiddle_bytes(int m);
+hipError_t fresnel_tables(int n, int m, double q, float4 *tw, float2 *hc, hipStream_t s);
+hipError_t fresnel_run(int n, int m, const float4 *tw, const float2 *hc, float2 scale,
                        const float2 *u, float2 *out, float2 *x, float2 *y, hipStream_t s);
 
 hipError_t launch_splitk_reduce(const float *partials, int splits, int M, int N, float *out,

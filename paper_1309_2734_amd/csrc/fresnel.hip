@@ -12,10 +12,12 @@
 //     2-D transform of h never exists.  The chirp phase (revolutions,
 //     p^2 a^2 / (2 lambda z), up to ~1e5) is reduced in FP64 before the FP32
 //     exponential.
-//   - 2-D transforms are row transforms with transposes between them; every
-//     row transform runs in LDS (a whole row, up to L = 16384 complex = 128 KB,
-//     in one workgroup) as a Stockham autosort FFT of radix-16 passes (plus one
-//     radix-2/4/8 pass), the small DFTs in registers.  Twiddles come from an
+//   - 2-D transforms are row transforms with transposes between them.  A
+//     row (up to L = 16384 complex) is one workgroup's: each thread holds 16
+//     of its values in registers through a Stockham autosort FFT of radix-16
+//     passes (plus one radix-2/4/8 pass), and LDS only carries the exchange
+//     between two passes (the first pass runs on the values as loaded, the
+//     last leaves the results in registers).  Twiddles come from an
 //     FP64-computed table, kept in LDS as two factors, w^t = w^(64 t_hi)
 //     w^t_lo (64 + L/64 entries), so a pass reads none from global memory.
 //     Inverse transforms are conj(F[conj(x)]).
@@ -107,29 +109,20 @@ __device__ __forceinline__ void dft(float2 *v)
     }
 }
 
-// Twiddle w_L^t from the two LDS factor tables (t < L).
-__device__ __forceinline__ float2 twiddle(const float2 *tw_hi, const float2 *tw_lo, int t)
+// The twiddles w^(r e), r = 1 .. 15, of one radix-16 butterfly from the four
+// table values w^e, w^(2e), w^(4e), w^(8e) (t01 = {w^e, w^2e}, t48 =
+// {w^4e, w^8e}): products of at most four table values, so each carries a
+// few roundings at most.
+__device__ __forceinline__ void butterfly_twiddles(float4 t01, float4 t48, float2 *w)
 {
-    return cmul(tw_hi[t >> 6], tw_lo[t & 63]);
-}
-
-// The twiddles w^(r e), r = 1 .. R-1, of one butterfly: table lookups for
-// r = 1, 2, 4, 8 and products of those (at most three) for the rest, so each
-// carries at most a few roundings; e (R - 1) < L.
-template <int R>
-__device__ __forceinline__ void butterfly_twiddles(const float2 *tw_hi, const float2 *tw_lo,
-                                                   int e, int lmask, float2 *w)
-{
-    float2 p[4];
+    const float2 p[4] = {float2{t01.x, t01.y}, float2{t01.z, t01.w}, float2{t48.x, t48.y},
+                         float2{t48.z, t48.w}};
 #pragma unroll
-    for (int b = 0; (1 << b) < R; ++b)
-        p[b] = twiddle(tw_hi, tw_lo, (e << b) & lmask);
-#pragma unroll
-    for (int r = 1; r < R; ++r) {
+    for (int r = 1; r < 16; ++r) {
         float2 acc{1.0f, 0.0f};
         bool first = true;
 #pragma unroll
-        for (int b = 0; (1 << b) < R; ++b)
+        for (int b = 0; b < 4; ++b)
             if (r & (1 << b)) {
                 acc = first ? p[b] : cmul(acc, p[b]);
                 first = false;
@@ -162,9 +155,26 @@ struct Fft {
     static constexpr int NB0 = 16 / R0;                      // first-pass butterflies per thread
     static constexpr int PASSES = 1 + (M - LR0) / 4;
     static constexpr int ROW_SLOTS = L + L / 16;             // padded row in LDS
-    // LDS: the rows, then the twiddle factors w^t (t < 64) and w^(64 t) (t < L / 64)
-    static constexpr size_t lds_bytes = sizeof(float2) * (ROWS * ROW_SLOTS + 64 + L / 64 + 1);
+    static constexpr size_t lds_bytes = sizeof(float2) * ROWS * ROW_SLOTS;
+    // sub-transform size of radix-16 pass p >= 1, and the first entry of its
+    // twiddle sets in the pass table (one set per k < ns)
+    static constexpr int ns(int p) { return 1 << (LR0 + 4 * (p - 1)); }
+    static constexpr int tw_first(int p) { return p <= 1 ? 0 : tw_first(p - 1) + ns(p - 1); }
+    // LDS addressing with constant offsets needs TR to be a multiple of 16
+    static constexpr bool FAST_SLOTS = M >= 8;
 };
+
+// Entries of the pass twiddle table of a length-2^m transform: one per
+// (radix-16 pass p >= 1, k < ns(p)), each the four values w^e, w^(2e),
+// w^(4e), w^(8e), e = k L / (16 ns(p)), 32 bytes.
+int pass_table_entries(int m)
+{
+    const int lr0 = m % 4 == 0 ? 4 : m % 4;
+    int total = 0;
+    for (int lns = lr0; lns + 4 <= m; lns += 4)
+        total += 1 << lns;
+    return total;
+}
 
 // LDS slot of row position i: one spare slot after every 16 values spreads
 // the strided stores of the early passes over the banks.
@@ -184,16 +194,26 @@ __device__ __forceinline__ int out_pos(int p, int j, int idx)
 }
 
 // Forward transform of one row; x[r] = X[j + r TR] in, x[q] = F[X][j + q TR]
-// out.  s is the row's LDS.  Every thread of the workgroup calls it (it
-// holds barriers).  The twiddle tables must be in LDS by the first barrier.
+// out.  s is the row's LDS, twp the pass twiddle table.  Every thread of the
+// workgroup calls it (it holds barriers).
 template <int M>
 __device__ __forceinline__ void fft_row(float2 (&x)[16], float2 *s, int j,
-                                        const float2 *tw_hi, const float2 *tw_lo)
+                                        const float4 *__restrict__ twp)
 {
     using F = Fft<M>;
-    // Opaque copy of j: the LDS addresses of two transforms in one kernel
-    // are then computed twice instead of being held through both.
+    // Opaque copy of j: the addresses of two transforms in one kernel are
+    // then computed twice instead of being held through both.
     asm volatile("" : "+v"(j));
+    // this thread's twiddle sets, one per radix-16 pass, loaded first (they
+    // do not depend on the data)
+    constexpr int NP = F::PASSES - 1;
+    float4 tq[2 * NP];
+#pragma unroll
+    for (int p = 1; p <= NP; ++p) {
+        const float4 *e = twp + 2 * (F::tw_first(p) + (j & (F::ns(p) - 1)));
+        tq[2 * p - 2] = e[0];
+        tq[2 * p - 1] = e[1];
+    }
 #pragma unroll
     for (int b = 0; b < F::NB0; ++b) {
         float2 v[F::R0];
@@ -206,19 +226,39 @@ __device__ __forceinline__ void fft_row(float2 (&x)[16], float2 *s, int j,
             x[b + q * F::NB0] = v[q];
     }
 #pragma unroll
-    for (int p = 1; p < F::PASSES; ++p) {
+    for (int p = 1; p <= NP; ++p) {
         __syncthreads();   // the previous exchange's reads are done
+        if constexpr (F::FAST_SLOTS) {
+            // slot(out_pos(p - 1, j, idx)) = base + a constant per idx
+            if (p == 1) {
+                float2 *w = s + F::R0 * j + ((F::R0 * j) >> 4);
 #pragma unroll
-        for (int idx = 0; idx < 16; ++idx)
-            s[slot(out_pos<M>(p - 1, j, idx))] = x[idx];
-        __syncthreads();
+                for (int idx = 0; idx < 16; ++idx)
+                    w[idx / F::NB0 + (idx % F::NB0) * (F::R0 * F::TR / 16 * 17)] = x[idx];
+            } else {
+                const int ns = F::ns(p - 1);
+                const int k = j & (ns - 1);
+                float2 *w = s + 17 * (j - k) + k + (k >> 4);
 #pragma unroll
-        for (int r = 0; r < 16; ++r)
-            x[r] = s[slot(j + r * F::TR)];
-        const int lns = F::LR0 + 4 * (p - 1);
-        const int k = j & ((1 << lns) - 1);
+                for (int idx = 0; idx < 16; ++idx)
+                    w[idx * ns + ((idx * ns) >> 4)] = x[idx];
+            }
+            __syncthreads();
+            const float2 *r0 = s + j + (j >> 4);
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                x[r] = r0[r * (F::TR / 16 * 17)];
+        } else {
+#pragma unroll
+            for (int idx = 0; idx < 16; ++idx)
+                s[slot(out_pos<M>(p - 1, j, idx))] = x[idx];
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                x[r] = s[slot(j + r * F::TR)];
+        }
         float2 w[16];
-        butterfly_twiddles<16>(tw_hi, tw_lo, k << (M - lns - 4), F::L - 1, w);
+        butterfly_twiddles(tq[2 * p - 2], tq[2 * p - 1], w);
 #pragma unroll
         for (int r = 1; r < 16; ++r)
             x[r] = cmul(x[r], w[r]);
@@ -240,18 +280,12 @@ template <RowOp OP, int M>
 __global__ __launch_bounds__(Fft<M>::T) __attribute__((amdgpu_waves_per_eu(4))) void k_fft_rows(const float2 *in, int64_t in_ld,
                                                         int in_len, float2 *out, int64_t out_ld,
                                                         int out_len, int n_rows,
-                                                        const float2 *__restrict__ tw,
+                                                        const float4 *__restrict__ twp,
                                                         const float2 *__restrict__ hc,
                                                         float2 scale)
 {
     using F = Fft<M>;
     extern __shared__ float2 lds[];
-    float2 *tw_lo = lds + F::ROWS * F::ROW_SLOTS;
-    float2 *tw_hi = tw_lo + 64;
-    for (int t = threadIdx.x; t < 64; t += F::T)
-        tw_lo[t] = tw[t & (F::L - 1)];
-    for (int t = threadIdx.x; t * 64 < F::L; t += F::T)
-        tw_hi[t] = tw[t * 64];
     const int rl = threadIdx.x / F::TR;
     const int j = threadIdx.x % F::TR;
     const int64_t row = (int64_t)blockIdx.x * F::ROWS + rl;
@@ -271,27 +305,30 @@ __global__ __launch_bounds__(Fft<M>::T) __attribute__((amdgpu_waves_per_eu(4))) 
                 x[r] = OP == RowOp::Inverse ? conjf2(src[i]) : src[i];
         }
     }
-    fft_row<M>(x, s, j, tw_hi, tw_lo);
+    fft_row<M>(x, s, j, twp);
+    float2 crow{1.0f, 0.0f};
     if (OP == RowOp::Fresnel) {
         if (live) {
             // All 17 spectrum loads in flight at once, then the products.
             // The empty asm hides the index from the compiler, so the loads
             // cannot be hoisted into the transform, where they would hold
             // 32 more registers.
+            // The row's factor hc[row] scale is one constant of the whole
+            // row: it commutes with the inverse transform and is applied to
+            // the stored outputs only.
             int jj = j;
             asm volatile("" : "+v"(jj));
             float2 h[16];
-            const float2 hrow = hc[row];
 #pragma unroll
             for (int r = 0; r < 16; ++r)
                 h[r] = hc[jj + r * F::TR];
             __builtin_amdgcn_sched_barrier(0);
-            const float2 hr = cmul(hrow, scale);
 #pragma unroll
             for (int r = 0; r < 16; ++r)
-                x[r] = conjf2(cmul(x[r], cmul(h[r], hr)));
+                x[r] = conjf2(cmul(x[r], h[r]));
+            crow = cmul(hc[row], scale);
         }
-        fft_row<M>(x, s, j, tw_hi, tw_lo);
+        fft_row<M>(x, s, j, twp);
     }
     if (live) {
         // store addresses from here on (hoisted, they would hold 32 registers)
@@ -301,8 +338,14 @@ __global__ __launch_bounds__(Fft<M>::T) __attribute__((amdgpu_waves_per_eu(4))) 
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             const int i = jo + q * F::TR;
-            if (i < out_len)
-                dst[i] = OP == RowOp::Forward ? x[q] : conjf2(x[q]);
+            if (i < out_len) {
+                if (OP == RowOp::Forward)
+                    dst[i] = x[q];
+                else if (OP == RowOp::Inverse)
+                    dst[i] = conjf2(x[q]);
+                else
+                    dst[i] = cmul(conjf2(x[q]), crow);
+            }
         }
     }
 }
@@ -330,14 +373,28 @@ __global__ __launch_bounds__(256) void k_transpose(const float2 *__restrict__ in
     }
 }
 
-// tw[t] = exp(-2 pi i t / L), computed in FP64.
-__global__ void k_twiddles(int m, float2 *tw)
+// The pass twiddle table of a length-2^m transform (layout at
+// pass_table_entries), computed in FP64: w = exp(-2 pi i / L).
+__global__ void k_twiddles(int m, int entries, float4 *tw)
 {
     const int L = 1 << m;
-    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < L; t += gridDim.x * blockDim.x) {
-        double sn, cs;
-        sincospi(2.0 * (double)t / (double)L, &sn, &cs);
-        tw[t] = float2{(float)cs, (float)-sn};
+    const int lr0 = m % 4 == 0 ? 4 : m % 4;
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < entries;
+         t += gridDim.x * blockDim.x) {
+        int first = 0, lns = lr0;
+        while (t >= first + (1 << lns)) {
+            first += 1 << lns;
+            lns += 4;
+        }
+        const int e = (t - first) << (m - lns - 4);
+        float2 v[4];
+        for (int b = 0; b < 4; ++b) {
+            double sn, cs;
+            sincospi(2.0 * (double)((e << b) & (L - 1)) / (double)L, &sn, &cs);
+            v[b] = float2{(float)cs, (float)-sn};
+        }
+        tw[2 * t] = float4{v[0].x, v[0].y, v[1].x, v[1].y};
+        tw[2 * t + 1] = float4{v[2].x, v[2].y, v[3].x, v[3].y};
     }
 }
 
@@ -359,7 +416,7 @@ __global__ void k_chirp(int m, int n, double q, float2 *h)
 
 template <RowOp OP, int M = kMinLog2>
 hipError_t rows(const float2 *in, int64_t in_ld, int in_len, float2 *out, int64_t out_ld,
-                int out_len, int n_rows, int m, const float2 *tw, const float2 *hc, float2 scale,
+                int out_len, int n_rows, int m, const float4 *tw, const float2 *hc, float2 scale,
                 hipStream_t s)
 {
     if constexpr (M > kMaxLog2) {
@@ -409,13 +466,18 @@ hipError_t transpose(const float2 *in, int64_t in_ld, float2 *out, int64_t out_l
 
 hipError_t fresnel_prepare_kernels() { return prepare_rows(); }
 
-hipError_t fresnel_tables(int n, int m, double q, float2 *tw, float2 *hc, hipStream_t s)
+size_t fresnel_twiddle_bytes(int m)
+{
+    return m < kMinLog2 || m > kMaxLog2 ? 0 : (size_t)pass_table_entries(m) * 2 * sizeof(float4);
+}
+
+hipError_t fresnel_tables(int n, int m, double q, float4 *tw, float2 *hc, hipStream_t s)
 {
     if (n < 1 || m < kMinLog2 || m > kMaxLog2 || (2 * n) != (1 << m))
         return hipErrorInvalidValue;
     const int L = 1 << m;
     const unsigned blocks = (unsigned)((L + 255) / 256);
-    hipLaunchKernelGGL(k_twiddles, dim3(blocks), dim3(256), 0, s, m, tw);
+    hipLaunchKernelGGL(k_twiddles, dim3(blocks), dim3(256), 0, s, m, pass_table_entries(m), tw);
     hipLaunchKernelGGL(k_chirp, dim3(blocks), dim3(256), 0, s, m, n, q, hc);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
@@ -424,7 +486,7 @@ hipError_t fresnel_tables(int n, int m, double q, float2 *tw, float2 *hc, hipStr
     return rows<RowOp::Forward>(hc, L, L, hc, L, L, 1, m, tw, nullptr, float2{0.0f, 0.0f}, s);
 }
 
-hipError_t fresnel_run(int n, int m, const float2 *tw, const float2 *hc, float2 scale,
+hipError_t fresnel_run(int n, int m, const float4 *tw, const float2 *hc, float2 scale,
                        const float2 *u, float2 *out, float2 *x, float2 *y, hipStream_t s)
 {
     if (n < 1 || m < kMinLog2 || m > kMaxLog2 || (2 * n) != (1 << m))
