@@ -155,11 +155,16 @@ struct Fft {
     static constexpr int NB0 = 16 / R0;                      // first-pass butterflies per thread
     static constexpr int PASSES = 1 + (M - LR0) / 4;
     static constexpr int ROW_SLOTS = L + L / 16;             // padded row in LDS
-    static constexpr size_t lds_bytes = sizeof(float2) * ROWS * ROW_SLOTS;
+    static constexpr int NP = PASSES - 1;                    // radix-16 passes
     // sub-transform size of radix-16 pass p >= 1, and the first entry of its
     // twiddle sets in the pass table (one set per k < ns)
     static constexpr int ns(int p) { return 1 << (LR0 + 4 * (p - 1)); }
     static constexpr int tw_first(int p) { return p <= 1 ? 0 : tw_first(p - 1) + ns(p - 1); }
+    // LDS: the rows, then the twiddle sets of passes 1 .. NP-1 (the last
+    // pass's set of a thread, k = j, stays in its registers)
+    static constexpr int LDS_SETS = tw_first(NP);
+    static constexpr size_t lds_bytes =
+        sizeof(float2) * ROWS * ROW_SLOTS + 2 * sizeof(float4) * LDS_SETS;
     // LDS addressing with constant offsets needs TR to be a multiple of 16
     static constexpr bool FAST_SLOTS = M >= 8;
 };
@@ -174,6 +179,15 @@ int pass_table_entries(int m)
     for (int lns = lr0; lns + 4 <= m; lns += 4)
         total += 1 << lns;
     return total;
+}
+
+// Workgroup barrier that orders LDS accesses only: global loads issued
+// before it stay in flight (a full barrier would wait for them).
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
 // LDS slot of row position i: one spare slot after every 16 values spreads
@@ -194,26 +208,18 @@ __device__ __forceinline__ int out_pos(int p, int j, int idx)
 }
 
 // Forward transform of one row; x[r] = X[j + r TR] in, x[q] = F[X][j + q TR]
-// out.  s is the row's LDS, twp the pass twiddle table.  Every thread of the
-// workgroup calls it (it holds barriers).
+// out.  s is the row's LDS, sets the LDS copy of the twiddle sets of passes
+// 1 .. NP-1, (l01, l48) this thread's set of the last pass.  Every thread of
+// the workgroup calls it (it holds barriers).
 template <int M>
-__device__ __forceinline__ void fft_row(float2 (&x)[16], float2 *s, int j,
-                                        const float4 *__restrict__ twp)
+__device__ __forceinline__ void fft_row(float2 (&x)[16], float2 *s, int j, const float4 *sets,
+                                        float4 l01, float4 l48)
 {
     using F = Fft<M>;
     // Opaque copy of j: the addresses of two transforms in one kernel are
     // then computed twice instead of being held through both.
     asm volatile("" : "+v"(j));
-    // this thread's twiddle sets, one per radix-16 pass, loaded first (they
-    // do not depend on the data)
-    constexpr int NP = F::PASSES - 1;
-    float4 tq[2 * NP];
-#pragma unroll
-    for (int p = 1; p <= NP; ++p) {
-        const float4 *e = twp + 2 * (F::tw_first(p) + (j & (F::ns(p) - 1)));
-        tq[2 * p - 2] = e[0];
-        tq[2 * p - 1] = e[1];
-    }
+    constexpr int NP = F::NP;
 #pragma unroll
     for (int b = 0; b < F::NB0; ++b) {
         float2 v[F::R0];
@@ -227,7 +233,7 @@ __device__ __forceinline__ void fft_row(float2 (&x)[16], float2 *s, int j,
     }
 #pragma unroll
     for (int p = 1; p <= NP; ++p) {
-        __syncthreads();   // the previous exchange's reads are done
+        lds_barrier();   // the previous exchange's reads are done
         if constexpr (F::FAST_SLOTS) {
             // slot(out_pos(p - 1, j, idx)) = base + a constant per idx
             if (p == 1) {
@@ -243,7 +249,7 @@ __device__ __forceinline__ void fft_row(float2 (&x)[16], float2 *s, int j,
                 for (int idx = 0; idx < 16; ++idx)
                     w[idx * ns + ((idx * ns) >> 4)] = x[idx];
             }
-            __syncthreads();
+            lds_barrier();
             const float2 *r0 = s + j + (j >> 4);
 #pragma unroll
             for (int r = 0; r < 16; ++r)
@@ -252,13 +258,19 @@ __device__ __forceinline__ void fft_row(float2 (&x)[16], float2 *s, int j,
 #pragma unroll
             for (int idx = 0; idx < 16; ++idx)
                 s[slot(out_pos<M>(p - 1, j, idx))] = x[idx];
-            __syncthreads();
+            lds_barrier();
 #pragma unroll
             for (int r = 0; r < 16; ++r)
                 x[r] = s[slot(j + r * F::TR)];
         }
+        float4 t01 = l01, t48 = l48;
+        if (p < NP) {
+            const float4 *te = sets + 2 * (F::tw_first(p) + (j & (F::ns(p) - 1)));
+            t01 = te[0];
+            t48 = te[1];
+        }
         float2 w[16];
-        butterfly_twiddles(tq[2 * p - 2], tq[2 * p - 1], w);
+        butterfly_twiddles(t01, t48, w);
 #pragma unroll
         for (int r = 1; r < 16; ++r)
             x[r] = cmul(x[r], w[r]);
@@ -268,83 +280,111 @@ __device__ __forceinline__ void fft_row(float2 (&x)[16], float2 *s, int j,
 
 enum class RowOp { Forward, Fresnel, Inverse };
 
-// ROWS rows per workgroup.  Loads in[row][0 .. in_len) (zeros beyond), then
-//   Forward: F;   Inverse: conj F conj;
-//   Fresnel: F, times hc[i] hc[row] scale (the spectrum of the separable
-//            impulse response at frequency (row, i), and the constant), then
-//            conj F conj;
-// and stores the first out_len outputs to out[row], rows < n_rows.  in and
-// out may be the same rows (a thread's loads precede its stores, and a row
-// is read by its own threads only).
-template <RowOp OP, int M>
-__global__ __launch_bounds__(Fft<M>::T) __attribute__((amdgpu_waves_per_eu(4))) void k_fft_rows(const float2 *in, int64_t in_ld,
-                                                        int in_len, float2 *out, int64_t out_ld,
-                                                        int out_len, int n_rows,
-                                                        const float4 *__restrict__ twp,
-                                                        const float2 *__restrict__ hc,
-                                                        float2 scale)
+// Row inputs of this thread: x[r] = in[row][j + r TR] for r < NIN, zeros
+// beyond.  No branch: a load under a branch is waited for where the branch
+// joins, which would serialise the loads and end the prefetch.
+template <int M, int NIN>
+__device__ __forceinline__ void load_row(float2 (&x)[16], const float2 *src, int j)
 {
     using F = Fft<M>;
+#pragma unroll
+    for (int r = 0; r < 16; ++r)
+        x[r] = r < NIN ? src[j + r * F::TR] : float2{0.0f, 0.0f};
+}
+
+// Persistent over row groups (ROWS rows each): workgroup b takes groups
+// b, b + G, b + 2G, ... (G = gridDim.x, sized to what is resident at once),
+// and the loads of its next group are in flight while it transforms the
+// current one.  Per row: loads in[row][0 .. n_in) (zeros beyond; n_in = L/2
+// if HALF_IN, else L), then
+//   Forward: F (all L outputs stored);
+//   Inverse: conj F conj (outputs 0 .. L/2 stored);
+//   Fresnel: F, times hc[i] hc[row] scale (the spectrum of the separable
+//            impulse response at frequency (row, i), and the constant), then
+//            conj F conj (outputs 0 .. L/2 stored);
+// into out[row], rows < n_rows.  in and out may be the same rows (a
+// thread's loads of a row precede its stores, and a row is read by its own
+// threads only).  Rows of a last, partial group are computed from a
+// repeated row and not stored.
+template <RowOp OP, int M, bool HALF_IN>
+__global__ __launch_bounds__(Fft<M>::T) __attribute__((amdgpu_waves_per_eu(4))) void k_fft_rows(
+    const float2 *in, int64_t in_ld, float2 *out, int64_t out_ld, int n_rows,
+    const float4 *__restrict__ twp, const float2 *__restrict__ hc, float2 scale)
+{
+    using F = Fft<M>;
+    constexpr int NIN = HALF_IN ? 8 : 16;
+    constexpr int NOUT = OP == RowOp::Forward ? 16 : 8;
     extern __shared__ float2 lds[];
     const int rl = threadIdx.x / F::TR;
     const int j = threadIdx.x % F::TR;
-    const int64_t row = (int64_t)blockIdx.x * F::ROWS + rl;
-    const bool live = row < n_rows;
     float2 *s = lds + rl * F::ROW_SLOTS;
+    float4 *sets = reinterpret_cast<float4 *>(lds + F::ROWS * F::ROW_SLOTS);
+    const int64_t groups = ((int64_t)n_rows + F::ROWS - 1) / F::ROWS;
+    auto row_of = [&](int64_t g) {
+        const int64_t r = g * F::ROWS + rl;
+        return F::ROWS == 1 || r < n_rows ? r : (int64_t)n_rows - 1;
+    };
 
-    float2 x[16];
+    // twiddle sets: passes 1 .. NP-1 to LDS (ordered before their first use
+    // by the transform's first barrier), the last pass's in registers
+    for (int t = threadIdx.x; t < 2 * F::LDS_SETS; t += F::T)
+        sets[t] = twp[t];
+    const float4 *tl = twp + 2 * (F::tw_first(F::NP) + j);
+    const float4 l01 = tl[0], l48 = tl[1];
+
+    float2 xn[16];
+    load_row<M, NIN>(xn, in + row_of(blockIdx.x) * in_ld, j);
+    for (int64_t g = blockIdx.x; g < groups; g += gridDim.x) {
+        const int64_t row = g * F::ROWS + rl;
+        const bool live = F::ROWS == 1 || row < n_rows;
+        const bool more = g + gridDim.x < groups;
+        float2 x[16];
 #pragma unroll
-    for (int r = 0; r < 16; ++r)
-        x[r] = float2{0.0f, 0.0f};
-    if (live) {
-        const float2 *src = in + row * in_ld;
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int i = j + r * F::TR;
-            if (i < in_len)
-                x[r] = OP == RowOp::Inverse ? conjf2(src[i]) : src[i];
-        }
-    }
-    fft_row<M>(x, s, j, twp);
-    float2 crow{1.0f, 0.0f};
-    if (OP == RowOp::Fresnel) {
-        if (live) {
+        for (int r = 0; r < 16; ++r)
+            x[r] = OP == RowOp::Inverse ? conjf2(xn[r]) : xn[r];
+        // The next group's loads, in flight through this group's transforms
+        // (their barriers wait for LDS operations only).  The Fresnel row
+        // issues them after its spectrum loads, which it waits for mid-row.
+        if (OP != RowOp::Fresnel && more)
+            load_row<M, NIN>(xn, in + row_of(g + gridDim.x) * in_ld, j);
+        fft_row<M>(x, s, j, sets, l01, l48);
+        float2 crow{1.0f, 0.0f};
+        if (OP == RowOp::Fresnel) {
             // All 17 spectrum loads in flight at once, then the products.
             // The empty asm hides the index from the compiler, so the loads
             // cannot be hoisted into the transform, where they would hold
-            // 32 more registers.
-            // The row's factor hc[row] scale is one constant of the whole
-            // row: it commutes with the inverse transform and is applied to
-            // the stored outputs only.
+            // 32 more registers.  The row's factor hc[row] scale is one
+            // constant of the whole row: it commutes with the inverse
+            // transform and is applied to the stored outputs.
             int jj = j;
             asm volatile("" : "+v"(jj));
             float2 h[16];
 #pragma unroll
             for (int r = 0; r < 16; ++r)
                 h[r] = hc[jj + r * F::TR];
+            const float2 hrow = hc[row_of(g)];
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int r = 0; r < 16; ++r)
                 x[r] = conjf2(cmul(x[r], h[r]));
-            crow = cmul(hc[row], scale);
+            crow = cmul(hrow, scale);
+            if (more)
+                load_row<M, NIN>(xn, in + row_of(g + gridDim.x) * in_ld, j);
+            fft_row<M>(x, s, j, sets, l01, l48);
         }
-        fft_row<M>(x, s, j, twp);
-    }
-    if (live) {
-        // store addresses from here on (hoisted, they would hold 32 registers)
-        int jo = j;
-        asm volatile("" : "+v"(jo));
-        float2 *dst = out + row * out_ld;
+        if (live) {
+            // store addresses from here on (hoisted, they would hold 32 registers)
+            int jo = j;
+            asm volatile("" : "+v"(jo));
+            float2 *dst = out + row * out_ld + jo;
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int i = jo + q * F::TR;
-            if (i < out_len) {
-                if (OP == RowOp::Forward)
-                    dst[i] = x[q];
-                else if (OP == RowOp::Inverse)
-                    dst[i] = conjf2(x[q]);
-                else
-                    dst[i] = cmul(conjf2(x[q]), crow);
+            for (int q = 0; q < NOUT; ++q) {
+                float2 v = x[q];
+                if (OP == RowOp::Inverse)
+                    v = conjf2(v);
+                else if (OP == RowOp::Fresnel)
+                    v = cmul(conjf2(v), crow);
+                dst[q * F::TR] = v;
             }
         }
     }
@@ -414,24 +454,65 @@ __global__ void k_chirp(int m, int n, double q, float2 *h)
     }
 }
 
+template <RowOp OP, int M, bool HALF_IN>
+hipError_t launch_rows(const float2 *in, int64_t in_ld, float2 *out, int64_t out_ld, int n_rows,
+                       int64_t groups, const float4 *tw, const float2 *hc, float2 scale,
+                       hipStream_t s)
+{
+    using F = Fft<M>;
+    // as many workgroups as are resident at once (queried once per kernel)
+    static int resident = 0;
+    if (resident == 0) {
+        int dev = 0, cus = 0, per_cu = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e == hipSuccess)
+            e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e == hipSuccess)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &per_cu, (const void *)k_fft_rows<OP, M, HALF_IN>, F::T, F::lds_bytes);
+        if (e != hipSuccess)
+            return e;
+        resident = (per_cu > 0 ? per_cu : 1) * (cus > 0 ? cus : 1);
+    }
+    const unsigned grid = (unsigned)(groups < resident ? groups : resident);
+    hipLaunchKernelGGL((k_fft_rows<OP, M, HALF_IN>), dim3(grid), dim3(F::T), F::lds_bytes, s, in,
+                       in_ld, out, out_ld, n_rows, tw, hc, scale);
+    return hipGetLastError();
+}
+
+// Row transforms of n_rows rows of length L = 2^m: n_in inputs per row
+// (L/2 or L; the Fresnel rows take L/2, the inverse rows L) and the stored
+// outputs of the operation (Forward: L, else L/2).
 template <RowOp OP, int M = kMinLog2>
-hipError_t rows(const float2 *in, int64_t in_ld, int in_len, float2 *out, int64_t out_ld,
-                int out_len, int n_rows, int m, const float4 *tw, const float2 *hc, float2 scale,
+hipError_t rows(const float2 *in, int64_t in_ld, int n_in, float2 *out, int64_t out_ld,
+                int n_rows, int m, const float4 *tw, const float2 *hc, float2 scale,
                 hipStream_t s)
 {
     if constexpr (M > kMaxLog2) {
         return hipErrorInvalidValue;
     } else {
         if (m != M)
-            return rows<OP, M + 1>(in, in_ld, in_len, out, out_ld, out_len, n_rows, m, tw, hc,
-                                   scale, s);
+            return rows<OP, M + 1>(in, in_ld, n_in, out, out_ld, n_rows, m, tw, hc, scale, s);
         using F = Fft<M>;
+        const bool half = n_in == F::L / 2;
+        if ((!half && n_in != F::L) || (OP == RowOp::Fresnel && !half) ||
+            (OP == RowOp::Inverse && half))
+            return hipErrorInvalidValue;
         if (n_rows <= 0)
             return hipSuccess;
-        hipLaunchKernelGGL((k_fft_rows<OP, M>), dim3((unsigned)((n_rows + F::ROWS - 1) / F::ROWS)),
-                           dim3(F::T), F::lds_bytes, s, in, in_ld, in_len, out, out_ld, out_len,
-                           n_rows, tw, hc, scale);
-        return hipGetLastError();
+        const int64_t groups = ((int64_t)n_rows + F::ROWS - 1) / F::ROWS;
+        if constexpr (OP == RowOp::Fresnel)
+            return launch_rows<OP, M, true>(in, in_ld, out, out_ld, n_rows, groups, tw, hc, scale,
+                                            s);
+        else if constexpr (OP == RowOp::Inverse)
+            return launch_rows<OP, M, false>(in, in_ld, out, out_ld, n_rows, groups, tw, hc,
+                                             scale, s);
+        else if (half)
+            return launch_rows<OP, M, true>(in, in_ld, out, out_ld, n_rows, groups, tw, hc, scale,
+                                            s);
+        else
+            return launch_rows<OP, M, false>(in, in_ld, out, out_ld, n_rows, groups, tw, hc,
+                                             scale, s);
     }
 }
 
@@ -442,9 +523,10 @@ hipError_t prepare_rows()
         return hipSuccess;
     } else {
         const int lds = (int)Fft<M>::lds_bytes;
-        const void *kernels[] = {(const void *)k_fft_rows<RowOp::Forward, M>,
-                                 (const void *)k_fft_rows<RowOp::Fresnel, M>,
-                                 (const void *)k_fft_rows<RowOp::Inverse, M>};
+        const void *kernels[] = {(const void *)k_fft_rows<RowOp::Forward, M, true>,
+                                 (const void *)k_fft_rows<RowOp::Forward, M, false>,
+                                 (const void *)k_fft_rows<RowOp::Fresnel, M, true>,
+                                 (const void *)k_fft_rows<RowOp::Inverse, M, false>};
         for (const void *k : kernels) {
             hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
             if (e != hipSuccess)
@@ -483,7 +565,7 @@ hipError_t fresnel_tables(int n, int m, double q, float4 *tw, float2 *hc, hipStr
     if (e != hipSuccess)
         return e;
     // hc <- F[h1], in place (one row)
-    return rows<RowOp::Forward>(hc, L, L, hc, L, L, 1, m, tw, nullptr, float2{0.0f, 0.0f}, s);
+    return rows<RowOp::Forward>(hc, L, L, hc, L, 1, m, tw, nullptr, float2{0.0f, 0.0f}, s);
 }
 
 hipError_t fresnel_run(int n, int m, const float4 *tw, const float2 *hc, float2 scale,
@@ -495,21 +577,21 @@ hipError_t fresnel_run(int n, int m, const float4 *tw, const float2 *hc, float2 
     const float2 none{0.0f, 0.0f};
     hipError_t e;
     // rows of u, zero-padded: X[k][0 .. L) = F_row(u[k]), k < n (rows >= n are zero)
-    e = rows<RowOp::Forward>(u, n, n, x, L, L, n, m, tw, nullptr, none, s);
+    e = rows<RowOp::Forward>(u, n, n, x, L, n, m, tw, nullptr, none, s);
     if (e != hipSuccess)
         return e;
     e = transpose(x, L, y, n, n, L, s);                       // Y = X^T: L x n
     if (e != hipSuccess)
         return e;
     // columns: forward transform (n nonzeros), spectrum product, inverse, crop to n
-    e = rows<RowOp::Fresnel>(y, n, n, y, n, n, L, m, tw, hc, scale, s);
+    e = rows<RowOp::Fresnel>(y, n, n, y, n, L, m, tw, hc, scale, s);
     if (e != hipSuccess)
         return e;
     e = transpose(y, n, x, L, L, n, s);                       // X = Y^T: n x L
     if (e != hipSuccess)
         return e;
     // rows: inverse transform, crop to n
-    e = rows<RowOp::Inverse>(x, L, L, out, n, n, n, m, tw, nullptr, none, s);
+    e = rows<RowOp::Inverse>(x, L, L, out, n, n, m, tw, nullptr, none, s);
     return e;
 }
 
