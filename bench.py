@@ -256,9 +256,16 @@ def bench_fresnel(args, torch, cgh, check: bool):
                                   "whole diffraction time"}}
         if check and n == 1024:
             import oracle
-            ref = oracle.diffraction_fft(u.cpu().numpy().astype(np.complex128), p, lam, z)
+            uh = u.cpu().numpy().astype(np.complex128)
+            t0 = time.perf_counter()
+            ref = oracle.diffraction_fft(uh, p, lam, z)
+            cpu_s = time.perf_counter() - t0
             got = out.cpu().numpy().astype(np.complex128)
             r["nrms"] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+            r["cpu_baseline"] = {"value": cpu_s * 1e3, "unit": "ms per diffraction", "cores": 1,
+                                 "kind": "oracle",
+                                 "sample": "the whole n = 1024 diffraction, FP64 Fourier form "
+                                           "(numpy FFTs, one thread)"}
         plan.close()
         log(f"fresnel n={n}: {ms:.3f} ms {r}")
         res[str(n)] = r
