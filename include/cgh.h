@@ -223,8 +223,8 @@ typedef struct cgh_fresnel cgh_fresnel;
 /* Plan for n x n fields: n a power of two in [16, 8192]; pitch_m and
  * wavelength_m finite and > 0; z_m finite and non-zero (negative z
  * propagates backwards); device as for cgh_create.  Allocates 32 n^2 + 16 n
- * bytes of device workspace and computes the transform of the impulse
- * response (blocks until done).
+ * bytes of device workspace plus a twiddle table of at most 5 n bytes, and
+ * computes the transform of the impulse response (blocks until done).
  * Errors: CGH_EINVAL, CGH_EDEVICE, CGH_ENOMEM.  Free with cgh_fresnel_destroy. */
 CGH_API cgh_status cgh_fresnel_create(cgh_fresnel **out, int32_t n, double pitch_m,
                                       double wavelength_m, double z_m, int32_t device);
@@ -232,7 +232,9 @@ CGH_API cgh_status cgh_fresnel_create(cgh_fresnel **out, int32_t n, double pitch
 /* Propagate u_dev to out_dev, both device buffers of n*n complex values
  * stored as interleaved float pairs (re, im), row-major; caller-owned; they
  * may be the same buffer.  Ordered on `stream`.  Calls on one plan must not
- * overlap (they share its workspace).
+ * overlap (they share its workspace).  Five kernel launches and nothing
+ * else, so a call may be captured into a HIP graph (the plan must then
+ * outlive the graph).
  * Errors: CGH_EINVAL (NULL plan or buffer), CGH_EDEVICE (launch failure). */
 CGH_API cgh_status cgh_fresnel_run(cgh_fresnel *f, const float *u_dev, float *out_dev,
                                    void *stream);

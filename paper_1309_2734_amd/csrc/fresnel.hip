@@ -26,6 +26,8 @@
 //     never stored.  The forward column transform, the spectrum product and
 //     the inverse column transform of a column are one kernel, so the L x L
 //     spectrum never reaches HBM.  Five kernels, HBM traffic 18 n^2 x 8 bytes.
+#include <atomic>
+
 #include "common.h"
 
 namespace cgh {
@@ -454,26 +456,41 @@ __global__ void k_chirp(int m, int n, double q, float2 *h)
     }
 }
 
+// Workgroups of a row kernel resident at once on the current device (the
+// persistent grid), queried once per kernel: at plan set-up, so a run that
+// is being captured into a graph makes no query.
 template <RowOp OP, int M, bool HALF_IN>
-hipError_t launch_rows(const float2 *in, int64_t in_ld, float2 *out, int64_t out_ld, int n_rows,
-                       int64_t groups, const float4 *tw, const float2 *hc, float2 scale,
-                       hipStream_t s)
+hipError_t resident_groups(int *out)
 {
-    using F = Fft<M>;
-    // as many workgroups as are resident at once (queried once per kernel)
-    static int resident = 0;
-    if (resident == 0) {
+    static std::atomic<int> cached{0};
+    int r = cached.load(std::memory_order_relaxed);
+    if (r == 0) {
         int dev = 0, cus = 0, per_cu = 0;
         hipError_t e = hipGetDevice(&dev);
         if (e == hipSuccess)
             e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         if (e == hipSuccess)
             e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                &per_cu, (const void *)k_fft_rows<OP, M, HALF_IN>, F::T, F::lds_bytes);
+                &per_cu, (const void *)k_fft_rows<OP, M, HALF_IN>, Fft<M>::T, Fft<M>::lds_bytes);
         if (e != hipSuccess)
             return e;
-        resident = (per_cu > 0 ? per_cu : 1) * (cus > 0 ? cus : 1);
+        r = (per_cu > 0 ? per_cu : 1) * (cus > 0 ? cus : 1);
+        cached.store(r, std::memory_order_relaxed);
     }
+    *out = r;
+    return hipSuccess;
+}
+
+template <RowOp OP, int M, bool HALF_IN>
+hipError_t launch_rows(const float2 *in, int64_t in_ld, float2 *out, int64_t out_ld, int n_rows,
+                       int64_t groups, const float4 *tw, const float2 *hc, float2 scale,
+                       hipStream_t s)
+{
+    using F = Fft<M>;
+    int resident = 0;
+    hipError_t e = resident_groups<OP, M, HALF_IN>(&resident);
+    if (e != hipSuccess)
+        return e;
     const unsigned grid = (unsigned)(groups < resident ? groups : resident);
     hipLaunchKernelGGL((k_fft_rows<OP, M, HALF_IN>), dim3(grid), dim3(F::T), F::lds_bytes, s, in,
                        in_ld, out, out_ld, n_rows, tw, hc, scale);
@@ -532,6 +549,16 @@ hipError_t prepare_rows()
             if (e != hipSuccess)
                 return e;
         }
+        int r = 0;
+        hipError_t e = resident_groups<RowOp::Forward, M, true>(&r);
+        if (e == hipSuccess)
+            e = resident_groups<RowOp::Forward, M, false>(&r);
+        if (e == hipSuccess)
+            e = resident_groups<RowOp::Fresnel, M, true>(&r);
+        if (e == hipSuccess)
+            e = resident_groups<RowOp::Inverse, M, false>(&r);
+        if (e != hipSuccess)
+            return e;
         return prepare_rows<M + 1>();
     }
 }

@@ -117,3 +117,42 @@ def test_run_argument_checks():
         plan.run(torch.zeros((16, 16), dtype=torch.complex64, device="cuda"),
                  torch.zeros((16, 16), dtype=torch.complex64, device="cuda"))
     plan.close()
+
+
+def test_graph_replays_match_eager():
+    """A run captured into a HIP graph (torch's graph capture) replays the
+    eager result bit for bit, with other eager diffraction work and
+    synchronisations between the replays."""
+    import torch
+    n, p, lam, z = 512, 8e-6, 532e-9, 0.04
+    u = torch.from_numpy(field(n, 11)).cuda()
+    plan = cgh.FresnelPlan(n, p, lam, z)
+    eager = torch.empty_like(u)
+    plan.run(u, eager)
+    torch.cuda.synchronize()
+    ref = eager.cpu().numpy()
+    out = torch.empty_like(u)
+    other = cgh.FresnelPlan(256, 4e-6, 633e-9, -0.02)
+    v = torch.from_numpy(field(256, 12)).cuda()
+    w = torch.empty_like(v)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(side):
+        plan.run(u, out, torch.cuda.current_stream())        # warm-up on the side stream
+        side.synchronize()
+        with torch.cuda.graph(g, stream=side):
+            plan.run(u, out, side)
+    torch.cuda.synchronize()
+    for rep in range(4):
+        say(f"graph replay {rep}")
+        out.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), ref), f"replay {rep}"
+        other.run(v, w)                                   # eager work between replays
+        torch.cuda.synchronize()
+    del g
+    plan.close()
+    other.close()
