@@ -84,12 +84,17 @@ TRAFFIC = [
      "sha": "d5d17ae7d96a2dcc", "fetch_kib": 776234.7, "write_kib": 8100.0},
     {"kernel": "direct_fp32", "plan": "16", "src": "paper_1309_2734_amd/csrc/direct.hip",
      "sha": "d5d17ae7d96a2dcc", "fetch_kib": 474243.2, "write_kib": 8100.0},
+    # the five kernels of one n = 8192 diffraction, summed
+    {"kernel": "fresnel_diffraction", "plan": "8192", "src": "paper_1309_2734_amd/csrc/fresnel.hip",
+     "sha": "dc4e102d0ea31476", "fetch_kib": 2373001.9, "write_kib": 4718592.3},
 ]
 TRAFFIC_PLANS = {"gemm_split_mfma": ["384,192,4,2,2,8", "192,384,2,4,2,8"],
-                 "direct_fp32": ["8", "16"]}
+                 "direct_fp32": ["8", "16"], "fresnel_diffraction": ["8192"]}
 
 
 def _plan_in_tuned(kernel: str, plan: str, tuned) -> bool:
+    if kernel == "fresnel_diffraction":
+        return plan == tuned
     if kernel.startswith("direct"):
         return (tuned is None and plan == "16") or bool(tuned and f"rows={plan} " in tuned)
     bm, bn, wm, wn, st, sp = plan.split(",")
@@ -251,9 +256,11 @@ def bench_fresnel(args, torch, cgh, check: bool):
         gbs = 18.0 * n * n * 8 / (ms * 1e-3) / 1e9
         r = {"ms": ms, "hbm_gb_per_s": gbs,
              "roofline": {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                          "frac": gbs / PEAK_HBM_GBS, "traffic": None,
+                          "frac": gbs / PEAK_HBM_GBS,
+                          "traffic": traffic_bytes("fresnel_diffraction", str(n)),
                           "note": "achieved = the five-kernel pipeline's 18 n^2 x 8 B over the "
-                                  "whole diffraction time"}}
+                                  "whole diffraction time; traffic = counter-measured HBM "
+                                  "bytes of one diffraction (recorded for n = 8192)"}}
         if check and n == 1024:
             import oracle
             uh = u.cpu().numpy().astype(np.complex128)
@@ -280,7 +287,8 @@ def traffic_driver(torch, cghgen, cgh) -> int:
     """Kernel sequence for `rocprofv3 --pmc FETCH_SIZE|WRITE_SIZE -- python bench.py
     --traffic-driver`: the per-launch counters of the split-BF16 GEMM in each recorded
     launch shape (3 computes each), of the direct kernel at each recorded row count
-    (2 computes each), and of a plain 256 MiB device copy (3 copies) whose true byte
+    (2 computes each), of the five kernels of a Fresnel diffraction at each recorded
+    size (2 runs), and of a plain 256 MiB device copy (3 copies) whose true byte
     counts calibrate them."""
     c = cghgen.make_config(2)
     ctx = cgh.Context(c.width, c.height, c.pitch, c.wavelength)
@@ -300,6 +308,17 @@ def traffic_driver(torch, cghgen, cgh) -> int:
         torch.cuda.synchronize()
         log(f"traffic driver: direct rows {rows}")
     os.environ.pop("CGH_DIRECT_ROWS", None)
+    for n in TRAFFIC_PLANS["fresnel_diffraction"]:
+        g = torch.Generator(device="cuda:0").manual_seed(int(n))
+        u = torch.randn((int(n), int(n)), dtype=torch.complex64, device="cuda:0", generator=g)
+        o = torch.empty_like(u)
+        plan = cgh.FresnelPlan(int(n), 8e-6, 532e-9, 0.05)
+        for _ in range(2):
+            plan.run(u, o)
+        torch.cuda.synchronize()
+        plan.close()
+        del u, o
+        log(f"traffic driver: Fresnel diffraction n={n}")
     src = torch.ones(64 << 20, device="cuda:0")       # 256 MiB of float32
     dst = torch.empty_like(src)
     for _ in range(3):
