@@ -18,9 +18,12 @@
 //     passes (plus one radix-2/4/8 pass), and LDS only carries the exchange
 //     between two passes (the first pass runs on the values as loaded, the
 //     last leaves the results in registers).  Twiddles come from an
-//     FP64-computed table, kept in LDS as two factors, w^t = w^(64 t_hi)
-//     w^t_lo (64 + L/64 entries), so a pass reads none from global memory.
-//     Inverse transforms are conj(F[conj(x)]).
+//     FP64-computed table of four values per butterfly and pass (w^e, w^2e,
+//     w^4e, w^8e; the other eleven are products of these), copied to LDS
+//     for the early passes and held in registers for the last one.
+//     Workgroups are persistent, and the loads of a workgroup's next row are
+//     in flight while it transforms the current one (its barriers order LDS
+//     only).  Inverse transforms are conj(F[conj(x)]).
 //   - Zero padding and cropping are pruned: rows that are all zero are never
 //     transformed, zeros are never loaded, and outputs outside the crop are
 //     never stored.  The forward column transform, the spectrum product and
