@@ -119,6 +119,53 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+def measured_clock_mhz(run, sync, seconds: float = 0.5):
+    """Shader clock while `run` (one step) repeats for about `seconds`: the
+    current level of the driver's pp_dpm_sclk files, sampled every ~2 ms from a
+    second thread (the step calls release the interpreter lock).  None where
+    the files are not readable."""
+    import glob
+    import re
+    import threading
+    files = glob.glob("/sys/class/drm/card*/device/pp_dpm_sclk")
+    if not files:
+        return None
+    samples, stop = [], threading.Event()
+
+    def sampler():
+        while not stop.is_set():
+            best = 0
+            for f in files:
+                try:
+                    with open(f) as fh:
+                        txt = fh.read()
+                except OSError:
+                    continue
+                for ln in txt.splitlines():
+                    mt = re.search(r"(\d+)\s*mhz\s*\*\s*$", ln.strip(), re.I)
+                    if mt:
+                        best = max(best, int(mt.group(1)))
+            if best:
+                samples.append(best)
+            time.sleep(0.002)
+
+    th = threading.Thread(target=sampler, daemon=True)
+    th.start()
+    t_end = time.perf_counter() + seconds
+    while time.perf_counter() < t_end:
+        for _ in range(20):
+            run()
+        sync()
+    stop.set()
+    th.join()
+    busy = sorted(v for v in samples if v >= 500)     # idle gaps read ~100 MHz
+    if not busy:
+        return None
+    return {"mean": sum(busy) / len(busy), "median": busy[len(busy) // 2], "min": busy[0],
+            "max": busy[-1], "samples": len(busy), "source": "pp_dpm_sclk, sampled every ~2 ms "
+            "while the step repeats for ~0.5 s after its timing"}
+
+
 def bench_batch(args, torch, cghgen, cgh):
     """Side measurement: the batched workload -- F holograms of 1920 x 1080,
     RGB wavelengths cycled, point counts log-uniform in [1e3, 5e4] -- in the
@@ -412,9 +459,10 @@ def main() -> int:
         ctx.compute(out, mode, stream)
         torch.cuda.synchronize()
         sample = out.cpu().numpy()[rows].astype(np.float64)
+        clock = measured_clock_mhz(lambda: ctx.compute(out, mode, stream), torch.cuda.synchronize)
         r = {"ms_per_step": wall_ms, "ms_per_step_events": ev_ms, "pp_per_s": pp / (wall_ms * 1e-3),
              "kernels_ms": {k: v[1] / v[0] for k, v in kern.items()}, "sample": sample,
-             "dtype": MODE_DTYPE[m], "tuned": tuned}
+             "dtype": MODE_DTYPE[m], "tuned": tuned, "clock_mhz": clock}
         if m in ALU_MODES:
             kname, peak = ALU_MODES[m]
             t = r["kernels_ms"].get(kname)
@@ -435,7 +483,12 @@ def main() -> int:
                                  "unit": "TFLOP/s", "frac": ach / peak,
                                  "traffic": traffic_bytes(kname, tuned) if m == "split_bf16"
                                  else None, "kernel": kname, "kernel_ms": t}
-        log(f"mode {m}: {wall_ms:.4f} ms/step, {r['pp_per_s']:.3e} pp/s, kernels {r['kernels_ms']}")
+        if r.get("roofline") and clock:
+            # the same kernel against the peak scaled to the clock it ran at
+            r["roofline"]["frac_at_measured_clock"] = (
+                r["roofline"]["frac"] * CLOCK_HZ / (clock["median"] * 1e6))
+        log(f"mode {m}: {wall_ms:.4f} ms/step, {r['pp_per_s']:.3e} pp/s, kernels {r['kernels_ms']}, "
+            f"clock {clock and round(clock['median'])} MHz")
         results[m] = r
     ctx.close()
 
