@@ -235,7 +235,8 @@ CGH_API cgh_status cgh_fresnel_create(cgh_fresnel **out, int32_t n, double pitch
  * overlap (they share its workspace).  Five kernel launches and nothing
  * else, so a call may be captured into a HIP graph (the plan must then
  * outlive the graph).
- * Errors: CGH_EINVAL (NULL plan or buffer), CGH_EDEVICE (launch failure). */
+ * Errors: CGH_EINVAL (NULL plan or buffer, or a buffer not 8-byte aligned),
+ * CGH_EDEVICE (launch failure). */
 CGH_API cgh_status cgh_fresnel_run(cgh_fresnel *f, const float *u_dev, float *out_dev,
                                    void *stream);
 

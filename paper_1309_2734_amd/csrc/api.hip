@@ -1050,6 +1050,8 @@ cgh_status cgh_fresnel_run(cgh_fresnel *f, const float *u_dev, float *out_dev, v
         return fail(CGH_EINVAL, "plan is NULL");
     if (!u_dev || !out_dev)
         return fail(CGH_EINVAL, "field or output is NULL");
+    if ((uintptr_t)u_dev % 8 != 0 || (uintptr_t)out_dev % 8 != 0)
+        return fail(CGH_EINVAL, "field and output must be 8-byte aligned (complex float pairs)");
     DeviceGuard g;
     CGH_HIP(g.set(f->device), "hipSetDevice");
     CGH_HIP(fresnel_run(f->n, f->m, (const float4 *)f->tw.p, (const float2 *)f->hc.p, f->scale,

@@ -116,6 +116,12 @@ def test_run_argument_checks():
     with pytest.raises(TypeError):
         plan.run(torch.zeros((16, 16), dtype=torch.complex64, device="cuda"),
                  torch.zeros((16, 16), dtype=torch.complex64, device="cuda"))
+    # through the C-ABI: a buffer off its 8-byte alignment is refused before
+    # anything is launched
+    buf = torch.zeros((33, 32), dtype=torch.complex64, device="cuda")
+    assert cgh.lib().cgh_fresnel_run(plan._h, buf.data_ptr() + 4, buf.data_ptr(), None) == cgh.EINVAL
+    assert cgh.lib().cgh_fresnel_run(plan._h, buf.data_ptr(), buf.data_ptr() + 4, None) == cgh.EINVAL
+    torch.cuda.synchronize()
     plan.close()
 
 
