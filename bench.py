@@ -16,8 +16,8 @@ measurements: the 64-frame batched workload ("batch"), the phase-only
 hologram of Eq. (3) of the bench cloud ("kinoform"), and the Fresnel
 diffraction of Eq. (10) at the paper's plane sizes ("fresnel_diffraction").
 
-Prints one JSON line (rank 0).  --gpus N > 1 is refused: this build runs on
-one GPU.
+Prints one JSON line (rank 0).  --gpus N > 1 is refused: the benchmark
+measures one GPU.
 """
 from __future__ import annotations
 
@@ -402,7 +402,8 @@ def main() -> int:
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
+        print("bench.py: the library runs on one GPU per process and this benchmark measures one; "
+              "--gpus must be 1", file=sys.stderr)
         return 2
 
     import torch

@@ -62,7 +62,7 @@ typedef enum {
     CGH_EINVAL = 1,  /* an argument is out of its documented range            */
     CGH_ENOMEM = 2,  /* host or device allocation failed                      */
     CGH_EDEVICE = 3, /* no usable gfx950 device, or a HIP call failed         */
-    CGH_ENOTSUP = 4, /* valid request this build does not support             */
+    CGH_ENOTSUP = 4, /* valid request the library does not support            */
     CGH_ESTATE = 5   /* call out of order (e.g. compute before any upload)    */
 } cgh_status;
 
