@@ -165,11 +165,11 @@ struct Fft {
     // twiddle sets in the pass table (one set per k < ns)
     static constexpr int ns(int p) { return 1 << (LR0 + 4 * (p - 1)); }
     static constexpr int tw_first(int p) { return p <= 1 ? 0 : tw_first(p - 1) + ns(p - 1); }
-    // LDS: the rows, then the twiddle sets of passes 1 .. NP-1 (the last
-    // pass's set of a thread, k = j, stays in its registers)
+    // LDS: the rows, then the 15 twiddles of every set of passes 1 .. NP-1
+    // (the last pass's set of a thread, k = j, stays in its registers as the
+    // four table values)
     static constexpr int LDS_SETS = tw_first(NP);
-    static constexpr size_t lds_bytes =
-        sizeof(float2) * ROWS * ROW_SLOTS + 2 * sizeof(float4) * LDS_SETS;
+    static constexpr size_t lds_bytes = sizeof(float2) * (ROWS * ROW_SLOTS + 15 * LDS_SETS);
     // LDS addressing with constant offsets needs TR to be a multiple of 16
     static constexpr bool FAST_SLOTS = M >= 8;
 };
@@ -213,11 +213,11 @@ __device__ __forceinline__ int out_pos(int p, int j, int idx)
 }
 
 // Forward transform of one row; x[r] = X[j + r TR] in, x[q] = F[X][j + q TR]
-// out.  s is the row's LDS, sets the LDS copy of the twiddle sets of passes
-// 1 .. NP-1, (l01, l48) this thread's set of the last pass.  Every thread of
-// the workgroup calls it (it holds barriers).
+// out.  s is the row's LDS, sets the 15 twiddles of each set of passes
+// 1 .. NP-1 (in LDS), (l01, l48) the table values of this thread's set of
+// the last pass.  Every thread of the workgroup calls it (it holds barriers).
 template <int M>
-__device__ __forceinline__ void fft_row(float2 (&x)[16], float2 *s, int j, const float4 *sets,
+__device__ __forceinline__ void fft_row(float2 (&x)[16], float2 *s, int j, const float2 *sets,
                                         float4 l01, float4 l48)
 {
     using F = Fft<M>;
@@ -268,14 +268,15 @@ __device__ __forceinline__ void fft_row(float2 (&x)[16], float2 *s, int j, const
             for (int r = 0; r < 16; ++r)
                 x[r] = s[slot(j + r * F::TR)];
         }
-        float4 t01 = l01, t48 = l48;
-        if (p < NP) {
-            const float4 *te = sets + 2 * (F::tw_first(p) + (j & (F::ns(p) - 1)));
-            t01 = te[0];
-            t48 = te[1];
-        }
         float2 w[16];
-        butterfly_twiddles(t01, t48, w);
+        if (p < NP) {
+            const float2 *te = sets + 15 * (F::tw_first(p) + (j & (F::ns(p) - 1)));
+#pragma unroll
+            for (int r = 1; r < 16; ++r)
+                w[r] = te[r - 1];
+        } else {
+            butterfly_twiddles(l01, l48, w);
+        }
 #pragma unroll
         for (int r = 1; r < 16; ++r)
             x[r] = cmul(x[r], w[r]);
@@ -323,17 +324,23 @@ __global__ __launch_bounds__(Fft<M>::T) __attribute__((amdgpu_waves_per_eu(4))) 
     const int rl = threadIdx.x / F::TR;
     const int j = threadIdx.x % F::TR;
     float2 *s = lds + rl * F::ROW_SLOTS;
-    float4 *sets = reinterpret_cast<float4 *>(lds + F::ROWS * F::ROW_SLOTS);
+    float2 *sets = lds + F::ROWS * F::ROW_SLOTS;
     const int64_t groups = ((int64_t)n_rows + F::ROWS - 1) / F::ROWS;
     auto row_of = [&](int64_t g) {
         const int64_t r = g * F::ROWS + rl;
         return F::ROWS == 1 || r < n_rows ? r : (int64_t)n_rows - 1;
     };
 
-    // twiddle sets: passes 1 .. NP-1 to LDS (ordered before their first use
-    // by the transform's first barrier), the last pass's in registers
-    for (int t = threadIdx.x; t < 2 * F::LDS_SETS; t += F::T)
-        sets[t] = twp[t];
+    // twiddle sets of passes 1 .. NP-1, expanded to their 15 values in LDS
+    // (ordered before their first use by the transform's first barrier); the
+    // last pass's set stays in registers
+    for (int t = threadIdx.x; t < F::LDS_SETS; t += F::T) {
+        float2 w[16];
+        butterfly_twiddles(twp[2 * t], twp[2 * t + 1], w);
+#pragma unroll
+        for (int r = 1; r < 16; ++r)
+            sets[15 * t + r - 1] = w[r];
+    }
     const float4 *tl = twp + 2 * (F::tw_first(F::NP) + j);
     const float4 l01 = tl[0], l48 = tl[1];
 
