@@ -1028,7 +1028,7 @@ cgh_status cgh_fresnel_create(cgh_fresnel **out, int32_t n, double pitch_m, doub
         e = f->y.ensure((size_t)n * L * sizeof(float2));
     if (e == hipSuccess)
         e = fresnel_tables(n, m, pitch_m * pitch_m / (2.0 * wavelength_m * z_m),
-                           (float4 *)f->tw.p, (float2 *)f->hc.p, nullptr);
+                           (float2 *)f->tw.p, (float2 *)f->hc.p, nullptr);
     if (e == hipSuccess)
         e = hipStreamSynchronize(nullptr);
     if (e != hipSuccess) {
@@ -1054,7 +1054,7 @@ cgh_status cgh_fresnel_run(cgh_fresnel *f, const float *u_dev, float *out_dev, v
         return fail(CGH_EINVAL, "field and output must be 8-byte aligned (complex float pairs)");
     DeviceGuard g;
     CGH_HIP(g.set(f->device), "hipSetDevice");
-    CGH_HIP(fresnel_run(f->n, f->m, (const float4 *)f->tw.p, (const float2 *)f->hc.p, f->scale,
+    CGH_HIP(fresnel_run(f->n, f->m, (const float2 *)f->tw.p, (const float2 *)f->hc.p, f->scale,
                         (const float2 *)u_dev, (float2 *)out_dev, (float2 *)f->x.p,
                         (float2 *)f->y.p, (hipStream_t)stream),
             "Fresnel diffraction launch");

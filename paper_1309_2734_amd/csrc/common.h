@@ -178,8 +178,8 @@ hipError_t launch_kinoform(const float *re, const float *im, int64_t n, uint8_t 
 // (once, before any capture).
 hipError_t fresnel_prepare_kernels();
 size_t fresnel_twiddle_bytes(int m);
-hipError_t fresnel_tables(int n, int m, double q, float4 *tw, float2 *hc, hipStream_t s);
-hipError_t fresnel_run(int n, int m, const float4 *tw, const float2 *hc, float2 scale,
+hipError_t fresnel_tables(int n, int m, double q, float2 *tw, float2 *hc, hipStream_t s);
+hipError_t fresnel_run(int n, int m, const float2 *tw, const float2 *hc, float2 scale,
                        const float2 *u, float2 *out, float2 *x, float2 *y, hipStream_t s);
 
 hipError_t launch_splitk_reduce(const float *partials, int splits, int M, int N, float *out,

@@ -47,56 +47,65 @@ __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return float2{a.x +
 __device__ __forceinline__ float2 csub(float2 a, float2 b) { return float2{a.x - b.x, a.y - b.y}; }
 __device__ __forceinline__ float2 conjf2(float2 a) { return float2{a.x, -a.y}; }
 
-// exp(-2 pi i q / 16), q = 0 .. 15: cos and -sin of multiples of pi / 8
-constexpr float kC8 = 0.923879532511286756f;   // cos(pi / 8)
-constexpr float kS8 = 0.382683432365089772f;   // sin(pi / 8)
-constexpr float kR2 = 0.707106781186547524f;   // cos(pi / 4)
+// cos(2 pi q / 32), q = 0 .. 8
+constexpr float kCos32[9] = {1.0f,
+                             0.980785280403230449f,    // cos(pi / 16)
+                             0.923879532511286756f,    // cos(pi / 8)
+                             0.831469612302545237f,    // cos(3 pi / 16)
+                             0.707106781186547524f,    // cos(pi / 4)
+                             0.555570233019602225f,    // cos(5 pi / 16)
+                             0.382683432365089772f,    // cos(3 pi / 8)
+                             0.195090322016128268f,    // cos(7 pi / 16)
+                             0.0f};
+constexpr float kR2 = 0.707106781186547524f;           // cos(pi / 4)
 
-__device__ __forceinline__ float2 root16(int q)
+constexpr float cos32(int q)
 {
-    constexpr float c[16] = {1.0f, kC8, kR2, kS8, 0.0f, -kS8, -kR2, -kC8,
-                             -1.0f, -kC8, -kR2, -kS8, 0.0f, kS8, kR2, kC8};
-    return float2{c[q & 15], -c[(q + 12) & 15]};   // sin(x) = cos(x - pi/2)
+    q &= 31;
+    return q <= 8 ? kCos32[q] : q <= 16 ? -kCos32[16 - q] : q <= 24 ? -kCos32[q - 16]
+                                                                    : kCos32[32 - q];
 }
 
-// x * exp(-2 pi i Q / 16) with the exact forms of the multiples of pi / 2
+// x * exp(-2 pi i Q / 32) with the exact forms of the multiples of pi / 2
 // (a swap and a sign) and pi / 4 (two products) spelled out.
 template <int Q>
-__device__ __forceinline__ float2 mul_root16(float2 x)
+__device__ __forceinline__ float2 mul_root32(float2 x)
 {
-    constexpr int q = Q & 15;
+    constexpr int q = Q & 31;
     if constexpr (q == 0)
         return x;
-    else if constexpr (q == 4)
-        return float2{x.y, -x.x};                           // * (-i)
     else if constexpr (q == 8)
+        return float2{x.y, -x.x};                           // * (-i)
+    else if constexpr (q == 16)
         return float2{-x.x, -x.y};                          // * (-1)
-    else if constexpr (q == 12)
+    else if constexpr (q == 24)
         return float2{-x.y, x.x};                           // * i
-    else if constexpr (q == 2)
+    else if constexpr (q == 4)
         return float2{kR2 * (x.x + x.y), kR2 * (x.y - x.x)};   // * (1 - i) / sqrt 2
-    else if constexpr (q == 6)
+    else if constexpr (q == 12)
         return float2{kR2 * (x.y - x.x), -kR2 * (x.x + x.y)};  // * (-1 - i) / sqrt 2
-    else if constexpr (q == 10)
+    else if constexpr (q == 20)
         return float2{-kR2 * (x.x + x.y), kR2 * (x.x - x.y)};  // * (-1 + i) / sqrt 2
-    else if constexpr (q == 14)
+    else if constexpr (q == 28)
         return float2{kR2 * (x.x - x.y), kR2 * (x.x + x.y)};   // * (1 + i) / sqrt 2
-    else
-        return cmul(x, root16(q));
+    else {
+        constexpr float c = cos32(q), sn = cos32(q + 24);      // sin(x) = cos(x - pi/2)
+        return cmul(x, float2{c, -sn});
+    }
 }
 
 template <int R, int Q>
 __device__ __forceinline__ void dft_combine(float2 *v, const float2 *e, const float2 *o)
 {
     if constexpr (Q < R / 2) {
-        const float2 t = mul_root16<Q *(16 / R)>(o[Q]);
+        const float2 t = mul_root32<Q *(32 / R)>(o[Q]);
         v[Q] = cadd(e[Q], t);
         v[Q + R / 2] = csub(e[Q], t);
         dft_combine<R, Q + 1>(v, e, o);
     }
 }
 
-// In-register forward DFT of size R (R = 1, 2, 4, 8, 16): v[q] <- sum_r v[r]
+// In-register forward DFT of size R (R = 1, 2, 4, .., 32): v[q] <- sum_r v[r]
 // exp(-2 pi i r q / R), by radix-2 decimation in time.
 template <int R>
 __device__ __forceinline__ void dft(float2 *v)
@@ -114,20 +123,18 @@ __device__ __forceinline__ void dft(float2 *v)
     }
 }
 
-// The twiddles w^(r e), r = 1 .. 15, of one radix-16 butterfly from the four
-// table values w^e, w^(2e), w^(4e), w^(8e) (t01 = {w^e, w^2e}, t48 =
-// {w^4e, w^8e}): products of at most four table values, so each carries a
-// few roundings at most.
-__device__ __forceinline__ void butterfly_twiddles(float4 t01, float4 t48, float2 *w)
+// The twiddles w^(r e), r = 1 .. 2^LV - 1, of one radix-2^LV butterfly from
+// the LV table values p[b] = w^(2^b e): products of at most LV table values,
+// so each carries a few roundings at most.
+template <int LV>
+__device__ __forceinline__ void butterfly_twiddles(const float2 *p, float2 *w)
 {
-    const float2 p[4] = {float2{t01.x, t01.y}, float2{t01.z, t01.w}, float2{t48.x, t48.y},
-                         float2{t48.z, t48.w}};
 #pragma unroll
-    for (int r = 1; r < 16; ++r) {
+    for (int r = 1; r < (1 << LV); ++r) {
         float2 acc{1.0f, 0.0f};
         bool first = true;
 #pragma unroll
-        for (int b = 0; b < 4; ++b)
+        for (int b = 0; b < LV; ++b)
             if (r & (1 << b)) {
                 acc = first ? p[b] : cmul(acc, p[b]);
                 first = false;
@@ -136,52 +143,62 @@ __device__ __forceinline__ void butterfly_twiddles(float4 t01, float4 t48, float
     }
 }
 
-// Shape of a row transform of length L = 2^M.  Every thread holds 16
-// values of its row in registers, so a row takes TR = L / 16 threads and a
-// workgroup takes ROWS rows (at least one wave).  The transform is a Stockham
-// autosort FFT: one radix-R0 pass (R0 = 2^(M mod 4), or 16), then radix-16
-// passes.  Pass with sub-transform size ns and radix R: butterfly b
-// (k = b mod ns) takes X[b + r L/R], multiplies input r by w^(r k L/(ns R))
-// (w = exp(-2 pi i / L)), applies the size-R DFT and puts output q at
-// (b - k) R + k + q ns.  Thread j's values are X[j + r TR] (r < 16): exactly
-// the inputs of its butterflies in every pass, and, after the last pass
-// (ns = TR), the outputs X[j + q TR] in natural order.  So the first pass
-// runs on the values as loaded, the last one leaves results in registers,
-// and LDS only carries the exchange between two passes.
+// log2 of the values a thread holds for a row of length 2^m: 32 for the
+// longest rows (one exchange fewer per transform), else 16
+constexpr int values_log2(int m) { return m >= 13 ? 5 : 4; }
+
+// Shape of a row transform of length L = 2^M.  Every thread holds V values
+// of its row in registers (V = 16, or 32 for the longest rows), so a row
+// takes TR = L / V threads and a workgroup takes ROWS rows (at least one
+// wave).  The transform is a Stockham autosort FFT: one radix-R0 pass
+// (R0 = 2^(M mod log2 V), or V), then radix-V passes.  Pass with
+// sub-transform size ns and radix R: butterfly b (k = b mod ns) takes
+// X[b + r L/R], multiplies input r by w^(r k L/(ns R)) (w = exp(-2 pi i / L)),
+// applies the size-R DFT and puts output q at (b - k) R + k + q ns.  Thread
+// j's values are X[j + r TR] (r < V): exactly the inputs of its butterflies
+// in every pass, and, after the last pass (ns = TR), the outputs X[j + q TR]
+// in natural order.  So the first pass runs on the values as loaded, the
+// last one leaves results in registers, and LDS only carries the exchange
+// between two passes.
 template <int M>
 struct Fft {
     static_assert(M >= kMinLog2 && M <= kMaxLog2, "row length");
     static constexpr int L = 1 << M;
-    static constexpr int TR = L / 16;                        // threads per row
+    static constexpr int LV = values_log2(M);
+    static constexpr int V = 1 << LV;                        // values per thread
+    static constexpr int TR = L / V;                         // threads per row
     static constexpr int ROWS = TR >= 64 ? 1 : 64 / TR;      // rows per workgroup
     static constexpr int T = TR * ROWS;                      // threads per workgroup
-    static constexpr int LR0 = M % 4 == 0 ? 4 : M % 4;       // log2 of the first radix
+    static constexpr int LR0 = M % LV == 0 ? LV : M % LV;    // log2 of the first radix
     static constexpr int R0 = 1 << LR0;
-    static constexpr int NB0 = 16 / R0;                      // first-pass butterflies per thread
-    static constexpr int PASSES = 1 + (M - LR0) / 4;
+    static constexpr int NB0 = V / R0;                       // first-pass butterflies per thread
+    static constexpr int PASSES = 1 + (M - LR0) / LV;
     static constexpr int ROW_SLOTS = L + L / 16;             // padded row in LDS
-    static constexpr int NP = PASSES - 1;                    // radix-16 passes
-    // sub-transform size of radix-16 pass p >= 1, and the first entry of its
+    static constexpr int NP = PASSES - 1;                    // radix-V passes
+    // sub-transform size of radix-V pass p >= 1, and the first entry of its
     // twiddle sets in the pass table (one set per k < ns)
-    static constexpr int ns(int p) { return 1 << (LR0 + 4 * (p - 1)); }
+    static constexpr int ns(int p) { return 1 << (LR0 + LV * (p - 1)); }
     static constexpr int tw_first(int p) { return p <= 1 ? 0 : tw_first(p - 1) + ns(p - 1); }
-    // LDS: the rows, then the 15 twiddles of every set of passes 1 .. NP-1
-    // (the last pass's set of a thread, k = j, stays in its registers as the
-    // four table values)
+    // LDS: the rows, then the V - 1 twiddles of every set of passes
+    // 1 .. NP-1 (the last pass's set of a thread, k = j, stays in its
+    // registers as the LV table values)
     static constexpr int LDS_SETS = tw_first(NP);
-    static constexpr size_t lds_bytes = sizeof(float2) * (ROWS * ROW_SLOTS + 15 * LDS_SETS);
+    static constexpr size_t lds_bytes = sizeof(float2) * (ROWS * ROW_SLOTS + (V - 1) * LDS_SETS);
     // LDS addressing with constant offsets needs TR to be a multiple of 16
-    static constexpr bool FAST_SLOTS = M >= 8;
+    static constexpr bool FAST_SLOTS = TR % 16 == 0;
+    // waves per SIMD the register budget is sized for
+    static constexpr int WAVES_PER_EU = V == 32 ? 2 : 4;
 };
 
 // Entries of the pass twiddle table of a length-2^m transform: one per
-// (radix-16 pass p >= 1, k < ns(p)), each the four values w^e, w^(2e),
-// w^(4e), w^(8e), e = k L / (16 ns(p)), 32 bytes.
+// (radix-V pass p >= 1, k < ns(p)), each the LV = log2 V values w^e, w^(2e),
+// .., w^(2^(LV-1) e), e = k L / (V ns(p)).
 int pass_table_entries(int m)
 {
-    const int lr0 = m % 4 == 0 ? 4 : m % 4;
+    const int lv = values_log2(m);
+    const int lr0 = m % lv == 0 ? lv : m % lv;
     int total = 0;
-    for (int lns = lr0; lns + 4 <= m; lns += 4)
+    for (int lns = lr0; lns + lv <= m; lns += lv)
         total += 1 << lns;
     return total;
 }
@@ -207,20 +224,21 @@ __device__ __forceinline__ int out_pos(int p, int j, int idx)
     using F = Fft<M>;
     if (p == 0)   // butterfly j + b TR, output q, held in x[b + q NB0]
         return (j + (idx % F::NB0) * F::TR) * F::R0 + idx / F::NB0;
-    const int ns = 1 << (F::LR0 + 4 * (p - 1));
+    const int ns = F::ns(p);
     const int k = j & (ns - 1);
-    return ((j - k) << 4) + k + idx * ns;
+    return (j - k) * F::V + k + idx * ns;
 }
 
 // Forward transform of one row; x[r] = X[j + r TR] in, x[q] = F[X][j + q TR]
-// out.  s is the row's LDS, sets the 15 twiddles of each set of passes
-// 1 .. NP-1 (in LDS), (l01, l48) the table values of this thread's set of
-// the last pass.  Every thread of the workgroup calls it (it holds barriers).
+// out.  s is the row's LDS, sets the V - 1 twiddles of each set of passes
+// 1 .. NP-1 (in LDS), lt the LV table values of this thread's set of the last
+// pass.  Every thread of the workgroup calls it (it holds barriers).
 template <int M>
-__device__ __forceinline__ void fft_row(float2 (&x)[16], float2 *s, int j, const float2 *sets,
-                                        float4 l01, float4 l48)
+__device__ __forceinline__ void fft_row(float2 (&x)[Fft<M>::V], float2 *s, int j,
+                                        const float2 *sets, const float2 (&lt)[Fft<M>::LV])
 {
     using F = Fft<M>;
+    constexpr int V = F::V;
     // Opaque copy of j: the addresses of two transforms in one kernel are
     // then computed twice instead of being held through both.
     asm volatile("" : "+v"(j));
@@ -244,43 +262,45 @@ __device__ __forceinline__ void fft_row(float2 (&x)[16], float2 *s, int j, const
             if (p == 1) {
                 float2 *w = s + F::R0 * j + ((F::R0 * j) >> 4);
 #pragma unroll
-                for (int idx = 0; idx < 16; ++idx)
-                    w[idx / F::NB0 + (idx % F::NB0) * (F::R0 * F::TR / 16 * 17)] = x[idx];
+                for (int idx = 0; idx < V; ++idx) {
+                    const int q = idx / F::NB0, b = idx % F::NB0;
+                    w[q + (F::R0 >= 16 ? q >> 4 : 0) + b * (F::R0 * F::TR / 16 * 17)] = x[idx];
+                }
             } else {
                 const int ns = F::ns(p - 1);
                 const int k = j & (ns - 1);
-                float2 *w = s + 17 * (j - k) + k + (k >> 4);
+                float2 *w = s + (V / 16 * 17) * (j - k) + k + (k >> 4);
 #pragma unroll
-                for (int idx = 0; idx < 16; ++idx)
+                for (int idx = 0; idx < V; ++idx)
                     w[idx * ns + ((idx * ns) >> 4)] = x[idx];
             }
             lds_barrier();
             const float2 *r0 = s + j + (j >> 4);
 #pragma unroll
-            for (int r = 0; r < 16; ++r)
+            for (int r = 0; r < V; ++r)
                 x[r] = r0[r * (F::TR / 16 * 17)];
         } else {
 #pragma unroll
-            for (int idx = 0; idx < 16; ++idx)
+            for (int idx = 0; idx < V; ++idx)
                 s[slot(out_pos<M>(p - 1, j, idx))] = x[idx];
             lds_barrier();
 #pragma unroll
-            for (int r = 0; r < 16; ++r)
+            for (int r = 0; r < V; ++r)
                 x[r] = s[slot(j + r * F::TR)];
         }
-        float2 w[16];
+        float2 w[V];
         if (p < NP) {
-            const float2 *te = sets + 15 * (F::tw_first(p) + (j & (F::ns(p) - 1)));
+            const float2 *te = sets + (V - 1) * (F::tw_first(p) + (j & (F::ns(p) - 1)));
 #pragma unroll
-            for (int r = 1; r < 16; ++r)
+            for (int r = 1; r < V; ++r)
                 w[r] = te[r - 1];
         } else {
-            butterfly_twiddles(l01, l48, w);
+            butterfly_twiddles<F::LV>(lt, w);
         }
 #pragma unroll
-        for (int r = 1; r < 16; ++r)
+        for (int r = 1; r < V; ++r)
             x[r] = cmul(x[r], w[r]);
-        dft<16>(x);
+        dft<V>(x);
     }
 }
 
@@ -290,11 +310,11 @@ enum class RowOp { Forward, Fresnel, Inverse };
 // beyond.  No branch: a load under a branch is waited for where the branch
 // joins, which would serialise the loads and end the prefetch.
 template <int M, int NIN>
-__device__ __forceinline__ void load_row(float2 (&x)[16], const float2 *src, int j)
+__device__ __forceinline__ void load_row(float2 (&x)[Fft<M>::V], const float2 *src, int j)
 {
     using F = Fft<M>;
 #pragma unroll
-    for (int r = 0; r < 16; ++r)
+    for (int r = 0; r < F::V; ++r)
         x[r] = r < NIN ? src[j + r * F::TR] : float2{0.0f, 0.0f};
 }
 
@@ -313,13 +333,16 @@ __device__ __forceinline__ void load_row(float2 (&x)[16], const float2 *src, int
 // threads only).  Rows of a last, partial group are computed from a
 // repeated row and not stored.
 template <RowOp OP, int M, bool HALF_IN>
-__global__ __launch_bounds__(Fft<M>::T) __attribute__((amdgpu_waves_per_eu(4))) void k_fft_rows(
-    const float2 *in, int64_t in_ld, float2 *out, int64_t out_ld, int n_rows,
-    const float4 *__restrict__ twp, const float2 *__restrict__ hc, float2 scale)
+__global__ __launch_bounds__(Fft<M>::T) __attribute__((amdgpu_waves_per_eu(
+    Fft<M>::WAVES_PER_EU))) void k_fft_rows(const float2 *in, int64_t in_ld, float2 *out,
+                                            int64_t out_ld, int n_rows,
+                                            const float2 *__restrict__ twp,
+                                            const float2 *__restrict__ hc, float2 scale)
 {
     using F = Fft<M>;
-    constexpr int NIN = HALF_IN ? 8 : 16;
-    constexpr int NOUT = OP == RowOp::Forward ? 16 : 8;
+    constexpr int V = F::V;
+    constexpr int NIN = HALF_IN ? V / 2 : V;
+    constexpr int NOUT = OP == RowOp::Forward ? V : V / 2;
     extern __shared__ float2 lds[];
     const int rl = threadIdx.x / F::TR;
     const int j = threadIdx.x % F::TR;
@@ -331,61 +354,63 @@ __global__ __launch_bounds__(Fft<M>::T) __attribute__((amdgpu_waves_per_eu(4))) 
         return F::ROWS == 1 || r < n_rows ? r : (int64_t)n_rows - 1;
     };
 
-    // twiddle sets of passes 1 .. NP-1, expanded to their 15 values in LDS
-    // (ordered before their first use by the transform's first barrier); the
-    // last pass's set stays in registers
+    // twiddle sets of passes 1 .. NP-1, expanded to their V - 1 values in
+    // LDS (ordered before their first use by the transform's first barrier);
+    // the last pass's set stays in registers
     for (int t = threadIdx.x; t < F::LDS_SETS; t += F::T) {
-        float2 w[16];
-        butterfly_twiddles(twp[2 * t], twp[2 * t + 1], w);
+        float2 w[V];
+        butterfly_twiddles<F::LV>(twp + F::LV * t, w);
 #pragma unroll
-        for (int r = 1; r < 16; ++r)
-            sets[15 * t + r - 1] = w[r];
+        for (int r = 1; r < V; ++r)
+            sets[(V - 1) * t + r - 1] = w[r];
     }
-    const float4 *tl = twp + 2 * (F::tw_first(F::NP) + j);
-    const float4 l01 = tl[0], l48 = tl[1];
+    float2 lt[F::LV];
+#pragma unroll
+    for (int b = 0; b < F::LV; ++b)
+        lt[b] = twp[F::LV * (F::tw_first(F::NP) + j) + b];
 
-    float2 xn[16];
+    float2 xn[V];
     load_row<M, NIN>(xn, in + row_of(blockIdx.x) * in_ld, j);
     for (int64_t g = blockIdx.x; g < groups; g += gridDim.x) {
         const int64_t row = g * F::ROWS + rl;
         const bool live = F::ROWS == 1 || row < n_rows;
         const bool more = g + gridDim.x < groups;
-        float2 x[16];
+        float2 x[V];
 #pragma unroll
-        for (int r = 0; r < 16; ++r)
+        for (int r = 0; r < V; ++r)
             x[r] = OP == RowOp::Inverse ? conjf2(xn[r]) : xn[r];
         // The next group's loads, in flight through this group's transforms
         // (their barriers wait for LDS operations only).  The Fresnel row
         // issues them after its spectrum loads, which it waits for mid-row.
         if (OP != RowOp::Fresnel && more)
             load_row<M, NIN>(xn, in + row_of(g + gridDim.x) * in_ld, j);
-        fft_row<M>(x, s, j, sets, l01, l48);
+        fft_row<M>(x, s, j, sets, lt);
         float2 crow{1.0f, 0.0f};
         if (OP == RowOp::Fresnel) {
-            // All 17 spectrum loads in flight at once, then the products.
+            // All V + 1 spectrum loads in flight at once, then the products.
             // The empty asm hides the index from the compiler, so the loads
             // cannot be hoisted into the transform, where they would hold
-            // 32 more registers.  The row's factor hc[row] scale is one
+            // 2 V more registers.  The row's factor hc[row] scale is one
             // constant of the whole row: it commutes with the inverse
             // transform and is applied to the stored outputs.
             int jj = j;
             asm volatile("" : "+v"(jj));
-            float2 h[16];
+            float2 h[V];
 #pragma unroll
-            for (int r = 0; r < 16; ++r)
+            for (int r = 0; r < V; ++r)
                 h[r] = hc[jj + r * F::TR];
             const float2 hrow = hc[row_of(g)];
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int r = 0; r < 16; ++r)
+            for (int r = 0; r < V; ++r)
                 x[r] = conjf2(cmul(x[r], h[r]));
             crow = cmul(hrow, scale);
             if (more)
                 load_row<M, NIN>(xn, in + row_of(g + gridDim.x) * in_ld, j);
-            fft_row<M>(x, s, j, sets, l01, l48);
+            fft_row<M>(x, s, j, sets, lt);
         }
         if (live) {
-            // store addresses from here on (hoisted, they would hold 32 registers)
+            // store addresses from here on (hoisted, they would hold 2 V registers)
             int jo = j;
             asm volatile("" : "+v"(jo));
             float2 *dst = out + row * out_ld + jo;
@@ -427,26 +452,24 @@ __global__ __launch_bounds__(256) void k_transpose(const float2 *__restrict__ in
 
 // The pass twiddle table of a length-2^m transform (layout at
 // pass_table_entries), computed in FP64: w = exp(-2 pi i / L).
-__global__ void k_twiddles(int m, int entries, float4 *tw)
+__global__ void k_twiddles(int m, int entries, float2 *tw)
 {
     const int L = 1 << m;
-    const int lr0 = m % 4 == 0 ? 4 : m % 4;
+    const int lv = values_log2(m);
+    const int lr0 = m % lv == 0 ? lv : m % lv;
     for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < entries;
          t += gridDim.x * blockDim.x) {
         int first = 0, lns = lr0;
         while (t >= first + (1 << lns)) {
             first += 1 << lns;
-            lns += 4;
+            lns += lv;
         }
-        const int e = (t - first) << (m - lns - 4);
-        float2 v[4];
-        for (int b = 0; b < 4; ++b) {
+        const int e = (t - first) << (m - lns - lv);
+        for (int b = 0; b < lv; ++b) {
             double sn, cs;
             sincospi(2.0 * (double)((e << b) & (L - 1)) / (double)L, &sn, &cs);
-            v[b] = float2{(float)cs, (float)-sn};
+            tw[lv * t + b] = float2{(float)cs, (float)-sn};
         }
-        tw[2 * t] = float4{v[0].x, v[0].y, v[1].x, v[1].y};
-        tw[2 * t + 1] = float4{v[2].x, v[2].y, v[3].x, v[3].y};
     }
 }
 
@@ -493,7 +516,7 @@ hipError_t resident_groups(int *out)
 
 template <RowOp OP, int M, bool HALF_IN>
 hipError_t launch_rows(const float2 *in, int64_t in_ld, float2 *out, int64_t out_ld, int n_rows,
-                       int64_t groups, const float4 *tw, const float2 *hc, float2 scale,
+                       int64_t groups, const float2 *tw, const float2 *hc, float2 scale,
                        hipStream_t s)
 {
     using F = Fft<M>;
@@ -512,7 +535,7 @@ hipError_t launch_rows(const float2 *in, int64_t in_ld, float2 *out, int64_t out
 // outputs of the operation (Forward: L, else L/2).
 template <RowOp OP, int M = kMinLog2>
 hipError_t rows(const float2 *in, int64_t in_ld, int n_in, float2 *out, int64_t out_ld,
-                int n_rows, int m, const float4 *tw, const float2 *hc, float2 scale,
+                int n_rows, int m, const float2 *tw, const float2 *hc, float2 scale,
                 hipStream_t s)
 {
     if constexpr (M > kMaxLog2) {
@@ -587,10 +610,12 @@ hipError_t fresnel_prepare_kernels() { return prepare_rows(); }
 
 size_t fresnel_twiddle_bytes(int m)
 {
-    return m < kMinLog2 || m > kMaxLog2 ? 0 : (size_t)pass_table_entries(m) * 2 * sizeof(float4);
+    return m < kMinLog2 || m > kMaxLog2
+               ? 0
+               : (size_t)pass_table_entries(m) * values_log2(m) * sizeof(float2);
 }
 
-hipError_t fresnel_tables(int n, int m, double q, float4 *tw, float2 *hc, hipStream_t s)
+hipError_t fresnel_tables(int n, int m, double q, float2 *tw, float2 *hc, hipStream_t s)
 {
     if (n < 1 || m < kMinLog2 || m > kMaxLog2 || (2 * n) != (1 << m))
         return hipErrorInvalidValue;
@@ -605,7 +630,7 @@ hipError_t fresnel_tables(int n, int m, double q, float4 *tw, float2 *hc, hipStr
     return rows<RowOp::Forward>(hc, L, L, hc, L, 1, m, tw, nullptr, float2{0.0f, 0.0f}, s);
 }
 
-hipError_t fresnel_run(int n, int m, const float4 *tw, const float2 *hc, float2 scale,
+hipError_t fresnel_run(int n, int m, const float2 *tw, const float2 *hc, float2 scale,
                        const float2 *u, float2 *out, float2 *x, float2 *y, hipStream_t s)
 {
     if (n < 1 || m < kMinLog2 || m > kMaxLog2 || (2 * n) != (1 << m))
