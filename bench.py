@@ -86,7 +86,7 @@ TRAFFIC = [
      "sha": "d5d17ae7d96a2dcc", "fetch_kib": 474243.2, "write_kib": 8100.0},
     # the five kernels of one n = 8192 diffraction, summed
     {"kernel": "fresnel_diffraction", "plan": "8192", "src": "paper_1309_2734_amd/csrc/fresnel.hip",
-     "sha": "9beeb5555191f7f8", "fetch_kib": 2373468.5, "write_kib": 4718593.0},
+     "sha": "c493e180b5d1e9be", "fetch_kib": 2376938.1, "write_kib": 4718593.0},
 ]
 TRAFFIC_PLANS = {"gemm_split_mfma": ["384,192,4,2,2,8", "192,384,2,4,2,8"],
                  "direct_fp32": ["8", "16"], "fresnel_diffraction": ["8192"]}

@@ -14,13 +14,14 @@
 //     exponential.
 //   - 2-D transforms are row transforms with transposes between them.  A
 //     row (up to L = 16384 complex) is one workgroup's: each thread holds 16
-//     of its values in registers through a Stockham autosort FFT of radix-16
-//     passes (plus one radix-2/4/8 pass), and LDS only carries the exchange
+//     of its values (32 for rows of 8192 and more) in registers through a
+//     Stockham autosort FFT of radix-16 (radix-32) passes plus one smaller
+//     pass, and LDS only carries the exchange
 //     between two passes (the first pass runs on the values as loaded, the
 //     last leaves the results in registers).  Twiddles come from an
-//     FP64-computed table of four values per butterfly and pass (w^e, w^2e,
-//     w^4e, w^8e; the other eleven are products of these), copied to LDS
-//     for the early passes and held in registers for the last one.
+//     FP64-computed table of log2 V values per butterfly and pass (w^e,
+//     w^2e, w^4e, ..; the other twiddles are products of these), expanded
+//     into LDS for the early passes and held in registers for the last one.
 //     Workgroups are persistent, and the loads of a workgroup's next row are
 //     in flight while it transforms the current one (its barriers order LDS
 //     only).  Inverse transforms are conj(F[conj(x)]).
@@ -37,7 +38,7 @@ namespace cgh {
 namespace {
 
 constexpr int kMinLog2 = 5;                // L >= 32 (n >= 16)
-constexpr int kMaxLog2 = 14;               // L <= 16384: a row is 136 KB of LDS, 1024 threads
+constexpr int kMaxLog2 = 14;               // L <= 16384: a row is 136 KB of LDS, 512 threads
 
 __device__ __forceinline__ float2 cmul(float2 a, float2 b)
 {
