@@ -226,10 +226,19 @@ def bench_kinoform(args, torch, cghgen, cgh, check: bool):
     field = torch.empty((2, H, W), device="cuda:0")
     rows = np.arange(0, H, 16)
     ref = None
+    cpu = None
     if check:
         import oracle
+        t0 = time.perf_counter()
         ref = oracle.fresnel_complex(W, H, c.pitch, c.wavelength, c.x, c.y, c.z, c.amp,
                                      rows=rows, threads=oracle.host_threads())
+        dt = time.perf_counter() - t0
+        spp = len(rows) * W * N
+        cpu = {"value": spp / dt, "unit": "point*pixel/s", "cores": oracle.host_threads(),
+               "kind": "oracle",
+               "sample": f"complex field (Eq. (2)) of every 16th row ({len(rows)} rows x {W} "
+                         f"columns), all {N} points: {spp:.3e} point*pixels in {dt:.1f} s; "
+                         f"codes taken from it in FP64"}
     res = {}
     for m in ("split_bf16", "separable_fp32", "direct_fp32"):
         mode = cgh.MODES[m]
@@ -270,7 +279,8 @@ def bench_kinoform(args, torch, cghgen, cgh, check: bool):
     return {"workload": "phase-only hologram (Eq. 3) of the 1920x1080, 10000-point cloud: "
                         "complex field + 8-bit phase codes", "modes": res,
             "check": "codes on every 16th row vs the FP64 oracle field, where the device "
-                     "field's error cannot cross a code boundary" if check else None}
+                     "field's error cannot cross a code boundary" if check else None,
+            "cpu_baseline": cpu}
 
 
 def bench_fresnel(args, torch, cgh, check: bool):
@@ -523,8 +533,17 @@ def main() -> int:
             if m == "spherical_fp32":
                 # Eq. (1) has its own reference: every 4th sample row
                 srows = rows[::4]
+                t0 = time.perf_counter()
                 sph_ref = orc.spherical_complex(W, H, c.pitch, c.wavelength, c.x, c.y, c.z,
                                                 c.amp, rows=srows, threads=threads)[0]
+                dt = time.perf_counter() - t0
+                spp = len(srows) * W * N
+                r["cpu_baseline"] = {"value": spp / dt, "unit": "point*pixel/s", "cores": threads,
+                                     "kind": "oracle",
+                                     "sample": f"Eq. (1) with its imaginary part, every "
+                                               f"{4 * args.sample_row_step}th row ({len(srows)} "
+                                               f"rows x {W} columns), all {N} points: "
+                                               f"{spp:.3e} point*pixels in {dt:.1f} s"}
                 got, want = r["sample"][::4], sph_ref
             else:
                 got, want = r["sample"], ref
