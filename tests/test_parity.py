@@ -165,6 +165,22 @@ def test_ragged_hologram_sizes(wh):
             check(f"{W}x{H}", got, ref, mode)
 
 
+@pytest.mark.parametrize("wh", [(65536, 5), (5, 65536)], ids=["65536x5", "5x65536"])
+def test_maximum_width_and_height(wh):
+    """The largest width (height) cgh_create accepts, with a thin other side:
+    every index of a 65,536-pixel line, the last tiles of the padded table
+    and factor layouts, and the widest launch grids.  Phases reach ~4e5
+    revolutions at the far pixels, far past Nyquist, which the FP64 reduction
+    must still hold."""
+    W, H = wh
+    c0 = cghgen.make_config(1, n=40)
+    c = cghgen.Cloud("max", W, H, c0.pitch, c0.wavelength, c0.x, c0.y, c0.z, c0.amp)
+    ref = oracle.cloud_fresnel(c)
+    for mode in ALL_MODES:
+        say(f"size {W}x{H} {NAMES[mode]}")
+        check(f"{W}x{H}", gpu_hologram(c, mode), ref, mode)
+
+
 def test_empty_cloud_and_zero_amplitudes_give_zero():
     import torch
     c = cghgen.make_config(1, n=40)
