@@ -182,13 +182,21 @@ def kinoform(re: np.ndarray, im: np.ndarray) -> np.ndarray:
     """Phase-only hologram of Eq. (3): theta = atan2(Im O, Re O) wrapped to
     [0, 2 pi), quantised to 8 bits as floor(theta * 255 / (2 pi)).
 
-    The decision is taken in FP64 here; a device path that decides in another
-    precision is compared on the codes that are not within one rounding of a
-    code boundary.
+    The quantisation is an integer decided by floating point, so it is taken
+    in the precision the paper's program takes the argument in, FP32 (Section 4.1):
+    the field is rounded to FP32, theta is the FP32 atan2 of it, 2 pi (FP32)
+    is added when theta < 0, and the code is floor of theta times the FP32
+    quotient 255 / (2 pi).  A device that decides in FP32 from the same FP32
+    field agrees except within a few ulps of a code boundary, where either
+    neighbour is correct.
     """
-    theta = np.arctan2(im, re)
-    theta = np.where(theta < 0.0, theta + 2.0 * np.pi, theta)
-    code = np.floor(theta * (255.0 / (2.0 * np.pi)))
+    r = np.asarray(re, dtype=np.float64).astype(np.float32)
+    i = np.asarray(im, dtype=np.float64).astype(np.float32)
+    theta = np.arctan2(i, r).astype(np.float32)
+    two_pi = np.float32(6.28318530717958647692)
+    theta = np.where(theta < np.float32(0.0), theta + two_pi, theta).astype(np.float32)
+    codes_per_rad = np.float32(255.0) / two_pi
+    code = np.floor((theta * codes_per_rad).astype(np.float32))
     return np.clip(code, 0, 255).astype(np.uint8)
 
 

@@ -1,7 +1,7 @@
 // Phase-only hologram (kinoform) of Eq. (3): the argument of the complex
 // object wave, wrapped to [0, 2 pi) and quantised to 256 levels,
 //     theta = atan2(Im O, Re O) (+ 2 pi if negative),  code = floor(theta * 255 / (2 pi)),
-// in FP32, the precision the paper computes the argument in (Section 3).
+// in FP32, the precision the paper's program takes the argument in (Section 4.1).
 // Memory-bound: 8 bytes read and 1 byte written per pixel; each thread takes
 // four consecutive pixels (two 16-byte loads, one 4-byte store).
 #include "common.h"
