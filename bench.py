@@ -166,13 +166,13 @@ def measured_clock_mhz(run, sync, seconds: float = 0.5):
             "while the step repeats for ~0.5 s after its timing"}
 
 
-def bench_batch(args, torch, cghgen, cgh):
+def bench_batch(args, torch, cghgen, cgh, check: bool):
     """Side measurement: the batched workload -- F holograms of 1920 x 1080,
     RGB wavelengths cycled, point counts log-uniform in [1e3, 5e4] -- in the
     FP16 hi/lo split mode through one graph-captured launch sequence on a
-    side stream.  Reports point*pixel/s over all frames and the NRMS of two
-    frames against the FP64 oracle on a strided sample."""
-    import oracle
+    side stream.  Reports point*pixel/s over all frames and (with the CPU
+    baseline on) the NRMS of two frames against the FP64 oracle on a strided
+    sample."""
     b = cghgen.make_batch(n_frames=args.batch_frames)
     frames = cgh.batch_frames(b)
     pp = b.point_pixels
@@ -196,7 +196,8 @@ def bench_batch(args, torch, cghgen, cgh):
     ms = e0.elapsed_time(e1) / reps
     rows, cols = np.arange(0, b.height, 16), np.arange(0, b.width, 16)
     errs = []
-    for f in (0, len(frames) - 1):
+    for f in ((0, len(frames) - 1) if check else ()):
+        import oracle
         o, n, lam = frames[f]
         ref = oracle.fresnel(b.width, b.height, b.pitch, lam, b.x[o:o + n], b.y[o:o + n],
                              b.z[o:o + n], b.amp[o:o + n], cols=cols, rows=rows)
@@ -340,6 +341,101 @@ def bench_fresnel(args, torch, cgh, check: bool):
             "paper_hardware": "NVIDIA Tesla K20, CUFFT (context only)"}
 
 
+LARGE_MODES = ("split_bf16", "separable_fp32", "direct_fp32")
+
+
+def _large_sample(c, cfg: int):
+    """The strided pixel sample the parity tests use at these sizes."""
+    if cfg == 5:
+        return np.arange(7, c.width, 160), np.arange(3, c.height, 160)
+    cols = np.array(sorted(set(range(0, c.width, 64)) | {c.width - 1}))
+    rows = np.array(sorted(set(range(0, c.height, 64)) | {c.height - 1}))
+    return cols, rows
+
+
+def bench_large(args, torch, cghgen, cgh, check: bool):
+    """Side measurement: the two large clouds -- 2048 x 2048 with 65,536
+    points (8 um, 532 nm) and 4096 x 4096 with 10^6 points on an ellipsoid
+    surface (4 um; evaluated in point chunks that fit the 16 GiB workspace)
+    -- in split BF16, FP32 separable and direct FP32, each tuned first.  One
+    step = one cgh_compute of the whole cloud; the GEMM (or direct) kernel's
+    time is the sum of its launches per step.  With the CPU baseline on,
+    NRMS and max error against the FP64 oracle on the strided sample the
+    parity tests use."""
+    res = {}
+    for cfg in (3, 5):
+        c = cghgen.make_config(cfg)
+        W, H, N = c.width, c.height, c.n
+        pp = W * H * N
+        steps = 3 if cfg == 3 else 1
+        ctx = cgh.Context(W, H, c.pitch, c.wavelength, device=0)
+        ctx.upload_cloud(c)
+        out = torch.empty((H, W), dtype=torch.float32, device="cuda:0")
+        stream = torch.cuda.current_stream()
+        cols, rows = _large_sample(c, cfg)
+        ref = None
+        if check:
+            import oracle
+            t0 = time.perf_counter()
+            ref = oracle.cloud_fresnel(c, cols=cols, rows=rows, threads=oracle.host_threads())
+            log(f"large C{cfg}: oracle sample {len(rows)}x{len(cols)} in "
+                f"{time.perf_counter() - t0:.1f} s")
+        modes = {}
+        for m in LARGE_MODES:
+            mode = cgh.MODES[m]
+            tuned = ctx.tune(mode, repeats=2, stream=stream) if not args.no_tune else None
+            ctx.compute(out, mode, stream)               # warm-up
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            ctx.profile(True)
+            ctx.profile_reset()
+            e0.record(stream)
+            for _ in range(steps):
+                ctx.compute(out, mode, stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            kern = ctx.profile_read()
+            ctx.profile(False)
+            ms = e0.elapsed_time(e1) / steps
+            r = {"ms_per_step": ms, "pp_per_s": pp / (ms * 1e-3), "tuned": tuned,
+                 "kernels_ms_per_step": {k: v[1] / steps for k, v in kern.items()}}
+            if m in ALU_MODES:
+                kname, peak = ALU_MODES[m]
+                t = r["kernels_ms_per_step"].get(kname)
+                if t:
+                    ach = pp / (t * 1e-3)
+                    r["roofline"] = {"bound": "alu", "achieved": ach, "peak": peak,
+                                     "unit": "point*pixel/s", "frac": ach / peak,
+                                     "kernel": kname, "kernel_ms": t}
+            else:
+                kname = GEMM_KERNEL[m]
+                t = r["kernels_ms_per_step"].get(kname)
+                if t:
+                    ach = FLOP_PER_PP[m] * pp / (t * 1e-3) / 1e12
+                    r["roofline"] = {"bound": "mfma", "achieved": ach, "peak": GEMM_PEAK[m],
+                                     "unit": "TFLOP/s", "frac": ach / GEMM_PEAK[m],
+                                     "kernel": kname, "kernel_ms": t}
+            if ref is not None:
+                import oracle
+                got = out.cpu().numpy()[np.ix_(rows, cols)].astype(np.float64)
+                r["nrms"] = oracle.nrms(got, ref)
+                r["max_err"] = oracle.max_err(got, ref)
+            log(f"large C{cfg} {m}: {ms:.3f} ms/step, {r['pp_per_s']:.3e} pp/s, "
+                f"frac {r.get('roofline', {}).get('frac')}, nrms {r.get('nrms')}")
+            modes[m] = r
+        ctx.close()
+        del out
+        torch.cuda.empty_cache()
+        res[f"{W}x{H}_{N}"] = {
+            "workload": (f"{W}x{H} hologram, {N} points, pitch {c.pitch * 1e6:g} um, "
+                         f"{c.wavelength * 1e9:g} nm (seed {cfg})"),
+            "point_pixels_per_step": pp, "steps": steps,
+            "sample": f"{len(rows)} rows x {len(cols)} columns, strided" if check else None,
+            "modes": modes}
+    return res
+
+
 def traffic_driver(torch, cghgen, cgh) -> int:
     """Kernel sequence for `rocprofv3 --pmc FETCH_SIZE|WRITE_SIZE -- python bench.py
     --traffic-driver`: the per-launch counters of the split-BF16 GEMM in each recorded
@@ -402,6 +498,8 @@ def main() -> int:
                     help="skip the phase-only hologram side measurement")
     ap.add_argument("--no-fresnel", action="store_true",
                     help="skip the Fresnel-diffraction side measurement")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the 2048x2048 / 4096x4096 side measurement")
     ap.add_argument("--batch-frames", type=int, default=64,
                     help="frames of the batched-workload side measurement (0 = skip)")
     ap.add_argument("--traffic-driver", action="store_true",
@@ -505,10 +603,13 @@ def main() -> int:
 
     batch = None
     if args.batch_frames > 0:
-        batch = bench_batch(args, torch, cghgen, cgh)
+        batch = bench_batch(args, torch, cghgen, cgh, check=not args.no_cpu_baseline)
     kino = None
     if not args.no_kinoform:
         kino = bench_kinoform(args, torch, cghgen, cgh, check=not args.no_cpu_baseline)
+    large = None
+    if not args.no_large:
+        large = bench_large(args, torch, cghgen, cgh, check=not args.no_cpu_baseline)
     fres = None
     if not args.no_fresnel:
         fres = bench_fresnel(args, torch, cgh, check=not args.no_cpu_baseline)
@@ -574,6 +675,7 @@ def main() -> int:
         "batch": batch,
         "kinoform": kino,
         "fresnel_diffraction": fres,
+        "large": large,
     }
     print(json.dumps(line), flush=True)
     return 0
