@@ -77,16 +77,16 @@ MODE_DTYPE = {"split_bf16": "bf16", "split_fp16": "f16", "fp16": "f16", "direct_
 TRAFFIC_SCALE = {"fetch": 2.0, "write": 1.0}
 TRAFFIC = [
     {"kernel": "gemm_split_mfma", "plan": "384,192,4,2,2,8", "src": "paper_1309_2734_amd/csrc/gemm.hip",
-     "sha": "43a39a102b14df66", "fetch_kib": 120352.0, "write_kib": 64800.1},
+     "sha": "c2a5d793680ad21f", "fetch_kib": 120352.0, "write_kib": 64800.1},
     {"kernel": "gemm_split_mfma", "plan": "192,384,2,4,2,8", "src": "paper_1309_2734_amd/csrc/gemm.hip",
-     "sha": "43a39a102b14df66", "fetch_kib": 120352.0, "write_kib": 64800.6},
+     "sha": "c2a5d793680ad21f", "fetch_kib": 120352.0, "write_kib": 64800.6},
     {"kernel": "direct_fp32", "plan": "8", "src": "paper_1309_2734_amd/csrc/direct.hip",
      "sha": "d5d17ae7d96a2dcc", "fetch_kib": 776234.7, "write_kib": 8100.0},
     {"kernel": "direct_fp32", "plan": "16", "src": "paper_1309_2734_amd/csrc/direct.hip",
      "sha": "d5d17ae7d96a2dcc", "fetch_kib": 474243.2, "write_kib": 8100.0},
     # the five kernels of one n = 8192 diffraction, summed
     {"kernel": "fresnel_diffraction", "plan": "8192", "src": "paper_1309_2734_amd/csrc/fresnel.hip",
-     "sha": "c493e180b5d1e9be", "fetch_kib": 2376938.1, "write_kib": 4718593.0},
+     "sha": "901dbb79b87cb5d5", "fetch_kib": 2376938.1, "write_kib": 4718593.0},
 ]
 TRAFFIC_PLANS = {"gemm_split_mfma": ["384,192,4,2,2,8", "192,384,2,4,2,8"],
                  "direct_fp32": ["8", "16"], "fresnel_diffraction": ["8192"]}

@@ -1095,6 +1095,11 @@ cgh_status cgh_create(cgh_ctx **out, int32_t width, int32_t height, double pitch
     cgh_status dst = check_device(device, arch);
     if (dst != CGH_OK)
         return dst;
+    {
+        DeviceGuard g;
+        CGH_HIP(g.set(device), "hipSetDevice");
+        CGH_HIP(gemm_prepare_kernels(), "GEMM kernel attributes");
+    }
 
     cgh_ctx *c = new (std::nothrow) cgh_ctx();
     if (!c)

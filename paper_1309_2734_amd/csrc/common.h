@@ -150,6 +150,9 @@ struct GemmPlan {
 hipError_t launch_gemm(const GemmPlan &plan, FactorType ft, const FactorSet &fs, int M, int N,
                        float *out, int64_t ldo, float *partials, bool accumulate, hipStream_t s);
 bool gemm_tile_supported(int bm, int bn, int waves_m, int waves_n, int stages);
+// Raises the GEMM kernels' LDS limit on the current device; called once per
+// context, before any launch or capture.
+hipError_t gemm_prepare_kernels();
 
 // a6: one (frame, tile) work item of the persistent batched GEMM.  The
 // factors of all frames sit side by side along K in one factor set; an

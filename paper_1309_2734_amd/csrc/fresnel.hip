@@ -491,25 +491,31 @@ __global__ void k_chirp(int m, int n, double q, float2 *h)
 }
 
 // Workgroups of a row kernel resident at once on the current device (the
-// persistent grid), queried once per kernel: at plan set-up, so a run that
-// is being captured into a graph makes no query.
+// persistent grid), queried once per kernel and device: at plan set-up, so a
+// run that is being captured into a graph makes no query.
+constexpr int kMaxDevices = 64;
+
 template <RowOp OP, int M, bool HALF_IN>
 hipError_t resident_groups(int *out)
 {
-    static std::atomic<int> cached{0};
-    int r = cached.load(std::memory_order_relaxed);
+    static std::atomic<int> cached[kMaxDevices];   // zero-initialised (static storage)
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return e;
+    if (dev < 0 || dev >= kMaxDevices)
+        return hipErrorInvalidDevice;
+    int r = cached[dev].load(std::memory_order_relaxed);
     if (r == 0) {
-        int dev = 0, cus = 0, per_cu = 0;
-        hipError_t e = hipGetDevice(&dev);
-        if (e == hipSuccess)
-            e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        int cus = 0, per_cu = 0;
+        e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         if (e == hipSuccess)
             e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
                 &per_cu, (const void *)k_fft_rows<OP, M, HALF_IN>, Fft<M>::T, Fft<M>::lds_bytes);
         if (e != hipSuccess)
             return e;
         r = (per_cu > 0 ? per_cu : 1) * (cus > 0 ? cus : 1);
-        cached.store(r, std::memory_order_relaxed);
+        cached[dev].store(r, std::memory_order_relaxed);
     }
     *out = r;
     return hipSuccess;

@@ -381,6 +381,13 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(const float *__restrict__
     }
 }
 
+// LDS of a workgroup: the copy ring, STAGES x (hi, lo) x (BM + BN) / 16 blocks.
+template <int BM, int BN, int PRODUCTS, int STAGES>
+constexpr int ring_bytes()
+{
+    return STAGES * (PRODUCTS == 3 ? 2 : 1) * (BM + BN) / kFragLines * kBlockBytes;
+}
+
 // The plan's tiles and K range stay inside the factor set, whose halves
 // match the product count.
 bool plan_fits(const GemmPlan &plan, int BM, int BN, int M, int N, const FactorSet &fs)
@@ -399,17 +406,8 @@ hipError_t launch_tile(const GemmPlan &plan, const FactorSet &fs, int M, int N, 
 {
     if (!plan_fits(plan, BM, BN, M, N, fs))
         return hipErrorInvalidValue;     // tiles would read past the factor set
-    constexpr int HL = PRODUCTS == 3 ? 2 : 1;
-    const int lds_bytes = STAGES * HL * (BM + BN) / kFragLines * kBlockBytes;
+    const int lds_bytes = ring_bytes<BM, BN, PRODUCTS, STAGES>();
     auto kern = k_gemm<BM, BN, WM, WN, PRODUCTS, T, STAGES>;
-    static bool attr = false;      // set once, outside any graph capture
-    if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void *)kern,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
-        if (e != hipSuccess)
-            return e;
-        attr = true;
-    }
     const int tiles_m = plan.mblocks / (BM / kFragLines);
     const int tiles_n = plan.nblocks / (BN / kFragLines);
     const int64_t per = (plan.kblocks + plan.splits - 1) / plan.splits;
@@ -428,17 +426,8 @@ hipError_t launch_tile_batch(const GemmPlan &plan, const FactorSet &fs, const Ba
 {
     if (!plan_fits(plan, BM, BN, M, N, fs))
         return hipErrorInvalidValue;     // tiles would read past the factor set
-    constexpr int HL = PRODUCTS == 3 ? 2 : 1;
-    const int lds_bytes = STAGES * HL * (BM + BN) / kFragLines * kBlockBytes;
+    const int lds_bytes = ring_bytes<BM, BN, PRODUCTS, STAGES>();
     auto kern = k_gemm_batch<BM, BN, WM, WN, PRODUCTS, T, STAGES>;
-    static bool attr = false;      // set once, outside any graph capture
-    if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void *)kern,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
-        if (e != hipSuccess)
-            return e;
-        attr = true;
-    }
     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, s, counter);
     hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * WM * WN), lds_bytes, s, fs, items, n_items,
                        counter, M, N, out);
@@ -486,7 +475,46 @@ hipError_t launch_products_batch(const GemmPlan &plan, const FactorSet &fs,
     return hipErrorInvalidValue;
 }
 
+// Raise the LDS limit of both kernels of every built shape and operand type
+// on the current device (the ring exceeds the default 64 KB).
+template <int BM, int BN, int WM, int WN, int STAGES, int PRODUCTS, typename T>
+hipError_t prepare_one()
+{
+    const int lds = ring_bytes<BM, BN, PRODUCTS, STAGES>();
+    hipError_t e = hipFuncSetAttribute((const void *)k_gemm<BM, BN, WM, WN, PRODUCTS, T, STAGES>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void *)k_gemm_batch<BM, BN, WM, WN, PRODUCTS, T, STAGES>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    return e;
+}
+
+template <int BM, int BN, int WM, int WN, int STAGES>
+hipError_t prepare_shape()
+{
+    hipError_t e = prepare_one<BM, BN, WM, WN, STAGES, 3, __bf16>();
+    if (e == hipSuccess)
+        e = prepare_one<BM, BN, WM, WN, STAGES, 3, _Float16>();
+    if (e == hipSuccess)
+        e = prepare_one<BM, BN, WM, WN, STAGES, 1, __bf16>();
+    if (e == hipSuccess)
+        e = prepare_one<BM, BN, WM, WN, STAGES, 1, _Float16>();
+    if (e == hipSuccess)
+        e = prepare_one<BM, BN, WM, WN, STAGES, 1, float>();
+    return e;
+}
+
 }  // namespace
+
+hipError_t gemm_prepare_kernels()
+{
+#define CGH_TILE(TBM, TBN, TWM, TWN, TST)                                                     \
+    if (hipError_t e = prepare_shape<TBM, TBN, TWM, TWN, TST>(); e != hipSuccess)            \
+        return e;
+    CGH_GEMM_SHAPES(CGH_TILE)
+#undef CGH_TILE
+    return hipSuccess;
+}
 
 hipError_t launch_gemm_batch(const GemmPlan &plan, FactorType ft, const FactorSet &fs,
                              const BatchItem *items, int n_items, int *counter, int M, int N,
