@@ -47,7 +47,12 @@ struct alignas(16) Vec16B {
     T v[kValues];
 };
 
-// Grid: x = K block * 64 + lane, y = line block (L blocks first, then R).
+// Grid: x = (group of kKBlocks consecutive K blocks) * 64 + lane, y = line
+// block (L blocks first, then R).  A thread loads the constants of all its
+// points first, then computes and stores block by block, so one wave has
+// several blocks' loads in flight and its stores follow back to back.
+constexpr int kKBlocks = 2;
+
 template <typename T, bool SPLIT>
 __global__ __launch_bounds__(256) void k_factors(PointConsts pc, int64_t slot0, int64_t kblocks,
                                                  int height, int width, int cplx, int mblocks,
@@ -56,55 +61,76 @@ __global__ __launch_bounds__(256) void k_factors(PointConsts pc, int64_t slot0, 
     constexpr int kLanePoints = Vec16B<T>::kValues / 2;      // (cos, sin) pairs per lane
     constexpr int kBlockPoints = 4 * kLanePoints;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= kblocks * 64)
+    const int64_t kb0 = (t >> 6) * kKBlocks;
+    if (kb0 >= kblocks)
         return;
     const int lane = (int)(t & 63);
-    const int64_t kb = t >> 6;
     const bool is_l = (int)blockIdx.y < mblocks;
     const int rb = is_l ? (int)blockIdx.y : (int)blockIdx.y - mblocks;
     const int line = rb * kFragLines + (lane & (kFragLines - 1));
     const int lines = is_l ? (cplx ? 2 * height : height) : width;
+    const bool valid = line < lines;
     const bool im_part = is_l && line >= height;           // rows of L' (complex only)
     const int src_line = im_part ? line - height : line;
-    const int64_t j0 = slot0 + kb * kBlockPoints + kLanePoints * (lane / kFragLines);
+    const double dline = (double)src_line;
+    const int nkb = kblocks - kb0 < kKBlocks ? (int)(kblocks - kb0) : kKBlocks;
 
-    Vec16B<T> hi, lo;
+    // constants of this lane's points in the group's blocks (blocks past
+    // kblocks re-read the last one; their results are not stored)
+    double ctr[kKBlocks][kLanePoints], beta[kKBlocks][kLanePoints];
+    float amp[kKBlocks][kLanePoints];
 #pragma unroll
-    for (int p = 0; p < kLanePoints; ++p) {
-        float c = 0.0f, s = 0.0f;
-        if (line < lines) {
-            const int64_t j = j0 + p;
-            const double ctr = is_l ? pc.cy[j] : pc.cx[j];
-            const double d = (double)src_line - ctr;
-            const float ph = (float)__builtin_amdgcn_fract(pc.beta[j] * (d * d));
-            c = __builtin_amdgcn_cosf(ph);     // cos(2 pi ph)
-            s = __builtin_amdgcn_sinf(ph);     // sin(2 pi ph)
+    for (int b = 0; b < kKBlocks; ++b) {
+        const int64_t kb = kb0 + (b < nkb ? b : nkb - 1);
+        const int64_t j0 = slot0 + kb * kBlockPoints + kLanePoints * (lane / kFragLines);
+#pragma unroll
+        for (int p = 0; p < kLanePoints; ++p) {
+            ctr[b][p] = is_l ? pc.cy[j0 + p] : pc.cx[j0 + p];
+            beta[b][p] = pc.beta[j0 + p];
+            amp[b][p] = pc.amp[j0 + p];
+        }
+    }
+
+    Vec16B<T> *out = reinterpret_cast<Vec16B<T> *>(fs.base);
+    const int hi_blk = (is_l ? fs.first_l(false) : fs.first_r(false)) + rb;
+    const int lo_blk = (is_l ? fs.first_l(true) : fs.first_r(true)) + rb;
+#pragma unroll
+    for (int b = 0; b < kKBlocks; ++b) {
+        if (b >= nkb)
+            break;
+        Vec16B<T> hi, lo;
+#pragma unroll
+        for (int p = 0; p < kLanePoints; ++p) {
+            const double d = dline - ctr[b][p];
+            const float ph = (float)__builtin_amdgcn_fract(beta[b][p] * (d * d));
+            float c = __builtin_amdgcn_cosf(ph);     // cos(2 pi ph)
+            float s = __builtin_amdgcn_sinf(ph);     // sin(2 pi ph)
             if (im_part) {
-                const float a = pc.amp[j];
+                const float a = amp[b][p];
                 const float ac = a * c;
                 c = a * s;
                 s = ac;
             } else if (is_l) {
-                const float a = pc.amp[j];
+                const float a = amp[b][p];
                 c = a * c;
                 s = -a * s;
             }
+            if (!valid) {
+                c = 0.0f;
+                s = 0.0f;
+            }
+            const T ch = to_t<T>(c), sh = to_t<T>(s);
+            hi.v[2 * p] = ch;
+            hi.v[2 * p + 1] = sh;
+            if (SPLIT) {
+                lo.v[2 * p] = to_t<T>(c - (float)ch);
+                lo.v[2 * p + 1] = to_t<T>(s - (float)sh);
+            }
         }
-        const T ch = to_t<T>(c), sh = to_t<T>(s);
-        hi.v[2 * p] = ch;
-        hi.v[2 * p + 1] = sh;
-        if (SPLIT) {
-            lo.v[2 * p] = to_t<T>(c - (float)ch);
-            lo.v[2 * p + 1] = to_t<T>(s - (float)sh);
-        }
-    }
-    Vec16B<T> *out = reinterpret_cast<Vec16B<T> *>(fs.base);
-    const int64_t slab = kb * fs.slab_blocks();
-    const int hi_blk = (is_l ? fs.first_l(false) : fs.first_r(false)) + rb;
-    out[(slab + hi_blk) * 64 + lane] = hi;
-    if (SPLIT) {
-        const int lo_blk = (is_l ? fs.first_l(true) : fs.first_r(true)) + rb;
-        out[(slab + lo_blk) * 64 + lane] = lo;
+        const int64_t slab = (kb0 + b) * fs.slab_blocks();
+        out[(slab + hi_blk) * 64 + lane] = hi;
+        if (SPLIT)
+            out[(slab + lo_blk) * 64 + lane] = lo;
     }
 }
 
@@ -113,7 +139,8 @@ hipError_t launch_t(PointConsts pc, int64_t slot0, int width, int height, int cp
                     int64_t kblocks, int mblocks, int nblocks, const FactorSet &fs,
                     hipStream_t s)
 {
-    const dim3 grid((unsigned)((kblocks * 64 + 255) / 256), (unsigned)(mblocks + nblocks));
+    const int64_t groups = (kblocks + kKBlocks - 1) / kKBlocks;
+    const dim3 grid((unsigned)((groups * 64 + 255) / 256), (unsigned)(mblocks + nblocks));
     if (fs.hl == 2)
         hipLaunchKernelGGL((k_factors<T, sizeof(T) == 2>), grid, dim3(256), 0, s, pc, slot0,
                            kblocks, height, width, cplx, mblocks, fs);
@@ -129,7 +156,7 @@ hipError_t launch_factors(PointConsts pc, int64_t slot0, int width, int height, 
                           int64_t kblocks, int mblocks, int nblocks, FactorType ft,
                           const FactorSet &fs, hipStream_t s)
 {
-    if (kblocks <= 0)
+    if (kblocks <= 0 || mblocks + nblocks <= 0)
         return hipSuccess;
     // the written blocks must lie in the set
     if (fs.base == nullptr || kblocks > fs.kblocks || mblocks > fs.amb || nblocks > fs.anb ||

@@ -211,6 +211,25 @@ def test_point_chunking_matches_oracle(monkeypatch):
         check("chunked", got, ref, mode)
 
 
+@pytest.mark.parametrize("splits", [0, 2, 9, 11, 24], ids=lambda s: f"splits{s or '_auto'}")
+def test_split_k_counts(splits, monkeypatch):
+    """K split counts across the reduce kernel's load batches of eight
+    partials (9, 11: one whole batch and a ragged one; 24: three; 0: the
+    library's own count: 24 in BF16, 48 in FP32) on a small hologram of many points (one
+    output tile), including a width that leaves the 4-wide reduce path."""
+    for w, h in ((96, 80), (97, 80)):
+        c0 = cghgen.make_config(1, n=3072)
+        c = cghgen.Cloud("splits", w, h, c0.pitch, c0.wavelength, c0.x, c0.y, c0.z, c0.amp)
+        key = f"splits{w}x{h}"
+        if key not in _REFS:
+            _REFS[key] = oracle.cloud_fresnel(c)
+        if splits:
+            monkeypatch.setenv("CGH_GEMM_PLAN", f"192,192,2,4,3,{splits}")
+        for mode in (cgh.SPLIT_BF16, cgh.SEPARABLE_FP32):
+            say(f"{w}x{h} N=3072 {NAMES[mode]} splits {splits or 'auto'}")
+            check(f"splits={splits}", gpu_hologram(c, mode), _REFS[key], mode)
+
+
 def test_bitwise_repeatable():
     c = cghgen.make_config(2, n=2000)
     for mode in ALL_MODES:
