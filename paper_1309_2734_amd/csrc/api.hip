@@ -723,10 +723,44 @@ cgh_status eval_batch_gemm(cgh_ctx *c, int mode, const cgh_frame *frames, int n_
     const int64_t budget = std::max<int64_t>(
         (int64_t)workspace_budget() / (int64_t)per_slot / kSlotAlign * kSlotAlign, kSlotAlign);
 
-    // Groups of frames [f0, f1) whose padded slots fit the budget (at least
-    // one frame each).  All groups' segments and work items go to the device
-    // in one table each, so a repeated call (and its graph capture) copies
-    // nothing.
+    // Frames into groups whose padded slots fit the budget (a frame larger
+    // than the budget is a group of its own): as few groups as the budget
+    // allows, filled largest frame first, each frame into the least-loaded
+    // group with room, so that every group holds a balanced share of large
+    // and small frames and its (frame, tile) items spread evenly over the
+    // workgroups (consecutive runs of frames could leave a last group of a
+    // few large frames, whose launch is one item long).  All groups' segments
+    // and work items go to the device in one table each, so a repeated call
+    // (and its graph capture) copies nothing.
+    auto padded_slots = [&](int f) { return round_up(frames[f].point_count, kSlotAlign); };
+    std::vector<int> order(n_frames);
+    for (int f = 0; f < n_frames; ++f)
+        order[f] = f;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        return frames[a].point_count > frames[b].point_count;
+    });
+    int64_t all_slots = 0;
+    for (int f = 0; f < n_frames; ++f)
+        all_slots += padded_slots(f);
+    std::vector<std::vector<int>> members((size_t)std::max<int64_t>(
+        1, std::min<int64_t>(n_frames, (all_slots + budget - 1) / budget)));
+    std::vector<int64_t> load(members.size(), 0);
+    for (int f : order) {
+        const int64_t ps = padded_slots(f);
+        int best = -1;
+        for (int g = 0; g < (int)members.size(); ++g)
+            if ((members[g].empty() || load[g] + ps <= budget) &&
+                (best < 0 || load[g] < load[best]))
+                best = g;
+        if (best < 0) {
+            members.emplace_back();
+            load.push_back(0);
+            best = (int)members.size() - 1;
+        }
+        members[best].push_back(f);
+        load[best] += ps;
+    }
+
     struct Group {
         int seg0, nseg;
         int item0, nitem;
@@ -735,28 +769,26 @@ cgh_status eval_batch_gemm(cgh_ctx *c, int mode, const cgh_frame *frames, int n_
     std::vector<Group> groups;
     std::vector<Segment> segs;
     std::vector<BatchItem> items;
-    for (int f0 = 0; f0 < n_frames;) {
+    for (auto &mem : members) {
+        if (mem.empty())
+            continue;
+        std::sort(mem.begin(), mem.end());
         Group gr{(int)segs.size(), 0, (int)items.size(), 0, 0, 0};
-        int f1 = f0;
-        while (f1 < n_frames) {
-            const int64_t ps = round_up(frames[f1].point_count, kSlotAlign);
-            if (f1 > f0 && gr.slots + ps > budget)
-                break;
-            segs.push_back({frames[f1].point_offset, frames[f1].point_count, gr.slots,
-                            frames[f1].wavelength});
+        for (int f : mem) {
+            const int64_t ps = padded_slots(f);
+            segs.push_back({frames[f].point_offset, frames[f].point_count, gr.slots,
+                            frames[f].wavelength});
             for (int tm = 0; tm < p.tiles_m; ++tm)
                 for (int tn = 0; tn < p.tiles_n; ++tn)
-                    items.push_back({gr.slots / mi.kbp, ps / mi.kbp, f1 * plane, tm, tn});
+                    items.push_back({gr.slots / mi.kbp, ps / mi.kbp, f * plane, tm, tn});
             gr.slots += ps;
-            gr.max_count = std::max(gr.max_count, frames[f1].point_count);
-            ++f1;
+            gr.max_count = std::max(gr.max_count, frames[f].point_count);
         }
         gr.nseg = (int)segs.size() - gr.seg0;
         gr.nitem = (int)items.size() - gr.item0;
         std::stable_sort(items.begin() + gr.item0, items.end(),
                          [](const BatchItem &x, const BatchItem &y) { return x.kblocks > y.kblocks; });
         groups.push_back(gr);
-        f0 = f1;
     }
     CGH_HIP(upload_small(c, c->segs, segs.data(), segs.size() * sizeof(Segment), s),
             "segment table upload");

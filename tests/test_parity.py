@@ -308,6 +308,43 @@ def test_batch_frames_match_oracle_and_single(mode):
 
 
 @pytest.mark.parametrize("mode", ALL_MODES, ids=[NAMES[m] for m in ALL_MODES])
+def test_batch_frame_groups_under_a_small_workspace(mode, monkeypatch):
+    """A workspace budget below the batch's factors splits the frames into
+    several groups (a frame larger than the budget alone in one), each with
+    its own factor and GEMM launches.  Every frame matches the oracle; in the
+    matrix-core modes a frame's sums do not depend on its group (one
+    workgroup per output tile over the frame's whole K range), so the
+    result equals the one-group batch bit for bit."""
+    import torch
+    b = _batch_case()
+    frames = cgh.batch_frames(b)
+    frames.append((int(b.offsets[3]) + 100, 1500, 633e-9))
+    ctx = cgh.Context(b.width, b.height, b.pitch, 532e-9)
+    ctx.upload_cloud(b)
+    F = len(frames)
+    whole = torch.empty((F, b.height, b.width), device="cuda")
+    ctx.batch_compute(frames, whole, mode)
+    torch.cuda.synchronize()
+    monkeypatch.setenv("CGH_WORKSPACE_BYTES", str(1 << 20))
+    say(f"batch {F} frames in groups {NAMES[mode]}")
+    out = torch.empty_like(whole)
+    ctx.batch_compute(frames, out, mode)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().astype(np.float64)
+    for f, (o, n, lam) in enumerate(frames):
+        sl = slice(o, o + n)
+        if n == 0:
+            assert np.all(got[f] == 0.0)
+            continue
+        ref = oracle.fresnel(b.width, b.height, b.pitch, lam, b.x[sl], b.y[sl], b.z[sl],
+                             b.amp[sl])
+        check(f"grouped batch frame {f} N={n}", got[f], ref, mode)
+    if mode != cgh.DIRECT_FP32:
+        assert np.array_equal(out.cpu().numpy(), whole.cpu().numpy())
+    ctx.close()
+
+
+@pytest.mark.parametrize("mode", ALL_MODES, ids=[NAMES[m] for m in ALL_MODES])
 def test_batch_graph_replays_match_eager(mode):
     """On a non-default stream a repeated batch call replays a captured HIP
     graph.  Replays, with eager work and synchronisations in between, must
