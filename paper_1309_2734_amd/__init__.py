@@ -45,8 +45,9 @@ MEM_DEVICE = 1
 # every symbol include/cgh.h declares
 EXPORTS = ("cgh_create", "cgh_points_upload", "cgh_compute", "cgh_compute_complex",
            "cgh_kinoform", "cgh_batch_compute", "cgh_tune", "cgh_fresnel_create",
-           "cgh_fresnel_run", "cgh_fresnel_destroy", "cgh_destroy", "cgh_strerror", "cgh_last_error", "cgh_profile_enable",
-           "cgh_profile_reset", "cgh_profile_read", "cgh_version")
+           "cgh_fresnel_run", "cgh_fresnel_destroy", "cgh_destroy", "cgh_strerror",
+           "cgh_last_error", "cgh_profile_enable", "cgh_profile_reset", "cgh_profile_read",
+           "cgh_version")
 
 
 class CghError(RuntimeError):
@@ -125,6 +126,12 @@ def _is_torch(a) -> bool:
     return type(a).__module__.startswith("torch")
 
 
+def _on_device(t, device: int, name: str) -> None:
+    """Device tensors must live on the device of the context or plan."""
+    if t.device.index != device:
+        raise ValueError(f"{name} is on {t.device}, the library object on cuda:{device}")
+
+
 def _stream_handle(stream, tensors: Iterable = ()) -> Optional[int]:
     """hipStream_t for a call: an explicit stream (torch.cuda.Stream or raw
     handle), else torch's current stream when device tensors take part."""
@@ -175,6 +182,8 @@ class Context:
         arrs = [x, y, z, amp]
         if all(_is_torch(a) and a.is_cuda for a in arrs):
             import torch
+            for a, name in zip(arrs, ("x", "y", "z", "amp")):
+                _on_device(a, self.device, name)
             ts = [a.detach().to(torch.float32).contiguous() for a in arrs]
             n = ts[0].numel()
             if any(t.numel() != n for t in ts):
@@ -205,6 +214,7 @@ class Context:
             raise TypeError(f"out must be contiguous {dtype}")
         if out.numel() != planes * self.width * self.height:
             raise ValueError(f"out must hold {planes} x {self.height} x {self.width} values")
+        _on_device(out, self.device, "out")
         return out.data_ptr()
 
     def compute(self, out, mode: int = DIRECT_FP32, stream=None):
@@ -273,6 +283,7 @@ class FresnelPlan:
                                         float(z), int(device)), "cgh_fresnel_create")
         self._h = h
         self.n, self.pitch, self.wavelength, self.z = int(n), float(pitch), float(wavelength), float(z)
+        self.device = int(device)
 
     def close(self) -> None:
         if getattr(self, "_h", None) and self._h.value:
@@ -293,6 +304,7 @@ class FresnelPlan:
                     and tuple(t.shape) == (self.n, self.n)):
                 raise TypeError(f"{name} must be a contiguous CUDA complex64 tensor of shape "
                                 f"({self.n}, {self.n})")
+            _on_device(t, self.device, name)
         _check(lib().cgh_fresnel_run(self._h, u.data_ptr(), out.data_ptr(),
                                      _stream_handle(stream, [out])), "cgh_fresnel_run")
         return out

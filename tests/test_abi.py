@@ -119,3 +119,19 @@ def test_fresnel_create_without_gpu_reports_device_error(L):
     out = ctypes.c_void_p(123)
     assert L.cgh_fresnel_create(ctypes.byref(out), 64, 8e-6, 5e-7, 0.1, 0) == cgh.EDEVICE
     assert out.value is None
+
+
+def test_binding_rejects_tensors_on_another_device():
+    """Device tensors must sit on the context's (or plan's) device: the
+    library writes through their pointers on its own device."""
+    class _Dev:
+        def __init__(self, i):
+            self.index = i
+
+    class _T:
+        def __init__(self, i):
+            self.device = _Dev(i)
+
+    cgh._on_device(_T(0), 0, "out")
+    with pytest.raises(ValueError, match="out is on"):
+        cgh._on_device(_T(1), 0, "out")
