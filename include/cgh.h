@@ -177,7 +177,8 @@ CGH_API cgh_status cgh_kinoform(cgh_ctx *c, cgh_mode mode, uint8_t *out_dev, voi
  * a repeated call with the same frame table replays a captured HIP graph.
  *   n_frames in [1, 65535]; each frame's points lie within the upload and
  *   its wavelength is finite and > 0.  The matrix-core modes process the
- *   frames in groups whose factors fit the workspace budget (one constants,
+ *   frames in groups whose factors fit the workspace budget, balanced by
+ *   size (one constants,
  *   one factor and one persistent GEMM launch per group; each (frame, tile)
  *   item runs its frame's whole K range in one workgroup, so a frame's sums
  *   are ordered differently from cgh_compute's split-K).  A call on a
