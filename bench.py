@@ -374,12 +374,19 @@ def bench_large(args, torch, cghgen, cgh, check: bool):
         stream = torch.cuda.current_stream()
         cols, rows = _large_sample(c, cfg)
         ref = None
+        oracle_rate = None
         if check:
             import oracle
+            threads = oracle.host_threads()
             t0 = time.perf_counter()
-            ref = oracle.cloud_fresnel(c, cols=cols, rows=rows, threads=oracle.host_threads())
-            log(f"large C{cfg}: oracle sample {len(rows)}x{len(cols)} in "
-                f"{time.perf_counter() - t0:.1f} s")
+            ref = oracle.cloud_fresnel(c, cols=cols, rows=rows, threads=threads)
+            dt = time.perf_counter() - t0
+            spp = len(rows) * len(cols) * N
+            oracle_rate = {"value": spp / dt, "unit": "point*pixel/s", "cores": threads,
+                           "kind": "oracle", "sample": f"{len(rows)} x {len(cols)} strided pixels, "
+                                                       f"all {N} points: {spp:.3e} point*pixels "
+                                                       f"in {dt:.2f} s"}
+            log(f"large C{cfg}: oracle sample {len(rows)}x{len(cols)} in {dt:.1f} s")
         modes = {}
         for m in LARGE_MODES:
             mode = cgh.MODES[m]
@@ -432,7 +439,7 @@ def bench_large(args, torch, cghgen, cgh, check: bool):
                          f"{c.wavelength * 1e9:g} nm (seed {cfg})"),
             "point_pixels_per_step": pp, "steps": steps,
             "sample": f"{len(rows)} rows x {len(cols)} columns, strided" if check else None,
-            "modes": modes}
+            "cpu_oracle": oracle_rate, "modes": modes}
     return res
 
 
@@ -628,6 +635,16 @@ def main() -> int:
                "sample": f"every {args.sample_row_step}th row ({len(rows)} rows x {W} columns) "
                          f"of the {W}x{H} hologram, all {N} points: {sample_pp:.3e} "
                          f"point*pixels in {dt:.1f} s (FP64, libm cos)"}
+        # the same oracle on one core, on the small 256 x 256, 128-point cloud
+        c1 = cghgen.make_config(1)
+        t0 = time.perf_counter()
+        oracle.cloud_fresnel(c1, threads=1)
+        dt1 = time.perf_counter() - t0
+        pp1 = c1.width * c1.height * c1.n
+        cpu["one_core"] = {"value": pp1 / dt1, "unit": "point*pixel/s", "cores": 1,
+                           "sample": f"full {c1.width}x{c1.height} grid, {c1.n} points: "
+                                     f"{pp1:.3e} point*pixels in {dt1:.3f} s"}
+        log(f"oracle on one core, 256x256 x 128: {pp1 / dt1:.3e} pp/s")
         import oracle as orc
         sph_ref = None
         for m, r in results.items():
