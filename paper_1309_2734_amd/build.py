@@ -4,7 +4,8 @@
 
 Every HIP source under csrc/ is compiled for gfx950 only, with packed-FP32
 instruction selection switched off, and linked into
-paper_1309_2734_amd/libcgh.so next to this file.
+paper_1309_2734_amd/libcgh.so next to this file; microbench.hip becomes the
+program paper_1309_2734_amd/cgh_microbench.
 """
 from __future__ import annotations
 
@@ -20,6 +21,9 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libcgh.so")
+# the rate and accuracy microbenchmarks (a program, not part of the library)
+MICROBENCH_SRC = os.path.join(HERE, "microbench.hip")
+MICROBENCH = os.path.join(HERE, "cgh_microbench")
 
 SOURCES = ["api.hip", "points.hip", "direct.hip", "spherical.hip", "factors.hip", "gemm.hip",
            "phase.hip", "fresnel.hip"]
@@ -62,7 +66,18 @@ def build(verbose: bool = False) -> str:
     _run([HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", *[o for _, o in jobs],
           "-o", tmp])
     os.replace(tmp, LIB)
+    build_microbench()
     return LIB
+
+
+def build_microbench() -> str:
+    """Compile the microbenchmark program next to the library."""
+    tmp = MICROBENCH + ".tmp"
+    _run([HIPCC, "-O3", "-std=c++17", f"--offload-arch={ARCH}",
+          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          MICROBENCH_SRC, "-o", tmp])
+    os.replace(tmp, MICROBENCH)
+    return MICROBENCH
 
 
 if __name__ == "__main__":
