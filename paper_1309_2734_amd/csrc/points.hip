@@ -53,28 +53,33 @@ __device__ __forceinline__ float reduce_line(double beta, double d)
     return (float)__builtin_amdgcn_fract(beta * (d * d));
 }
 
-// a2: U blocked as [group][column][kGroup], V as [group][row][kGroup].  One
-// thread per table entry of a group (blockIdx.y strides over the groups);
-// consecutive threads write consecutive floats.
+// a2: U blocked as [group][column][kGroup], V as [group][row][kGroup].  A
+// thread writes four consecutive entries of one table line of a group (one
+// 16-byte store; consecutive threads write consecutive 16 bytes);
+// blockIdx.y strides over the groups.
 __global__ __launch_bounds__(256) void k_phase_tables(PointConsts pc, int64_t n_groups, int width,
                                                       int height, float *__restrict__ U,
                                                       float *__restrict__ V)
 {
+    constexpr int kQuads = kGroup / 4;
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    const int line_all = idx / kGroup;
-    const int q = idx % kGroup;
+    const int line_all = idx / kQuads;
+    const int q0 = 4 * (idx % kQuads);
     if (line_all >= width + height)
         return;
     const bool is_u = line_all < width;
     const int line = is_u ? line_all : line_all - width;
+    const double *ctr = is_u ? pc.cx : pc.cy;
+    float *tab = is_u ? U : V;
+    const int64_t lines = is_u ? width : height;
     for (int64_t g = blockIdx.y; g < n_groups; g += gridDim.y) {
-        const int64_t j = g * kGroup + q;
-        const double c = is_u ? pc.cx[j] : pc.cy[j];
-        const float t = reduce_line(pc.beta[j], (double)line - c);
-        if (is_u)
-            U[(g * width + line) * kGroup + q] = t;
-        else
-            V[(g * height + line) * kGroup + q] = t;
+        const int64_t j = g * kGroup + q0;
+        float4 t;
+        t.x = reduce_line(pc.beta[j], (double)line - ctr[j]);
+        t.y = reduce_line(pc.beta[j + 1], (double)line - ctr[j + 1]);
+        t.z = reduce_line(pc.beta[j + 2], (double)line - ctr[j + 2]);
+        t.w = reduce_line(pc.beta[j + 3], (double)line - ctr[j + 3]);
+        *reinterpret_cast<float4 *>(tab + (g * lines + line) * kGroup + q0) = t;
     }
 }
 
@@ -100,7 +105,7 @@ hipError_t launch_phase_tables(PointConsts pc, int64_t n_slots, int width, int h
     if (n_slots <= 0)
         return hipSuccess;
     const int64_t groups = n_slots / kGroup;
-    const unsigned bx = (unsigned)(((int64_t)(width + height) * kGroup + 255) / 256);
+    const unsigned bx = (unsigned)(((int64_t)(width + height) * (kGroup / 4) + 255) / 256);
     const unsigned by = (unsigned)(groups < 65535 ? groups : 65535);
     hipLaunchKernelGGL(k_phase_tables, dim3(bx, by), dim3(256), 0, s, pc, groups, width, height,
                        U, V);

@@ -181,8 +181,10 @@ __global__ __launch_bounds__(256) void k_direct_sphere(
     }
 }
 
-// a2s: one thread per table entry of a group (blockIdx.y strides over the
-// groups).  Padding slots (zlam = 0, amplitude 0) get zero offsets.
+// a2s: a thread writes four consecutive entries of one table line of a
+// group in each of its two tables (16-byte stores; consecutive threads write
+// consecutive 16 bytes); blockIdx.y strides over the groups.  Padding slots
+// (zlam = 0, amplitude 0) get zero offsets.
 __global__ __launch_bounds__(256) void k_sphere_tables(PointConsts pc, int64_t n_groups,
                                                        int wpad, int hpad,
                                                        float *__restrict__ U,
@@ -190,30 +192,35 @@ __global__ __launch_bounds__(256) void k_sphere_tables(PointConsts pc, int64_t n
                                                        float *__restrict__ X,
                                                        float *__restrict__ Y)
 {
+    constexpr int kQuads = kGroup / 4;
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    const int line_all = idx / kGroup;
-    const int q = idx % kGroup;
+    const int line_all = idx / kQuads;
+    const int q0 = 4 * (idx % kQuads);
     if (line_all >= wpad + hpad)
         return;
     const bool is_u = line_all < wpad;
     const int line = is_u ? line_all : line_all - wpad;
+    const double *ctr = is_u ? pc.cx : pc.cy;
+    float *phase = is_u ? U : V;
+    float *offset = is_u ? X : Y;
+    const int64_t lines = is_u ? wpad : hpad;
     for (int64_t g = blockIdx.y; g < n_groups; g += gridDim.y) {
-        const int64_t j = g * kGroup + q;
-        const double beta = pc.beta[j], zl = pc.zlam[j];
-        const double d = (double)line - (is_u ? pc.cx[j] : pc.cy[j]);
-        const double d2 = d * d;
-        // (p / z)^2 = 2 beta / (z / lambda)
-        const double rs = zl > 0.0 ? 2.0 * beta / zl : 0.0;
-        const float off = (float)(d2 * rs);
-        if (is_u) {
-            const int64_t e = (g * wpad + line) * kGroup + q;
-            U[e] = (float)__builtin_amdgcn_fract(beta * d2);
-            X[e] = off;
-        } else {
-            const int64_t e = (g * hpad + line) * kGroup + q;
-            V[e] = (float)__builtin_amdgcn_fract(beta * d2 + zl);
-            Y[e] = off;
+        const int64_t j0 = g * kGroup + q0;
+        float ph[4], off[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t j = j0 + u;
+            const double beta = pc.beta[j], zl = pc.zlam[j];
+            const double d = (double)line - ctr[j];
+            const double d2 = d * d;
+            // (p / z)^2 = 2 beta / (z / lambda)
+            const double rs = zl > 0.0 ? 2.0 * beta / zl : 0.0;
+            off[u] = (float)(d2 * rs);
+            ph[u] = (float)__builtin_amdgcn_fract(is_u ? beta * d2 : beta * d2 + zl);
         }
+        const int64_t e = (g * lines + line) * kGroup + q0;
+        *reinterpret_cast<float4 *>(phase + e) = float4{ph[0], ph[1], ph[2], ph[3]};
+        *reinterpret_cast<float4 *>(offset + e) = float4{off[0], off[1], off[2], off[3]};
     }
 }
 
@@ -242,7 +249,7 @@ hipError_t launch_sphere_tables(PointConsts pc, int64_t n_slots, int wpad, int h
     if (n_slots <= 0)
         return hipSuccess;
     const int64_t groups = n_slots / kGroup;
-    const unsigned bx = (unsigned)(((int64_t)(wpad + hpad) * kGroup + 255) / 256);
+    const unsigned bx = (unsigned)(((int64_t)(wpad + hpad) * (kGroup / 4) + 255) / 256);
     const unsigned by = (unsigned)(groups < 65535 ? groups : 65535);
     hipLaunchKernelGGL(k_sphere_tables, dim3(bx, by), dim3(256), 0, s, pc, groups, wpad, hpad, U,
                        V, X, Y);
