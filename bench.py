@@ -96,7 +96,9 @@ def _plan_in_tuned(kernel: str, plan: str, tuned) -> bool:
     if kernel == "fresnel_diffraction":
         return plan == tuned
     if kernel.startswith("direct"):
-        return (tuned is None and plan == "16") or bool(tuned and f"rows={plan} " in tuned)
+        # the recorded traffic is that of an unsplit launch
+        unsplit = bool(tuned and ("splits=1 " in tuned or "splits=0 " in tuned))
+        return (tuned is None and plan == "16") or (unsplit and f"rows={plan} " in tuned)
     bm, bn, wm, wn, st, sp = plan.split(",")
     return bool(tuned and f"bm={bm} bn={bn} waves={wm}x{wn} stages={st} splits={sp}" in tuned)
 

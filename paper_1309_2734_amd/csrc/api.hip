@@ -166,6 +166,7 @@ struct cgh_ctx {
     DevBuf fac;                       // Lh | Ll | Rh | Rl in one allocation
     DevBuf partials;                  // split-K partial tiles
     DevBuf segs, frames;              // small device tables
+    DevBuf dsplit;                    // point-split frame table of a direct evaluation
     DevBuf tune_out;                  // scratch hologram for cgh_tune
     DevBuf field;                     // complex object wave for cgh_kinoform
     DevBuf items, counter;            // batched GEMM work list and its queue counter
@@ -550,6 +551,72 @@ cgh_status run_direct(cgh_ctx *c, int mode, const FrameDesc *fd_dev, int n_frame
     return CGH_OK;
 }
 
+// Point split of a direct evaluation: the K split count (CGH_DIRECT_SPLITS,
+// 1, 2 or 4, used to sweep; else the tuned choice; else 1).
+int direct_splits(cgh_ctx *c, int mode)
+{
+    const TuneEntry *t = find_tuned(c, tune_key(c, mode, 0, c->height));
+    int sp = t && t->splits > 0 ? t->splits : 1;
+    if (const char *env = std::getenv("CGH_DIRECT_SPLITS")) {
+        const int v = std::atoi(env);
+        if (v == 1 || v == 2 || v == 4)
+            sp = v;
+    }
+    return sp;
+}
+
+// Frame descriptors of one frame's points cut into at most `splits` runs of
+// whole group pairs (the direct kernel takes a frame's groups two at a
+// time), run r writing partial plane r; uploaded to c->dsplit.  Returns the
+// number of runs.
+int direct_split_table(cgh_ctx *c, const FrameDesc &fd, int splits, hipStream_t s,
+                       cgh_status *st)
+{
+    const int64_t plane = (int64_t)c->width * c->height;
+    const int64_t pairs = fd.groups / 2;
+    const int64_t per = std::max<int64_t>(1, (pairs + splits - 1) / splits);
+    std::vector<FrameDesc> d;
+    for (int64_t p = 0; p < pairs; p += per) {
+        const int64_t np = std::min(per, pairs - p);
+        d.push_back({fd.first + p * 2 * kGroup, 2 * np, (int64_t)d.size() * plane});
+    }
+    *st = CGH_OK;
+    const hipError_t e = upload_small(c, c->dsplit, d.data(), d.size() * sizeof(FrameDesc), s);
+    if (e != hipSuccess)
+        *st = hip_fail(e, "split table upload");
+    return (int)d.size();
+}
+
+// Direct mode for one frame (host copy fd, device copy fd_dev), split over
+// its points when the split count asks for it and there is no imaginary
+// part: the runs accumulate into partial planes, summed in a fixed order
+// (more workgroups for a small hologram, the same numbers on every run).
+cgh_status run_direct_one(cgh_ctx *c, int mode, const FrameDesc &fd, const FrameDesc *fd_dev,
+                          int64_t total_slots, float *out, float *out_im, bool accumulate,
+                          hipStream_t s)
+{
+    const int splits = out_im ? 1 : direct_splits(c, mode);
+    if (splits <= 1 || fd.groups < 4)
+        return run_direct(c, mode, fd_dev, 1, total_slots, out, out_im, accumulate, s);
+    cgh_status st = CGH_OK;
+    const int runs = direct_split_table(c, fd, splits, s, &st);
+    if (st != CGH_OK)
+        return st;
+    const size_t plane = (size_t)c->width * c->height;
+    CGH_HIP(ensure_ws(c, c->partials, (size_t)runs * plane * sizeof(float)),
+            "split-K workspace allocation");
+    st = run_direct(c, mode, (const FrameDesc *)c->dsplit.p, runs, total_slots,
+                    (float *)c->partials.p, nullptr, false, s);
+    if (st != CGH_OK)
+        return st;
+    Bracket br(c, "splitk_reduce", s);
+    CGH_HIP(launch_splitk_reduce((const float *)c->partials.p, runs, c->height, c->width, out,
+                                 c->width, accumulate, s),
+            "split-K reduce launch");
+    br.done();
+    return CGH_OK;
+}
+
 // Matrix-core modes for one frame whose constants are slots [slot0, slot0 + slots).
 // With `cplx`, L holds the real- and imaginary-part rows stacked (M = 2H) and
 // `out` receives [Re; Im] as two consecutive H x W planes.
@@ -653,9 +720,9 @@ cgh_status eval_one(cgh_ctx *c, int mode, int64_t p0, int64_t count, double lam,
             return st;
         const bool acc = i > 0;
         if (is_direct(mode) || segs[i].count == 0)
-            st = run_direct(c, is_direct(mode) ? mode : CGH_DIRECT_FP32,
-                            (const FrameDesc *)c->frames.p + i, 1,
-                            round_up(segs[i].count, kSlotAlign), out, out_im, acc, s);
+            st = run_direct_one(c, is_direct(mode) ? mode : CGH_DIRECT_FP32, fds[i],
+                                (const FrameDesc *)c->frames.p + i,
+                                round_up(segs[i].count, kSlotAlign), out, out_im, acc, s);
         else
             st = run_gemm(c, mode, 0, slots, out, cplx, acc, s);
         if (st != CGH_OK)
@@ -1173,6 +1240,7 @@ void cgh_destroy(cgh_ctx *c)
     c->partials.release();
     c->segs.release();
     c->frames.release();
+    c->dsplit.release();
     c->tune_out.release();
     c->field.release();
     c->items.release();
@@ -1406,22 +1474,45 @@ cgh_status cgh_tune(cgh_ctx *c, cgh_mode mode, int32_t repeats, char *report, in
         st = direct_tables(c, mode, slots, s);
         if (st != CGH_OK)
             return st;
-        for (int rows : {4, 8, 16}) {
-            if (!direct_rows_ok(mode, rows))
-                continue;
-            double us = 0;
-            st = time_launches(
-                [&] {
-                    return launch_direct_mode(c, mode, (const FrameDesc *)c->frames.p, 1, rows,
-                                              out, nullptr, false, s);
-                },
-                repeats, s, &us);
-            if (st != CGH_OK)
-                return st;
-            ++tried;
-            if (best.rows == 0 || us < best.us) {
-                best.rows = rows;
-                best.us = us;
+        for (int splits : {1, 2, 4}) {
+            // the point split's frame table (uploaded outside the timing)
+            int runs = 1;
+            if (splits > 1) {
+                if (fds[0].groups < 4)
+                    continue;
+                runs = direct_split_table(c, fds[0], splits, s, &st);
+                if (st != CGH_OK)
+                    return st;
+                CGH_HIP(ensure_ws(c, c->partials,
+                                  (size_t)runs * c->height * (size_t)c->width * sizeof(float)),
+                        "split-K workspace allocation");
+            }
+            for (int rows : {4, 8, 16}) {
+                if (!direct_rows_ok(mode, rows))
+                    continue;
+                double us = 0;
+                st = time_launches(
+                    [&] {
+                        if (splits == 1)
+                            return launch_direct_mode(c, mode, (const FrameDesc *)c->frames.p, 1,
+                                                      rows, out, nullptr, false, s);
+                        hipError_t e = launch_direct_mode(c, mode, (const FrameDesc *)c->dsplit.p,
+                                                          runs, rows, (float *)c->partials.p,
+                                                          nullptr, false, s);
+                        if (e == hipSuccess)
+                            e = launch_splitk_reduce((const float *)c->partials.p, runs,
+                                                     c->height, c->width, out, c->width, false, s);
+                        return e;
+                    },
+                    repeats, s, &us);
+                if (st != CGH_OK)
+                    return st;
+                ++tried;
+                if (best.rows == 0 || us < best.us) {
+                    best.rows = rows;
+                    best.splits = splits;
+                    best.us = us;
+                }
             }
         }
     } else {

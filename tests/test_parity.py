@@ -230,6 +230,40 @@ def test_split_k_counts(splits, monkeypatch):
             check(f"splits={splits}", gpu_hologram(c, mode), _REFS[key], mode)
 
 
+@pytest.mark.parametrize("splits,rows", [(2, "4"), (4, "16"), (4, "8")])
+def test_direct_point_splits(splits, rows, monkeypatch):
+    """The direct modes split over the points (runs of whole group pairs into
+    partial planes, summed in a fixed order): the full-size 1920 x 1080 case,
+    small clouds with fewer group pairs than splits, a chunked cloud, the
+    exact spherical wave, and bitwise repeatability."""
+    monkeypatch.setenv("CGH_DIRECT_SPLITS", str(splits))
+    monkeypatch.setenv("CGH_DIRECT_ROWS", rows)
+    c = cghgen.make_config(2)
+    cols, rows_s = _strided(c, 8)
+    key = "c2_strided8"
+    if key not in _REFS:
+        _REFS[key] = oracle.cloud_fresnel(c, cols=cols, rows=rows_s)
+    say(f"direct splits {splits} rows {rows} C2")
+    a = gpu_hologram(c, cgh.DIRECT_FP32)
+    check(f"split {splits}", a[np.ix_(rows_s, cols)], _REFS[key], cgh.DIRECT_FP32)
+    assert np.array_equal(a, gpu_hologram(c, cgh.DIRECT_FP32))
+    for n in (1, 33, 100, 3000):
+        s = cghgen.make_config(1, n=n)
+        say(f"direct splits {splits} rows {rows} N={n}")
+        check(f"split {splits} N={n}", gpu_hologram(s, cgh.DIRECT_FP32), oracle.cloud_fresnel(s),
+              cgh.DIRECT_FP32)
+    s = cghgen.make_config(1, n=500)
+    sph = oracle.spherical_complex(s.width, s.height, s.pitch, s.wavelength, s.x, s.y, s.z,
+                                   s.amp)[0]
+    e = oracle.nrms(gpu_hologram(s, cgh.SPHERICAL_FP32), sph)
+    say(f"spherical split {splits}: nrms={e:.3e}")
+    assert e <= 1e-5
+    monkeypatch.setenv("CGH_WORKSPACE_BYTES", str(1 << 20))
+    s = cghgen.make_config(1, n=3000)
+    check(f"split {splits} chunked", gpu_hologram(s, cgh.DIRECT_FP32), oracle.cloud_fresnel(s),
+          cgh.DIRECT_FP32)
+
+
 def test_bitwise_repeatable():
     c = cghgen.make_config(2, n=2000)
     for mode in ALL_MODES:

@@ -178,6 +178,6 @@ def test_tune_spherical():
     ctx.upload_cloud(c)
     rep = ctx.tune(MODE, repeats=2)
     say(rep)
-    assert "(2 candidates)" in rep
+    assert "(6 candidates)" in rep          # rows 4, 8 x point splits 1, 2, 4
     check("tuned", gpu(c, ctx), re)
     ctx.close()
