@@ -98,7 +98,7 @@ def _plan_in_tuned(kernel: str, plan: str, tuned) -> bool:
     if kernel.startswith("direct"):
         # the recorded traffic is that of an unsplit launch
         unsplit = bool(tuned and ("splits=1 " in tuned or "splits=0 " in tuned))
-        return (tuned is None and plan == "16") or (unsplit and f"rows={plan} " in tuned)
+        return unsplit and f"rows={plan} " in tuned
     bm, bn, wm, wn, st, sp = plan.split(",")
     return bool(tuned and f"bm={bm} bn={bn} waves={wm}x{wn} stages={st} splits={sp}" in tuned)
 
@@ -463,6 +463,7 @@ def traffic_driver(torch, cghgen, cgh) -> int:
         torch.cuda.synchronize()
         log(f"traffic driver: split_bf16 plan {plan}")
     os.environ.pop("CGH_GEMM_PLAN", None)
+    os.environ["CGH_DIRECT_SPLITS"] = "1"           # the recorded launches are unsplit
     for rows in TRAFFIC_PLANS["direct_fp32"]:
         os.environ["CGH_DIRECT_ROWS"] = rows
         for _ in range(2):
@@ -470,6 +471,7 @@ def traffic_driver(torch, cghgen, cgh) -> int:
         torch.cuda.synchronize()
         log(f"traffic driver: direct rows {rows}")
     os.environ.pop("CGH_DIRECT_ROWS", None)
+    os.environ.pop("CGH_DIRECT_SPLITS", None)
     for n in TRAFFIC_PLANS["fresnel_diffraction"]:
         g = torch.Generator(device="cuda:0").manual_seed(int(n))
         u = torch.randn((int(n), int(n)), dtype=torch.complex64, device="cuda:0", generator=g)

@@ -193,7 +193,8 @@ CGH_API cgh_status cgh_batch_compute(cgh_ctx *c, const cgh_frame *frames, int32_
 /* Autotune the launch shape of `mode` for this context's hologram size:
  * times every candidate (matrix-core modes: each built GEMM tile shape with a
  * few split-K counts, the time of the GEMM plus its split-K reduce; direct
- * mode: 4, 8 or 16 rows per lane) `repeats` times on the uploaded cloud (its
+ * modes: 4, 8 or 16 rows per lane, each with the points in 1, 2 or 4 runs
+ * summed in a fixed order) `repeats` times on the uploaded cloud (its
  * first point chunk) with HIP events on `stream`, and keeps the fastest for
  * later evaluations of this size and mode whose K size falls in the same
  * power-of-two bucket.  With the environment variable CGH_TUNE_CACHE set to

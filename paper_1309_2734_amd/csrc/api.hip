@@ -523,6 +523,21 @@ hipError_t launch_direct_mode(cgh_ctx *c, int mode, const FrameDesc *fd_dev, int
                          accumulate, s);
 }
 
+// Rows per lane of a direct launch: CGH_DIRECT_ROWS (4, 8 or 16; used to
+// sweep), else the tuned choice, else the default.
+int direct_rows(cgh_ctx *c, int mode)
+{
+    const TuneEntry *t = find_tuned(c, tune_key(c, mode, 0, c->height));
+    int rows = t && direct_rows_ok(mode, t->rows) ? t->rows
+                                                   : (mode == CGH_SPHERICAL_FP32 ? 8 : 16);
+    if (const char *env = std::getenv("CGH_DIRECT_ROWS")) {
+        const int r = std::atoi(env);
+        if (direct_rows_ok(mode, r))
+            rows = r;
+    }
+    return rows;
+}
+
 // Direct kernel over frames whose constants occupy slots [0, total_slots)
 // (tables built here).  `fd_dev` points at the device copy of the frames.
 cgh_status run_direct(cgh_ctx *c, int mode, const FrameDesc *fd_dev, int n_frames,
@@ -533,15 +548,7 @@ cgh_status run_direct(cgh_ctx *c, int mode, const FrameDesc *fd_dev, int n_frame
     if (st != CGH_OK)
         return st;
     const bool sph = mode == CGH_SPHERICAL_FP32;
-    // rows per lane: CGH_DIRECT_ROWS (4, 8 or 16; used to sweep), else the
-    // tuned choice, else the default
-    const TuneEntry *t = find_tuned(c, tune_key(c, mode, 0, c->height));
-    int rows = t && direct_rows_ok(mode, t->rows) ? t->rows : (sph ? 8 : 16);
-    if (const char *env = std::getenv("CGH_DIRECT_ROWS")) {
-        const int r = std::atoi(env);
-        if (direct_rows_ok(mode, r))
-            rows = r;
-    }
+    const int rows = direct_rows(c, mode);
     const char *name = sph ? (out_im ? "direct_sphere_complex" : "direct_sphere")
                            : (out_im ? "direct_fp32_complex" : "direct_fp32");
     Bracket br(c, name, s);
@@ -552,11 +559,21 @@ cgh_status run_direct(cgh_ctx *c, int mode, const FrameDesc *fd_dev, int n_frame
 }
 
 // Point split of a direct evaluation: the K split count (CGH_DIRECT_SPLITS,
-// 1, 2 or 4, used to sweep; else the tuned choice; else 1).
+// 1, 2 or 4, used to sweep; else the tuned choice; else enough runs, up to 4,
+// for about 2048 workgroups of four waves, eight waves per SIMD).
 int direct_splits(cgh_ctx *c, int mode)
 {
     const TuneEntry *t = find_tuned(c, tune_key(c, mode, 0, c->height));
-    int sp = t && t->splits > 0 ? t->splits : 1;
+    int sp = 1;
+    if (t && t->splits > 0) {
+        sp = t->splits;
+    } else {
+        const int64_t wgs = (int64_t)((c->width + 63) / 64) *
+                               ((c->height + 4 * direct_rows(c, mode) - 1) /
+                                (4 * direct_rows(c, mode)));
+        while (sp < 4 && wgs * sp < 2048)
+            sp *= 2;
+    }
     if (const char *env = std::getenv("CGH_DIRECT_SPLITS")) {
         const int v = std::atoi(env);
         if (v == 1 || v == 2 || v == 4)

@@ -303,8 +303,11 @@ def _batch_case():
 
 
 @pytest.mark.parametrize("mode", ALL_MODES, ids=[NAMES[m] for m in ALL_MODES])
-def test_batch_frames_match_oracle_and_single(mode):
+def test_batch_frames_match_oracle_and_single(mode, monkeypatch):
     import torch
+    # the single evaluations below unsplit, as a batch frame is: a small
+    # hologram's points are otherwise split into runs summed separately
+    monkeypatch.setenv("CGH_DIRECT_SPLITS", "1")
     b = _batch_case()
     frames = cgh.batch_frames(b)
     # an overlapping frame and a repeated frame
@@ -326,7 +329,7 @@ def test_batch_frames_match_oracle_and_single(mode):
             continue
         check(f"batch frame {f} N={n}", got[f], ref, mode)
         # a single-hologram evaluation of that frame: the same numbers for the
-        # direct kernel; the matrix-core batch runs each frame's whole K range
+        # (unsplit) direct kernel; the matrix-core batch runs each frame's whole K range
         # in one workgroup (no split-K), so its sums are ordered differently
         single = cgh.Context(b.width, b.height, b.pitch, lam)
         single.upload(b.x[sl], b.y[sl], b.z[sl], b.amp[sl])
