@@ -584,9 +584,10 @@ int direct_splits(cgh_ctx *c, int mode)
 
 // Frame descriptors of one frame's points cut into at most `splits` runs of
 // whole group pairs (the direct kernel takes a frame's groups two at a
-// time), run r writing partial plane r; uploaded to c->dsplit.  Returns the
-// number of runs.
-int direct_split_table(cgh_ctx *c, const FrameDesc &fd, int splits, hipStream_t s,
+// time), run r writing partial planes r * planes .. (planes = 2 for a
+// complex evaluation: real, then imaginary); uploaded to c->dsplit.  Returns
+// the number of runs.
+int direct_split_table(cgh_ctx *c, const FrameDesc &fd, int splits, int planes, hipStream_t s,
                        cgh_status *st)
 {
     const int64_t plane = (int64_t)c->width * c->height;
@@ -595,7 +596,7 @@ int direct_split_table(cgh_ctx *c, const FrameDesc &fd, int splits, hipStream_t 
     std::vector<FrameDesc> d;
     for (int64_t p = 0; p < pairs; p += per) {
         const int64_t np = std::min(per, pairs - p);
-        d.push_back({fd.first + p * 2 * kGroup, 2 * np, (int64_t)d.size() * plane});
+        d.push_back({fd.first + p * 2 * kGroup, 2 * np, (int64_t)d.size() * planes * plane});
     }
     *st = CGH_OK;
     const hipError_t e = upload_small(c, c->dsplit, d.data(), d.size() * sizeof(FrameDesc), s);
@@ -605,30 +606,34 @@ int direct_split_table(cgh_ctx *c, const FrameDesc &fd, int splits, hipStream_t 
 }
 
 // Direct mode for one frame (host copy fd, device copy fd_dev), split over
-// its points when the split count asks for it and there is no imaginary
-// part: the runs accumulate into partial planes, summed in a fixed order
-// (more workgroups for a small hologram, the same numbers on every run).
+// its points when the split count asks for it: the runs accumulate into
+// partial planes, summed in a fixed order (more workgroups for a small
+// hologram, the same numbers on every run).
 cgh_status run_direct_one(cgh_ctx *c, int mode, const FrameDesc &fd, const FrameDesc *fd_dev,
                           int64_t total_slots, float *out, float *out_im, bool accumulate,
                           hipStream_t s)
 {
-    const int splits = out_im ? 1 : direct_splits(c, mode);
+    const size_t plane = (size_t)c->width * c->height;
+    // a complex evaluation's planes [Re; Im] are consecutive: each run writes
+    // its own pair, and the pairs are summed as planes of 2H rows
+    const int planes = out_im ? 2 : 1;
+    const int splits = out_im && out_im != out + plane ? 1 : direct_splits(c, mode);
     if (splits <= 1 || fd.groups < 4)
         return run_direct(c, mode, fd_dev, 1, total_slots, out, out_im, accumulate, s);
     cgh_status st = CGH_OK;
-    const int runs = direct_split_table(c, fd, splits, s, &st);
+    const int runs = direct_split_table(c, fd, splits, planes, s, &st);
     if (st != CGH_OK)
         return st;
-    const size_t plane = (size_t)c->width * c->height;
-    CGH_HIP(ensure_ws(c, c->partials, (size_t)runs * plane * sizeof(float)),
+    CGH_HIP(ensure_ws(c, c->partials, (size_t)runs * planes * plane * sizeof(float)),
             "split-K workspace allocation");
-    st = run_direct(c, mode, (const FrameDesc *)c->dsplit.p, runs, total_slots,
-                    (float *)c->partials.p, nullptr, false, s);
+    float *part = (float *)c->partials.p;
+    st = run_direct(c, mode, (const FrameDesc *)c->dsplit.p, runs, total_slots, part,
+                    out_im ? part + plane : nullptr, false, s);
     if (st != CGH_OK)
         return st;
     Bracket br(c, "splitk_reduce", s);
-    CGH_HIP(launch_splitk_reduce((const float *)c->partials.p, runs, c->height, c->width, out,
-                                 c->width, accumulate, s),
+    CGH_HIP(launch_splitk_reduce(part, runs, planes * c->height, c->width, out, c->width,
+                                 accumulate, s),
             "split-K reduce launch");
     br.done();
     return CGH_OK;
@@ -1497,7 +1502,7 @@ cgh_status cgh_tune(cgh_ctx *c, cgh_mode mode, int32_t repeats, char *report, in
             if (splits > 1) {
                 if (fds[0].groups < 4)
                     continue;
-                runs = direct_split_table(c, fds[0], splits, s, &st);
+                runs = direct_split_table(c, fds[0], splits, 1, s, &st);
                 if (st != CGH_OK)
                     return st;
                 CGH_HIP(ensure_ws(c, c->partials,
