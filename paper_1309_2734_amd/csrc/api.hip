@@ -8,13 +8,22 @@
 // or
 //   a4 hi/lo line factors                  k_factors        (matrix-core modes)
 //   a5 split GEMM (+ fixed-order split-K)  k_gemm, k_splitk_reduce
-// Large clouds are cut into point chunks that fit the workspace budget; the
-// chunks accumulate into the output in order.
+// Large clouds are cut into point chunks that fit the workspace; the chunks
+// accumulate into the output in order.
+//
+// Streams.  Every call only enqueues work on its stream.  A single
+// hologram's segment and frame descriptors travel in the kernel arguments; a
+// batch's tables go to device memory through a page-locked staging ring with
+// asynchronous copies.  Calls on one context share its workspace, so each
+// call's stream first waits for an event recorded behind the previous call
+// (on whatever stream that ran).  The host blocks only where a workspace
+// buffer must grow (the allocator synchronises the device).
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <deque>
 #include <new>
 #include <string>
 #include <vector>
@@ -47,6 +56,13 @@ cgh_status hip_fail(hipError_t e, const char *what)
             return hip_fail(e_, what);                                                        \
     } while (0)
 
+#define CGH_TRY(call)                                                                         \
+    do {                                                                                      \
+        cgh_status s_ = (call);                                                               \
+        if (s_ != CGH_OK)                                                                     \
+            return s_;                                                                        \
+    } while (0)
+
 // Restores the caller's current device on scope exit.
 struct DeviceGuard {
     int prev = -1;
@@ -70,7 +86,8 @@ struct DeviceGuard {
 };
 
 // Grow-only device buffer.  `shadow` keeps the bytes last copied into a
-// small table, so an unchanged table is not copied (or waited for) again.
+// small table, so an unchanged table is not copied again.  Growing waits for
+// the device first: queued work may still read the old allocation.
 struct DevBuf {
     void *p = nullptr;
     size_t cap = 0;
@@ -81,7 +98,9 @@ struct DevBuf {
             return hipSuccess;
         shadow.clear();
         if (p) {
-            hipError_t e = hipFree(p);
+            hipError_t e = hipDeviceSynchronize();
+            if (e == hipSuccess)
+                e = hipFree(p);
             p = nullptr;
             cap = 0;
             if (e != hipSuccess)
@@ -126,6 +145,114 @@ size_t workspace_budget()
     return (size_t)16 << 30;
 }
 
+// True while `s` records into a graph.
+bool capturing(hipStream_t s)
+{
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &st) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return st != hipStreamCaptureStatusNone;
+}
+
+// Page-locked staging ring for the small device tables of batch calls.  A
+// table is written into the ring and copied to the device asynchronously on
+// the call's stream; an event recorded behind the copy tells when its ring
+// region may be written again.  Enqueuing a copy never waits for earlier
+// kernels, only (after the ring wraps) for earlier copies still pending.
+struct Staging {
+    char *host = nullptr;
+    size_t cap = 0, head = 0;
+    struct Use {
+        size_t off, len;
+        hipEvent_t ev;
+    };
+    std::deque<Use> busy;
+    std::vector<hipEvent_t> spare;
+
+    hipError_t wait_all()
+    {
+        for (auto &u : busy) {
+            hipError_t e = hipEventSynchronize(u.ev);
+            if (e != hipSuccess)
+                return e;
+            spare.push_back(u.ev);
+        }
+        busy.clear();
+        return hipSuccess;
+    }
+    // A region of `len` bytes no pending copy reads; *off receives its offset.
+    hipError_t reserve(size_t len, size_t *off)
+    {
+        len = (len + 255) / 256 * 256;
+        if (len > cap) {
+            hipError_t e = wait_all();
+            if (e != hipSuccess)
+                return e;
+            const size_t want = std::max({len, 2 * cap, (size_t)1 << 20});
+            if (host)
+                (void)hipHostFree(host);
+            host = nullptr;
+            cap = head = 0;
+            e = hipHostMalloc((void **)&host, want, hipHostMallocDefault);
+            if (e != hipSuccess) {
+                host = nullptr;
+                return e;
+            }
+            cap = want;
+        }
+        if (head + len > cap)
+            head = 0;
+        for (auto it = busy.begin(); it != busy.end();) {
+            const bool overlap = it->off < head + len && head < it->off + it->len;
+            const hipError_t e = overlap ? hipEventSynchronize(it->ev) : hipEventQuery(it->ev);
+            if (e == hipSuccess) {
+                spare.push_back(it->ev);
+                it = busy.erase(it);
+            } else if (e == hipErrorNotReady) {
+                ++it;
+            } else {
+                return e;
+            }
+        }
+        *off = head;
+        head += len;
+        return hipSuccess;
+    }
+    // The copy out of [off, off + len) was enqueued on s.
+    hipError_t mark(size_t off, size_t len, hipStream_t s)
+    {
+        hipEvent_t ev = nullptr;
+        if (!spare.empty()) {
+            ev = spare.back();
+            spare.pop_back();
+        } else {
+            hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+            if (e != hipSuccess)
+                return e;
+        }
+        hipError_t e = hipEventRecord(ev, s);
+        if (e != hipSuccess) {
+            spare.push_back(ev);
+            return e;
+        }
+        busy.push_back({off, len, ev});
+        return hipSuccess;
+    }
+    void release()
+    {
+        (void)wait_all();
+        for (auto ev : spare)
+            (void)hipEventDestroy(ev);
+        spare.clear();
+        if (host)
+            (void)hipHostFree(host);
+        host = nullptr;
+        cap = head = 0;
+    }
+};
+
 struct ProfRecord {
     const char *name;
     hipEvent_t start, stop;
@@ -158,29 +285,31 @@ struct cgh_ctx {
     int64_t n = 0, n_cap = 0;
     bool uploaded = false;
 
-    // workspace
+    // workspace, shared by all evaluations (each call rewrites what it reads)
     DevBuf consts;                    // beta | cx | cy | zlam (double) | amp | zhalf (float)
-    int64_t consts_cap = 0;           // slots
     DevBuf tab_u, tab_v;              // a2 tables
     DevBuf tab_x, tab_y;              // a2s offset tables (exact spherical wave)
     DevBuf fac;                       // Lh | Ll | Rh | Rl in one allocation
-    DevBuf partials;                  // split-K partial tiles
-    DevBuf segs, frames;              // small device tables
-    DevBuf dsplit;                    // point-split frame table of a direct evaluation
+    DevBuf partials;                  // split-K partial tiles / point-split planes
     DevBuf tune_out;                  // scratch hologram for cgh_tune
     DevBuf field;                     // complex object wave for cgh_kinoform
-    DevBuf items, counter;            // batched GEMM work list and its queue counter
+    // device tables of batch calls only (a captured batch graph reads them;
+    // no other call writes them)
+    DevBuf bsegs, bframes, items, counter;
+    Staging staging;                  // host side of the batch tables' copies
     uint64_t ws_generation = 0;       // bumps when a buffer moves
+
+    // ordering of calls made on different streams
+    hipEvent_t order_ev = nullptr;
+    hipStream_t order_stream = nullptr;
+    bool order_valid = false;
 
     // batch graph cache
     hipGraphExec_t graph_exec = nullptr;
     std::vector<cgh_frame> graph_frames;
     int graph_mode = -1;
     float *graph_out = nullptr;
-    hipStream_t graph_stream = nullptr;
     uint64_t graph_generation = 0;
-    uint64_t points_generation = 0;
-    uint64_t graph_points_generation = 0;
 
     // autotuned plans (from cgh_tune or the cache file), see plan lookup
     std::string arch;
@@ -214,6 +343,65 @@ hipError_t ensure_ws(cgh_ctx *c, DevBuf &b, size_t bytes)
     return e;
 }
 
+// Calls on one context share its workspace: a call's stream waits for the
+// end of the previous call when that ran on another stream (nothing is
+// recorded or waited for inside a stream capture).
+struct CallOrder {
+    cgh_ctx *c;
+    hipStream_t s;
+    bool active;
+    CallOrder(cgh_ctx *c_, hipStream_t s_) : c(c_), s(s_), active(!capturing(s_)) {}
+    hipError_t enter()
+    {
+        if (!active || !c->order_valid || c->order_stream == s)
+            return hipSuccess;
+        return hipStreamWaitEvent(s, c->order_ev, 0);
+    }
+    ~CallOrder()
+    {
+        if (!active)
+            return;
+        if (!c->order_ev &&
+            hipEventCreateWithFlags(&c->order_ev, hipEventDisableTiming) != hipSuccess) {
+            c->order_ev = nullptr;
+            return;
+        }
+        if (hipEventRecord(c->order_ev, s) == hipSuccess) {
+            c->order_stream = s;
+            c->order_valid = true;
+        } else {
+            // without the marker a later stream cannot wait for this call
+            (void)hipStreamSynchronize(s);
+            c->order_valid = false;
+        }
+    }
+};
+
+// Copy a small host table into device buffer b, ordered on stream s, unless
+// b already holds those bytes (or will once s reaches the copy that put them
+// there).  Inside a stream capture a table that would change is refused,
+// which abandons the capture.
+cgh_status upload_small(cgh_ctx *c, DevBuf &b, const void *src, size_t bytes, hipStream_t s,
+                        const char *what)
+{
+    if (bytes == 0)
+        return CGH_OK;
+    if (b.p && b.shadow.size() == bytes && std::memcmp(b.shadow.data(), src, bytes) == 0)
+        return CGH_OK;
+    if (capturing(s))
+        return fail(CGH_ESTATE, std::string(what) + " would change inside a stream capture");
+    CGH_HIP(ensure_ws(c, b, bytes), what);
+    size_t off = 0;
+    CGH_HIP(c->staging.reserve(bytes, &off), what);
+    std::memcpy(c->staging.host + off, src, bytes);
+    b.shadow.clear();
+    CGH_HIP(hipMemcpyAsync(b.p, c->staging.host + off, bytes, hipMemcpyHostToDevice, s), what);
+    if (c->staging.mark(off, bytes, s) != hipSuccess)
+        CGH_HIP(hipStreamSynchronize(s), what);   // the region must not be reused early
+    b.shadow.assign((const char *)src, (const char *)src + bytes);
+    return CGH_OK;
+}
+
 hipEvent_t take_event(cgh_ctx *c)
 {
     if (!c->prof_free.empty()) {
@@ -228,7 +416,7 @@ hipEvent_t take_event(cgh_ctx *c)
 }
 
 // Launch bracket for profiling: record a start event before and a stop
-// event after a launch on stream s.
+// event after a launch on stream s (nothing without a profiling context).
 struct Bracket {
     cgh_ctx *c;
     const char *name;
@@ -236,7 +424,7 @@ struct Bracket {
     hipEvent_t a = nullptr, b = nullptr;
     Bracket(cgh_ctx *c_, const char *n, hipStream_t s_) : c(c_), name(n), s(s_)
     {
-        if (c->profiling) {
+        if (c && c->profiling) {
             a = take_event(c);
             b = take_event(c);
             if (a && b)
@@ -260,9 +448,9 @@ struct Bracket {
     }
 };
 
-PointConsts consts_view(cgh_ctx *c, int64_t slots)
+// Constants of `slots` slots laid out from `base`: 4 x 8 + 2 x 4 bytes per slot.
+PointConsts consts_at(char *base, int64_t slots)
 {
-    char *base = (char *)c->consts.p;
     PointConsts pc;
     pc.beta = (double *)base;
     pc.cx = (double *)(base + 8 * slots);
@@ -272,56 +460,7 @@ PointConsts consts_view(cgh_ctx *c, int64_t slots)
     pc.zhalf = (float *)(base + 36 * slots);
     return pc;
 }
-
-hipError_t ensure_consts(cgh_ctx *c, int64_t slots)
-{
-    // 4 x 8 + 2 x 4 bytes per slot; the view is laid out for `slots`
-    hipError_t e = ensure_ws(c, c->consts, (size_t)slots * 40 + 256);
-    if (e == hipSuccess)
-        c->consts_cap = slots;
-    return e;
-}
-
-// Factor set of a matrix-core evaluation: amb / anb line blocks of L / R,
-// kblocks K blocks, hl halves (common.h has the layout).
-cgh_status ensure_factors(cgh_ctx *c, int amb, int anb, int64_t kblocks, int hl, FactorSet &f)
-{
-    f.hl = hl;
-    f.amb = amb;
-    f.anb = anb;
-    f.kblocks = kblocks;
-    CGH_HIP(ensure_ws(c, c->fac, (size_t)std::max<int64_t>(f.bytes(), 1)), "factor allocation");
-    f.base = (char *)c->fac.p;
-    return CGH_OK;
-}
-
-// Segment and frame tables (small) go to device memory with a synchronous
-// copy, after the stream has drained (queued kernels may still read the old
-// contents).  A table whose bytes did not change since the last copy is left
-// alone, so repeated evaluations of one workload never block the host.
-hipError_t upload_small(cgh_ctx *c, DevBuf &b, const void *src, size_t bytes, hipStream_t s)
-{
-    if (b.p && b.shadow.size() == bytes && std::memcmp(b.shadow.data(), src, bytes) == 0)
-        return hipSuccess;
-    hipError_t e = ensure_ws(c, b, bytes);
-    if (e != hipSuccess)
-        return e;
-    e = hipStreamSynchronize(s);
-    if (e != hipSuccess)
-        return e;
-    e = hipMemcpy(b.p, src, bytes, hipMemcpyHostToDevice);
-    if (e != hipSuccess) {
-        b.shadow.clear();
-        return e;
-    }
-    b.shadow.assign((const char *)src, (const char *)src + bytes);
-    return hipSuccess;
-}
-
-const float *pts_x(cgh_ctx *c) { return (const float *)c->points.p; }
-const float *pts_y(cgh_ctx *c) { return pts_x(c) + c->n_cap; }
-const float *pts_z(cgh_ctx *c) { return pts_x(c) + 2 * c->n_cap; }
-const float *pts_a(cgh_ctx *c) { return pts_x(c) + 3 * c->n_cap; }
+size_t consts_bytes(int64_t slots) { return (size_t)slots * 40 + 256; }
 
 cgh_status check_mode(int mode)
 {
@@ -384,9 +523,6 @@ struct Plan {
     int tiles_m = 0, tiles_n = 0;
 };
 
-// Tile shape and split count for an M x N output over `slots` points.
-// CGH_GEMM_PLAN="bm,bn,waves_m,waves_n,stages,splits" overrides the choice
-// (used to sweep shapes; an unsupported shape is ignored, splits 0 = auto).
 int kblock_bucket(int64_t kblocks)
 {
     int b = 0;
@@ -405,12 +541,17 @@ std::string tune_key(const cgh_ctx *c, int mode, int64_t kblocks, int m_lines)
 
 const TuneEntry *find_tuned(const cgh_ctx *c, const std::string &key)
 {
+    if (!c)
+        return nullptr;
     for (auto &t : c->tuned)
         if (t.key == key)
             return &t;
     return nullptr;
 }
 
+// Tile shape and split count for an M x N output over `slots` points.
+// CGH_GEMM_PLAN="bm,bn,waves_m,waves_n,stages,splits" overrides the choice
+// (used to sweep shapes; an unsupported shape is ignored, splits 0 = auto).
 Plan plan_gemm(int M, int N, int64_t slots, const ModeInfo &mi, const TuneEntry *tuned = nullptr)
 {
     struct Shape {
@@ -470,32 +611,118 @@ Plan plan_gemm(int M, int N, int64_t slots, const ModeInfo &mi, const TuneEntry 
     return best;
 }
 
-// ------------------------------------------------------- one set of frames
-// Tables of a direct mode for constant slots [0, slots): a2 (Eq. (2)) or
-// a2s (Eq. (1)).
-cgh_status direct_tables(cgh_ctx *c, int mode, int64_t slots, hipStream_t s)
+// --------------------------------------------------------- evaluation core
+// Hologram geometry of one evaluation.
+struct Geo {
+    int width = 0, height = 0, wpad = 0, hpad = 0;
+    double pitch = 0.0;
+};
+
+Geo ctx_geo(const cgh_ctx *c) { return {c->width, c->height, c->wpad, c->hpad, c->pitch}; }
+
+// Where an evaluation's intermediates live.
+enum class Role { Consts = 0, TabU, TabV, TabX, TabY, Factors, Partials, Count };
+
+struct Ws {
+    virtual ~Ws() = default;
+    // at least `bytes` of device memory for `role`; stable for the evaluation
+    virtual cgh_status get(Role role, size_t bytes, void **p) = 0;
+};
+
+// The context's grow-only buffers.
+struct CtxWs final : Ws {
+    cgh_ctx *c;
+    explicit CtxWs(cgh_ctx *c_) : c(c_) {}
+    cgh_status get(Role role, size_t bytes, void **p) override
+    {
+        DevBuf *b = nullptr;
+        switch (role) {
+        case Role::Consts: b = &c->consts; break;
+        case Role::TabU: b = &c->tab_u; break;
+        case Role::TabV: b = &c->tab_v; break;
+        case Role::TabX: b = &c->tab_x; break;
+        case Role::TabY: b = &c->tab_y; break;
+        case Role::Factors: b = &c->fac; break;
+        default: b = &c->partials; break;
+        }
+        CGH_HIP(ensure_ws(c, *b, std::max<size_t>(bytes, 1)), "workspace allocation");
+        *p = b->p;
+        return CGH_OK;
+    }
+};
+
+// One evaluation: geometry, the points (device SoA), the workspace and, with
+// a context, its tuned plans and profiling.
+struct Eval {
+    cgh_ctx *c = nullptr;     // nullptr: default plans, no profiling
+    Geo g;
+    const float *x = nullptr, *y = nullptr, *z = nullptr, *a = nullptr;
+    Ws *ws = nullptr;
+    size_t partial_cap = 0;   // bytes of split partials allowed (0: no limit)
+    PointConsts pc{};         // set by ev_consts
+    float *tu = nullptr, *tv = nullptr, *tx = nullptr, *ty = nullptr;   // set by ev_tables
+};
+
+const float *pts_x(cgh_ctx *c) { return (const float *)c->points.p; }
+const float *pts_y(cgh_ctx *c) { return pts_x(c) + c->n_cap; }
+const float *pts_z(cgh_ctx *c) { return pts_x(c) + 2 * c->n_cap; }
+const float *pts_a(cgh_ctx *c) { return pts_x(c) + 3 * c->n_cap; }
+
+Eval ctx_eval(cgh_ctx *c, Ws *ws)
+{
+    Eval ev;
+    ev.c = c;
+    ev.g = ctx_geo(c);
+    ev.x = pts_x(c);
+    ev.y = pts_y(c);
+    ev.z = pts_z(c);
+    ev.a = pts_a(c);
+    ev.ws = ws;
+    return ev;
+}
+
+// a1: per-point constants of the segments into `slots` slots.
+cgh_status ev_consts(Eval &ev, const SegList &segs, int n_segs, int64_t max_count, int64_t slots,
+                     hipStream_t s)
+{
+    void *p = nullptr;
+    CGH_TRY(ev.ws->get(Role::Consts, consts_bytes(slots), &p));
+    ev.pc = consts_at((char *)p, slots);
+    Bracket br(ev.c, "point_consts", s);
+    CGH_HIP(launch_point_consts(ev.x, ev.y, ev.z, ev.a, segs, n_segs,
+                                std::max<int64_t>(max_count, 1), ev.g.width, ev.g.height,
+                                ev.g.pitch, ev.pc, s),
+            "point constant launch");
+    br.done();
+    return CGH_OK;
+}
+
+// a2 (Eq. (2)) or a2s (Eq. (1)) tables for constant slots [0, slots).
+cgh_status ev_tables(Eval &ev, int mode, int64_t slots, hipStream_t s)
 {
     const bool sph = mode == CGH_SPHERICAL_FP32;
-    const size_t tu = (size_t)std::max<int64_t>(slots, 1) * c->wpad * sizeof(float);
-    const size_t tv = (size_t)std::max<int64_t>(slots, 1) * c->hpad * sizeof(float);
-    CGH_HIP(ensure_ws(c, c->tab_u, tu), "table allocation");
-    CGH_HIP(ensure_ws(c, c->tab_v, tv), "table allocation");
+    const size_t tu = (size_t)std::max<int64_t>(slots, 1) * ev.g.wpad * sizeof(float);
+    const size_t tv = (size_t)std::max<int64_t>(slots, 1) * ev.g.hpad * sizeof(float);
+    void *p = nullptr;
+    CGH_TRY(ev.ws->get(Role::TabU, tu, &p));
+    ev.tu = (float *)p;
+    CGH_TRY(ev.ws->get(Role::TabV, tv, &p));
+    ev.tv = (float *)p;
     if (sph) {
-        CGH_HIP(ensure_ws(c, c->tab_x, tu), "table allocation");
-        CGH_HIP(ensure_ws(c, c->tab_y, tv), "table allocation");
+        CGH_TRY(ev.ws->get(Role::TabX, tu, &p));
+        ev.tx = (float *)p;
+        CGH_TRY(ev.ws->get(Role::TabY, tv, &p));
+        ev.ty = (float *)p;
     }
     if (slots <= 0)
         return CGH_OK;
-    const PointConsts pc = consts_view(c, c->consts_cap);
-    Bracket br(c, sph ? "sphere_tables" : "phase_tables", s);
+    Bracket br(ev.c, sph ? "sphere_tables" : "phase_tables", s);
     if (sph)
-        CGH_HIP(launch_sphere_tables(pc, slots, c->wpad, c->hpad, (float *)c->tab_u.p,
-                                     (float *)c->tab_v.p, (float *)c->tab_x.p,
-                                     (float *)c->tab_y.p, s),
+        CGH_HIP(launch_sphere_tables(ev.pc, slots, ev.g.wpad, ev.g.hpad, ev.tu, ev.tv, ev.tx,
+                                     ev.ty, s),
                 "sphere_tables launch");
     else
-        CGH_HIP(launch_phase_tables(pc, slots, c->wpad, c->hpad, (float *)c->tab_u.p,
-                                    (float *)c->tab_v.p, s),
+        CGH_HIP(launch_phase_tables(ev.pc, slots, ev.g.wpad, ev.g.hpad, ev.tu, ev.tv, s),
                 "phase_tables launch");
     br.done();
     return CGH_OK;
@@ -509,25 +736,22 @@ bool direct_rows_ok(int mode, int rows)
     return rows == 4 || rows == 8 || rows == 16;
 }
 
-hipError_t launch_direct_mode(cgh_ctx *c, int mode, const FrameDesc *fd_dev, int n_frames,
+hipError_t launch_direct_mode(const Eval &ev, int mode, const FrameList &frames, int n_frames,
                               int rows, float *out, float *out_im, bool accumulate, hipStream_t s)
 {
-    const PointConsts pc = consts_view(c, c->consts_cap);
     if (mode == CGH_SPHERICAL_FP32)
-        return launch_direct_sphere((const float *)c->tab_u.p, (const float *)c->tab_v.p,
-                                    (const float *)c->tab_x.p, (const float *)c->tab_y.p, pc.amp,
-                                    pc.zhalf, fd_dev, n_frames, c->width, c->height, c->wpad,
-                                    c->hpad, rows, out, out_im, accumulate, s);
-    return launch_direct((const float *)c->tab_u.p, (const float *)c->tab_v.p, pc.amp, fd_dev,
-                         n_frames, c->width, c->height, c->wpad, c->hpad, rows, out, out_im,
-                         accumulate, s);
+        return launch_direct_sphere(ev.tu, ev.tv, ev.tx, ev.ty, ev.pc.amp, ev.pc.zhalf, frames,
+                                    n_frames, ev.g.width, ev.g.height, ev.g.wpad, ev.g.hpad, rows,
+                                    out, out_im, accumulate, s);
+    return launch_direct(ev.tu, ev.tv, ev.pc.amp, frames, n_frames, ev.g.width, ev.g.height,
+                         ev.g.wpad, ev.g.hpad, rows, out, out_im, accumulate, s);
 }
 
 // Rows per lane of a direct launch: CGH_DIRECT_ROWS (4, 8 or 16; used to
 // sweep), else the tuned choice, else the default.
-int direct_rows(cgh_ctx *c, int mode)
+int direct_rows(const Eval &ev, int mode)
 {
-    const TuneEntry *t = find_tuned(c, tune_key(c, mode, 0, c->height));
+    const TuneEntry *t = ev.c ? find_tuned(ev.c, tune_key(ev.c, mode, 0, ev.g.height)) : nullptr;
     int rows = t && direct_rows_ok(mode, t->rows) ? t->rows
                                                    : (mode == CGH_SPHERICAL_FP32 ? 8 : 16);
     if (const char *env = std::getenv("CGH_DIRECT_ROWS")) {
@@ -538,39 +762,19 @@ int direct_rows(cgh_ctx *c, int mode)
     return rows;
 }
 
-// Direct kernel over frames whose constants occupy slots [0, total_slots)
-// (tables built here).  `fd_dev` points at the device copy of the frames.
-cgh_status run_direct(cgh_ctx *c, int mode, const FrameDesc *fd_dev, int n_frames,
-                      int64_t total_slots, float *out, float *out_im, bool accumulate,
-                      hipStream_t s)
-{
-    cgh_status st = direct_tables(c, mode, total_slots, s);
-    if (st != CGH_OK)
-        return st;
-    const bool sph = mode == CGH_SPHERICAL_FP32;
-    const int rows = direct_rows(c, mode);
-    const char *name = sph ? (out_im ? "direct_sphere_complex" : "direct_sphere")
-                           : (out_im ? "direct_fp32_complex" : "direct_fp32");
-    Bracket br(c, name, s);
-    CGH_HIP(launch_direct_mode(c, mode, fd_dev, n_frames, rows, out, out_im, accumulate, s),
-            "direct launch");
-    br.done();
-    return CGH_OK;
-}
-
 // Point split of a direct evaluation: the K split count (CGH_DIRECT_SPLITS,
 // 1, 2 or 4, used to sweep; else the tuned choice; else enough runs, up to 4,
 // for about 2048 workgroups of four waves, eight waves per SIMD).
-int direct_splits(cgh_ctx *c, int mode)
+int direct_splits(const Eval &ev, int mode)
 {
-    const TuneEntry *t = find_tuned(c, tune_key(c, mode, 0, c->height));
+    const TuneEntry *t = ev.c ? find_tuned(ev.c, tune_key(ev.c, mode, 0, ev.g.height)) : nullptr;
     int sp = 1;
     if (t && t->splits > 0) {
         sp = t->splits;
     } else {
-        const int64_t wgs = (int64_t)((c->width + 63) / 64) *
-                               ((c->height + 4 * direct_rows(c, mode) - 1) /
-                                (4 * direct_rows(c, mode)));
+        const int rows = direct_rows(ev, mode);
+        const int64_t wgs = (int64_t)((ev.g.width + 63) / 64) *
+                            ((ev.g.height + 4 * rows - 1) / (4 * rows));
         while (sp < 4 && wgs * sp < 2048)
             sp *= 2;
     }
@@ -582,102 +786,122 @@ int direct_splits(cgh_ctx *c, int mode)
     return sp;
 }
 
-// Frame descriptors of one frame's points cut into at most `splits` runs of
+// One frame's points cut into at most `splits` (<= kInlineFrames) runs of
 // whole group pairs (the direct kernel takes a frame's groups two at a
 // time), run r writing partial planes r * planes .. (planes = 2 for a
-// complex evaluation: real, then imaginary); uploaded to c->dsplit.  Returns
-// the number of runs.
-int direct_split_table(cgh_ctx *c, const FrameDesc &fd, int splits, int planes, hipStream_t s,
-                       cgh_status *st)
+// complex evaluation: real, then imaginary).  *runs receives the count.
+FrameList split_frames(const FrameDesc &fd, int splits, int planes, int64_t plane, int *runs)
 {
-    const int64_t plane = (int64_t)c->width * c->height;
+    FrameList fl{};
+    fl.dev = nullptr;
     const int64_t pairs = fd.groups / 2;
     const int64_t per = std::max<int64_t>(1, (pairs + splits - 1) / splits);
-    std::vector<FrameDesc> d;
-    for (int64_t p = 0; p < pairs; p += per) {
+    int r = 0;
+    for (int64_t p = 0; p < pairs && r < kInlineFrames; p += per, ++r) {
         const int64_t np = std::min(per, pairs - p);
-        d.push_back({fd.first + p * 2 * kGroup, 2 * np, (int64_t)d.size() * planes * plane});
+        fl.inl[r] = {fd.first + p * 2 * kGroup, 2 * np, (int64_t)r * planes * plane};
     }
-    *st = CGH_OK;
-    const hipError_t e = upload_small(c, c->dsplit, d.data(), d.size() * sizeof(FrameDesc), s);
-    if (e != hipSuccess)
-        *st = hip_fail(e, "split table upload");
-    return (int)d.size();
+    *runs = r;
+    return fl;
 }
 
-// Direct mode for one frame (host copy fd, device copy fd_dev), split over
-// its points when the split count asks for it: the runs accumulate into
-// partial planes, summed in a fixed order (more workgroups for a small
-// hologram, the same numbers on every run).
-cgh_status run_direct_one(cgh_ctx *c, int mode, const FrameDesc &fd, const FrameDesc *fd_dev,
-                          int64_t total_slots, float *out, float *out_im, bool accumulate,
-                          hipStream_t s)
+// Direct kernel over frames whose constants occupy slots [0, total_slots)
+// (tables built here).
+cgh_status ev_run_direct(Eval &ev, int mode, const FrameList &frames, int n_frames,
+                         int64_t total_slots, float *out, float *out_im, bool accumulate,
+                         hipStream_t s)
 {
-    const size_t plane = (size_t)c->width * c->height;
+    CGH_TRY(ev_tables(ev, mode, total_slots, s));
+    const bool sph = mode == CGH_SPHERICAL_FP32;
+    const int rows = direct_rows(ev, mode);
+    const char *name = sph ? (out_im ? "direct_sphere_complex" : "direct_sphere")
+                           : (out_im ? "direct_fp32_complex" : "direct_fp32");
+    Bracket br(ev.c, name, s);
+    CGH_HIP(launch_direct_mode(ev, mode, frames, n_frames, rows, out, out_im, accumulate, s),
+            "direct launch");
+    br.done();
+    return CGH_OK;
+}
+
+// Direct mode for one frame, split over its points when the split count asks
+// for it: the runs write partial planes, summed in a fixed order (more
+// workgroups for a small hologram, the same numbers on every run).
+cgh_status ev_run_direct_one(Eval &ev, int mode, const FrameDesc &fd, int64_t total_slots,
+                             float *out, float *out_im, bool accumulate, hipStream_t s)
+{
+    const int64_t plane = (int64_t)ev.g.width * ev.g.height;
     // a complex evaluation's planes [Re; Im] are consecutive: each run writes
     // its own pair, and the pairs are summed as planes of 2H rows
     const int planes = out_im ? 2 : 1;
-    const int splits = out_im && out_im != out + plane ? 1 : direct_splits(c, mode);
-    if (splits <= 1 || fd.groups < 4)
-        return run_direct(c, mode, fd_dev, 1, total_slots, out, out_im, accumulate, s);
-    cgh_status st = CGH_OK;
-    const int runs = direct_split_table(c, fd, splits, planes, s, &st);
-    if (st != CGH_OK)
-        return st;
-    CGH_HIP(ensure_ws(c, c->partials, (size_t)runs * planes * plane * sizeof(float)),
-            "split-K workspace allocation");
-    float *part = (float *)c->partials.p;
-    st = run_direct(c, mode, (const FrameDesc *)c->dsplit.p, runs, total_slots, part,
-                    out_im ? part + plane : nullptr, false, s);
-    if (st != CGH_OK)
-        return st;
-    Bracket br(c, "splitk_reduce", s);
-    CGH_HIP(launch_splitk_reduce(part, runs, planes * c->height, c->width, out, c->width,
+    int splits = out_im && out_im != out + plane ? 1 : direct_splits(ev, mode);
+    if (ev.partial_cap)
+        while (splits > 1 && (size_t)splits * planes * plane * sizeof(float) > ev.partial_cap)
+            splits /= 2;
+    if (splits <= 1 || fd.groups < 4) {
+        FrameList fl{};
+        fl.dev = nullptr;
+        fl.inl[0] = fd;
+        return ev_run_direct(ev, mode, fl, 1, total_slots, out, out_im, accumulate, s);
+    }
+    int runs = 0;
+    const FrameList fl = split_frames(fd, splits, planes, plane, &runs);
+    void *p = nullptr;
+    CGH_TRY(ev.ws->get(Role::Partials, (size_t)runs * planes * plane * sizeof(float), &p));
+    float *part = (float *)p;
+    CGH_TRY(ev_run_direct(ev, mode, fl, runs, total_slots, part, out_im ? part + plane : nullptr,
+                          false, s));
+    Bracket br(ev.c, "splitk_reduce", s);
+    CGH_HIP(launch_splitk_reduce(part, runs, planes * ev.g.height, ev.g.width, out, ev.g.width,
                                  accumulate, s),
             "split-K reduce launch");
     br.done();
     return CGH_OK;
 }
 
-// Matrix-core modes for one frame whose constants are slots [slot0, slot0 + slots).
-// With `cplx`, L holds the real- and imaginary-part rows stacked (M = 2H) and
-// `out` receives [Re; Im] as two consecutive H x W planes.
-cgh_status run_gemm(cgh_ctx *c, int mode, int64_t slot0, int64_t slots, float *out, bool cplx,
-                    bool accumulate, hipStream_t s)
+// Matrix-core modes for `slots` constant slots from slot 0.  With `cplx`, L
+// holds the real- and imaginary-part rows stacked (M = 2H) and `out`
+// receives [Re; Im] as two consecutive H x W planes.
+cgh_status ev_run_gemm(Eval &ev, int mode, int64_t slots, float *out, bool cplx, bool accumulate,
+                       hipStream_t s)
 {
     const ModeInfo mi = mode_info(mode);
-    const FactorType ft = mi.ft;
-    const int M = cplx ? 2 * c->height : c->height;
-    const Plan p = plan_gemm(M, c->width, slots, mi,
-                             find_tuned(c, tune_key(c, mode, slots / mi.kbp, M)));
-    const int hl = mi.hl;
+    const int M = cplx ? 2 * ev.g.height : ev.g.height;
+    const int N = ev.g.width;
+    Plan p = plan_gemm(M, N, slots, mi,
+                       ev.c ? find_tuned(ev.c, tune_key(ev.c, mode, slots / mi.kbp, M)) : nullptr);
+    const size_t per_split = (size_t)M * N * sizeof(float);
+    if (ev.partial_cap)
+        while (p.g.splits > 1 && (size_t)p.g.splits * per_split > ev.partial_cap)
+            --p.g.splits;
     FactorSet fs;
-    cgh_status fst = ensure_factors(c, p.g.mblocks, p.g.nblocks, p.g.kblocks, hl, fs);
-    if (fst != CGH_OK)
-        return fst;
-    if (p.g.splits > 1)
-        CGH_HIP(ensure_ws(c, c->partials,
-                          (size_t)p.g.splits * M * (size_t)c->width * sizeof(float)),
-                "split-K workspace allocation");
-    PointConsts pc = consts_view(c, c->consts_cap);
+    fs.hl = mi.hl;
+    fs.amb = p.g.mblocks;
+    fs.anb = p.g.nblocks;
+    fs.kblocks = p.g.kblocks;
+    void *fp = nullptr;
+    CGH_TRY(ev.ws->get(Role::Factors, (size_t)std::max<int64_t>(fs.bytes(), 1), &fp));
+    fs.base = (char *)fp;
+    float *part = nullptr;
+    if (p.g.splits > 1) {
+        void *pp = nullptr;
+        CGH_TRY(ev.ws->get(Role::Partials, (size_t)p.g.splits * per_split, &pp));
+        part = (float *)pp;
+    }
     {
-        Bracket br(c, mi.fac_name, s);
-        CGH_HIP(launch_factors(pc, slot0, c->width, c->height, cplx, p.g.kblocks, p.g.mblocks,
-                               p.g.nblocks, ft, fs, s),
+        Bracket br(ev.c, mi.fac_name, s);
+        CGH_HIP(launch_factors(ev.pc, 0, ev.g.width, ev.g.height, cplx, p.g.kblocks, p.g.mblocks,
+                               p.g.nblocks, mi.ft, fs, s),
                 "factor launch");
         br.done();
     }
     {
-        Bracket br(c, mi.gemm_name, s);
-        CGH_HIP(launch_gemm(p.g, ft, fs, M, c->width, out, c->width,
-                            (float *)c->partials.p, accumulate, s),
-                "gemm launch");
+        Bracket br(ev.c, mi.gemm_name, s);
+        CGH_HIP(launch_gemm(p.g, mi.ft, fs, M, N, out, N, part, accumulate, s), "gemm launch");
         br.done();
     }
     if (p.g.splits > 1) {
-        Bracket br(c, "splitk_reduce", s);
-        CGH_HIP(launch_splitk_reduce((const float *)c->partials.p, p.g.splits, M, c->width, out,
-                                     c->width, accumulate, s),
+        Bracket br(ev.c, "splitk_reduce", s);
+        CGH_HIP(launch_splitk_reduce(part, p.g.splits, M, N, out, N, accumulate, s),
                 "split-K reduce launch");
         br.done();
     }
@@ -685,74 +909,60 @@ cgh_status run_gemm(cgh_ctx *c, int mode, int64_t slot0, int64_t slots, float *o
 }
 
 // Bytes of workspace per constant slot for a mode (tables or factors).
-size_t bytes_per_slot(cgh_ctx *c, int mode, bool cplx)
+size_t bytes_per_slot(const Geo &g, int mode, bool cplx)
 {
     if (is_direct(mode))
-        return (size_t)(c->wpad + c->hpad) * sizeof(float) * (mode == CGH_SPHERICAL_FP32 ? 2 : 1);
-    const int64_t m = cplx ? 2 * (int64_t)c->height : c->height;
-    const int64_t w = pad_all_shapes(c->width, false);
+        return (size_t)(g.wpad + g.hpad) * sizeof(float) * (mode == CGH_SPHERICAL_FP32 ? 2 : 1);
+    const int64_t m = cplx ? 2 * (int64_t)g.height : g.height;
+    const int64_t w = pad_all_shapes(g.width, false);
     const int64_t h = pad_all_shapes(m, true);
     return (size_t)(w + h) * mode_info(mode).line_bytes();
 }
 
-int64_t chunk_slots(cgh_ctx *c, int mode, bool cplx = false)
+int64_t chunk_slots(const Geo &g, int mode, bool cplx = false)
 {
-    int64_t chunk = (int64_t)(workspace_budget() / bytes_per_slot(c, mode, cplx));
+    int64_t chunk = (int64_t)(workspace_budget() / bytes_per_slot(g, mode, cplx));
     return std::max<int64_t>(kSlotAlign, chunk / kSlotAlign * kSlotAlign);
 }
 
-// Per-point constants of segment `seg_index` of the uploaded segment table.
-cgh_status point_consts(cgh_ctx *c, int seg_index, int n_segs, int64_t max_count, int64_t slots,
-                        hipStream_t s)
+// Hologram of points [p0, p0 + count) at wavelength lam into out (H x W, or
+// [Re; Im] with cplx), in point chunks of `chunk` slots that accumulate into
+// the output in order.  Each chunk's segment travels in the kernel arguments.
+cgh_status ev_one(Eval &ev, int mode, int64_t p0, int64_t count, double lam, float *out,
+                  bool cplx, int64_t chunk, hipStream_t s)
 {
-    CGH_HIP(ensure_consts(c, slots), "constant allocation");
-    Bracket br(c, "point_consts", s);
-    CGH_HIP(launch_point_consts(pts_x(c), pts_y(c), pts_z(c), pts_a(c),
-                                (const Segment *)c->segs.p + seg_index, n_segs,
-                                std::max<int64_t>(max_count, 1), c->width, c->height, c->pitch,
-                                consts_view(c, slots), s),
-            "point constant launch");
-    br.done();
-    return CGH_OK;
-}
-
-// Hologram of points [p0, p0 + count) at wavelength lam into out (H x W),
-// cut into point chunks that fit the workspace budget.  Chunk i's segment
-// and frame descriptors are entry i of the two small tables.
-cgh_status eval_one(cgh_ctx *c, int mode, int64_t p0, int64_t count, double lam, float *out,
-                    bool cplx, hipStream_t s)
-{
-    const int64_t chunk = chunk_slots(c, mode, cplx);
-    float *out_im = cplx ? out + (int64_t)c->width * c->height : nullptr;
-    std::vector<Segment> segs;
-    std::vector<FrameDesc> fds;
-    for (int64_t off = 0; off < count || segs.empty(); off += chunk) {
+    float *out_im = cplx ? out + (int64_t)ev.g.width * ev.g.height : nullptr;
+    int64_t off = 0;
+    do {
         const int64_t cnt = std::min(chunk, count - off);
-        segs.push_back({p0 + off, cnt, 0, lam});
-        fds.push_back({0, round_up(cnt, kSlotAlign) / kGroup, 0});
-    }
-    CGH_HIP(upload_small(c, c->segs, segs.data(), segs.size() * sizeof(Segment), s),
-            "segment table upload");
-    CGH_HIP(upload_small(c, c->frames, fds.data(), fds.size() * sizeof(FrameDesc), s),
-            "frame table upload");
-    for (size_t i = 0; i < segs.size(); ++i) {
-        const int64_t slots = std::max<int64_t>(round_up(segs[i].count, kSlotAlign), kSlotAlign);
-        cgh_status st = point_consts(c, (int)i, 1, segs[i].count, slots, s);
-        if (st != CGH_OK)
-            return st;
-        const bool acc = i > 0;
-        if (is_direct(mode) || segs[i].count == 0)
-            st = run_direct_one(c, is_direct(mode) ? mode : CGH_DIRECT_FP32, fds[i],
-                                (const FrameDesc *)c->frames.p + i,
-                                round_up(segs[i].count, kSlotAlign), out, out_im, acc, s);
-        else
-            st = run_gemm(c, mode, 0, slots, out, cplx, acc, s);
-        if (st != CGH_OK)
-            return st;
-    }
+        const int64_t padded = round_up(cnt, kSlotAlign);
+        const int64_t slots = std::max<int64_t>(padded, kSlotAlign);
+        SegList sl{};
+        sl.dev = nullptr;
+        sl.one = {p0 + off, cnt, 0, lam};
+        CGH_TRY(ev_consts(ev, sl, 1, cnt, slots, s));
+        const bool acc = off > 0;
+        if (is_direct(mode) || cnt == 0) {
+            const FrameDesc fd{0, padded / kGroup, 0};
+            CGH_TRY(ev_run_direct_one(ev, is_direct(mode) ? mode : CGH_DIRECT_FP32, fd, padded,
+                                      out, out_im, acc, s));
+        } else {
+            CGH_TRY(ev_run_gemm(ev, mode, slots, out, cplx, acc, s));
+        }
+        off += chunk;
+    } while (off < count);
     return CGH_OK;
 }
 
+// A single hologram of the context's whole cloud.
+cgh_status eval_ctx(cgh_ctx *c, int mode, float *out, bool cplx, hipStream_t s)
+{
+    CtxWs ws(c);
+    Eval ev = ctx_eval(c, &ws);
+    return ev_one(ev, mode, 0, c->n, c->wavelength, out, cplx, chunk_slots(ev.g, mode, cplx), s);
+}
+
+// ------------------------------------------------------------------ batches
 // Direct mode over many frames with one launch per stage: all frames'
 // constants and tables side by side, the direct kernel's grid covering every
 // frame (largest first, so the longest workgroups start first).
@@ -777,18 +987,20 @@ cgh_status eval_batch_direct(cgh_ctx *c, int mode, const cgh_frame *frames, int 
         slot += padded;
         max_count = std::max(max_count, fr.point_count);
     }
-    CGH_HIP(upload_small(c, c->segs, segs.data(), segs.size() * sizeof(Segment), s),
-            "segment table upload");
-    CGH_HIP(upload_small(c, c->frames, fds.data(), fds.size() * sizeof(FrameDesc), s),
-            "frame table upload");
+    CGH_TRY(upload_small(c, c->bsegs, segs.data(), segs.size() * sizeof(Segment), s,
+                         "segment table upload"));
+    CGH_TRY(upload_small(c, c->bframes, fds.data(), fds.size() * sizeof(FrameDesc), s,
+                         "frame table upload"));
+    CtxWs ws(c);
+    Eval ev = ctx_eval(c, &ws);
     const int64_t slots = std::max<int64_t>(slot, kSlotAlign);
-    cgh_status st = point_consts(c, 0, n_frames, max_count, slots, s);
-    if (st != CGH_OK)
-        return st;
-    return run_direct(c, mode, (const FrameDesc *)c->frames.p, n_frames, slot, out, nullptr,
-                      false, s);
+    SegList sl{};
+    sl.dev = (const Segment *)c->bsegs.p;
+    CGH_TRY(ev_consts(ev, sl, n_frames, max_count, slots, s));
+    FrameList fl{};
+    fl.dev = (const FrameDesc *)c->bframes.p;
+    return ev_run_direct(ev, mode, fl, n_frames, slot, out, nullptr, false, s);
 }
-
 
 // Matrix-core modes over many frames: frames are grouped so that each
 // group's factors fit the workspace budget; per group one constants launch,
@@ -798,8 +1010,6 @@ cgh_status eval_batch_gemm(cgh_ctx *c, int mode, const cgh_frame *frames, int n_
                            float *out, hipStream_t s)
 {
     const ModeInfo mi = mode_info(mode);
-    const FactorType ft = mi.ft;
-    const int hl = mi.hl;
     const int64_t plane = (int64_t)c->width * c->height;
     // tile shape: the tuned (or default) shape for the largest frame
     int64_t max_count = 0;
@@ -879,41 +1089,46 @@ cgh_status eval_batch_gemm(cgh_ctx *c, int mode, const cgh_frame *frames, int n_
                          [](const BatchItem &x, const BatchItem &y) { return x.kblocks > y.kblocks; });
         groups.push_back(gr);
     }
-    CGH_HIP(upload_small(c, c->segs, segs.data(), segs.size() * sizeof(Segment), s),
-            "segment table upload");
-    CGH_HIP(upload_small(c, c->items, items.data(), items.size() * sizeof(BatchItem), s),
-            "work list upload");
+    CGH_TRY(upload_small(c, c->bsegs, segs.data(), segs.size() * sizeof(Segment), s,
+                         "segment table upload"));
+    CGH_TRY(upload_small(c, c->items, items.data(), items.size() * sizeof(BatchItem), s,
+                         "work list upload"));
     CGH_HIP(ensure_ws(c, c->counter, sizeof(int)), "counter allocation");
     int64_t max_group_slots = kSlotAlign;
     for (auto &gr : groups)
         max_group_slots = std::max(max_group_slots, gr.slots);
+    CtxWs ws(c);
+    Eval ev = ctx_eval(c, &ws);
     FactorSet fs;
-    cgh_status fst =
-        ensure_factors(c, p.g.mblocks, p.g.nblocks, max_group_slots / mi.kbp, hl, fs);
-    if (fst != CGH_OK)
-        return fst;
-    CGH_HIP(ensure_consts(c, max_group_slots), "constant allocation");
+    fs.hl = mi.hl;
+    fs.amb = p.g.mblocks;
+    fs.anb = p.g.nblocks;
+    fs.kblocks = max_group_slots / mi.kbp;
+    void *fp = nullptr, *cp = nullptr;
+    CGH_TRY(ws.get(Role::Factors, (size_t)fs.bytes(), &fp));
+    fs.base = (char *)fp;
+    // the largest group's constants first, so no group grows the buffer
+    CGH_TRY(ws.get(Role::Consts, consts_bytes(max_group_slots), &cp));
     for (auto &gr : groups) {
         const int64_t total = std::max<int64_t>(gr.slots, kSlotAlign);
-        cgh_status st = point_consts(c, gr.seg0, gr.nseg, gr.max_count, total, s);
-        if (st != CGH_OK)
-            return st;
+        SegList sl{};
+        sl.dev = (const Segment *)c->bsegs.p + gr.seg0;
+        CGH_TRY(ev_consts(ev, sl, gr.nseg, gr.max_count, total, s));
         GemmPlan g = p.g;
         g.kblocks = total / mi.kbp;
         FactorSet gfs = fs;            // this group's K extent
         gfs.kblocks = g.kblocks;
         {
             Bracket br(c, mi.fac_name, s);
-            CGH_HIP(launch_factors(consts_view(c, c->consts_cap), 0, c->width, c->height, false,
-                                   g.kblocks, g.mblocks, g.nblocks, ft, gfs, s),
+            CGH_HIP(launch_factors(ev.pc, 0, c->width, c->height, false, g.kblocks, g.mblocks,
+                                   g.nblocks, mi.ft, gfs, s),
                     "factor launch");
             br.done();
         }
         {
             Bracket br(c, mi.batch_name, s);
-            CGH_HIP(launch_gemm_batch(g, ft, gfs,
-                                      (const BatchItem *)c->items.p + gr.item0, gr.nitem,
-                                      (int *)c->counter.p, c->height, c->width, out,
+            CGH_HIP(launch_gemm_batch(g, mi.ft, gfs, (const BatchItem *)c->items.p + gr.item0,
+                                      gr.nitem, (int *)c->counter.p, c->height, c->width, out,
                                       std::min(256, gr.nitem), s),
                     "batched gemm launch");
             br.done();
@@ -931,14 +1146,14 @@ cgh_status batch_sequence(cgh_ctx *c, const cgh_frame *frames, int n_frames, int
         int64_t total = 0;
         for (int f = 0; f < n_frames; ++f)
             total += round_up(frames[f].point_count, kSlotAlign);
-        if (total <= chunk_slots(c, mode))
+        if (total <= chunk_slots(ctx_geo(c), mode))
             return eval_batch_direct(c, mode, frames, n_frames, out, s);
-        for (int f = 0; f < n_frames; ++f) {
-            cgh_status st = eval_one(c, mode, frames[f].point_offset, frames[f].point_count,
-                                     frames[f].wavelength, out + f * plane, false, s);
-            if (st != CGH_OK)
-                return st;
-        }
+        CtxWs ws(c);
+        Eval ev = ctx_eval(c, &ws);
+        const int64_t chunk = chunk_slots(ev.g, mode);
+        for (int f = 0; f < n_frames; ++f)
+            CGH_TRY(ev_one(ev, mode, frames[f].point_offset, frames[f].point_count,
+                           frames[f].wavelength, out + f * plane, false, chunk, s));
         return CGH_OK;
     }
     return eval_batch_gemm(c, mode, frames, n_frames, out, s);
@@ -1045,10 +1260,6 @@ cgh_status time_launches(F fn, int reps, hipStream_t s, double *us)
     return CGH_OK;
 }
 
-}  // namespace
-
-// ====================================================================== ABI
-namespace {
 // The device exists and is a gfx950; `arch` receives its name.
 cgh_status check_device(int32_t device, std::string &arch)
 {
@@ -1071,6 +1282,19 @@ cgh_status check_device(int32_t device, std::string &arch)
     return CGH_OK;
 }
 
+// Common checks of the single-hologram compute calls.
+cgh_status check_compute(cgh_ctx *c, int mode, const void *out)
+{
+    if (!c)
+        return fail(CGH_EINVAL, "context is NULL");
+    if (!out)
+        return fail(CGH_EINVAL, "output is NULL");
+    CGH_TRY(check_mode(mode));
+    if (!c->uploaded)
+        return fail(CGH_ESTATE, "no points uploaded");
+    return CGH_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1090,7 +1314,7 @@ const char *cgh_strerror(cgh_status s)
 
 const char *cgh_last_error(void) { return g_last_error.c_str(); }
 
-int32_t cgh_version(void) { return 10000; }
+int32_t cgh_version(void) { return 10100; }
 
 // ------------------------------------------------------ Fresnel diffraction
 struct cgh_fresnel {
@@ -1118,9 +1342,7 @@ cgh_status cgh_fresnel_create(cgh_fresnel **out, int32_t n, double pitch_m, doub
     if (device < 0)
         return fail(CGH_EINVAL, "device index must be >= 0");
     std::string arch;
-    cgh_status st = check_device(device, arch);
-    if (st != CGH_OK)
-        return st;
+    CGH_TRY(check_device(device, arch));
     DeviceGuard g;
     CGH_HIP(g.set(device), "hipSetDevice");
     cgh_fresnel *f = new (std::nothrow) cgh_fresnel();
@@ -1213,9 +1435,7 @@ cgh_status cgh_create(cgh_ctx **out, int32_t width, int32_t height, double pitch
         return fail(CGH_EINVAL, "device index must be >= 0");
 
     std::string arch;
-    cgh_status dst = check_device(device, arch);
-    if (dst != CGH_OK)
-        return dst;
+    CGH_TRY(check_device(device, arch));
     {
         DeviceGuard g;
         CGH_HIP(g.set(device), "hipSetDevice");
@@ -1252,21 +1472,13 @@ void cgh_destroy(cgh_ctx *c)
     }
     for (auto e : c->prof_free)
         (void)hipEventDestroy(e);
-    c->points.release();
-    c->consts.release();
-    c->tab_u.release();
-    c->tab_v.release();
-    c->tab_x.release();
-    c->tab_y.release();
-    c->fac.release();
-    c->partials.release();
-    c->segs.release();
-    c->frames.release();
-    c->dsplit.release();
-    c->tune_out.release();
-    c->field.release();
-    c->items.release();
-    c->counter.release();
+    if (c->order_ev)
+        (void)hipEventDestroy(c->order_ev);
+    c->staging.release();
+    for (DevBuf *b : {&c->points, &c->consts, &c->tab_u, &c->tab_v, &c->tab_x, &c->tab_y,
+                      &c->fac, &c->partials, &c->tune_out, &c->field, &c->bsegs, &c->bframes,
+                      &c->items, &c->counter})
+        b->release();
     delete c;
 }
 
@@ -1296,10 +1508,12 @@ cgh_status cgh_points_upload(cgh_ctx *c, const float *x, const float *y, const f
     DeviceGuard g;
     CGH_HIP(g.set(c->device), "hipSetDevice");
     hipStream_t s = (hipStream_t)stream;
+    CallOrder order(c, s);
+    CGH_HIP(order.enter(), "stream ordering");
     const int64_t cap = std::max<int64_t>(n, 1);
     if (cap > c->n_cap || !c->points.p) {
-        // the old cloud may still be read by queued work on this stream
-        CGH_HIP(hipStreamSynchronize(s), "stream synchronise");
+        // queued work (on any stream) may still read the old cloud
+        CGH_HIP(hipDeviceSynchronize(), "device synchronise");
         c->points.release();
         CGH_HIP(c->points.ensure((size_t)cap * 4 * sizeof(float)), "point allocation");
         c->n_cap = cap;
@@ -1309,80 +1523,61 @@ cgh_status cgh_points_upload(cgh_ctx *c, const float *x, const float *y, const f
     float *d = (float *)c->points.p;
     const float *src[4] = {x, y, z, amp};
     if (n > 0) {
+        if (where == CGH_MEM_HOST)   // queued work may still read the old cloud
+            CGH_HIP(hipStreamSynchronize(s), "stream synchronise");
         for (int k = 0; k < 4; ++k) {
-            if (where == CGH_MEM_HOST) {
-                CGH_HIP(hipStreamSynchronize(s), "stream synchronise");
+            if (where == CGH_MEM_HOST)
                 CGH_HIP(hipMemcpy(d + k * c->n_cap, src[k], (size_t)n * sizeof(float),
                                   hipMemcpyHostToDevice),
                         "point upload");
-            } else {
+            else
                 CGH_HIP(hipMemcpyAsync(d + k * c->n_cap, src[k], (size_t)n * sizeof(float),
                                        hipMemcpyDeviceToDevice, s),
                         "point upload");
-            }
         }
     }
     c->n = n;
     c->uploaded = true;
-    ++c->points_generation;
     return CGH_OK;
 }
 
 cgh_status cgh_compute(cgh_ctx *c, cgh_mode mode, float *out_dev, void *stream)
 {
     g_last_error.clear();
-    if (!c)
-        return fail(CGH_EINVAL, "context is NULL");
-    if (!out_dev)
-        return fail(CGH_EINVAL, "output is NULL");
-    cgh_status st = check_mode(mode);
-    if (st != CGH_OK)
-        return st;
-    if (!c->uploaded)
-        return fail(CGH_ESTATE, "no points uploaded");
+    CGH_TRY(check_compute(c, mode, out_dev));
     DeviceGuard g;
     CGH_HIP(g.set(c->device), "hipSetDevice");
-    return eval_one(c, mode, 0, c->n, c->wavelength, out_dev, false, (hipStream_t)stream);
+    hipStream_t s = (hipStream_t)stream;
+    CallOrder order(c, s);
+    CGH_HIP(order.enter(), "stream ordering");
+    return eval_ctx(c, mode, out_dev, false, s);
 }
 
 cgh_status cgh_compute_complex(cgh_ctx *c, cgh_mode mode, float *out_dev, void *stream)
 {
     g_last_error.clear();
-    if (!c)
-        return fail(CGH_EINVAL, "context is NULL");
-    if (!out_dev)
-        return fail(CGH_EINVAL, "output is NULL");
-    cgh_status st = check_mode(mode);
-    if (st != CGH_OK)
-        return st;
-    if (!c->uploaded)
-        return fail(CGH_ESTATE, "no points uploaded");
+    CGH_TRY(check_compute(c, mode, out_dev));
     DeviceGuard g;
     CGH_HIP(g.set(c->device), "hipSetDevice");
-    return eval_one(c, mode, 0, c->n, c->wavelength, out_dev, true, (hipStream_t)stream);
+    hipStream_t s = (hipStream_t)stream;
+    CallOrder order(c, s);
+    CGH_HIP(order.enter(), "stream ordering");
+    return eval_ctx(c, mode, out_dev, true, s);
 }
 
 cgh_status cgh_kinoform(cgh_ctx *c, cgh_mode mode, uint8_t *out_dev, void *stream)
 {
     g_last_error.clear();
-    if (!c)
-        return fail(CGH_EINVAL, "context is NULL");
-    if (!out_dev)
-        return fail(CGH_EINVAL, "output is NULL");
-    cgh_status st = check_mode(mode);
-    if (st != CGH_OK)
-        return st;
-    if (!c->uploaded)
-        return fail(CGH_ESTATE, "no points uploaded");
+    CGH_TRY(check_compute(c, mode, out_dev));
     DeviceGuard g;
     CGH_HIP(g.set(c->device), "hipSetDevice");
     hipStream_t s = (hipStream_t)stream;
+    CallOrder order(c, s);
+    CGH_HIP(order.enter(), "stream ordering");
     const int64_t plane = (int64_t)c->width * c->height;
     CGH_HIP(ensure_ws(c, c->field, (size_t)plane * 2 * sizeof(float)), "field allocation");
     float *field = (float *)c->field.p;
-    st = eval_one(c, mode, 0, c->n, c->wavelength, field, true, s);
-    if (st != CGH_OK)
-        return st;
+    CGH_TRY(eval_ctx(c, mode, field, true, s));
     Bracket br(c, "kinoform", s);
     CGH_HIP(launch_kinoform(field, field + plane, plane, out_dev, s), "kinoform launch");
     br.done();
@@ -1401,9 +1596,7 @@ cgh_status cgh_batch_compute(cgh_ctx *c, const cgh_frame *frames, int32_t n_fram
         return fail(CGH_EINVAL, "n_frames must be in [1, 65535]");
     if (!out_dev)
         return fail(CGH_EINVAL, "output is NULL");
-    cgh_status st = check_mode(mode);
-    if (st != CGH_OK)
-        return st;
+    CGH_TRY(check_mode(mode));
     if (!c->uploaded)
         return fail(CGH_ESTATE, "no points uploaded");
     for (int f = 0; f < n_frames; ++f) {
@@ -1417,21 +1610,27 @@ cgh_status cgh_batch_compute(cgh_ctx *c, const cgh_frame *frames, int32_t n_fram
     DeviceGuard g;
     CGH_HIP(g.set(c->device), "hipSetDevice");
     hipStream_t s = (hipStream_t)stream;
+    if (capturing(s))
+        return fail(CGH_ESTATE, "the stream is capturing: cgh_batch_compute records its own "
+                                "graph");
+    CallOrder order(c, s);
+    CGH_HIP(order.enter(), "stream ordering");
     // Replay: same mode, frames and output as the captured call, and no
-    // workspace buffer moved since (a move drops the graph).
+    // workspace buffer moved since (a move drops the graph).  The graph reads
+    // only the batch tables, which no other call writes.
     if (c->graph_exec && !c->profiling && c->graph_mode == (int)mode && c->graph_out == out_dev &&
         c->graph_generation == c->ws_generation && same_frames(c->graph_frames, frames, n_frames)) {
         CGH_HIP(hipGraphLaunch(c->graph_exec, s), "hipGraphLaunch");
         return CGH_OK;
     }
     drop_graph(c);
-    st = batch_sequence(c, frames, n_frames, (int)mode, out_dev, s);
-    if (st != CGH_OK || c->profiling || s == nullptr)
-        return st;
-    // Capture the same sequence for replay.  Its small tables and workspace
-    // are now in place, so the captured pass issues kernel launches only; if
-    // anything else would be recorded, the capture is abandoned and later
-    // calls run eagerly.
+    CGH_TRY(batch_sequence(c, frames, n_frames, (int)mode, out_dev, s));
+    if (c->profiling || s == nullptr)
+        return CGH_OK;
+    // Capture the same sequence for replay.  Its tables and workspace are now
+    // in place, so the captured pass issues kernel launches only; if anything
+    // else would be recorded, the capture is abandoned and later calls run
+    // eagerly.
     const uint64_t gen = c->ws_generation;
     hipGraph_t graph = nullptr;
     if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
@@ -1462,9 +1661,7 @@ cgh_status cgh_tune(cgh_ctx *c, cgh_mode mode, int32_t repeats, char *report, in
     g_last_error.clear();
     if (!c)
         return fail(CGH_EINVAL, "context is NULL");
-    cgh_status st = check_mode(mode);
-    if (st != CGH_OK)
-        return st;
+    CGH_TRY(check_mode(mode));
     if (repeats < 1 || repeats > 1000)
         return fail(CGH_EINVAL, "repeats must be in [1, 1000]");
     if (report_len < 0 || (report_len > 0 && !report))
@@ -1474,37 +1671,37 @@ cgh_status cgh_tune(cgh_ctx *c, cgh_mode mode, int32_t repeats, char *report, in
     DeviceGuard g;
     CGH_HIP(g.set(c->device), "hipSetDevice");
     hipStream_t s = (hipStream_t)stream;
+    CallOrder order(c, s);
+    CGH_HIP(order.enter(), "stream ordering");
     CGH_HIP(ensure_ws(c, c->tune_out, (size_t)c->width * c->height * sizeof(float)),
             "tuning output allocation");
     float *out = (float *)c->tune_out.p;
+    CtxWs ws(c);
+    Eval ev = ctx_eval(c, &ws);
 
     // the first point chunk of the cloud (at least one slot group)
-    const int64_t count = std::min(c->n, chunk_slots(c, mode));
-    std::vector<Segment> segs{{0, count, 0, c->wavelength}};
+    const int64_t count = std::min(c->n, chunk_slots(ev.g, mode));
     const int64_t slots = std::max<int64_t>(round_up(count, kSlotAlign), kSlotAlign);
-    std::vector<FrameDesc> fds{{0, slots / kGroup, 0}};
-    CGH_HIP(upload_small(c, c->segs, segs.data(), sizeof(Segment), s), "segment table upload");
-    CGH_HIP(upload_small(c, c->frames, fds.data(), sizeof(FrameDesc), s), "frame table upload");
-    st = point_consts(c, 0, 1, count, slots, s);
-    if (st != CGH_OK)
-        return st;
+    SegList sl{};
+    sl.dev = nullptr;
+    sl.one = {0, count, 0, c->wavelength};
+    CGH_TRY(ev_consts(ev, sl, 1, count, slots, s));
+    const FrameDesc fd{0, slots / kGroup, 0};
 
     TuneEntry best;
     int tried = 0;
     if (is_direct(mode)) {
         best.key = tune_key(c, mode, 0, c->height);
-        st = direct_tables(c, mode, slots, s);
-        if (st != CGH_OK)
-            return st;
+        CGH_TRY(ev_tables(ev, mode, slots, s));
         for (int splits : {1, 2, 4}) {
-            // the point split's frame table (uploaded outside the timing)
             int runs = 1;
+            FrameList fl{};
+            fl.dev = nullptr;
+            fl.inl[0] = fd;
             if (splits > 1) {
-                if (fds[0].groups < 4)
+                if (fd.groups < 4)
                     continue;
-                runs = direct_split_table(c, fds[0], splits, 1, s, &st);
-                if (st != CGH_OK)
-                    return st;
+                fl = split_frames(fd, splits, 1, (int64_t)c->width * c->height, &runs);
                 CGH_HIP(ensure_ws(c, c->partials,
                                   (size_t)runs * c->height * (size_t)c->width * sizeof(float)),
                         "split-K workspace allocation");
@@ -1513,22 +1710,20 @@ cgh_status cgh_tune(cgh_ctx *c, cgh_mode mode, int32_t repeats, char *report, in
                 if (!direct_rows_ok(mode, rows))
                     continue;
                 double us = 0;
-                st = time_launches(
+                CGH_TRY(time_launches(
                     [&] {
                         if (splits == 1)
-                            return launch_direct_mode(c, mode, (const FrameDesc *)c->frames.p, 1,
-                                                      rows, out, nullptr, false, s);
-                        hipError_t e = launch_direct_mode(c, mode, (const FrameDesc *)c->dsplit.p,
-                                                          runs, rows, (float *)c->partials.p,
-                                                          nullptr, false, s);
+                            return launch_direct_mode(ev, mode, fl, 1, rows, out, nullptr, false,
+                                                      s);
+                        hipError_t e = launch_direct_mode(ev, mode, fl, runs, rows,
+                                                          (float *)c->partials.p, nullptr, false,
+                                                          s);
                         if (e == hipSuccess)
                             e = launch_splitk_reduce((const float *)c->partials.p, runs,
                                                      c->height, c->width, out, c->width, false, s);
                         return e;
                     },
-                    repeats, s, &us);
-                if (st != CGH_OK)
-                    return st;
+                    repeats, s, &us));
                 ++tried;
                 if (best.rows == 0 || us < best.us) {
                     best.rows = rows;
@@ -1539,25 +1734,23 @@ cgh_status cgh_tune(cgh_ctx *c, cgh_mode mode, int32_t repeats, char *report, in
         }
     } else {
         const ModeInfo mi = mode_info(mode);
-        const FactorType ft = mi.ft;
-        const int hl = mi.hl;
         const int64_t kblocks = slots / mi.kbp;
         best.key = tune_key(c, mode, kblocks, c->height);
-        const auto &shapes = kShapes;
         // factors padded to whole tiles of every candidate shape
-        int mb = 0, nb = 0;
-        for (auto &sh : shapes) {
-            mb = std::max(mb, (int)(round_up(c->height, sh[0]) / kFragLines));
-            nb = std::max(nb, (int)(round_up(c->width, sh[1]) / kFragLines));
-        }
         FactorSet fs;
-        st = ensure_factors(c, mb, nb, kblocks, hl, fs);
-        if (st != CGH_OK)
-            return st;
-        CGH_HIP(launch_factors(consts_view(c, c->consts_cap), 0, c->width, c->height, false,
-                               kblocks, mb, nb, ft, fs, s),
+        fs.hl = mi.hl;
+        fs.kblocks = kblocks;
+        for (auto &sh : kShapes) {
+            fs.amb = std::max(fs.amb, (int)(round_up(c->height, sh[0]) / kFragLines));
+            fs.anb = std::max(fs.anb, (int)(round_up(c->width, sh[1]) / kFragLines));
+        }
+        void *fp = nullptr;
+        CGH_TRY(ws.get(Role::Factors, (size_t)fs.bytes(), &fp));
+        fs.base = (char *)fp;
+        CGH_HIP(launch_factors(ev.pc, 0, c->width, c->height, false, kblocks, fs.amb, fs.anb,
+                               mi.ft, fs, s),
                 "factor launch");
-        for (auto &sh : shapes) {
+        for (auto &sh : kShapes) {
             if (!gemm_tile_supported(sh[0], sh[1], sh[2], sh[3], sh[4]))
                 continue;
             const int tiles = (int)((c->height + sh[0] - 1) / sh[0] * ((c->width + sh[1] - 1) / sh[1]));
@@ -1589,19 +1782,16 @@ cgh_status cgh_tune(cgh_ctx *c, cgh_mode mode, int32_t repeats, char *report, in
                                       (size_t)sp * c->height * (size_t)c->width * sizeof(float)),
                             "split-K workspace allocation");
                 double us = 0;
-                st = time_launches(
+                CGH_TRY(time_launches(
                     [&] {
-                        hipError_t e = launch_gemm(gp, ft, fs, c->height,
-                                                   c->width, out, c->width,
-                                                   (float *)c->partials.p, false, s);
+                        hipError_t e = launch_gemm(gp, mi.ft, fs, c->height, c->width, out,
+                                                   c->width, (float *)c->partials.p, false, s);
                         if (e == hipSuccess && sp > 1)
                             e = launch_splitk_reduce((const float *)c->partials.p, sp, c->height,
                                                      c->width, out, c->width, false, s);
                         return e;
                     },
-                    repeats, s, &us);
-                if (st != CGH_OK)
-                    return st;
+                    repeats, s, &us));
                 ++tried;
                 if (best.bm == 0 || us < best.us) {
                     best.bm = sh[0];

@@ -69,12 +69,36 @@ struct FrameDesc {
     int64_t out_off;   // offset of the frame's output in floats
 };
 
+// Segments of a launch: a device table (dev != nullptr, entry blockIdx.y),
+// or one segment passed by value in the kernel arguments, so that a single
+// hologram's evaluation needs no table in device memory.
+struct SegList {
+    const Segment *dev;
+    Segment one;
+};
+
+// Frames of a direct launch: a device table, or up to kInlineFrames frames in
+// the kernel arguments (a single hologram, whole or cut into point runs).
+constexpr int kInlineFrames = 4;
+struct FrameList {
+    const FrameDesc *dev;
+    FrameDesc inl[kInlineFrames];
+};
+
+__device__ __forceinline__ FrameDesc frame_at(const FrameList &f, int i)
+{
+    if (f.dev)
+        return f.dev[i];
+    // uniform selects rather than an indexed kernel-argument array
+    return i == 0 ? f.inl[0] : i == 1 ? f.inl[1] : i == 2 ? f.inl[2] : f.inl[3];
+}
+
 // ---------------------------------------------------------------- launchers
 // Each returns the hipError_t of the launch.
 
 // a1: per-point constants for a list of segments.
 hipError_t launch_point_consts(const float *x, const float *y, const float *z, const float *amp,
-                               const Segment *segs_dev, int n_segs, int64_t max_count,
+                               const SegList &segs, int n_segs, int64_t max_count,
                                int width, int height, double pitch, PointConsts pc,
                                hipStream_t s);
 
@@ -94,7 +118,7 @@ hipError_t launch_sphere_tables(PointConsts pc, int64_t n_slots, int wpad, int h
 // a3s: direct FP32 accumulation of the exact spherical wave (tables from a2s).
 hipError_t launch_direct_sphere(const float *U, const float *V, const float *X, const float *Y,
                                 const float *amp, const float *zhalf,
-                                const FrameDesc *frames_dev, int n_frames, int width, int height,
+                                const FrameList &frames, int n_frames, int width, int height,
                                 int wpad, int hpad, int rows_per_wave, float *out,
                                 float *out_im, bool accumulate, hipStream_t s);
 
@@ -102,7 +126,7 @@ hipError_t launch_direct_sphere(const float *U, const float *V, const float *X, 
 // padded to wpad columns and hpad rows, multiples of kLinePad).  With out_im
 // != nullptr the imaginary part of the object wave goes there as well.
 hipError_t launch_direct(const float *U, const float *V, const float *amp,
-                         const FrameDesc *frames_dev, int n_frames, int width, int height,
+                         const FrameList &frames, int n_frames, int width, int height,
                          int wpad, int hpad, int rows_per_wave, float *out, float *out_im,
                          bool accumulate, hipStream_t s);
 

@@ -91,12 +91,12 @@ template <int R, bool CPLX>
 __global__ __launch_bounds__(256) void k_direct(const float *__restrict__ U,
                                                 const float *__restrict__ V,
                                                 const float *__restrict__ amp,
-                                                const FrameDesc *__restrict__ frames, int width,
+                                                FrameList frames, int width,
                                                 int height, int wpad, int hpad,
                                                 float *__restrict__ out,
                                                 float *__restrict__ out_im, int accumulate)
 {
-    const FrameDesc fd = frames[blockIdx.z];
+    const FrameDesc fd = frame_at(frames, blockIdx.z);
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int col = blockIdx.x * 64 + lane;
@@ -169,24 +169,24 @@ __global__ __launch_bounds__(256) void k_direct(const float *__restrict__ U,
 }
 
 template <int R>
-void launch_rows(const float *U, const float *V, const float *amp, const FrameDesc *frames_dev,
+void launch_rows(const float *U, const float *V, const float *amp, const FrameList &frames,
                  int n_frames, int width, int height, int wpad, int hpad, float *out,
                  float *out_im, int acc, hipStream_t s)
 {
     const dim3 grid((unsigned)((width + 63) / 64),
                     (unsigned)((height + kWaves * R - 1) / (kWaves * R)), (unsigned)n_frames);
     if (out_im != nullptr)
-        hipLaunchKernelGGL((k_direct<R, true>), grid, dim3(256), 0, s, U, V, amp, frames_dev,
+        hipLaunchKernelGGL((k_direct<R, true>), grid, dim3(256), 0, s, U, V, amp, frames,
                            width, height, wpad, hpad, out, out_im, acc);
     else
-        hipLaunchKernelGGL((k_direct<R, false>), grid, dim3(256), 0, s, U, V, amp, frames_dev,
+        hipLaunchKernelGGL((k_direct<R, false>), grid, dim3(256), 0, s, U, V, amp, frames,
                            width, height, wpad, hpad, out, (float *)nullptr, acc);
 }
 
 }  // namespace
 
 hipError_t launch_direct(const float *U, const float *V, const float *amp,
-                         const FrameDesc *frames_dev, int n_frames, int width, int height,
+                         const FrameList &frames, int n_frames, int width, int height,
                          int wpad, int hpad, int rows_per_wave, float *out, float *out_im,
                          bool accumulate, hipStream_t s)
 {
@@ -194,13 +194,13 @@ hipError_t launch_direct(const float *U, const float *V, const float *amp,
     if (n_frames <= 0)
         return hipSuccess;
     if (rows_per_wave == 8)
-        launch_rows<8>(U, V, amp, frames_dev, n_frames, width, height, wpad, hpad, out, out_im,
+        launch_rows<8>(U, V, amp, frames, n_frames, width, height, wpad, hpad, out, out_im,
                        acc, s);
     else if (rows_per_wave == 16)
-        launch_rows<16>(U, V, amp, frames_dev, n_frames, width, height, wpad, hpad, out, out_im,
+        launch_rows<16>(U, V, amp, frames, n_frames, width, height, wpad, hpad, out, out_im,
                         acc, s);
     else
-        launch_rows<4>(U, V, amp, frames_dev, n_frames, width, height, wpad, hpad, out, out_im,
+        launch_rows<4>(U, V, amp, frames, n_frames, width, height, wpad, hpad, out, out_im,
                        acc, s);
     return hipGetLastError();
 }

@@ -15,11 +15,11 @@ __global__ __launch_bounds__(256) void k_point_consts(const float *__restrict__ 
                                                       const float *__restrict__ y,
                                                       const float *__restrict__ z,
                                                       const float *__restrict__ amp,
-                                                      const Segment *__restrict__ segs,
-                                                      double half_w, double half_h, double pitch,
+                                                      SegList segs, double half_w,
+                                                      double half_h, double pitch,
                                                       PointConsts pc)
 {
-    const Segment sg = segs[blockIdx.y];
+    const Segment sg = segs.dev ? segs.dev[blockIdx.y] : segs.one;
     const int64_t padded = (sg.count + kSlotAlign - 1) / kSlotAlign * kSlotAlign;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= padded)
@@ -86,15 +86,17 @@ __global__ __launch_bounds__(256) void k_phase_tables(PointConsts pc, int64_t n_
 }  // namespace
 
 hipError_t launch_point_consts(const float *x, const float *y, const float *z, const float *amp,
-                               const Segment *segs_dev, int n_segs, int64_t max_count,
+                               const SegList &segs, int n_segs, int64_t max_count,
                                int width, int height, double pitch, PointConsts pc,
                                hipStream_t s)
 {
     if (n_segs <= 0 || max_count <= 0)
         return hipSuccess;
+    if (!segs.dev && n_segs != 1)
+        return hipErrorInvalidValue;
     const int64_t padded = (max_count + kSlotAlign - 1) / kSlotAlign * kSlotAlign;
     dim3 grid((unsigned)((padded + 255) / 256), (unsigned)n_segs);
-    hipLaunchKernelGGL(k_point_consts, grid, dim3(256), 0, s, x, y, z, amp, segs_dev,
+    hipLaunchKernelGGL(k_point_consts, grid, dim3(256), 0, s, x, y, z, amp, segs,
                        0.5 * (double)(width - 1), 0.5 * (double)(height - 1), pitch, pc);
     return hipGetLastError();
 }

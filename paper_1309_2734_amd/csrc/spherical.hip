@@ -109,10 +109,10 @@ template <int R, bool CPLX>
 __global__ __launch_bounds__(256) void k_direct_sphere(
     const float *__restrict__ U, const float *__restrict__ V, const float *__restrict__ X,
     const float *__restrict__ Y, const float *__restrict__ amp, const float *__restrict__ zhalf,
-    const FrameDesc *__restrict__ frames, int width, int height, int wpad, int hpad,
+    FrameList frames, int width, int height, int wpad, int hpad,
     float *__restrict__ out, float *__restrict__ out_im, int accumulate)
 {
-    const FrameDesc fd = frames[blockIdx.z];
+    const FrameDesc fd = frame_at(frames, blockIdx.z);
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int col = blockIdx.x * 64 + lane;
@@ -226,7 +226,7 @@ __global__ __launch_bounds__(256) void k_sphere_tables(PointConsts pc, int64_t n
 
 template <int R>
 void launch_rows(const float *U, const float *V, const float *X, const float *Y,
-                 const float *amp, const float *zhalf, const FrameDesc *frames_dev, int n_frames,
+                 const float *amp, const float *zhalf, const FrameList &frames, int n_frames,
                  int width, int height, int wpad, int hpad, float *out, float *out_im, int acc,
                  hipStream_t s)
 {
@@ -234,10 +234,10 @@ void launch_rows(const float *U, const float *V, const float *X, const float *Y,
                     (unsigned)((height + kWaves * R - 1) / (kWaves * R)), (unsigned)n_frames);
     if (out_im != nullptr)
         hipLaunchKernelGGL((k_direct_sphere<R, true>), grid, dim3(256), 0, s, U, V, X, Y, amp,
-                           zhalf, frames_dev, width, height, wpad, hpad, out, out_im, acc);
+                           zhalf, frames, width, height, wpad, hpad, out, out_im, acc);
     else
         hipLaunchKernelGGL((k_direct_sphere<R, false>), grid, dim3(256), 0, s, U, V, X, Y, amp,
-                           zhalf, frames_dev, width, height, wpad, hpad, out, (float *)nullptr,
+                           zhalf, frames, width, height, wpad, hpad, out, (float *)nullptr,
                            acc);
 }
 
@@ -258,7 +258,7 @@ hipError_t launch_sphere_tables(PointConsts pc, int64_t n_slots, int wpad, int h
 
 hipError_t launch_direct_sphere(const float *U, const float *V, const float *X, const float *Y,
                                 const float *amp, const float *zhalf,
-                                const FrameDesc *frames_dev, int n_frames, int width, int height,
+                                const FrameList &frames, int n_frames, int width, int height,
                                 int wpad, int hpad, int rows_per_wave, float *out,
                                 float *out_im, bool accumulate, hipStream_t s)
 {
@@ -266,10 +266,10 @@ hipError_t launch_direct_sphere(const float *U, const float *V, const float *X, 
     if (n_frames <= 0)
         return hipSuccess;
     if (rows_per_wave == 8)
-        launch_rows<8>(U, V, X, Y, amp, zhalf, frames_dev, n_frames, width, height, wpad, hpad,
+        launch_rows<8>(U, V, X, Y, amp, zhalf, frames, n_frames, width, height, wpad, hpad,
                        out, out_im, acc, s);
     else
-        launch_rows<4>(U, V, X, Y, amp, zhalf, frames_dev, n_frames, width, height, wpad, hpad,
+        launch_rows<4>(U, V, X, Y, amp, zhalf, frames, n_frames, width, height, wpad, hpad,
                        out, out_im, acc, s);
     return hipGetLastError();
 }

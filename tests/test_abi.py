@@ -43,7 +43,7 @@ def test_strerror_and_version(L):
     assert L.cgh_strerror(1) == b"invalid argument"
     assert L.cgh_strerror(5) == b"invalid call order"
     assert L.cgh_strerror(99) == b"unknown status"
-    assert L.cgh_version() == 10000
+    assert L.cgh_version() == 10100
 
 
 def _create(L, w=64, h=32, p=8e-6, lam=5e-7, dev=0, null_out=False):

@@ -103,25 +103,50 @@ def _strided(c, step):
     return np.array(cols), np.array(rows)
 
 
+# Full-size samples.  The matrix kernels' output fragments are 16 x 16 and the
+# direct kernel's lanes own bands of 4-16 rows, so a sample whose stride is
+# coprime to 16 (7, 9) reaches every fragment position and every row of a
+# band; the evaluation sets of the workloads (every 8th row and column, or a
+# crop) are checked as well.
 @pytest.mark.parametrize("mode", ALL_MODES, ids=[NAMES[m] for m in ALL_MODES])
 def test_c2_full_size_strided(mode):
     c = cghgen.make_config(2)
-    cols, rows = _strided(c, 8)
+    cols, rows = _strided(c, 7)
     say(f"C2 {c.width}x{c.height} N={c.n} {NAMES[mode]} sample {len(rows)}x{len(cols)}")
-    ref = oracle.cloud_fresnel(c, cols=cols, rows=rows)
+    if "c2_7" not in _REFS:
+        _REFS["c2_7"] = oracle.cloud_fresnel(c, cols=cols, rows=rows)
     got = gpu_hologram(c, mode)[np.ix_(rows, cols)]
-    check("C2", got, ref, mode)
+    check("C2", got, _REFS["c2_7"], mode)
+
+
+@pytest.mark.parametrize("mode", ALL_MODES, ids=[NAMES[m] for m in ALL_MODES])
+def test_c2_full_size_tuned_shapes(mode):
+    """The launch shape the tuner picks at 1920 x 1080 x 10,000 points (the
+    benchmark's configuration), checked on every 9th row and column."""
+    c = cghgen.make_config(2)
+    cols, rows = _strided(c, 9)
+    ctx = cgh.Context(c.width, c.height, c.pitch, c.wavelength)
+    ctx.upload_cloud(c)
+    say(f"C2 tuned {NAMES[mode]}: {ctx.tune(mode, repeats=2)}")
+    if "c2_9" not in _REFS:
+        _REFS["c2_9"] = oracle.cloud_fresnel(c, cols=cols, rows=rows)
+    got = gpu_hologram(c, mode, ctx)[np.ix_(rows, cols)]
+    ctx.close()
+    check("C2 tuned", got, _REFS["c2_9"], mode)
 
 
 @pytest.mark.parametrize("mode", (cgh.DIRECT_FP32, cgh.SPLIT_BF16, cgh.SEPARABLE_FP32),
                          ids=["direct_fp32", "split_bf16", "separable_fp32"])
-def test_c3_full_size_strided(mode):
+def test_c3_full_size_every_8th(mode):
+    """2048 x 2048, 65,536 points, on its evaluation set: every 8th row and
+    column (256 x 256 pixels, corners included)."""
     c = cghgen.make_config(3)
-    cols, rows = _strided(c, 64)
+    cols, rows = cghgen.strided_pixels(c.width, c.height, 8)
     say(f"C3 {c.width}x{c.height} N={c.n} {NAMES[mode]} sample {len(rows)}x{len(cols)}")
-    ref = oracle.cloud_fresnel(c, cols=cols, rows=rows)
+    if "c3" not in _REFS:
+        _REFS["c3"] = oracle.cloud_fresnel(c, cols=cols, rows=rows)
     got = gpu_hologram(c, mode)[np.ix_(rows, cols)]
-    check("C3", got, ref, mode)
+    check("C3", got, _REFS["c3"], mode)
 
 
 @pytest.mark.parametrize("mode", (cgh.SPLIT_BF16, cgh.SEPARABLE_FP32, cgh.DIRECT_FP32),
@@ -129,15 +154,19 @@ def test_c3_full_size_strided(mode):
 def test_c5_large_scene_chunked(mode):
     """4096 x 4096 at 4 um, 10^6 points on an ellipsoid surface: the factors
     or tables of the whole cloud exceed the workspace budget, so the cloud
-    is evaluated in point chunks that accumulate into the output."""
+    is evaluated in point chunks that accumulate into the output.  Checked
+    on the central 64 x 64 pixels of the workload's centred 256 x 256 crop
+    (rows and columns 2016 .. 2079) and on a sparse stride-161 grid."""
     c = cghgen.make_config(5)
-    cols, rows = np.arange(7, c.width, 160), np.arange(3, c.height, 160)
-    say(f"C5 {c.width}x{c.height} N={c.n} {NAMES[mode]} sample {len(rows)}x{len(cols)}")
+    cols, rows = cghgen.crop_pixels(2016, 2016, 64, 64)
+    scols, srows = np.arange(7, c.width, 161), np.arange(3, c.height, 161)
+    say(f"C5 {c.width}x{c.height} N={c.n} {NAMES[mode]} crop {len(rows)}x{len(cols)}")
     if "c5" not in _REFS:
         _REFS["c5"] = oracle.cloud_fresnel(c, cols=cols, rows=rows)
-    ref = _REFS["c5"]
-    got = gpu_hologram(c, mode)[np.ix_(rows, cols)]
-    check("C5", got, ref, mode)
+        _REFS["c5s"] = oracle.cloud_fresnel(c, cols=scols, rows=srows)
+    full = gpu_hologram(c, mode)
+    check("C5 crop", full[np.ix_(rows, cols)], _REFS["c5"], mode)
+    check("C5 sparse", full[np.ix_(srows, scols)], _REFS["c5s"], mode)
 
 
 # ------------------------------------------------------------ edge cases
@@ -420,7 +449,8 @@ def test_batch_graph_replays_match_eager(mode):
                          ids=["split_fp16", "split_bf16", "direct_fp32", "separable_fp32"])
 def test_batch_full_size_frames(mode):
     """Frames of the batch workload (1920 x 1080, RGB wavelengths, log-uniform
-    point counts), the first six, checked on strided pixels of every frame."""
+    point counts), the first six, each checked on its evaluation set: every
+    8th row and column."""
     import torch
     b = cghgen.make_batch(n_frames=6)
     frames = cgh.batch_frames(b)
@@ -430,8 +460,7 @@ def test_batch_full_size_frames(mode):
     out = torch.empty((len(frames), b.height, b.width), device="cuda")
     ctx.batch_compute(frames, out, mode)
     torch.cuda.synchronize()
-    cols = np.arange(0, b.width, 32)
-    rows = np.arange(0, b.height, 32)
+    cols, rows = cghgen.strided_pixels(b.width, b.height, 8)   # the workload's evaluation set
     for f, (o, n, lam) in enumerate(frames):
         sl = slice(o, o + n)
         ref = oracle.fresnel(b.width, b.height, b.pitch, lam, b.x[sl], b.y[sl], b.z[sl],
