@@ -28,8 +28,20 @@
  * Threads and streams
  *   - A context is not thread-safe: use one per host thread.
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
- *     Compute calls only enqueue work and never block the host; their
- *     results are ready when the stream reaches them.
+ *     Compute calls only enqueue work; their results are ready when the
+ *     stream reaches them.  A single hologram's descriptors travel in the
+ *     kernel arguments; a batch's tables are copied asynchronously from
+ *     library-owned page-locked memory.  The host blocks only when a
+ *     workspace buffer must grow (the first call of a larger evaluation):
+ *     the library then waits for the device before replacing the buffer.
+ *   - Calls on one context share its workspace.  A call on another stream
+ *     than the previous call's first makes its stream wait for the end of
+ *     that call (an event), so calls may be issued on any streams.
+ *   - cgh_compute, cgh_compute_complex and cgh_kinoform enqueue kernels only
+ *     (no copies or memsets), so once their workspace has grown they may be
+ *     captured into a caller's HIP graph; the graph then reads the
+ *     context's workspace and must not run concurrently with other calls on
+ *     the context.
  *   - Same inputs, mode and device give bitwise-identical output on every run
  *     (no floating-point atomics; all reductions run in a fixed order).
  *
@@ -185,8 +197,11 @@ CGH_API cgh_status cgh_kinoform(cgh_ctx *c, cgh_mode mode, uint8_t *out_dev, voi
  *   non-NULL stream runs eagerly and then records its kernel sequence in a
  *   HIP graph; a later call with the same mode, frame table and output
  *   replays that graph.  A call that changes any of them, or that must grow
- *   a workspace buffer, runs eagerly and replaces the graph.
- * Modes: all of cgh_mode.  Errors as cgh_compute. */
+ *   a workspace buffer, runs eagerly and replaces the graph.  The graph
+ *   reads device tables that only batch calls write, so single-hologram
+ *   calls on the context between replays do not disturb it.
+ * Modes: all of cgh_mode.  Errors as cgh_compute; CGH_ESTATE when `stream`
+ * is itself being captured (the call records its own graph). */
 CGH_API cgh_status cgh_batch_compute(cgh_ctx *c, const cgh_frame *frames, int32_t n_frames,
                              cgh_mode mode, float *out_dev, void *stream);
 
