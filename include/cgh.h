@@ -205,6 +205,40 @@ CGH_API cgh_status cgh_kinoform(cgh_ctx *c, cgh_mode mode, uint8_t *out_dev, voi
 CGH_API cgh_status cgh_batch_compute(cgh_ctx *c, const cgh_frame *frames, int32_t n_frames,
                              cgh_mode mode, float *out_dev, void *stream);
 
+/* For callers that cannot allocate device memory -- code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc: the hologram
+ * of cgh_compute (same quantity, conventions and modes) of n points given
+ * directly in device memory, evaluated without any allocation.  Every
+ * intermediate (constants, tables or factors, split partials) lives in one
+ * fixed 32 MiB array of static device memory per GPU, which the library's
+ * code object holds until the process ends; a large cloud is processed in
+ * point chunks that fit it and accumulate into the output in order, with
+ * fewer split-K or point-split partials than cgh_compute when they do not
+ * fit, so results agree with cgh_compute's to rounding, not bit for bit.
+ *   width, height in [1, 65536]; pitch_m, wavelength_m finite and > 0.
+ *   x_dev, y_dev, z_dev, amp_dev: float32 device arrays of n points (not
+ *   inspected; z must be > 0), non-NULL when n > 0; n in [0, 2^34].
+ *   out_dev: caller-owned device buffer of height*width floats.
+ *   device: HIP device index in [0, 64) (made current for the call).
+ * The call enqueues kernels on `stream` and nothing else (no allocation, no
+ * copy, no memset, no host wait), so it may be captured into a graph.  The
+ * first call on a device resolves the array's address there (call once
+ * outside a capture).  All calls on one device share its array and leave
+ * their intermediates in it: calls whose work overlaps on one device (other
+ * streams, or graphs replayed concurrently) race and must be ordered by the
+ * caller.
+ * Errors: CGH_EINVAL for a bad argument, or for a hologram whose
+ * intermediates of one group of 32 points exceed the array (the largest
+ * sizes only: about 32 x (W + H) x 8 bytes in CGH_SPLIT_*, CGH_SEPARABLE_FP32
+ * and CGH_SPHERICAL_FP32, half that in CGH_DIRECT_FP32 and CGH_FP16, so
+ * 65536 x 65536 is refused in the first three), both checked before any HIP
+ * call; CGH_EDEVICE (no gfx950 at `device`, launch failure). */
+CGH_API cgh_status cgh_compute_noalloc(int32_t width, int32_t height, double pitch_m,
+                                       double wavelength_m, const float *x_dev,
+                                       const float *y_dev, const float *z_dev,
+                                       const float *amp_dev, int64_t n, cgh_mode mode,
+                                       float *out_dev, int32_t device, void *stream);
+
 /* Autotune the launch shape of `mode` for this context's hologram size:
  * times every candidate (matrix-core modes: each built GEMM tile shape with a
  * few split-K counts, the time of the GEMM plus its split-K reduce; direct

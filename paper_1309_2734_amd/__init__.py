@@ -44,7 +44,8 @@ MEM_DEVICE = 1
 
 # every symbol include/cgh.h declares
 EXPORTS = ("cgh_create", "cgh_points_upload", "cgh_compute", "cgh_compute_complex",
-           "cgh_kinoform", "cgh_batch_compute", "cgh_tune", "cgh_fresnel_create",
+           "cgh_kinoform", "cgh_batch_compute", "cgh_compute_noalloc", "cgh_tune",
+           "cgh_fresnel_create",
            "cgh_fresnel_run", "cgh_fresnel_destroy", "cgh_destroy", "cgh_strerror",
            "cgh_last_error", "cgh_profile_enable", "cgh_profile_reset", "cgh_profile_read",
            "cgh_version")
@@ -89,6 +90,9 @@ def lib() -> ctypes.CDLL:
     L.cgh_kinoform.restype = st
     L.cgh_batch_compute.argtypes = [vp, ctypes.POINTER(Frame), i32, ctypes.c_int, vp, vp]
     L.cgh_batch_compute.restype = st
+    L.cgh_compute_noalloc.argtypes = [i32, i32, dbl, dbl, vp, vp, vp, vp, i64, ctypes.c_int, vp,
+                                      i32, vp]
+    L.cgh_compute_noalloc.restype = st
     L.cgh_tune.argtypes = [vp, ctypes.c_int, i32, ctypes.c_char_p, i32, vp]
     L.cgh_tune.restype = st
     L.cgh_destroy.argtypes = [vp]
@@ -308,6 +312,32 @@ class FresnelPlan:
         _check(lib().cgh_fresnel_run(self._h, u.data_ptr(), out.data_ptr(),
                                      _stream_handle(stream, [out])), "cgh_fresnel_run")
         return out
+
+
+def compute_noalloc(out, x, y, z, amp, width: int, height: int, pitch: float, wavelength: float,
+                    mode: int = DIRECT_FP32, device: int = 0, stream=None):
+    """cgh_compute_noalloc: the hologram of the points x, y, z, amp (CUDA
+    float32 tensors of one length) into `out` ([height, width] float32,
+    CUDA), evaluated in the library's static scratch with no allocation."""
+    import torch
+    pts = [x, y, z, amp]
+    for t, name in zip(pts, ("x", "y", "z", "amp")):
+        if not (_is_torch(t) and t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()
+                and t.dim() == 1):
+            raise TypeError(f"{name} must be a contiguous 1-D CUDA float32 tensor")
+        _on_device(t, device, name)
+    n = x.numel()
+    if any(t.numel() != n for t in pts):
+        raise ValueError("x, y, z, amp must have one length")
+    if not (_is_torch(out) and out.is_cuda and out.dtype == torch.float32 and out.is_contiguous()
+            and out.numel() == int(width) * int(height)):
+        raise TypeError("out must be a contiguous CUDA float32 tensor of height x width values")
+    _on_device(out, device, "out")
+    _check(lib().cgh_compute_noalloc(int(width), int(height), float(pitch), float(wavelength),
+                                     *[t.data_ptr() if n else None for t in pts], n, int(mode),
+                                     out.data_ptr(), int(device), _stream_handle(stream, [out])),
+           "cgh_compute_noalloc")
+    return out
 
 
 def version() -> int:

@@ -22,8 +22,10 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <cstdint>
 #include <cstring>
 #include <deque>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -658,7 +660,7 @@ struct Eval {
     Geo g;
     const float *x = nullptr, *y = nullptr, *z = nullptr, *a = nullptr;
     Ws *ws = nullptr;
-    size_t partial_cap = 0;   // bytes of split partials allowed (0: no limit)
+    size_t partial_cap = SIZE_MAX;   // bytes of split partials allowed
     PointConsts pc{};         // set by ev_consts
     float *tu = nullptr, *tv = nullptr, *tx = nullptr, *ty = nullptr;   // set by ev_tables
 };
@@ -834,9 +836,8 @@ cgh_status ev_run_direct_one(Eval &ev, int mode, const FrameDesc &fd, int64_t to
     // its own pair, and the pairs are summed as planes of 2H rows
     const int planes = out_im ? 2 : 1;
     int splits = out_im && out_im != out + plane ? 1 : direct_splits(ev, mode);
-    if (ev.partial_cap)
-        while (splits > 1 && (size_t)splits * planes * plane * sizeof(float) > ev.partial_cap)
-            splits /= 2;
+    while (splits > 1 && (size_t)splits * planes * plane * sizeof(float) > ev.partial_cap)
+        splits /= 2;
     if (splits <= 1 || fd.groups < 4) {
         FrameList fl{};
         fl.dev = nullptr;
@@ -870,9 +871,8 @@ cgh_status ev_run_gemm(Eval &ev, int mode, int64_t slots, float *out, bool cplx,
     Plan p = plan_gemm(M, N, slots, mi,
                        ev.c ? find_tuned(ev.c, tune_key(ev.c, mode, slots / mi.kbp, M)) : nullptr);
     const size_t per_split = (size_t)M * N * sizeof(float);
-    if (ev.partial_cap)
-        while (p.g.splits > 1 && (size_t)p.g.splits * per_split > ev.partial_cap)
-            --p.g.splits;
+    while (p.g.splits > 1 && (size_t)p.g.splits * per_split > ev.partial_cap)
+        --p.g.splits;
     FactorSet fs;
     fs.hl = mi.hl;
     fs.amb = p.g.mblocks;
@@ -1282,6 +1282,105 @@ cgh_status check_device(int32_t device, std::string &arch)
     return CGH_OK;
 }
 
+// ------------------------------------------- evaluation without allocation
+// Fixed workspace of cgh_compute_noalloc: one array per device (each device
+// holds its own copy, at its own address, until the process ends).  In host
+// code the name is only a stand-in: kernels get the device address that
+// hipGetSymbolAddress returns for the current device.
+constexpr size_t kScratchBytes = (size_t)32 << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+char *g_scratch_dev[kMaxDevices] = {};   // device address per device, once resolved
+
+// This device's scratch address (the device is current).  The first call on
+// a device checks it is a gfx950, resolves the address and raises the GEMM
+// kernels' LDS limit.
+cgh_status scratch_on(int device, char **p)
+{
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[device]) {
+        int count = 0;
+        CGH_HIP(hipGetDeviceCount(&count), "hipGetDeviceCount");
+        if (device >= count)
+            return fail(CGH_EDEVICE, "device index out of range");
+        hipDeviceProp_t prop;
+        CGH_HIP(hipGetDeviceProperties(&prop, device), "hipGetDeviceProperties");
+        if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+            return fail(CGH_EDEVICE, "this library is built for gfx950");
+        void *ptr = nullptr;
+        CGH_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "static scratch address");
+        if (!ptr)
+            return fail(CGH_EDEVICE, "static scratch address is NULL");
+        CGH_HIP(gemm_prepare_kernels(), "GEMM kernel attributes");
+        g_scratch_dev[device] = (char *)ptr;
+    }
+    *p = g_scratch_dev[device];
+    return CGH_OK;
+}
+
+// Regions of the scratch array, handed out in order of first request; a
+// later request of a role must fit the region it got first.
+struct ArenaWs final : Ws {
+    char *base = nullptr;
+    size_t cap = 0, used = 0;
+    size_t off[(int)Role::Count] = {}, len[(int)Role::Count] = {};
+    bool set[(int)Role::Count] = {};
+    cgh_status get(Role role, size_t bytes, void **p) override
+    {
+        const int r = (int)role;
+        bytes = (bytes + 255) / 256 * 256;
+        if (!set[r]) {
+            if (bytes > cap - used)
+                return fail(CGH_EINVAL, "evaluation does not fit the static scratch");
+            off[r] = used;
+            len[r] = bytes;
+            set[r] = true;
+            used += bytes;
+        } else if (bytes > len[r]) {
+            return fail(CGH_EINVAL, "evaluation does not fit the static scratch");
+        }
+        *p = base + off[r];
+        return CGH_OK;
+    }
+};
+
+// Point chunk (slots) and bytes of split partials of a no-allocation
+// evaluation, both within kScratchBytes: at most half of it for the partial
+// planes of the split counts the default plan would use, the rest for the
+// constants and the tables or factors of one chunk.  *chunk = 0 when not even
+// one slot group fits.
+void noalloc_plan(const Geo &g, int mode, int64_t *chunk, size_t *partial_cap)
+{
+    const size_t plane = (size_t)g.width * g.height * sizeof(float);
+    int splits = 1;
+    if (is_direct(mode)) {
+        Eval probe;
+        probe.g = g;
+        splits = direct_splits(probe, mode);
+    } else {
+        splits = plan_gemm(g.height, g.width, (int64_t)1 << 20, mode_info(mode)).g.splits;
+    }
+    const size_t want = splits > 1 ? (size_t)splits * plane : 0;
+    const size_t per_slot = 40 + bytes_per_slot(g, mode, false);
+    const size_t slack = 8 * 256;        // 256-byte rounding of every region
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        size_t part = attempt == 0 ? std::min(want, kScratchBytes / 2) / plane * plane : 0;
+        if (part < 2 * plane)
+            part = 0;
+        const int64_t ch =
+            (int64_t)((kScratchBytes - part - slack) / per_slot) / kSlotAlign * kSlotAlign;
+        if (ch >= kSlotAlign) {
+            *chunk = ch;
+            *partial_cap = part;
+            return;
+        }
+    }
+    *chunk = 0;
+    *partial_cap = 0;
+}
+
 // Common checks of the single-hologram compute calls.
 cgh_status check_compute(cgh_ctx *c, int mode, const void *out)
 {
@@ -1653,6 +1752,57 @@ cgh_status cgh_batch_compute(cgh_ctx *c, const cgh_frame *frames, int32_t n_fram
     (void)hipGetLastError();
     g_last_error.clear();
     return CGH_OK;
+}
+
+cgh_status cgh_compute_noalloc(int32_t width, int32_t height, double pitch_m,
+                               double wavelength_m, const float *x_dev, const float *y_dev,
+                               const float *z_dev, const float *amp_dev, int64_t n, cgh_mode mode,
+                               float *out_dev, int32_t device, void *stream)
+{
+    g_last_error.clear();
+    if (width < 1 || width > 65536 || height < 1 || height > 65536)
+        return fail(CGH_EINVAL, "width and height must be in [1, 65536]");
+    if (!finite_pos(pitch_m))
+        return fail(CGH_EINVAL, "pitch must be finite and > 0");
+    if (!finite_pos(wavelength_m))
+        return fail(CGH_EINVAL, "wavelength must be finite and > 0");
+    if (n < 0 || n > ((int64_t)1 << 34))
+        return fail(CGH_EINVAL, "n must be in [0, 2^34]");
+    if (n > 0 && (!x_dev || !y_dev || !z_dev || !amp_dev))
+        return fail(CGH_EINVAL, "point arrays must be non-NULL when n > 0");
+    if (!out_dev)
+        return fail(CGH_EINVAL, "output is NULL");
+    CGH_TRY(check_mode(mode));
+    if (device < 0 || device >= kMaxDevices)
+        return fail(CGH_EINVAL, "device index must be in [0, 64)");
+    Geo g;
+    g.width = width;
+    g.height = height;
+    g.wpad = (int)round_up(width, kLinePad);
+    g.hpad = (int)round_up(height, kLinePad);
+    g.pitch = pitch_m;
+    int64_t chunk = 0;
+    size_t part = 0;
+    noalloc_plan(g, mode, &chunk, &part);
+    if (chunk == 0)
+        return fail(CGH_EINVAL, "the hologram is too large for the 32 MiB static scratch in this "
+                                "mode (one group of 32 points does not fit)");
+    DeviceGuard dg;
+    CGH_HIP(dg.set(device), "hipSetDevice");
+    char *base = nullptr;
+    CGH_TRY(scratch_on(device, &base));
+    ArenaWs ws;
+    ws.base = base;
+    ws.cap = kScratchBytes;
+    Eval ev;
+    ev.g = g;
+    ev.x = x_dev;
+    ev.y = y_dev;
+    ev.z = z_dev;
+    ev.a = amp_dev;
+    ev.ws = &ws;
+    ev.partial_cap = part;
+    return ev_one(ev, mode, 0, n, wavelength_m, out_dev, false, chunk, (hipStream_t)stream);
 }
 
 cgh_status cgh_tune(cgh_ctx *c, cgh_mode mode, int32_t repeats, char *report, int32_t report_len,

@@ -135,3 +135,38 @@ def test_binding_rejects_tensors_on_another_device():
     cgh._on_device(_T(0), 0, "out")
     with pytest.raises(ValueError, match="out is on"):
         cgh._on_device(_T(1), 0, "out")
+
+
+def _noalloc(L, w=64, h=32, p=8e-6, lam=5e-7, pts=16, n=4, mode=0, out=16, dev=0):
+    ptr = ctypes.c_void_p(pts) if pts else None
+    return L.cgh_compute_noalloc(w, h, p, lam, ptr, ptr, ptr, ptr, n, mode,
+                                 ctypes.c_void_p(out) if out else None, dev, None)
+
+
+@pytest.mark.parametrize("kw", [
+    dict(w=0), dict(h=65537), dict(p=0.0), dict(lam=float("inf")), dict(n=-1),
+    dict(n=(1 << 34) + 1), dict(pts=0), dict(out=0), dict(mode=6), dict(mode=-1), dict(dev=-1),
+    dict(dev=64),
+    # the intermediates of one 32-point group exceed the 32 MiB array
+    dict(w=65536, h=65536, mode=cgh.SEPARABLE_FP32), dict(w=65536, h=65536, mode=cgh.SPLIT_BF16),
+    dict(w=65536, h=65536, mode=cgh.SPLIT_FP16), dict(w=65536, h=65536, mode=cgh.SPHERICAL_FP32),
+])
+def test_noalloc_rejects_bad_arguments_before_any_hip_call(L, kw):
+    """Checked before the device is touched, so identical on a GPU-less host."""
+    assert _noalloc(L, **kw) == cgh.EINVAL
+    assert len(L.cgh_last_error()) > 0
+
+
+def test_noalloc_largest_accepted_sizes_pass_the_checks(L):
+    """The direct FP32 and one-product FP16 modes fit one 32-point group of a
+    65536 x 65536 hologram into the static array, every mode fits 65536 x
+    32768; without a
+    GPU such calls then fail at the device, not at the argument checks."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is visible")
+    for mode in (cgh.DIRECT_FP32, cgh.FP16):
+        assert _noalloc(L, w=65536, h=65536, mode=mode) == cgh.EDEVICE, mode
+    for mode in range(6):
+        assert _noalloc(L, w=65536, h=32768, mode=mode) == cgh.EDEVICE, mode
+    assert _noalloc(L, n=0, pts=0) == cgh.EDEVICE
