@@ -50,6 +50,10 @@ def _load():
             fn.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
                            ctypes.c_int64, dp, dp, dp, dp, ctypes.c_int64, ip, ctypes.c_int64, ip,
                            dp, dp, ctypes.c_int32]
+        fn = lib.cgh_oracle_wrm_record
+        fn.restype = ctypes.c_int
+        fn.argtypes = [ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                       ctypes.c_int64, dp, dp, dp, dp, ctypes.c_int64, ip, dp, dp, ctypes.c_int32]
         fn = lib.cgh_oracle_diffraction
         fn.restype = ctypes.c_int
         fn.argtypes = [ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_double, dp, dp,
@@ -153,6 +157,29 @@ def diffraction(u: np.ndarray, pitch: float, wavelength: float, z: float, rows=N
                                     int(threads or host_threads()))
     if rc != 0:
         raise RuntimeError(f"cgh_oracle_diffraction failed with code {rc}")
+    return re + 1j * im
+
+
+def wrm_record(n: int, pitch: float, wavelength: float, zw: float, x, y, z, a, rows=None,
+               threads: Optional[int] = None) -> np.ndarray:
+    """First step of the wavefront-recording method (cgh_oracle.c): the
+    cloud's Fresnel wave recorded on the n x n virtual plane at distance zw
+    from the hologram, each point (at d_j = z_j - zw > 0 beyond the plane)
+    over its disc of radius lambda d_j / (2 p); complex128 [len(rows), n]."""
+    lib = _load()
+    arrs = [np.ascontiguousarray(np.asarray(v, dtype=np.float64)) for v in (x, y, z, a)]
+    npts = arrs[0].shape[0]
+    if any(v.shape[0] != npts for v in arrs):
+        raise ValueError("x, y, z, amp must have one length")
+    r32 = np.ascontiguousarray(np.arange(n, dtype=np.int32) if rows is None
+                               else np.asarray(rows, dtype=np.int32))
+    re = np.zeros((r32.shape[0], n), dtype=np.float64)
+    im = np.zeros_like(re)
+    rc = lib.cgh_oracle_wrm_record(int(n), float(pitch), float(wavelength), float(zw), npts,
+                                   *[_dp(v) for v in arrs], r32.shape[0], _ip(r32), _dp(re),
+                                   _dp(im), int(threads or host_threads()))
+    if rc != 0:
+        raise RuntimeError(f"cgh_oracle_wrm_record failed with code {rc}")
     return re + 1j * im
 
 

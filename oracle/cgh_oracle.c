@@ -275,3 +275,119 @@ int cgh_oracle_diffraction(int32_t n, double pitch, double wavelength, double z,
     free(tids);
     return rc;
 }
+
+
+/* ------------------------------------------------------------------------
+ * Wavefront-recording method, first step (Section 2.3): the object wave of
+ * the cloud recorded on a virtual plane placed at distance zw from the
+ * hologram, between the hologram and the points, with each point's wave
+ * written only over the small region of the plane its light crosses.
+ *
+ * The plane is an n x n grid of pitch p centred like the hologram: sample
+ * (m, c) sits at x_w = (c - (n-1)/2) p, y_w = (m - (n-1)/2) p.  Point j lies
+ * d_j = z_j - zw beyond the plane.  Its wave on the plane is Eq. (2) with
+ * z_j replaced by d_j, without the per-point constant phase 2 pi d_j / lambda
+ * (dropped as in the direct calculation):
+ *
+ *   u_w(x_w, y_w) = sum_{j : d_j > 0, (x_w - x_j)^2 + (y_w - y_j)^2 <= r_j^2}
+ *                   A_j exp( i pi ((x_w - x_j)^2 + (y_w - y_j)^2) / (lambda d_j) ),
+ *
+ * over the disc of radius r_j = lambda d_j / (2 p) around (x_j, y_j): the
+ * local frequency of the chirp, r / (lambda d_j) cycles per metre, reaches
+ * the grid's limit 1 / (2 p) at r = r_j, so a larger region would alias.
+ * Points at or in front of the plane (d_j <= 0) are not recorded.
+ *
+ * A plain loop over samples and points, FP64, libm cos/sin.  The region test
+ * is evaluated exactly as written above (differences in metres, squared and
+ * summed, against r_j squared), in FP64 without contraction.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t n;
+    double pitch, wavelength, zw;
+    const double *x, *y, *z, *a;
+    int64_t n_points;
+    const int32_t *rows;
+    double *out_re, *out_im;
+    int64_t row_begin, row_end;
+} wrm_job_t;
+
+static void *wrm_worker(void *arg)
+{
+    const wrm_job_t *jb = (const wrm_job_t *)arg;
+    const double pi = 3.14159265358979323846;
+    const double half = 0.5 * (double)(jb->n - 1);
+    for (int64_t r = jb->row_begin; r < jb->row_end; ++r) {
+        const double yw = ((double)jb->rows[r] - half) * jb->pitch;
+        for (int32_t c = 0; c < jb->n; ++c) {
+            const double xw = ((double)c - half) * jb->pitch;
+            double sum_re = 0.0, sum_im = 0.0;
+            for (int64_t i = 0; i < jb->n_points; ++i) {
+                const double d = jb->z[i] - jb->zw;          /* beyond the plane */
+                if (!(d > 0.0))
+                    continue;
+                const double dx = xw - jb->x[i];
+                const double dy = yw - jb->y[i];
+                const double rr = dx * dx + dy * dy;
+                const double rj = jb->wavelength * d / (2.0 * jb->pitch);
+                if (rr > rj * rj)
+                    continue;                                  /* outside the region */
+                const double theta = pi * rr / (jb->wavelength * d);
+                sum_re += jb->a[i] * cos(theta);
+                sum_im += jb->a[i] * sin(theta);
+            }
+            jb->out_re[r * jb->n + c] = sum_re;
+            jb->out_im[r * jb->n + c] = sum_im;
+        }
+    }
+    return NULL;
+}
+
+/* The recorded plane for rows rows[0 .. n_rows) (all n columns each);
+ * out_re, out_im: n_rows x n.  Returns 0 on success. */
+int cgh_oracle_wrm_record(int32_t n, double pitch, double wavelength, double zw,
+                          int64_t n_points, const double *x, const double *y, const double *z,
+                          const double *a, int64_t n_rows, const int32_t *rows, double *out_re,
+                          double *out_im, int32_t n_threads)
+{
+    if (n <= 0 || n_points < 0 || n_rows < 0 || !(pitch > 0.0) || !(wavelength > 0.0))
+        return 1;
+    if (!out_re || !out_im || (n_rows > 0 && !rows))
+        return 1;
+    if (n_points > 0 && (!x || !y || !z || !a))
+        return 1;
+    if (n_threads < 1)
+        n_threads = 1;
+    if (n_threads > n_rows)
+        n_threads = n_rows > 0 ? (int32_t)n_rows : 1;
+    wrm_job_t *jobs = (wrm_job_t *)calloc((size_t)n_threads, sizeof(wrm_job_t));
+    pthread_t *tids = (pthread_t *)calloc((size_t)n_threads, sizeof(pthread_t));
+    if (!jobs || !tids) {
+        free(jobs);
+        free(tids);
+        return 2;
+    }
+    for (int32_t t = 0; t < n_threads; ++t) {
+        wrm_job_t *jb = &jobs[t];
+        jb->n = n; jb->pitch = pitch; jb->wavelength = wavelength; jb->zw = zw;
+        jb->x = x; jb->y = y; jb->z = z; jb->a = a; jb->n_points = n_points;
+        jb->rows = rows; jb->out_re = out_re; jb->out_im = out_im;
+        jb->row_begin = n_rows * t / n_threads;
+        jb->row_end = n_rows * (t + 1) / n_threads;
+    }
+    int rc = 0;
+    int32_t started = 0;
+    for (int32_t t = 1; t < n_threads; ++t) {
+        if (pthread_create(&tids[t], NULL, wrm_worker, &jobs[t]) != 0) {
+            rc = 3;
+            break;
+        }
+        started = t;
+    }
+    if (rc == 0)
+        wrm_worker(&jobs[0]);
+    for (int32_t t = 1; t <= started; ++t)
+        pthread_join(tids[t], NULL);
+    free(jobs);
+    free(tids);
+    return rc;
+}

@@ -362,3 +362,88 @@ def test_diffraction_row_subset_is_consistent():
     full = oracle.diffraction(u, 8e-6, 532e-9, 0.02, threads=1)
     sub = oracle.diffraction(u, 8e-6, 532e-9, 0.02, rows=[15, 0, 7], threads=3)
     assert np.array_equal(sub, full[[15, 0, 7]])
+
+
+# -------------------------------------- wavefront recording, first step
+def _wrm_closed_form_setup():
+    # p = 2^-17 m, d = 2^-11 m, lambda = 5 * 2^-23 m (all exact): beta =
+    # p^2 / (2 lambda d) = 1/10 revolution per sample^2 and the region radius
+    # lambda d / (2 p) = 2.5 samples, so the disc holds the offsets with
+    # k^2 + l^2 <= 6 (squared radius 6.25 is no sum of two squares: no ties).
+    p = 2.0 ** -17
+    d = 2.0 ** -11
+    lam = 5.0 * 2.0 ** -23
+    zw = 2.0 ** -10
+    return p, d, lam, zw
+
+
+def test_wrm_one_point_closed_form():
+    """One point at sample (m, c) = (5, 9) of a 16 x 16 plane (x_j = 1.5 p,
+    y_j = -2.5 p from the centre 7.5), d = z_j - zw = 2^-11 m beyond the
+    plane: the recorded wave is exp(i pi s / 5) at the 21 samples of squared
+    offset s in {0, 1, 2, 4, 5} and zero everywhere else.  The values are
+    the exact algebraic cos / sin of multiples of pi / 5.  A second point in
+    front of the plane (d < 0) and a third whose disc lies outside the plane
+    add nothing.  Pins the region radius lambda d / (2 p), the distance
+    d = z - zw, the phase scaling pi / (lambda d), the centre convention and
+    the sign of the exponent."""
+    p, d, lam, zw = _wrm_closed_form_setup()
+    x = [1.5 * p, 1.5 * p, 40.0 * p]
+    y = [-2.5 * p, -2.5 * p, 40.0 * p]
+    z = [zw + d, zw - d, zw + d]
+    u = oracle.wrm_record(16, p, lam, zw, x, y, z, [1.0, 0.5, 1.0], threads=3)
+    r5 = math.sqrt(5.0)
+    cos_k = {0: 1.0, 1: (1 + r5) / 4, 2: (r5 - 1) / 4, 4: -(1 + r5) / 4, 5: -1.0}
+    sin_k = {0: 0.0, 1: math.sqrt(10 - 2 * r5) / 4, 2: math.sqrt(10 + 2 * r5) / 4,
+             4: math.sqrt(10 - 2 * r5) / 4, 5: 0.0}
+    exp = np.zeros((16, 16), dtype=np.complex128)
+    for m in range(16):
+        for c in range(16):
+            s = (m - 5) ** 2 + (c - 9) ** 2
+            if s in cos_k:
+                exp[m, c] = cos_k[s] + 1j * sin_k[s]
+    assert np.count_nonzero(exp) == 21
+    assert np.max(np.abs(u - exp)) < 1e-12
+
+
+def test_wrm_equals_direct_sum_where_regions_cover_the_plane():
+    """With every disc larger than the plane's diagonal the recorded plane is
+    the unrestricted Fresnel sum of Eq. (2) at the depths d_j = z_j - zw: the
+    direct-calculation oracle (pinned above) on the n x n grid."""
+    n, p, lam, zw = 12, 8e-6, 532e-9, 0.05
+    rng = np.random.default_rng(11)
+    N = 9
+    x = rng.uniform(-3 * p, 3 * p, N).astype(np.float32)
+    y = rng.uniform(-3 * p, 3 * p, N).astype(np.float32)
+    dmin = 2.0 * p * 40 * p / lam        # radius >= 40 p > the diagonal 12 sqrt(2) p
+    d = rng.uniform(dmin, 2 * dmin, N)
+    z = (zw + d).astype(np.float32)
+    a = rng.uniform(0.2, 1.0, N).astype(np.float32)
+    u = oracle.wrm_record(n, p, lam, zw, x, y, z, a)
+    dd = z.astype(np.float64) - zw           # the same FP64 depths
+    re, im = oracle.fresnel_complex(n, n, p, lam, x, y, dd, a)
+    assert np.max(np.abs(u - (re + 1j * im))) < 1e-12
+
+
+def test_wrm_superposition_mirror_and_rows():
+    """Partial discs: the plane of two point sets is the sum of their planes;
+    mirroring x_j mirrors the columns bit for bit (centred grid); a row
+    subset gives the same rows bit for bit."""
+    n, p, lam, zw = 40, 8e-6, 532e-9, 0.4
+    rng = np.random.default_rng(12)
+    N = 14
+    x = rng.uniform(-18 * p, 18 * p, N).astype(np.float32)
+    y = rng.uniform(-18 * p, 18 * p, N).astype(np.float32)
+    z = (zw + rng.uniform(0.0005, 0.0015, N)).astype(np.float32)   # radii 2 .. 6 samples
+    a = rng.uniform(0.2, 1.0, N).astype(np.float32)
+    full = oracle.wrm_record(n, p, lam, zw, x, y, z, a)
+    parts = (oracle.wrm_record(n, p, lam, zw, x[:6], y[:6], z[:6], a[:6]) +
+             oracle.wrm_record(n, p, lam, zw, x[6:], y[6:], z[6:], a[6:]))
+    assert np.max(np.abs(full - parts)) < 1e-12
+    mir = oracle.wrm_record(n, p, lam, zw, -x, y, z, a)
+    assert np.array_equal(mir[:, ::-1], full)
+    rows = [0, 7, 19, 39]
+    assert np.array_equal(oracle.wrm_record(n, p, lam, zw, x, y, z, a, rows=rows, threads=2),
+                          full[rows])
+    # some discs are clipped by the plane's edge, some samples are outside all
+    assert 0 < np.count_nonzero(full) < n * n

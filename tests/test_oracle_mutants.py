@@ -53,6 +53,24 @@ MUTANTS = [
      "const double q = jb->pitch * jb->pitch / (jb->wavelength * jb->z);"),
     ("diffraction: prefactor without the -i", "const double pr = s * ei, pi_ = -s * er;",
      "const double pr = s * er, pi_ = s * ei;"),
+    ("recording: region radius doubled",
+     "const double rj = jb->wavelength * d / (2.0 * jb->pitch);",
+     "const double rj = jb->wavelength * d / jb->pitch;"),
+    ("recording: depth from the hologram, not the plane",
+     "const double d = jb->z[i] - jb->zw;", "const double d = jb->z[i];"),
+    ("recording: points in front of the plane recorded", "if (!(d > 0.0))\n                    continue;",
+     "if (d == 0.0)\n                    continue;"),
+    ("recording: phase sign", "const double theta = pi * rr / (jb->wavelength * d);",
+     "const double theta = -pi * rr / (jb->wavelength * d);"),
+    ("recording: centre off by half a sample", "const double half = 0.5 * (double)(jb->n - 1);",
+     "const double half = 0.5 * (double)(jb->n);"),
+    ("recording: x offset from the point's y", "const double dx = xw - jb->x[i];",
+     "const double dx = xw - jb->y[i];"),
+    ("recording: amplitude dropped", "sum_re += jb->a[i] * cos(theta);", "sum_re += cos(theta);"),
+    ("recording: region not applied", "if (rr > rj * rj)\n                    continue;",
+     "if (rr < 0.0)\n                    continue;"),
+    ("recording: last point skipped", "for (int64_t i = 0; i < jb->n_points; ++i) {",
+     "for (int64_t i = 0; i + 1 < jb->n_points; ++i) {"),
 ]
 
 
