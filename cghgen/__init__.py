@@ -18,7 +18,7 @@ Conventions
   order x, y, z, amplitude (one length-N vector each), then cast to float32:
   the float32 values are the inputs both the GPU path and the oracle see.
 * Seed = configuration number (1..5); frame f of the batch workload uses
-  seed 400 + f.
+  seed 400 + f; the wavefront-recording workload uses seed 7.
 """
 from __future__ import annotations
 
@@ -27,8 +27,8 @@ from typing import List, Optional
 
 import numpy as np
 
-__all__ = ["Cloud", "Batch", "make_config", "make_batch", "uniform_cloud",
-           "ellipsoid_cloud", "CONFIG_NAMES", "BATCH_WAVELENGTHS"]
+__all__ = ["Cloud", "Batch", "make_config", "make_batch", "make_wrm", "uniform_cloud",
+           "ellipsoid_cloud", "CONFIG_NAMES", "BATCH_WAVELENGTHS", "WRM_PLANE_Z", "WRM_PLANE_N"]
 
 
 @dataclass
@@ -167,6 +167,25 @@ def make_config(k: int, n: Optional[int] = None, seed: Optional[int] = None) -> 
         return ellipsoid_cloud(CONFIG_NAMES[5], 4096, 4096, 4e-6, 532e-9, n or 1_000_000,
                                seed=s)
     raise ValueError(f"no single-hologram configuration {k}")
+
+
+# Wavefront-recording workload: a shallow object 5 mm deep, the virtual plane
+# 5 mm in front of its nearest points (distances to the plane 5 .. 10 mm, disc
+# radii 21 .. 42 samples), on a 2048 x 2048 plane holding the 1920 x 1080
+# hologram centred.
+WRM_PLANE_Z = 0.495
+WRM_PLANE_N = 2048
+
+
+def make_wrm(n: int = 10000, seed: int = 7) -> Cloud:
+    """The wavefront-recording workload (Table 8's hologram: 1920 x 1080, 8 um;
+    1e3 .. 1e5 points): x, y ~ U(+-3 mm), z ~ U[0.5, 0.505] m, A ~ U[0, 1],
+    532 nm.  The virtual plane lies at WRM_PLANE_Z from the hologram."""
+    c = uniform_cloud(f"W 1920x1080 p=8um 532nm N={n} z 0.5..0.505", 1920, 1080, 8e-6, 532e-9,
+                      n, 3e-3, 0.5, 0.505, 0.0, 1.0, seed)
+    c.meta["plane_z"] = WRM_PLANE_Z
+    c.meta["plane_n"] = WRM_PLANE_N
+    return c
 
 
 def make_batch(n_frames: int = 64, width: int = 1920, height: int = 1080,

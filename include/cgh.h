@@ -294,6 +294,47 @@ CGH_API cgh_status cgh_fresnel_run(cgh_fresnel *f, const float *u_dev, float *ou
 /* Free the plan (synchronises its device first).  NULL-safe. */
 CGH_API void cgh_fresnel_destroy(cgh_fresnel *f);
 
+/* ---------------------------------------------------------------------
+ * Wavefront-recording method (Section 2.3): a virtual plane between the
+ * points and the hologram first records the object wave (step 1), which
+ * Fresnel diffraction (Eq. (10), step 2) then carries to the hologram.
+ *
+ * The plane is an n x n grid with the context's pitch p, centred like the
+ * hologram, at distance zw from the hologram: sample (m, c) sits at
+ * x_w = (c - (n-1)/2) p, y_w = (m - (n-1)/2) p.  Point j lies
+ * d_j = z_j - zw beyond it; points with d_j <= 0 are not recorded.  Step 1
+ * writes each point's Fresnel wave of Eq. (2) at depth d_j, without the
+ * constant phase 2 pi d_j / lambda (as cgh_compute drops it), only over the
+ * disc of radius r_j = lambda d_j / (2 p) around (x_j, y_j), beyond which the
+ * wave's local frequency exceeds what the grid samples:
+ *   u_w = sum over j with d_j > 0, (x_w - x_j)^2 + (y_w - y_j)^2 <= r_j^2 of
+ *         A_j exp(i pi ((x_w - x_j)^2 + (y_w - y_j)^2) / (lambda d_j)).
+ * The membership test is evaluated in FP64 exactly as written; the phase is
+ * range-reduced in FP64 and the sum accumulated in FP32, in point order.
+ * --------------------------------------------------------------------- */
+
+/* Step 1 for the uploaded cloud: the plane at distance plane_z_m (finite;
+ * metres) into field_dev, a caller-owned device buffer of n*n complex values
+ * (interleaved float pairs, row-major, 8-byte aligned); n a power of two in
+ * [16, 8192] (the plane sizes the diffraction step takes).  Every sample is
+ * written.  Ordered on `stream` like cgh_compute.
+ * Errors: CGH_EINVAL, CGH_ESTATE (no upload), CGH_ENOMEM, CGH_EDEVICE. */
+CGH_API cgh_status cgh_wrm_record(cgh_ctx *c, double plane_z_m, int32_t n, float *field_dev,
+                                  void *stream);
+
+/* The whole method: step 1 on the plane of `plan` (its n, at its distance z
+ * from the hologram) into field_dev (n*n complex, caller-owned, also the
+ * diffraction's in-place buffer), step 2 = cgh_fresnel_run of that field
+ * with `plan`, and the amplitude hologram of Eq. (5) (phi_r = 0, 2 A_r
+ * dropped), Re O over the hologram's W x H window of the n x n result, into
+ * out_dev (height*width floats, row-major).  The plan must have the
+ * context's pitch and wavelength (equal values), z > 0, and n >= width,
+ * height with n - width and n - height even (so the two grids' samples
+ * coincide).  Calls on one plan must not overlap.
+ * Errors: CGH_EINVAL, CGH_ESTATE, CGH_ENOMEM, CGH_EDEVICE. */
+CGH_API cgh_status cgh_wrm_compute(cgh_ctx *c, cgh_fresnel *plan, float *field_dev,
+                                   float *out_dev, void *stream);
+
 /* Free the context and all its device memory (synchronises the device it
  * used first).  NULL-safe. */
 CGH_API void cgh_destroy(cgh_ctx *c);

@@ -45,7 +45,7 @@ MEM_DEVICE = 1
 # every symbol include/cgh.h declares
 EXPORTS = ("cgh_create", "cgh_points_upload", "cgh_compute", "cgh_compute_complex",
            "cgh_kinoform", "cgh_batch_compute", "cgh_compute_noalloc", "cgh_tune",
-           "cgh_fresnel_create",
+           "cgh_fresnel_create", "cgh_wrm_record", "cgh_wrm_compute",
            "cgh_fresnel_run", "cgh_fresnel_destroy", "cgh_destroy", "cgh_strerror",
            "cgh_last_error", "cgh_profile_enable", "cgh_profile_reset", "cgh_profile_read",
            "cgh_version")
@@ -116,6 +116,10 @@ def lib() -> ctypes.CDLL:
     L.cgh_fresnel_run.restype = st
     L.cgh_fresnel_destroy.argtypes = [vp]
     L.cgh_fresnel_destroy.restype = None
+    L.cgh_wrm_record.argtypes = [vp, dbl, i32, vp, vp]
+    L.cgh_wrm_record.restype = st
+    L.cgh_wrm_compute.argtypes = [vp, vp, vp, vp, vp]
+    L.cgh_wrm_compute.restype = st
     _lib = L
     return L
 
@@ -259,6 +263,27 @@ class Context:
                               _stream_handle(stream)), "cgh_tune")
         return buf.value.decode()
 
+    # -- wavefront recording (Section 2.3)
+    def wrm_record(self, plane_z: float, field, stream=None):
+        """Step 1: the cloud recorded on the n x n virtual plane at distance
+        plane_z from the hologram, into `field` (CUDA complex64 [n, n])."""
+        n = _plane_size(field)
+        _on_device(field, self.device, "field")
+        _check(lib().cgh_wrm_record(self._h, float(plane_z), n, field.data_ptr(),
+                                    _stream_handle(stream, [field])), "cgh_wrm_record")
+        return field
+
+    def wrm_compute(self, plan: "FresnelPlan", field, out, stream=None):
+        """Both steps: record on the plan's plane (distance plan.z) into
+        `field`, propagate it with the plan, and write Re O over the
+        hologram's window into `out` ([H, W] float32)."""
+        if _plane_size(field) != plan.n:
+            raise ValueError(f"field must be ({plan.n}, {plan.n})")
+        _on_device(field, self.device, "field")
+        _check(lib().cgh_wrm_compute(self._h, plan._h, field.data_ptr(), self._out_ptr(out, 1),
+                                     _stream_handle(stream, [out])), "cgh_wrm_compute")
+        return out
+
     # -- measurement
     def profile(self, on: bool = True) -> None:
         _check(lib().cgh_profile_enable(self._h, 1 if on else 0), "cgh_profile_enable")
@@ -276,6 +301,14 @@ class Context:
         _check(lib().cgh_profile_read(self._h, names, launches, ms, cap, ctypes.byref(cnt)),
                "cgh_profile_read")
         return {names[i].decode(): (int(launches[i]), float(ms[i])) for i in range(cnt.value)}
+
+
+def _plane_size(field) -> int:
+    import torch
+    if not (_is_torch(field) and field.is_cuda and field.dtype == torch.complex64 and
+            field.is_contiguous() and field.dim() == 2 and field.shape[0] == field.shape[1]):
+        raise TypeError("field must be a contiguous square CUDA complex64 tensor")
+    return int(field.shape[0])
 
 
 class FresnelPlan:

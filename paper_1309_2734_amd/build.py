@@ -26,7 +26,7 @@ MICROBENCH_SRC = os.path.join(HERE, "microbench.hip")
 MICROBENCH = os.path.join(HERE, "cgh_microbench")
 
 SOURCES = ["api.hip", "points.hip", "direct.hip", "spherical.hip", "factors.hip", "gemm.hip",
-           "phase.hip", "fresnel.hip"]
+           "phase.hip", "fresnel.hip", "wrm.hip"]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

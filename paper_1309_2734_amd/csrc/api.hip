@@ -1381,6 +1381,43 @@ void noalloc_plan(const Geo &g, int mode, int64_t *chunk, size_t *partial_cap)
     *partial_cap = 0;
 }
 
+// First step of the wavefront-recording method for the context's cloud: the
+// per-point constants in the constants workspace, then the n x n plane.
+cgh_status wrm_record(cgh_ctx *c, double zw, int n, float2 *field, hipStream_t s)
+{
+    const int64_t np = c->n;
+    const size_t cap = (size_t)std::max<int64_t>(np, 1);
+    void *p = nullptr;
+    CGH_HIP(ensure_ws(c, c->consts, cap * kWrmBytesPerPoint + 8 * 256), "workspace allocation");
+    p = c->consts.p;
+    char *b = (char *)p;
+    auto take = [&](size_t bytes) {
+        char *r = b;
+        b += (bytes + 255) / 256 * 256;
+        return r;
+    };
+    WrmConsts wc;
+    wc.x = (double *)take(cap * sizeof(double));
+    wc.y = (double *)take(cap * sizeof(double));
+    wc.r2 = (double *)take(cap * sizeof(double));
+    wc.beta = (double *)take(cap * sizeof(double));
+    wc.cx = (double *)take(cap * sizeof(double));
+    wc.cy = (double *)take(cap * sizeof(double));
+    wc.amp = (float *)take(cap * sizeof(float));
+    wc.box = (float4 *)take(cap * sizeof(float4));
+    {
+        Bracket br(c, "wrm_consts", s);
+        CGH_HIP(launch_wrm_consts(pts_x(c), pts_y(c), pts_z(c), pts_a(c), np, n, c->pitch,
+                                  c->wavelength, zw, wc, s),
+                "recording constants launch");
+        br.done();
+    }
+    Bracket br(c, "wrm_record", s);
+    CGH_HIP(launch_wrm_record(wc, np, n, c->pitch, field, s), "recording launch");
+    br.done();
+    return CGH_OK;
+}
+
 // Common checks of the single-hologram compute calls.
 cgh_status check_compute(cgh_ctx *c, int mode, const void *out)
 {
@@ -1419,6 +1456,7 @@ int32_t cgh_version(void) { return 10100; }
 struct cgh_fresnel {
     int device = 0;
     int n = 0, m = 0;              // field size, log2 of the padded size 2n
+    double pitch = 0.0, wavelength = 0.0, z = 0.0;
     float2 scale{0.0f, 0.0f};      // exp(i 2 pi z / lambda) / (i lambda z) p^2 / (2n)^2
     DevBuf tw, hc, x, y;
 };
@@ -1449,6 +1487,9 @@ cgh_status cgh_fresnel_create(cgh_fresnel **out, int32_t n, double pitch_m, doub
         return fail(CGH_ENOMEM, "plan allocation");
     f->device = device;
     f->n = n;
+    f->pitch = pitch_m;
+    f->wavelength = wavelength_m;
+    f->z = z_m;
     int m = 0;
     while ((1 << m) < 2 * n)
         ++m;
@@ -1803,6 +1844,73 @@ cgh_status cgh_compute_noalloc(int32_t width, int32_t height, double pitch_m,
     ev.ws = &ws;
     ev.partial_cap = part;
     return ev_one(ev, mode, 0, n, wavelength_m, out_dev, false, chunk, (hipStream_t)stream);
+}
+
+cgh_status cgh_wrm_record(cgh_ctx *c, double plane_z_m, int32_t n, float *field_dev,
+                          void *stream)
+{
+    g_last_error.clear();
+    if (!c)
+        return fail(CGH_EINVAL, "context is NULL");
+    if (!field_dev || (uintptr_t)field_dev % 8 != 0)
+        return fail(CGH_EINVAL, "field must be a non-NULL, 8-byte aligned device buffer");
+    if (!std::isfinite(plane_z_m))
+        return fail(CGH_EINVAL, "plane distance must be finite");
+    if (n < 16 || n > 8192 || (n & (n - 1)) != 0)
+        return fail(CGH_EINVAL, "n must be a power of two in [16, 8192]");
+    if (!c->uploaded)
+        return fail(CGH_ESTATE, "no points uploaded");
+    DeviceGuard g;
+    CGH_HIP(g.set(c->device), "hipSetDevice");
+    hipStream_t s = (hipStream_t)stream;
+    CallOrder order(c, s);
+    CGH_HIP(order.enter(), "stream ordering");
+    return wrm_record(c, plane_z_m, n, (float2 *)field_dev, s);
+}
+
+cgh_status cgh_wrm_compute(cgh_ctx *c, cgh_fresnel *plan, float *field_dev, float *out_dev,
+                           void *stream)
+{
+    g_last_error.clear();
+    if (!c || !plan)
+        return fail(CGH_EINVAL, "context or plan is NULL");
+    if (!field_dev || (uintptr_t)field_dev % 8 != 0)
+        return fail(CGH_EINVAL, "field must be a non-NULL, 8-byte aligned device buffer");
+    if (!out_dev)
+        return fail(CGH_EINVAL, "output is NULL");
+    if (plan->device != c->device)
+        return fail(CGH_EINVAL, "the plan and the context are on different devices");
+    if (plan->pitch != c->pitch || plan->wavelength != c->wavelength)
+        return fail(CGH_EINVAL, "the plan's pitch and wavelength must equal the context's");
+    if (!(plan->z > 0.0))
+        return fail(CGH_EINVAL, "the plan's distance (the virtual plane's) must be > 0");
+    if (plan->n < c->width || plan->n < c->height || (plan->n - c->width) % 2 != 0 ||
+        (plan->n - c->height) % 2 != 0)
+        return fail(CGH_EINVAL, "the plane must hold the hologram centred: n >= width, height, "
+                                "with n - width and n - height even");
+    if (!c->uploaded)
+        return fail(CGH_ESTATE, "no points uploaded");
+    DeviceGuard g;
+    CGH_HIP(g.set(c->device), "hipSetDevice");
+    hipStream_t s = (hipStream_t)stream;
+    CallOrder order(c, s);
+    CGH_HIP(order.enter(), "stream ordering");
+    float2 *field = (float2 *)field_dev;
+    CGH_TRY(wrm_record(c, plan->z, plan->n, field, s));
+    {
+        Bracket br(c, "fresnel_diffraction", s);
+        CGH_HIP(fresnel_run(plan->n, plan->m, (const float2 *)plan->tw.p,
+                            (const float2 *)plan->hc.p, plan->scale, field, field,
+                            (float2 *)plan->x.p, (float2 *)plan->y.p, s),
+                "Fresnel diffraction launch");
+        br.done();
+    }
+    Bracket br(c, "hologram_window", s);
+    CGH_HIP(launch_window_real(field, plan->n, (plan->n - c->width) / 2,
+                               (plan->n - c->height) / 2, c->width, c->height, out_dev, s),
+            "window launch");
+    br.done();
+    return CGH_OK;
 }
 
 cgh_status cgh_tune(cgh_ctx *c, cgh_mode mode, int32_t repeats, char *report, int32_t report_len,

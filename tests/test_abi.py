@@ -86,6 +86,9 @@ def test_null_context_is_rejected_everywhere(L):
     assert L.cgh_fresnel_run(None, ctypes.c_void_p(16), ctypes.c_void_p(16), None) == cgh.EINVAL
     L.cgh_fresnel_destroy(None)
     assert L.cgh_batch_compute(None, f, 1, 0, ctypes.c_void_p(16), None) == cgh.EINVAL
+    assert L.cgh_wrm_record(None, 0.3, 64, ctypes.c_void_p(16), None) == cgh.EINVAL
+    assert L.cgh_wrm_compute(None, None, ctypes.c_void_p(16), ctypes.c_void_p(16),
+                             None) == cgh.EINVAL
     assert L.cgh_profile_enable(None, 1) == cgh.EINVAL
     assert L.cgh_profile_reset(None) == cgh.EINVAL
     cnt = ctypes.c_int32()

@@ -1,0 +1,170 @@
+"""GPU parity of the wavefront-recording method (Section 2.3) against the oracle.
+
+Step 1 (cgh_wrm_record) against the oracle's region-restricted FP64 sum, as
+complex fields: NRMS ||got - ref|| / ||ref|| <= 1e-5 (the FP32 modes' bound;
+every decision of which samples a disc covers is taken in FP64 on both sides
+from the same formula, so it agrees sample by sample).  The whole method
+(cgh_wrm_compute: step 1, Fresnel diffraction, Re O over the hologram window)
+against the oracle's step 1 followed by its FP64 Fourier form of Eq. (10).
+"""
+import numpy as np
+import pytest
+
+import cghgen
+import oracle
+import paper_1309_2734_amd as cgh
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+def say(*a):
+    print("[wrm]", *a, flush=True)
+
+
+def _nrms(got, ref):
+    return float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+
+
+def _cloud(n_pts, n, p, lam, zw, d_lo, d_hi, seed, spread=None):
+    rng = np.random.default_rng(seed)
+    half = (spread if spread is not None else 0.45 * n) * p
+    x = rng.uniform(-half, half, n_pts)
+    y = rng.uniform(-half, half, n_pts)
+    z = zw + rng.uniform(d_lo, d_hi, n_pts)
+    a = rng.uniform(0.0, 1.0, n_pts)
+    return cghgen.Cloud("wrm test", n, n, p, lam, *[v.astype(np.float32) for v in (x, y, z, a)])
+
+
+def _record(c, zw, n, ctx=None):
+    import torch
+    own = ctx is None
+    if own:
+        ctx = cgh.Context(c.width, c.height, c.pitch, c.wavelength)
+        ctx.upload_cloud(c)
+    field = torch.full((n, n), complex(float("nan"), 0.0), dtype=torch.complex64, device="cuda")
+    ctx.wrm_record(zw, field)
+    torch.cuda.synchronize()
+    if own:
+        ctx.close()
+    return field.cpu().numpy().astype(np.complex128)
+
+
+@pytest.mark.parametrize("n,n_pts,d_lo,d_hi,seed", [
+    (16, 5, 0.0005, 0.002, 1),        # one partial tile, discs wider than the plane
+    (64, 40, 0.0005, 0.004, 2),       # discs 2 .. 17 samples, clipped at the edges
+    (128, 300, 0.001, 0.008, 3),      # many overlaps, tiles of 64 x 32
+    (256, 1000, 0.0002, 0.003, 4),    # small discs, many tiles with no point
+])
+def test_record_matches_oracle_full_plane(n, n_pts, d_lo, d_hi, seed):
+    p, lam, zw = 8e-6, 532e-9, 0.3
+    c = _cloud(n_pts, n, p, lam, zw, d_lo, d_hi, seed, spread=0.55 * n)
+    say(f"record n={n} N={n_pts}")
+    ref = oracle.wrm_record(n, p, lam, zw, c.x, c.y, c.z, c.amp)
+    got = _record(c, zw, n)
+    assert np.all(np.isfinite(got))
+    e = _nrms(got, ref)
+    say(f"  nrms {e:.3e}")
+    assert e <= TOL
+    # samples covered by no disc are exact zeros on both sides
+    assert np.array_equal(got == 0, ref == 0)
+
+
+def test_record_skips_points_at_or_before_the_plane_and_outside_it():
+    p, lam, zw, n = 8e-6, 532e-9, 0.3, 64
+    c = _cloud(60, n, p, lam, zw, 0.0005, 0.003, 5)
+    z = c.z.copy()
+    z[::3] = np.float32(zw - 0.001)          # in front of the plane
+    z[1::7] = np.float32(zw)                 # d rounds to at most a few ulps
+    x = c.x.copy()
+    x[2::5] = np.float32(900 * p)            # discs far outside the plane
+    w = cghgen.Cloud("wrm skip", n, n, p, lam, x, c.y, z, c.amp)
+    ref = oracle.wrm_record(n, p, lam, zw, w.x, w.y, w.z, w.amp)
+    got = _record(w, zw, n)
+    assert _nrms(got, ref) <= TOL
+
+
+def test_record_empty_cloud_is_zero():
+    import torch
+    ctx = cgh.Context(64, 64, 8e-6, 532e-9)
+    ctx.upload(*[np.zeros(0, np.float32)] * 4)
+    field = torch.full((64, 64), 3 + 1j, dtype=torch.complex64, device="cuda")
+    ctx.wrm_record(0.3, field)
+    torch.cuda.synchronize()
+    assert torch.count_nonzero(field).item() == 0
+    ctx.close()
+
+
+@pytest.mark.parametrize("n_pts,step", [(1000, 1), (10000, 37), (100000, 331)])
+def test_record_full_size_workload(n_pts, step):
+    """The 1920 x 1080 workload's 2048 x 2048 plane, 10^3 .. 10^5 points, on
+    rows and columns at a stride coprime to the 64 x 32 tiles."""
+    c = cghgen.make_wrm(n_pts)
+    zw, n = cghgen.WRM_PLANE_Z, cghgen.WRM_PLANE_N
+    rows = np.arange(5, n, step) if step > 1 else np.arange(600, 1450)
+    say(f"full-size record N={n_pts}, {len(rows)} rows")
+    ref = oracle.wrm_record(n, c.pitch, c.wavelength, zw, c.x, c.y, c.z, c.amp, rows=rows)
+    got = _record(c, zw, n)
+    e = _nrms(got[rows], ref)
+    say(f"  nrms {e:.3e}")
+    assert e <= TOL
+    a = _record(c, zw, n)
+    assert np.array_equal(a, got)              # bitwise repeatable
+
+
+@pytest.mark.parametrize("w,h,n,zw", [(48, 40, 64, 0.02), (120, 64, 128, 0.05)])
+def test_wrm_compute_matches_oracle_composition(w, h, n, zw):
+    """Step 1, Fresnel diffraction to the hologram, Re O over the centred
+    window, against the oracle's own two steps in FP64."""
+    import torch
+    p, lam = 8e-6, 532e-9
+    c0 = _cloud(200, n, p, lam, zw, 0.0005, 0.003, 6, spread=0.4 * n)
+    c = cghgen.Cloud("wrm compute", w, h, p, lam, c0.x, c0.y, c0.z, c0.amp)
+    u = oracle.wrm_record(n, p, lam, zw, c.x, c.y, c.z, c.amp)
+    o = oracle.diffraction_fft(u, p, lam, zw)
+    oy, ox = (n - h) // 2, (n - w) // 2
+    ref = o[oy:oy + h, ox:ox + w].real
+    ctx = cgh.Context(w, h, p, lam)
+    ctx.upload_cloud(c)
+    plan = cgh.FresnelPlan(n, p, lam, zw)
+    field = torch.empty((n, n), dtype=torch.complex64, device="cuda")
+    out = torch.empty((h, w), device="cuda")
+    ctx.wrm_compute(plan, field, out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().astype(np.float64)
+    e = oracle.nrms(got, ref)
+    say(f"compute {w}x{h} on {n}: nrms {e:.3e}")
+    assert e <= TOL
+    # the field buffer holds the propagated plane
+    eo = _nrms(field.cpu().numpy().astype(np.complex128), o)
+    assert eo <= TOL
+    plan.close()
+    ctx.close()
+
+
+def test_wrm_compute_argument_checks():
+    import torch
+    ctx = cgh.Context(48, 40, 8e-6, 532e-9)
+    ctx.upload(*[np.ones(3, np.float32)] * 4)
+    field = torch.empty((64, 64), dtype=torch.complex64, device="cuda")
+    out = torch.empty((40, 48), device="cuda")
+    for args, bad in (((64, 8e-6, 633e-9, 0.02), "wavelength"), ((64, 4e-6, 532e-9, 0.02), "pitch"),
+                      ((64, 8e-6, 532e-9, -0.02), "distance"), ((32, 8e-6, 532e-9, 0.02), "size")):
+        plan = cgh.FresnelPlan(*args)
+        f = torch.empty((args[0], args[0]), dtype=torch.complex64, device="cuda")
+        with pytest.raises(cgh.CghError) as e:
+            ctx.wrm_compute(plan, f, out)
+        assert e.value.status == cgh.EINVAL, bad
+        plan.close()
+    odd = cgh.Context(47, 40, 8e-6, 532e-9)       # 64 - 47 is odd: grids do not coincide
+    odd.upload(*[np.ones(3, np.float32)] * 4)
+    plan = cgh.FresnelPlan(64, 8e-6, 532e-9, 0.02)
+    with pytest.raises(cgh.CghError) as e:
+        odd.wrm_compute(plan, field, torch.empty((40, 47), device="cuda"))
+    assert e.value.status == cgh.EINVAL
+    with pytest.raises(cgh.CghError) as e:
+        ctx.wrm_record(0.3, torch.empty((48, 48), dtype=torch.complex64, device="cuda"))
+    assert e.value.status == cgh.EINVAL          # not a power of two
+    plan.close()
+    odd.close()
+    ctx.close()
