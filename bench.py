@@ -9,12 +9,21 @@ cgh_compute of the whole cloud in the headline mode (BF16 hi/lo split on the
 matrix cores: per-point constants, factor build, split GEMM, split-K reduce).
 The direct FP32 kernel and the other modes are timed the same way and
 reported under "modes" (spherical_fp32 evaluates the exact spherical wave of
-Eq. (1) instead of the Fresnel sum).  NRMS and max error of every mode are
-measured against the FP64 oracle on the CPU-baseline sample (every 4th row;
-every 16th for the spherical mode, against the oracle's Eq. (1)).  Side
-measurements: the 64-frame batched workload ("batch"), the phase-only
-hologram of Eq. (3) of the bench cloud ("kinoform"), and the Fresnel
+Eq. (1) instead of the Fresnel sum).
+
+Side measurements, each on its own workload: the 64-frame batch ("batch",
+tuned, replayed as a graph), the phase-only hologram of Eq. (3) ("kinoform"),
+the 2048 x 2048 and 4096 x 4096 clouds ("large"), the wavefront-recording
+method at 1920 x 1080 with 10^3 .. 10^5 points ("wrm") and the Fresnel
 diffraction of Eq. (10) at the paper's plane sizes ("fresnel_diffraction").
+
+Every GPU measurement runs first, keeping host copies of its outputs on the
+evaluation sets; the FP64 oracle then runs on the host alone: first the CPU
+baseline (the oracle on every 3rd row of the headline workload, all host
+cores, timed), which is also the reference of every mode's NRMS, then the
+other legs' references -- every 8th row and column of the 2048^2 cloud and
+of all 64 batch frames, the centred 256 x 256 crop of the 4096^2 cloud,
+sampled rows of the recorded planes.
 
 Prints one JSON line (rank 0).  --gpus N > 1 is refused: the benchmark
 measures one GPU.
@@ -53,6 +62,10 @@ def alu_peak_pps(instr_per_pp: int, trans_per_pp: int) -> float:
 
 # direct kernel: v_add_f32_dpp, v_cos_f32, v_fmac_f32 per point*pixel
 PEAK_DIRECT_PPS = alu_peak_pps(3, 1)          # 1.311e13 point*pixel/s
+# The same three instructions with the cosine holding its SIMD for two issue
+# slots (it does not overlap its neighbours in this loop; the kernel's VALU
+# counters then read 95 % busy): 4 slots per point*pixel.
+PEAK_DIRECT_ISSUE_PPS = CUS * CLOCK_HZ * VALU_PER_CLK / 4      # 9.830e12 point*pixel/s
 # exact spherical wave: 2 v_add_f32_dpp, 2 v_add_f32, 2 v_mul_f32, v_fma_f32,
 # v_fmac_f32 and v_sqrt_f32, v_rcp_f32, v_cos_f32 per point*pixel
 PEAK_SPHERE_PPS = alu_peak_pps(11, 3)         # 3.575e12 point*pixel/s
@@ -90,6 +103,9 @@ TRAFFIC = [
 ]
 TRAFFIC_PLANS = {"gemm_split_mfma": ["384,192,4,2,2,8", "192,384,2,4,2,8"],
                  "direct_fp32": ["8", "16"], "fresnel_diffraction": ["8192"]}
+
+# the paper's wavefront-recording times on its K20 (Table 8; context only)
+PAPER_TABLE8_GPU_S = {"1000": 0.029, "10000": 0.030, "100000": 0.035}
 
 
 def _plan_in_tuned(kernel: str, plan: str, tuned) -> bool:
@@ -168,13 +184,113 @@ def measured_clock_mhz(run, sync, seconds: float = 0.5):
             "while the step repeats for ~0.5 s after its timing"}
 
 
-def bench_batch(args, torch, cghgen, cgh, check: bool):
-    """Side measurement: the batched workload -- F holograms of 1920 x 1080,
-    RGB wavelengths cycled, point counts log-uniform in [1e3, 5e4] -- in the
-    FP16 hi/lo split mode through one graph-captured launch sequence on a
-    side stream.  Reports point*pixel/s over all frames and (with the CPU
-    baseline on) the NRMS of two frames against the FP64 oracle on a strided
-    sample."""
+def _events(torch, stream):
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    return e0, e1
+
+
+def _mfma_roofline(flops, t_ms, peak, kname, traffic=None):
+    ach = flops / (t_ms * 1e-3) / 1e12
+    return {"bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s", "frac": ach / peak,
+            "traffic": traffic, "kernel": kname, "kernel_ms": t_ms}
+
+
+def _oracle_rate(pp, dt, threads, sample):
+    return {"value": pp / dt, "unit": "point*pixel/s", "cores": threads, "kind": "oracle",
+            "sample": sample}
+
+
+# ------------------------------------------------------------------ legs
+# Each leg measures on the GPU and returns (result dict, check), where
+# check() runs the oracle on the host afterwards and adds NRMS and max
+# errors to the dict.
+
+def bench_modes(args, torch, cghgen, cgh, modes, rows):
+    """The headline workload in every mode: tuned, warmed up, K timed steps
+    between two synchronisations; per-kernel times from the library's HIP
+    events; the shader clock while the step repeats."""
+    c = cghgen.make_config(2)
+    W, H, N = c.width, c.height, c.n
+    pp = W * H * N
+    ctx = cgh.Context(W, H, c.pitch, c.wavelength, device=0)
+    ctx.upload_cloud(c)
+    out = torch.empty((H, W), dtype=torch.float32, device="cuda:0")
+    stream = torch.cuda.current_stream()
+    results = {}
+    for m in modes:
+        mode = cgh.MODES[m]
+        tuned = None
+        if not args.no_tune:
+            tuned = ctx.tune(mode, repeats=3, stream=stream)
+            log(f"mode {m}: tuned {tuned}")
+        log(f"mode {m}: warmup {args.warmup}")
+        for _ in range(args.warmup):
+            ctx.compute(out, mode, stream)
+        torch.cuda.synchronize()
+        # timed region: K whole steps between two device-wide synchronisations
+        log(f"mode {m}: timing {args.steps} steps")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e0, e1 = _events(torch, stream)
+        for _ in range(args.steps):
+            ctx.compute(out, mode, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        wall_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        ev_ms = e0.elapsed_time(e1) / args.steps
+        # per-kernel durations: HIP events around each launch on the same stream
+        ctx.profile(True)
+        ctx.profile_reset()
+        for _ in range(args.steps):
+            ctx.compute(out, mode, stream)
+        kern = ctx.profile_read()
+        ctx.profile(False)
+        ctx.compute(out, mode, stream)
+        torch.cuda.synchronize()
+        sample = out.cpu().numpy()[rows].astype(np.float64)
+        clock = measured_clock_mhz(lambda: ctx.compute(out, mode, stream), torch.cuda.synchronize)
+        r = {"ms_per_step": wall_ms, "ms_per_step_events": ev_ms, "pp_per_s": pp / (wall_ms * 1e-3),
+             "kernels_ms": {k: v[1] / v[0] for k, v in kern.items()},
+             "kernels_ms_per_step": {k: v[1] / args.steps for k, v in kern.items()},
+             "dtype": MODE_DTYPE[m], "tuned": tuned, "clock_mhz": clock, "_sample": sample}
+        if m in ALU_MODES:
+            kname, peak = ALU_MODES[m]
+            t = r["kernels_ms"].get(kname)
+            if t:
+                ach = pp / (t * 1e-3)
+                r["roofline"] = {"bound": "alu", "achieved": ach, "peak": peak,
+                                 "unit": "point*pixel/s", "frac": ach / peak,
+                                 "traffic": traffic_bytes(kname, tuned),
+                                 "kernel": kname, "kernel_ms": t}
+                if m == "direct_fp32":
+                    r["roofline"]["peak_issue"] = PEAK_DIRECT_ISSUE_PPS
+                    r["roofline"]["frac_issue"] = ach / PEAK_DIRECT_ISSUE_PPS
+        else:
+            kname = GEMM_KERNEL[m]
+            t = r["kernels_ms"].get(kname)
+            if t:
+                r["roofline"] = _mfma_roofline(
+                    FLOP_PER_PP[m] * pp, t, GEMM_PEAK[m], kname,
+                    traffic_bytes(kname, tuned) if m == "split_bf16" else None)
+        if r.get("roofline") and clock:
+            # the same kernel against the peak scaled to the clock it ran at
+            r["roofline"]["frac_at_measured_clock"] = (
+                r["roofline"]["frac"] * CLOCK_HZ / (clock["median"] * 1e6))
+        log(f"mode {m}: {wall_ms:.4f} ms/step, {r['pp_per_s']:.3e} pp/s, kernels {r['kernels_ms']}, "
+            f"clock {clock and round(clock['median'])} MHz")
+        results[m] = r
+    ctx.close()
+    return c, results
+
+
+def bench_batch(args, torch, cghgen, cgh):
+    """The batched workload -- F holograms of 1920 x 1080, RGB wavelengths
+    cycled, point counts log-uniform in [1e3, 5e4] -- in the FP16 hi/lo split
+    mode: tuned for this frame table (cgh_tune_batch), then one
+    graph-captured call replayed on a side stream.  The GEMM roofline is the
+    persistent batch kernel's 12 flop per point*pixel over its time."""
     b = cghgen.make_batch(n_frames=args.batch_frames)
     frames = cgh.batch_frames(b)
     pp = b.point_pixels
@@ -184,41 +300,75 @@ def bench_batch(args, torch, cghgen, cgh, check: bool):
     side = torch.cuda.Stream()
     mode = cgh.SPLIT_FP16
     log(f"batch: {len(frames)} frames, {int(b.counts.sum())} points, {pp:.3e} point*pixels")
+    tuned = None if args.no_tune else ctx.tune_batch(frames, out, mode, repeats=2, stream=side)
+    log(f"batch: tuned {tuned}")
     for _ in range(2):                      # eager run, then capture
         ctx.batch_compute(frames, out, mode, stream=side)
     side.synchronize()
     reps = max(1, min(args.steps, 5))
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(side)
+    e0, e1 = _events(torch, side)
     for _ in range(reps):
         ctx.batch_compute(frames, out, mode, stream=side)
     e1.record(side)
     side.synchronize()
     ms = e0.elapsed_time(e1) / reps
-    rows, cols = np.arange(0, b.height, 16), np.arange(0, b.width, 16)
-    errs = []
-    for f in ((0, len(frames) - 1) if check else ()):
-        import oracle
-        o, n, lam = frames[f]
-        ref = oracle.fresnel(b.width, b.height, b.pitch, lam, b.x[o:o + n], b.y[o:o + n],
-                             b.z[o:o + n], b.amp[o:o + n], cols=cols, rows=rows)
-        got = out[f].cpu().numpy().astype(np.float64)[np.ix_(rows, cols)]
-        errs.append(oracle.nrms(got, ref))
+    # per-kernel times of eager calls (profiling runs the sequence eagerly)
+    ctx.profile(True)
+    ctx.profile_reset()
+    for _ in range(2):
+        ctx.batch_compute(frames, out, mode, stream=side)
+    kern = ctx.profile_read()
+    ctx.profile(False)
+    side.synchronize()
+    kms = {k: v[1] / 2 for k, v in kern.items()}
+    gemm_ms = kms.get("gemm_split_mfma_batch")
+    cols, rows = cghgen.strided_pixels(b.width, b.height, 8)
+    got = out.cpu().numpy()[:, rows][:, :, cols].astype(np.float64)
     ctx.close()
-    log(f"batch: {ms:.3f} ms per batch, {pp / (ms * 1e-3):.3e} pp/s, nrms {errs}")
-    return {"workload": f"{len(frames)} x 1920x1080, RGB 633/532/473 nm, N_f log-uniform "
-                        f"[1e3,5e4] (seeds 400+f), {int(b.counts.sum())} points",
-            "mode": "split_fp16", "ms_per_batch": ms, "pp_per_s": pp / (ms * 1e-3),
-            "launch": "hipGraph replay", "nrms_sampled_frames": errs}
+    del out
+    torch.cuda.empty_cache()
+    log(f"batch: {ms:.3f} ms per batch, {pp / (ms * 1e-3):.3e} pp/s, kernels/batch {kms}")
+    res = {"workload": f"{len(frames)} x 1920x1080, RGB 633/532/473 nm, N_f log-uniform "
+                       f"[1e3,5e4] (seeds 400+f), {int(b.counts.sum())} points",
+           "mode": "split_fp16", "ms_per_batch": ms, "pp_per_s": pp / (ms * 1e-3),
+           "launch": "hipGraph replay", "tuned": tuned, "kernels_ms_per_batch": kms,
+           "roofline": _mfma_roofline(12 * pp, gemm_ms, PEAK_MFMA_FP16_TFLOPS,
+                                      "gemm_split_mfma_batch") if gemm_ms else None}
+
+    def check():
+        import oracle
+        threads = oracle.host_threads()
+        t0 = time.perf_counter()
+        errs, maxes, num, den = [], [], 0.0, 0.0
+        for f, (o, n, lam) in enumerate(frames):
+            ref = oracle.fresnel(b.width, b.height, b.pitch, lam, b.x[o:o + n], b.y[o:o + n],
+                                 b.z[o:o + n], b.amp[o:o + n], cols=cols, rows=rows,
+                                 threads=threads)
+            errs.append(oracle.nrms(got[f], ref))
+            maxes.append(oracle.max_err(got[f], ref))
+            num += float(np.sum((got[f] - ref) ** 2))
+            den += float(np.sum(ref * ref))
+        dt = time.perf_counter() - t0
+        spp = len(rows) * len(cols) * int(b.counts.sum())
+        res["nrms"] = float(np.sqrt(num / den))
+        res["nrms_per_frame_max"] = float(max(errs))
+        res["nrms_per_frame_median"] = float(np.median(errs))
+        res["max_err"] = float(max(maxes))
+        res["cpu_baseline"] = _oracle_rate(
+            spp, dt, threads, f"every 8th row and column ({len(rows)} x {len(cols)}) of all "
+                              f"{len(frames)} frames, each frame's own points: {spp:.3e} "
+                              f"point*pixels in {dt:.1f} s")
+        log(f"batch: nrms {res['nrms']:.3e} (frames max {res['nrms_per_frame_max']:.3e}), "
+            f"oracle {dt:.1f} s")
+    return res, check
 
 
-def bench_kinoform(args, torch, cghgen, cgh, check: bool):
-    """Side measurement: the phase-only hologram of Eq. (3) (the paper's
-    timed workload) of the same 1920 x 1080, 10k-point cloud -- complex
-    field, then the 8-bit phase codes -- in three modes.  With `check`, the
-    codes on every 16th row are compared with the oracle's FP64 field where
-    the device field's error cannot move the phase across a code boundary."""
+def bench_kinoform(args, torch, cghgen, cgh):
+    """The phase-only hologram of Eq. (3) (the paper's timed workload) of the
+    same 1920 x 1080, 10k-point cloud -- complex field, then the 8-bit phase
+    codes -- in three modes.  The codes on every 16th row are then compared
+    with the oracle's FP64 field where the device field's error cannot move
+    the phase across a code boundary."""
     c = cghgen.make_config(2)
     W, H, N = c.width, c.height, c.n
     pp = W * H * N
@@ -228,73 +378,243 @@ def bench_kinoform(args, torch, cghgen, cgh, check: bool):
     codes = torch.empty((H, W), dtype=torch.uint8, device="cuda:0")
     field = torch.empty((2, H, W), device="cuda:0")
     rows = np.arange(0, H, 16)
-    ref = None
-    cpu = None
-    if check:
-        import oracle
-        t0 = time.perf_counter()
-        ref = oracle.fresnel_complex(W, H, c.pitch, c.wavelength, c.x, c.y, c.z, c.amp,
-                                     rows=rows, threads=oracle.host_threads())
-        dt = time.perf_counter() - t0
-        spp = len(rows) * W * N
-        cpu = {"value": spp / dt, "unit": "point*pixel/s", "cores": oracle.host_threads(),
-               "kind": "oracle",
-               "sample": f"complex field (Eq. (2)) of every 16th row ({len(rows)} rows x {W} "
-                         f"columns), all {N} points: {spp:.3e} point*pixels in {dt:.1f} s; "
-                         f"codes taken from it in FP64"}
-    res = {}
+    res, kept = {}, {}
     for m in ("split_bf16", "separable_fp32", "direct_fp32"):
         mode = cgh.MODES[m]
         for _ in range(2):
             ctx.kinoform(codes, mode, stream)
         torch.cuda.synchronize()
         reps = max(1, args.steps)
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
+        e0, e1 = _events(torch, stream)
         for _ in range(reps):
             ctx.kinoform(codes, mode, stream)
         e1.record(stream)
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / reps
-        r = {"ms_per_hologram": ms, "pp_per_s": pp / (ms * 1e-3)}
-        if ref is not None:
-            ctx.compute_complex(field, mode, stream)
-            torch.cuda.synchronize()
-            f = field.cpu().numpy().astype(np.float64)[:, rows]
-            got = codes.cpu().numpy()[rows]
-            import oracle
-            t = np.arctan2(ref[1], ref[0])
-            t = np.where(t < 0, t + 2 * np.pi, t) * 255.0 / (2 * np.pi)
-            mag = np.hypot(ref[0], ref[1])
+        ctx.compute_complex(field, mode, stream)
+        torch.cuda.synchronize()
+        kept[m] = (field.cpu().numpy().astype(np.float64)[:, rows], codes.cpu().numpy()[rows])
+        res[m] = {"ms_per_hologram": ms, "pp_per_s": pp / (ms * 1e-3)}
+        log(f"kinoform {m}: {ms:.4f} ms, {res[m]['pp_per_s']:.3e} pp/s")
+    ctx.close()
+    out = {"workload": "phase-only hologram (Eq. 3) of the 1920x1080, 10000-point cloud: "
+                       "complex field + 8-bit phase codes", "modes": res,
+           "check": "codes on every 16th row vs the FP64 oracle field, where the device "
+                    "field's error cannot cross a code boundary"}
+
+    def check():
+        import oracle
+        t0 = time.perf_counter()
+        ref = oracle.fresnel_complex(W, H, c.pitch, c.wavelength, c.x, c.y, c.z, c.amp,
+                                     rows=rows, threads=oracle.host_threads())
+        dt = time.perf_counter() - t0
+        spp = len(rows) * W * N
+        out["cpu_baseline"] = _oracle_rate(
+            spp, dt, oracle.host_threads(),
+            f"complex field (Eq. (2)) of every 16th row ({len(rows)} rows x {W} columns), all "
+            f"{N} points: {spp:.3e} point*pixels in {dt:.1f} s; codes taken from it in FP32")
+        t = np.arctan2(ref[1], ref[0])
+        t = np.where(t < 0, t + 2 * np.pi, t) * 255.0 / (2 * np.pi)
+        mag = np.hypot(ref[0], ref[1])
+        want = oracle.kinoform(ref[0], ref[1])
+        for m, (f, got) in kept.items():
             e = float(np.max(np.hypot(f[0] - ref[0], f[1] - ref[1])))
             ratio = np.where(mag > 0, e / np.maximum(mag, 1e-300), np.inf)
             margin = np.where(ratio < 0.5, 2 * np.arcsin(np.minimum(ratio, 0.5)) * 255 / (2 * np.pi),
                               np.inf) + 1e-3
             sure = np.abs(t - np.round(t)) > margin
-            want = oracle.kinoform(ref[0], ref[1])
-            r["codes_checked"] = int(np.sum(sure))
-            r["codes_differing"] = int(np.sum(got[sure] != want[sure]))
-            r["codes_differing_any"] = int(np.sum(got != want))
-        log(f"kinoform {m}: {ms:.4f} ms, {r['pp_per_s']:.3e} pp/s {r}")
-        res[m] = r
-    ctx.close()
-    return {"workload": "phase-only hologram (Eq. 3) of the 1920x1080, 10000-point cloud: "
-                        "complex field + 8-bit phase codes", "modes": res,
-            "check": "codes on every 16th row vs the FP64 oracle field, where the device "
-                     "field's error cannot cross a code boundary" if check else None,
-            "cpu_baseline": cpu}
+            res[m]["codes_checked"] = int(np.sum(sure))
+            res[m]["codes_differing"] = int(np.sum(got[sure] != want[sure]))
+            res[m]["codes_differing_any"] = int(np.sum(got != want))
+            log(f"kinoform {m}: {res[m]}")
+    return out, check
 
 
-def bench_fresnel(args, torch, cgh, check: bool):
-    """Side measurement: Fresnel diffraction of a sampled n x n field (Eq. (10),
-    the second step of the wavefront-recording method) at the paper's plane sizes
-    (Table 7: n = 1024 .. 8192), random complex fields, z = 0.05 m, 8 um, 532 nm.
-    Reports ms per diffraction and the effective HBM rate of the pruned pipeline
-    (18 n^2 complex values moved); with `check`, the NRMS of n = 1024 against the
+LARGE_MODES = ("split_bf16", "separable_fp32", "direct_fp32")
+
+
+def _large_set(c, cfg: int):
+    """The workload's evaluation set: every 8th row and column of the 2048^2
+    cloud; the centred 256 x 256 crop (rows and columns 1920 .. 2175) of the
+    4096^2 one."""
+    import cghgen
+    if cfg == 5:
+        return cghgen.crop_pixels(1920, 1920, 256, 256)
+    return cghgen.strided_pixels(c.width, c.height, 8)
+
+
+def bench_large(args, torch, cghgen, cgh):
+    """The two large clouds -- 2048 x 2048 with 65,536 points (8 um, 532 nm)
+    and 4096 x 4096 with 10^6 points on an ellipsoid surface (4 um; evaluated
+    in point chunks that fit the 16 GiB workspace) -- in split BF16, FP32
+    separable and direct FP32, each tuned first.  One step = one cgh_compute
+    of the whole cloud; the GEMM (or direct) kernel's time is the sum of its
+    launches per step.  NRMS and max error against the FP64 oracle on each
+    workload's evaluation set."""
+    res = {}
+    for cfg in (3, 5):
+        c = cghgen.make_config(cfg)
+        W, H, N = c.width, c.height, c.n
+        pp = W * H * N
+        steps = 3 if cfg == 3 else 1
+        ctx = cgh.Context(W, H, c.pitch, c.wavelength, device=0)
+        ctx.upload_cloud(c)
+        out = torch.empty((H, W), dtype=torch.float32, device="cuda:0")
+        stream = torch.cuda.current_stream()
+        cols, rows = _large_set(c, cfg)
+        modes = {}
+        for m in LARGE_MODES:
+            mode = cgh.MODES[m]
+            tuned = ctx.tune(mode, repeats=2, stream=stream) if not args.no_tune else None
+            ctx.compute(out, mode, stream)               # warm-up
+            torch.cuda.synchronize()
+            ctx.profile(True)
+            ctx.profile_reset()
+            e0, e1 = _events(torch, stream)
+            for _ in range(steps):
+                ctx.compute(out, mode, stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            kern = ctx.profile_read()
+            ctx.profile(False)
+            ms = e0.elapsed_time(e1) / steps
+            r = {"ms_per_step": ms, "pp_per_s": pp / (ms * 1e-3), "tuned": tuned,
+                 "kernels_ms_per_step": {k: v[1] / steps for k, v in kern.items()},
+                 "_got": out.cpu().numpy()[np.ix_(rows, cols)].astype(np.float64)}
+            if m in ALU_MODES:
+                kname, peak = ALU_MODES[m]
+                t = r["kernels_ms_per_step"].get(kname)
+                if t:
+                    ach = pp / (t * 1e-3)
+                    r["roofline"] = {"bound": "alu", "achieved": ach, "peak": peak,
+                                     "unit": "point*pixel/s", "frac": ach / peak,
+                                     "peak_issue": PEAK_DIRECT_ISSUE_PPS,
+                                     "frac_issue": ach / PEAK_DIRECT_ISSUE_PPS,
+                                     "kernel": kname, "kernel_ms": t}
+            else:
+                kname = GEMM_KERNEL[m]
+                t = r["kernels_ms_per_step"].get(kname)
+                if t:
+                    r["roofline"] = _mfma_roofline(FLOP_PER_PP[m] * pp, t, GEMM_PEAK[m], kname)
+            log(f"large C{cfg} {m}: {ms:.3f} ms/step, {r['pp_per_s']:.3e} pp/s, "
+                f"frac {r.get('roofline', {}).get('frac')}")
+            modes[m] = r
+        ctx.close()
+        del out
+        torch.cuda.empty_cache()
+        res[f"{W}x{H}_{N}"] = {
+            "workload": (f"{W}x{H} hologram, {N} points, pitch {c.pitch * 1e6:g} um, "
+                         f"{c.wavelength * 1e9:g} nm (seed {cfg})"),
+            "point_pixels_per_step": pp, "steps": steps,
+            "evaluation_set": ("every 8th row and column (256 x 256)" if cfg == 3 else
+                               "centred 256 x 256 crop, rows and columns 1920..2175"),
+            "modes": modes, "_cloud": c, "_set": (cols, rows)}
+
+    def check():
+        import oracle
+        threads = oracle.host_threads()
+        for key, e in res.items():
+            c = e.pop("_cloud")
+            cols, rows = e.pop("_set")
+            t0 = time.perf_counter()
+            ref = oracle.cloud_fresnel(c, cols=cols, rows=rows, threads=threads)
+            dt = time.perf_counter() - t0
+            spp = len(rows) * len(cols) * c.n
+            e["cpu_oracle"] = _oracle_rate(spp, dt, threads,
+                                           f"{e['evaluation_set']}, all {c.n} points: "
+                                           f"{spp:.3e} point*pixels in {dt:.1f} s")
+            for m, r in e["modes"].items():
+                got = r.pop("_got")
+                r["nrms"] = oracle.nrms(got, ref)
+                r["max_err"] = oracle.max_err(got, ref)
+                log(f"large {key} {m}: nrms {r['nrms']:.3e} max {r['max_err']:.3e}")
+    return res, check
+
+
+def bench_wrm(args, torch, cghgen, cgh):
+    """The wavefront-recording method (Section 2.3, Table 8's conditions:
+    1920 x 1080 hologram, 8 um, 10^3 .. 10^5 points): per call, the recording
+    on the 2048 x 2048 virtual plane 5 mm in front of the shallow object
+    (step 1), its Fresnel diffraction to the hologram (step 2) and Re O over
+    the hologram window.  NRMS of the recorded plane against the oracle's
+    step 1 on sampled rows."""
+    zw, n = cghgen.WRM_PLANE_Z, cghgen.WRM_PLANE_N
+    res, kept = {}, {}
+    stream = torch.cuda.current_stream()
+    for npts in (1000, 10000, 100000):
+        c = cghgen.make_wrm(npts)
+        ctx = cgh.Context(c.width, c.height, c.pitch, c.wavelength)
+        ctx.upload_cloud(c)
+        plan = cgh.FresnelPlan(n, c.pitch, c.wavelength, zw)
+        field = torch.empty((n, n), dtype=torch.complex64, device="cuda:0")
+        out = torch.empty((c.height, c.width), device="cuda:0")
+        for _ in range(2):
+            ctx.wrm_compute(plan, field, out, stream)
+        torch.cuda.synchronize()
+        reps = max(3, min(args.steps, 10))
+        e0, e1 = _events(torch, stream)
+        for _ in range(reps):
+            ctx.wrm_compute(plan, field, out, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        ctx.profile(True)
+        ctx.profile_reset()
+        for _ in range(reps):
+            ctx.wrm_compute(plan, field, out, stream)
+        kern = ctx.profile_read()
+        ctx.profile(False)
+        ctx.wrm_record(zw, field, stream)
+        torch.cuda.synchronize()
+        step = 37 if npts < 100000 else 113
+        rows = np.arange(5, n, step)
+        kept[npts] = (c, rows, field.cpu().numpy()[rows].astype(np.complex128))
+        # point*sample pairs inside the discs: sum of pi r_j^2 / p^2
+        d = c.z.astype(np.float64) - zw
+        rad = c.wavelength * d / (2 * c.pitch) / c.pitch
+        pairs = float(np.sum(np.pi * rad * rad))
+        kms = {k: v[1] / v[0] for k, v in kern.items()}
+        rec = kms.get("wrm_record")
+        r = {"ms_per_hologram": ms, "kernels_ms": kms, "disc_pairs": pairs,
+             "record_pairs_per_s": pairs / (rec * 1e-3) if rec else None,
+             "paper_table8_gpu_ms": PAPER_TABLE8_GPU_S[str(npts)] * 1e3}
+        log(f"wrm N={npts}: {ms:.3f} ms per hologram, kernels {kms}")
+        res[str(npts)] = r
+        plan.close()
+        ctx.close()
+        del field, out
+    out_res = {"workload": "wavefront-recording method: 1920x1080 hologram, 8 um, 532 nm, "
+                           "x,y ~ U(+-3 mm), z ~ U[0.5,0.505] m, A ~ U[0,1] (seed 7); virtual "
+                           f"plane {n}x{n} at {zw} m from the hologram (discs 21..42 samples)",
+               "points": res, "paper_hardware": "NVIDIA Tesla K20 (Table 8, context only)"}
+
+    def check():
+        import oracle
+        threads = oracle.host_threads()
+        for npts, (c, rows, got) in kept.items():
+            t0 = time.perf_counter()
+            ref = oracle.wrm_record(n, c.pitch, c.wavelength, zw, c.x, c.y, c.z, c.amp, rows=rows,
+                                    threads=threads)
+            dt = time.perf_counter() - t0
+            e = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+            res[str(npts)]["record_nrms"] = e
+            res[str(npts)]["record_cpu_oracle"] = _oracle_rate(
+                len(rows) * n * npts, dt, threads,
+                f"recorded plane, {len(rows)} rows x {n} samples, all {npts} points (plain loop, "
+                f"no culling) in {dt:.1f} s")
+            log(f"wrm N={npts}: record nrms {e:.3e}")
+    return out_res, check
+
+
+def bench_fresnel(args, torch, cgh):
+    """Fresnel diffraction of a sampled n x n field (Eq. (10), the second step
+    of the wavefront-recording method) at the paper's plane sizes (Table 7:
+    n = 1024 .. 8192), random complex fields, z = 0.05 m, 8 um, 532 nm.
+    Reports ms per diffraction and the effective HBM rate of the pruned
+    pipeline (18 n^2 complex values moved); the NRMS of n = 1024 against the
     oracle's FP64 Fourier form."""
     p, lam, z = 8e-6, 532e-9, 0.05
-    res = {}
+    res, kept = {}, None
     for n in (1024, 2048, 4096, 8192):
         g = torch.Generator(device="cuda:0").manual_seed(n)
         u = torch.randn((n, n), dtype=torch.complex64, device="cuda:0", generator=g)
@@ -305,9 +625,7 @@ def bench_fresnel(args, torch, cgh, check: bool):
             plan.run(u, out, stream)
         torch.cuda.synchronize()
         reps = max(3, min(args.steps, 10))
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
+        e0, e1 = _events(torch, stream)
         for _ in range(reps):
             plan.run(u, out, stream)
         e1.record(stream)
@@ -321,128 +639,31 @@ def bench_fresnel(args, torch, cgh, check: bool):
                           "note": "achieved = the five-kernel pipeline's 18 n^2 x 8 B over the "
                                   "whole diffraction time; traffic = counter-measured HBM "
                                   "bytes of one diffraction (recorded for n = 8192)"}}
-        if check and n == 1024:
-            import oracle
-            uh = u.cpu().numpy().astype(np.complex128)
-            t0 = time.perf_counter()
-            ref = oracle.diffraction_fft(uh, p, lam, z)
-            cpu_s = time.perf_counter() - t0
-            got = out.cpu().numpy().astype(np.complex128)
-            r["nrms"] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
-            r["cpu_baseline"] = {"value": cpu_s * 1e3, "unit": "ms per diffraction", "cores": 1,
-                                 "kind": "oracle",
-                                 "sample": "the whole n = 1024 diffraction, FP64 Fourier form "
-                                           "(numpy FFTs, one thread)"}
+        if n == 1024:
+            kept = (u.cpu().numpy().astype(np.complex128), out.cpu().numpy().astype(np.complex128))
         plan.close()
-        log(f"fresnel n={n}: {ms:.3f} ms {r}")
+        log(f"fresnel n={n}: {ms:.3f} ms")
         res[str(n)] = r
-    return {"workload": "Fresnel diffraction (Eq. 10) of a random complex n x n field, "
-                        "zero-padded FFTs on the 2n grid, 8 um, 532 nm, z = 0.05 m",
-            "n": res,
-            "paper_table7_gpu_s": {"1024": 0.011, "2048": 0.027, "4096": 0.125, "8192": None},
-            "paper_hardware": "NVIDIA Tesla K20, CUFFT (context only)"}
+    out_res = {"workload": "Fresnel diffraction (Eq. 10) of a random complex n x n field, "
+                           "zero-padded FFTs on the 2n grid, 8 um, 532 nm, z = 0.05 m",
+               "n": res,
+               "paper_table7_gpu_s": {"1024": 0.011, "2048": 0.027, "4096": 0.125, "8192": None},
+               "paper_hardware": "NVIDIA Tesla K20, CUFFT (context only)"}
 
-
-LARGE_MODES = ("split_bf16", "separable_fp32", "direct_fp32")
-
-
-def _large_sample(c, cfg: int):
-    """The strided pixel sample the parity tests use at these sizes."""
-    if cfg == 5:
-        return np.arange(7, c.width, 160), np.arange(3, c.height, 160)
-    cols = np.array(sorted(set(range(0, c.width, 64)) | {c.width - 1}))
-    rows = np.array(sorted(set(range(0, c.height, 64)) | {c.height - 1}))
-    return cols, rows
-
-
-def bench_large(args, torch, cghgen, cgh, check: bool):
-    """Side measurement: the two large clouds -- 2048 x 2048 with 65,536
-    points (8 um, 532 nm) and 4096 x 4096 with 10^6 points on an ellipsoid
-    surface (4 um; evaluated in point chunks that fit the 16 GiB workspace)
-    -- in split BF16, FP32 separable and direct FP32, each tuned first.  One
-    step = one cgh_compute of the whole cloud; the GEMM (or direct) kernel's
-    time is the sum of its launches per step.  With the CPU baseline on,
-    NRMS and max error against the FP64 oracle on the strided sample the
-    parity tests use."""
-    res = {}
-    for cfg in (3, 5):
-        c = cghgen.make_config(cfg)
-        W, H, N = c.width, c.height, c.n
-        pp = W * H * N
-        steps = 3 if cfg == 3 else 1
-        ctx = cgh.Context(W, H, c.pitch, c.wavelength, device=0)
-        ctx.upload_cloud(c)
-        out = torch.empty((H, W), dtype=torch.float32, device="cuda:0")
-        stream = torch.cuda.current_stream()
-        cols, rows = _large_sample(c, cfg)
-        ref = None
-        oracle_rate = None
-        if check:
-            import oracle
-            threads = oracle.host_threads()
-            t0 = time.perf_counter()
-            ref = oracle.cloud_fresnel(c, cols=cols, rows=rows, threads=threads)
-            dt = time.perf_counter() - t0
-            spp = len(rows) * len(cols) * N
-            oracle_rate = {"value": spp / dt, "unit": "point*pixel/s", "cores": threads,
-                           "kind": "oracle", "sample": f"{len(rows)} x {len(cols)} strided pixels, "
-                                                       f"all {N} points: {spp:.3e} point*pixels "
-                                                       f"in {dt:.2f} s"}
-            log(f"large C{cfg}: oracle sample {len(rows)}x{len(cols)} in {dt:.1f} s")
-        modes = {}
-        for m in LARGE_MODES:
-            mode = cgh.MODES[m]
-            tuned = ctx.tune(mode, repeats=2, stream=stream) if not args.no_tune else None
-            ctx.compute(out, mode, stream)               # warm-up
-            torch.cuda.synchronize()
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            ctx.profile(True)
-            ctx.profile_reset()
-            e0.record(stream)
-            for _ in range(steps):
-                ctx.compute(out, mode, stream)
-            e1.record(stream)
-            torch.cuda.synchronize()
-            kern = ctx.profile_read()
-            ctx.profile(False)
-            ms = e0.elapsed_time(e1) / steps
-            r = {"ms_per_step": ms, "pp_per_s": pp / (ms * 1e-3), "tuned": tuned,
-                 "kernels_ms_per_step": {k: v[1] / steps for k, v in kern.items()}}
-            if m in ALU_MODES:
-                kname, peak = ALU_MODES[m]
-                t = r["kernels_ms_per_step"].get(kname)
-                if t:
-                    ach = pp / (t * 1e-3)
-                    r["roofline"] = {"bound": "alu", "achieved": ach, "peak": peak,
-                                     "unit": "point*pixel/s", "frac": ach / peak,
-                                     "kernel": kname, "kernel_ms": t}
-            else:
-                kname = GEMM_KERNEL[m]
-                t = r["kernels_ms_per_step"].get(kname)
-                if t:
-                    ach = FLOP_PER_PP[m] * pp / (t * 1e-3) / 1e12
-                    r["roofline"] = {"bound": "mfma", "achieved": ach, "peak": GEMM_PEAK[m],
-                                     "unit": "TFLOP/s", "frac": ach / GEMM_PEAK[m],
-                                     "kernel": kname, "kernel_ms": t}
-            if ref is not None:
-                import oracle
-                got = out.cpu().numpy()[np.ix_(rows, cols)].astype(np.float64)
-                r["nrms"] = oracle.nrms(got, ref)
-                r["max_err"] = oracle.max_err(got, ref)
-            log(f"large C{cfg} {m}: {ms:.3f} ms/step, {r['pp_per_s']:.3e} pp/s, "
-                f"frac {r.get('roofline', {}).get('frac')}, nrms {r.get('nrms')}")
-            modes[m] = r
-        ctx.close()
-        del out
-        torch.cuda.empty_cache()
-        res[f"{W}x{H}_{N}"] = {
-            "workload": (f"{W}x{H} hologram, {N} points, pitch {c.pitch * 1e6:g} um, "
-                         f"{c.wavelength * 1e9:g} nm (seed {cfg})"),
-            "point_pixels_per_step": pp, "steps": steps,
-            "sample": f"{len(rows)} rows x {len(cols)} columns, strided" if check else None,
-            "cpu_oracle": oracle_rate, "modes": modes}
-    return res
+    def check():
+        import oracle
+        uh, got = kept
+        t0 = time.perf_counter()
+        ref = oracle.diffraction_fft(uh, p, lam, z)
+        cpu_s = time.perf_counter() - t0
+        r = res["1024"]
+        r["nrms"] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        r["cpu_baseline"] = {"value": cpu_s * 1e3, "unit": "ms per diffraction", "cores": 1,
+                             "kind": "oracle",
+                             "sample": "the whole n = 1024 diffraction, FP64 Fourier form "
+                                       "(numpy FFTs, one thread)"}
+        log(f"fresnel n=1024: nrms {r['nrms']:.3e}")
+    return out_res, check
 
 
 def traffic_driver(torch, cghgen, cgh) -> int:
@@ -503,7 +724,7 @@ def main() -> int:
                     help="comma list; the first is the headline mode")
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the oracle (profiling runs)")
-    ap.add_argument("--sample-row-step", type=int, default=4)
+    ap.add_argument("--sample-row-step", type=int, default=3)
     ap.add_argument("--no-tune", action="store_true", help="use the default launch shapes")
     ap.add_argument("--no-kinoform", action="store_true",
                     help="skip the phase-only hologram side measurement")
@@ -511,6 +732,8 @@ def main() -> int:
                     help="skip the Fresnel-diffraction side measurement")
     ap.add_argument("--no-large", action="store_true",
                     help="skip the 2048x2048 / 4096x4096 side measurement")
+    ap.add_argument("--no-wrm", action="store_true",
+                    help="skip the wavefront-recording side measurement")
     ap.add_argument("--batch-frames", type=int, default=64,
                     help="frames of the batched-workload side measurement (0 = skip)")
     ap.add_argument("--traffic-driver", action="store_true",
@@ -536,95 +759,26 @@ def main() -> int:
     modes = [m.strip() for m in args.modes.split(",") if m.strip()]
     head = modes[0]
     torch.cuda.set_device(0)
-    c = cghgen.make_config(2)
-    W, H, N = c.width, c.height, c.n
-    pp = W * H * N
-    ctx = cgh.Context(W, H, c.pitch, c.wavelength, device=0)
-    ctx.upload_cloud(c)
-    out = torch.empty((H, W), dtype=torch.float32, device="cuda:0")
-    stream = torch.cuda.current_stream()
+    H = 1080
     rows = np.arange(0, H, args.sample_row_step)
 
-    results = {}
-    for m in modes:
-        mode = cgh.MODES[m]
-        tuned = None
-        if not args.no_tune:
-            tuned = ctx.tune(mode, repeats=3, stream=stream)
-            log(f"mode {m}: tuned {tuned}")
-        log(f"mode {m}: warmup {args.warmup}")
-        for _ in range(args.warmup):
-            ctx.compute(out, mode, stream)
-        torch.cuda.synchronize()
-        # timed region: K whole steps between two device-wide synchronisations
-        log(f"mode {m}: timing {args.steps} steps")
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        e0.record(stream)
-        for _ in range(args.steps):
-            ctx.compute(out, mode, stream)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        wall_ms = (time.perf_counter() - t0) * 1e3 / args.steps
-        ev_ms = e0.elapsed_time(e1) / args.steps
-        # per-kernel durations: HIP events around each launch on the same stream
-        ctx.profile(True)
-        ctx.profile_reset()
-        for _ in range(args.steps):
-            ctx.compute(out, mode, stream)
-        kern = ctx.profile_read()
-        ctx.profile(False)
-        ctx.compute(out, mode, stream)
-        torch.cuda.synchronize()
-        sample = out.cpu().numpy()[rows].astype(np.float64)
-        clock = measured_clock_mhz(lambda: ctx.compute(out, mode, stream), torch.cuda.synchronize)
-        r = {"ms_per_step": wall_ms, "ms_per_step_events": ev_ms, "pp_per_s": pp / (wall_ms * 1e-3),
-             "kernels_ms": {k: v[1] / v[0] for k, v in kern.items()}, "sample": sample,
-             "dtype": MODE_DTYPE[m], "tuned": tuned, "clock_mhz": clock}
-        if m in ALU_MODES:
-            kname, peak = ALU_MODES[m]
-            t = r["kernels_ms"].get(kname)
-            if t:
-                ach = pp / (t * 1e-3)
-                r["roofline"] = {"bound": "alu", "achieved": ach, "peak": peak,
-                                 "unit": "point*pixel/s", "frac": ach / peak,
-                                 "traffic": traffic_bytes(kname, tuned),
-                                 "kernel": kname, "kernel_ms": t}
-        else:
-            kname = GEMM_KERNEL[m]
-            t = r["kernels_ms"].get(kname)
-            if t:
-                flops = FLOP_PER_PP[m] * pp
-                ach = flops / (t * 1e-3) / 1e12
-                peak = GEMM_PEAK[m]
-                r["roofline"] = {"bound": "mfma", "achieved": ach, "peak": peak,
-                                 "unit": "TFLOP/s", "frac": ach / peak,
-                                 "traffic": traffic_bytes(kname, tuned) if m == "split_bf16"
-                                 else None, "kernel": kname, "kernel_ms": t}
-        if r.get("roofline") and clock:
-            # the same kernel against the peak scaled to the clock it ran at
-            r["roofline"]["frac_at_measured_clock"] = (
-                r["roofline"]["frac"] * CLOCK_HZ / (clock["median"] * 1e6))
-        log(f"mode {m}: {wall_ms:.4f} ms/step, {r['pp_per_s']:.3e} pp/s, kernels {r['kernels_ms']}, "
-            f"clock {clock and round(clock['median'])} MHz")
-        results[m] = r
-    ctx.close()
-
-    batch = None
+    # ---- GPU phase
+    c, results = bench_modes(args, torch, cghgen, cgh, modes, rows)
+    W, H, N = c.width, c.height, c.n
+    pp = W * H * N
+    legs = {}
     if args.batch_frames > 0:
-        batch = bench_batch(args, torch, cghgen, cgh, check=not args.no_cpu_baseline)
-    kino = None
+        legs["batch"] = bench_batch(args, torch, cghgen, cgh)
     if not args.no_kinoform:
-        kino = bench_kinoform(args, torch, cghgen, cgh, check=not args.no_cpu_baseline)
-    large = None
+        legs["kinoform"] = bench_kinoform(args, torch, cghgen, cgh)
     if not args.no_large:
-        large = bench_large(args, torch, cghgen, cgh, check=not args.no_cpu_baseline)
-    fres = None
+        legs["large"] = bench_large(args, torch, cghgen, cgh)
+    if not args.no_wrm:
+        legs["wrm"] = bench_wrm(args, torch, cghgen, cgh)
     if not args.no_fresnel:
-        fres = bench_fresnel(args, torch, cgh, check=not args.no_cpu_baseline)
+        legs["fresnel_diffraction"] = bench_fresnel(args, torch, cgh)
 
+    # ---- host phase: the oracle alone on the host cores
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -634,11 +788,10 @@ def main() -> int:
         ref = oracle.cloud_fresnel(c, rows=rows, threads=threads)
         dt = time.perf_counter() - t0
         sample_pp = len(rows) * W * N
-        cpu = {"value": sample_pp / dt, "unit": "point*pixel/s", "cores": threads,
-               "kind": "oracle",
-               "sample": f"every {args.sample_row_step}th row ({len(rows)} rows x {W} columns) "
-                         f"of the {W}x{H} hologram, all {N} points: {sample_pp:.3e} "
-                         f"point*pixels in {dt:.1f} s (FP64, libm cos)"}
+        cpu = _oracle_rate(sample_pp, dt, threads,
+                           f"every {args.sample_row_step}-th row ({len(rows)} rows x {W} columns) "
+                           f"of the {W}x{H} hologram, all {N} points: {sample_pp:.3e} "
+                           f"point*pixels in {dt:.1f} s (FP64, libm cos)")
         # the same oracle on one core, on the small 256 x 256, 128-point cloud
         c1 = cghgen.make_config(1)
         t0 = time.perf_counter()
@@ -649,29 +802,38 @@ def main() -> int:
                            "sample": f"full {c1.width}x{c1.height} grid, {c1.n} points: "
                                      f"{pp1:.3e} point*pixels in {dt1:.3f} s"}
         log(f"oracle on one core, 256x256 x 128: {pp1 / dt1:.3e} pp/s")
-        import oracle as orc
-        sph_ref = None
         for m, r in results.items():
             if m == "spherical_fp32":
                 # Eq. (1) has its own reference: every 4th sample row
                 srows = rows[::4]
                 t0 = time.perf_counter()
-                sph_ref = orc.spherical_complex(W, H, c.pitch, c.wavelength, c.x, c.y, c.z,
-                                                c.amp, rows=srows, threads=threads)[0]
+                sph = oracle.spherical_complex(W, H, c.pitch, c.wavelength, c.x, c.y, c.z, c.amp,
+                                               rows=srows, threads=threads)[0]
                 dt = time.perf_counter() - t0
                 spp = len(srows) * W * N
-                r["cpu_baseline"] = {"value": spp / dt, "unit": "point*pixel/s", "cores": threads,
-                                     "kind": "oracle",
-                                     "sample": f"Eq. (1) with its imaginary part, every "
-                                               f"{4 * args.sample_row_step}th row ({len(srows)} "
-                                               f"rows x {W} columns), all {N} points: "
-                                               f"{spp:.3e} point*pixels in {dt:.1f} s"}
-                got, want = r["sample"][::4], sph_ref
+                r["cpu_baseline"] = _oracle_rate(
+                    spp, dt, threads, f"Eq. (1) with its imaginary part, every "
+                                      f"{4 * args.sample_row_step}-th row ({len(srows)} rows x "
+                                      f"{W} columns), all {N} points: {spp:.3e} point*pixels in "
+                                      f"{dt:.1f} s")
+                got, want = r["_sample"][::4], sph
             else:
-                got, want = r["sample"], ref
-            r["nrms"] = orc.nrms(got, want)
-            r["max_err"] = orc.max_err(got, want)
+                got, want = r["_sample"], ref
+            r["nrms"] = oracle.nrms(got, want)
+            r["max_err"] = oracle.max_err(got, want)
             log(f"mode {m}: nrms {r['nrms']:.3e} max {r['max_err']:.3e}")
+        for name, (res, check) in legs.items():
+            log(f"oracle for {name}")
+            check()
+    for r in results.values():
+        r.pop("_sample", None)
+    for name in ("large",):
+        if name in legs:
+            for e in legs[name][0].values():
+                e.pop("_cloud", None)
+                e.pop("_set", None)
+                for r in e["modes"].values():
+                    r.pop("_got", None)
 
     h = results[head]
     line = {
@@ -690,14 +852,15 @@ def main() -> int:
         "config": {"workload": "1920x1080 hologram, 10000 points, pitch 8 um, 532 nm, "
                                "x,y ~ U(+-3 mm), z ~ U[0.5,0.6] m, A ~ U[0,1] (seed 2)",
                    "mode": head, "point_pixels_per_step": pp},
+        "nrms": h.get("nrms"),
+        "max_err": h.get("max_err"),
+        "nrms_set": f"every {args.sample_row_step}-th row of the hologram vs the FP64 oracle",
         "roofline": h.get("roofline"),
         "cpu_baseline": cpu,
-        "modes": {m: {k: v for k, v in r.items() if k != "sample"} for m, r in results.items()},
-        "batch": batch,
-        "kinoform": kino,
-        "fresnel_diffraction": fres,
-        "large": large,
+        "modes": results,
     }
+    for name, (res, _) in legs.items():
+        line[name] = res
     print(json.dumps(line), flush=True)
     return 0
 

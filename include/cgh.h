@@ -257,6 +257,21 @@ CGH_API cgh_status cgh_compute_noalloc(int32_t width, int32_t height, double pit
 CGH_API cgh_status cgh_tune(cgh_ctx *c, cgh_mode mode, int32_t repeats, char *report,
                             int32_t report_len, void *stream);
 
+/* Autotune the persistent batched launch of cgh_batch_compute for this
+ * frame table and mode: times `repeats` whole batch calls (after one
+ * warm-up) per candidate -- every built GEMM tile shape in the matrix-core
+ * modes, 4, 8 or 16 rows per lane in the direct modes -- writing into out_dev
+ * (as cgh_batch_compute would), and keeps the fastest for later batch calls
+ * of this hologram size and mode whose largest frame falls in the same
+ * power-of-two K bucket (appended to CGH_TUNE_CACHE as cgh_tune does).
+ * Drops any captured batch graph.  Blocks the host until the timing ends.
+ * Arguments as cgh_batch_compute, plus repeats in [1, 1000] and the report
+ * buffer as cgh_tune.  Errors as cgh_tune (CGH_ENOTSUP: a direct-mode batch
+ * whose tables exceed the workspace budget). */
+CGH_API cgh_status cgh_tune_batch(cgh_ctx *c, const cgh_frame *frames, int32_t n_frames,
+                                  cgh_mode mode, float *out_dev, int32_t repeats, char *report,
+                                  int32_t report_len, void *stream);
+
 /* ---------------------------------------------------------------------
  * Fresnel diffraction of a sampled field (Section 2.3, Eq. (10)): the second
  * step of the wavefront-recording method, a field u on an n x n grid of pitch

@@ -45,6 +45,7 @@ MEM_DEVICE = 1
 # every symbol include/cgh.h declares
 EXPORTS = ("cgh_create", "cgh_points_upload", "cgh_compute", "cgh_compute_complex",
            "cgh_kinoform", "cgh_batch_compute", "cgh_compute_noalloc", "cgh_tune",
+           "cgh_tune_batch",
            "cgh_fresnel_create", "cgh_wrm_record", "cgh_wrm_compute",
            "cgh_fresnel_run", "cgh_fresnel_destroy", "cgh_destroy", "cgh_strerror",
            "cgh_last_error", "cgh_profile_enable", "cgh_profile_reset", "cgh_profile_read",
@@ -94,6 +95,9 @@ def lib() -> ctypes.CDLL:
                                       i32, vp]
     L.cgh_compute_noalloc.restype = st
     L.cgh_tune.argtypes = [vp, ctypes.c_int, i32, ctypes.c_char_p, i32, vp]
+    L.cgh_tune_batch.argtypes = [vp, ctypes.POINTER(Frame), i32, ctypes.c_int, vp, i32,
+                                 ctypes.c_char_p, i32, vp]
+    L.cgh_tune_batch.restype = st
     L.cgh_tune.restype = st
     L.cgh_destroy.argtypes = [vp]
     L.cgh_destroy.restype = None
@@ -261,6 +265,20 @@ class Context:
         buf = ctypes.create_string_buffer(512)
         _check(lib().cgh_tune(self._h, int(mode), int(repeats), buf, 512,
                               _stream_handle(stream)), "cgh_tune")
+        return buf.value.decode()
+
+    def tune_batch(self, frames: Sequence[Tuple[int, int, float]], out, mode: int,
+                   repeats: int = 3, stream=None) -> str:
+        """Autotune the batched launch of `mode` for these frames
+        (cgh_tune_batch; writes into `out` [F, H, W]); returns the report."""
+        F = len(frames)
+        arr = (Frame * max(F, 1))()
+        for i, (o, c, lam) in enumerate(frames):
+            arr[i] = Frame(int(o), int(c), float(lam))
+        buf = ctypes.create_string_buffer(512)
+        _check(lib().cgh_tune_batch(self._h, arr, F, int(mode), self._out_ptr(out, F),
+                                    int(repeats), buf, 512, _stream_handle(stream, [out])),
+               "cgh_tune_batch")
         return buf.value.decode()
 
     # -- wavefront recording (Section 2.3)

@@ -551,6 +551,14 @@ const TuneEntry *find_tuned(const cgh_ctx *c, const std::string &key)
     return nullptr;
 }
 
+// Key of a batch's tuned launch: hologram size, mode and the K bucket of its
+// largest frame.
+std::string batch_tune_key(const cgh_ctx *c, int mode, int64_t max_kblocks)
+{
+    return c->arch + "/" + std::to_string(c->width) + "x" + std::to_string(c->height) + "/mode" +
+           std::to_string(mode) + "/batch/kb" + std::to_string(kblock_bucket(max_kblocks));
+}
+
 // Tile shape and split count for an M x N output over `slots` points.
 // CGH_GEMM_PLAN="bm,bn,waves_m,waves_n,stages,splits" overrides the choice
 // (used to sweep shapes; an unsupported shape is ignored, splits 0 = auto).
@@ -661,6 +669,7 @@ struct Eval {
     const float *x = nullptr, *y = nullptr, *z = nullptr, *a = nullptr;
     Ws *ws = nullptr;
     size_t partial_cap = SIZE_MAX;   // bytes of split partials allowed
+    int rows = 0;             // direct rows per lane chosen by the caller (0: own choice)
     PointConsts pc{};         // set by ev_consts
     float *tu = nullptr, *tv = nullptr, *tx = nullptr, *ty = nullptr;   // set by ev_tables
 };
@@ -753,6 +762,8 @@ hipError_t launch_direct_mode(const Eval &ev, int mode, const FrameList &frames,
 // sweep), else the tuned choice, else the default.
 int direct_rows(const Eval &ev, int mode)
 {
+    if (ev.rows && direct_rows_ok(mode, ev.rows))
+        return ev.rows;
     const TuneEntry *t = ev.c ? find_tuned(ev.c, tune_key(ev.c, mode, 0, ev.g.height)) : nullptr;
     int rows = t && direct_rows_ok(mode, t->rows) ? t->rows
                                                    : (mode == CGH_SPHERICAL_FP32 ? 8 : 16);
@@ -967,7 +978,7 @@ cgh_status eval_ctx(cgh_ctx *c, int mode, float *out, bool cplx, hipStream_t s)
 // constants and tables side by side, the direct kernel's grid covering every
 // frame (largest first, so the longest workgroups start first).
 cgh_status eval_batch_direct(cgh_ctx *c, int mode, const cgh_frame *frames, int n_frames,
-                             float *out, hipStream_t s)
+                             float *out, hipStream_t s, const TuneEntry *force = nullptr)
 {
     const int64_t plane = (int64_t)c->width * c->height;
     std::vector<int> order(n_frames);
@@ -993,6 +1004,10 @@ cgh_status eval_batch_direct(cgh_ctx *c, int mode, const cgh_frame *frames, int 
                          "frame table upload"));
     CtxWs ws(c);
     Eval ev = ctx_eval(c, &ws);
+    const TuneEntry *t =
+        force ? force : find_tuned(c, batch_tune_key(c, mode, round_up(max_count, kSlotAlign)));
+    if (t)
+        ev.rows = t->rows;
     const int64_t slots = std::max<int64_t>(slot, kSlotAlign);
     SegList sl{};
     sl.dev = (const Segment *)c->bsegs.p;
@@ -1007,17 +1022,20 @@ cgh_status eval_batch_direct(cgh_ctx *c, int mode, const cgh_frame *frames, int 
 // one factor launch (all frames side by side along K) and one persistent
 // GEMM launch over (frame, tile) items, largest K first.
 cgh_status eval_batch_gemm(cgh_ctx *c, int mode, const cgh_frame *frames, int n_frames,
-                           float *out, hipStream_t s)
+                           float *out, hipStream_t s, const TuneEntry *force = nullptr)
 {
     const ModeInfo mi = mode_info(mode);
     const int64_t plane = (int64_t)c->width * c->height;
-    // tile shape: the tuned (or default) shape for the largest frame
+    // tile shape: the batch's tuned shape, else the single-hologram tuned (or
+    // default) shape of its largest frame
     int64_t max_count = 0;
     for (int f = 0; f < n_frames; ++f)
         max_count = std::max(max_count, frames[f].point_count);
     const int64_t max_slots = std::max<int64_t>(round_up(max_count, kSlotAlign), kSlotAlign);
-    Plan p = plan_gemm(c->height, c->width, max_slots, mi,
-                       find_tuned(c, tune_key(c, mode, max_slots / mi.kbp, c->height)));
+    const TuneEntry *t = force ? force : find_tuned(c, batch_tune_key(c, mode, max_slots / mi.kbp));
+    if (!t)
+        t = find_tuned(c, tune_key(c, mode, max_slots / mi.kbp, c->height));
+    Plan p = plan_gemm(c->height, c->width, max_slots, mi, t);
     const size_t per_slot = (size_t)(p.g.mblocks + p.g.nblocks) * kFragLines * mi.line_bytes();
     const int64_t budget = std::max<int64_t>(
         (int64_t)workspace_budget() / (int64_t)per_slot / kSlotAlign * kSlotAlign, kSlotAlign);
@@ -1139,7 +1157,7 @@ cgh_status eval_batch_gemm(cgh_ctx *c, int mode, const cgh_frame *frames, int n_
 
 // The kernel sequence of one batch call, without graph handling.
 cgh_status batch_sequence(cgh_ctx *c, const cgh_frame *frames, int n_frames, int mode, float *out,
-                          hipStream_t s)
+                          hipStream_t s, const TuneEntry *force = nullptr)
 {
     const int64_t plane = (int64_t)c->width * c->height;
     if (is_direct(mode)) {
@@ -1147,7 +1165,7 @@ cgh_status batch_sequence(cgh_ctx *c, const cgh_frame *frames, int n_frames, int
         for (int f = 0; f < n_frames; ++f)
             total += round_up(frames[f].point_count, kSlotAlign);
         if (total <= chunk_slots(ctx_geo(c), mode))
-            return eval_batch_direct(c, mode, frames, n_frames, out, s);
+            return eval_batch_direct(c, mode, frames, n_frames, out, s, force);
         CtxWs ws(c);
         Eval ev = ctx_eval(c, &ws);
         const int64_t chunk = chunk_slots(ev.g, mode);
@@ -1156,7 +1174,7 @@ cgh_status batch_sequence(cgh_ctx *c, const cgh_frame *frames, int n_frames, int
                            frames[f].wavelength, out + f * plane, false, chunk, s));
         return CGH_OK;
     }
-    return eval_batch_gemm(c, mode, frames, n_frames, out, s);
+    return eval_batch_gemm(c, mode, frames, n_frames, out, s, force);
 }
 
 bool same_frames(const std::vector<cgh_frame> &a, const cgh_frame *b, int n)
@@ -1910,6 +1928,111 @@ cgh_status cgh_wrm_compute(cgh_ctx *c, cgh_fresnel *plan, float *field_dev, floa
                                (plan->n - c->height) / 2, c->width, c->height, out_dev, s),
             "window launch");
     br.done();
+    return CGH_OK;
+}
+
+cgh_status cgh_tune_batch(cgh_ctx *c, const cgh_frame *frames, int32_t n_frames, cgh_mode mode,
+                          float *out_dev, int32_t repeats, char *report, int32_t report_len,
+                          void *stream)
+{
+    g_last_error.clear();
+    if (!c)
+        return fail(CGH_EINVAL, "context is NULL");
+    if (!frames || n_frames < 1 || n_frames > 65535)
+        return fail(CGH_EINVAL, "frames must be non-NULL with n_frames in [1, 65535]");
+    if (!out_dev)
+        return fail(CGH_EINVAL, "output is NULL");
+    CGH_TRY(check_mode(mode));
+    if (repeats < 1 || repeats > 1000)
+        return fail(CGH_EINVAL, "repeats must be in [1, 1000]");
+    if (report_len < 0 || (report_len > 0 && !report))
+        return fail(CGH_EINVAL, "bad report buffer");
+    if (!c->uploaded)
+        return fail(CGH_ESTATE, "no points uploaded");
+    int64_t max_count = 0, total = 0;
+    for (int f = 0; f < n_frames; ++f) {
+        const cgh_frame &fr = frames[f];
+        if (fr.point_offset < 0 || fr.point_count < 0 || fr.point_offset > c->n ||
+            fr.point_count > c->n - fr.point_offset)
+            return fail(CGH_EINVAL, "frame " + std::to_string(f) + " is outside the upload");
+        if (!finite_pos(fr.wavelength))
+            return fail(CGH_EINVAL, "frame " + std::to_string(f) + " has a bad wavelength");
+        max_count = std::max(max_count, fr.point_count);
+        total += round_up(fr.point_count, kSlotAlign);
+    }
+    DeviceGuard g;
+    CGH_HIP(g.set(c->device), "hipSetDevice");
+    hipStream_t s = (hipStream_t)stream;
+    if (capturing(s))
+        return fail(CGH_ESTATE, "the stream is capturing");
+    CallOrder order(c, s);
+    CGH_HIP(order.enter(), "stream ordering");
+    drop_graph(c);
+    const int64_t max_slots = round_up(std::max<int64_t>(max_count, 1), kSlotAlign);
+    TuneEntry best;
+    int tried = 0;
+    auto try_one = [&](const TuneEntry &cand) -> cgh_status {
+        double us = 0;
+        cgh_status bst = CGH_OK;
+        std::string msg;
+        const cgh_status tst = time_launches(
+            [&] {
+                bst = batch_sequence(c, frames, n_frames, (int)mode, out_dev, s, &cand);
+                if (bst == CGH_OK)
+                    return hipSuccess;
+                msg = g_last_error;
+                return hipErrorLaunchFailure;
+            },
+            repeats, s, &us);
+        if (bst != CGH_OK)
+            return fail(bst, msg);
+        if (tst != CGH_OK)
+            return tst;
+        ++tried;
+        if (tried == 1 || us < best.us) {
+            best = cand;
+            best.us = us;
+        }
+        return CGH_OK;
+    };
+    if (is_direct(mode)) {
+        if (total > chunk_slots(ctx_geo(c), mode))
+            return fail(CGH_ENOTSUP, "the batch's tables exceed the workspace budget");
+        best.key = batch_tune_key(c, mode, max_slots);
+        for (int rows : {4, 8, 16}) {
+            if (!direct_rows_ok(mode, rows))
+                continue;
+            TuneEntry cand;
+            cand.key = best.key;
+            cand.rows = rows;
+            CGH_TRY(try_one(cand));
+        }
+    } else {
+        const ModeInfo mi = mode_info(mode);
+        const std::string key = batch_tune_key(c, mode, max_slots / mi.kbp);
+        for (auto &sh : kShapes) {
+            if (!gemm_tile_supported(sh[0], sh[1], sh[2], sh[3], sh[4]))
+                continue;
+            TuneEntry cand;
+            cand.key = key;
+            cand.bm = sh[0];
+            cand.bn = sh[1];
+            cand.wm = sh[2];
+            cand.wn = sh[3];
+            cand.stages = sh[4];
+            CGH_TRY(try_one(cand));
+        }
+    }
+    if (tried == 0)
+        return fail(CGH_ENOTSUP, "no launch shape fits this batch");
+    put_tuned(c, best);
+    append_tune_cache(best);
+    if (report_len > 0)
+        std::snprintf(report, (size_t)report_len,
+                      "%s: bm=%d bn=%d waves=%dx%d stages=%d rows=%d %.1f us per batch "
+                      "(%d candidates)",
+                      best.key.c_str(), best.bm, best.bn, best.wm, best.wn, best.stages,
+                      best.rows, best.us, tried);
     return CGH_OK;
 }
 

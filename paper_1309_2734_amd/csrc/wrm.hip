@@ -116,10 +116,13 @@ __global__ __launch_bounds__(256) void k_wrm_record(WrmConsts wc, int64_t n_poin
 #pragma unroll 1
         for (int w = 0; w < kWaves; ++w) {
             // the same mask in every lane: made scalar, so the loop and the
-            // point loads below are scalar too
+            // point loads below are scalar too (readfirstlane returns int:
+            // each half goes through uint32_t so the low one is not
+            // sign-extended into the high bits)
             const uint64_t hw = hits[w];
-            uint64_t mm = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(hw >> 32)) << 32) |
-                          (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)hw);
+            const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)hw);
+            const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(hw >> 32));
+            uint64_t mm = ((uint64_t)hi << 32) | (uint64_t)lo;
             while (mm) {
                 const int bit = __builtin_ctzll(mm);
                 mm &= mm - 1;

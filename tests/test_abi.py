@@ -83,6 +83,7 @@ def test_null_context_is_rejected_everywhere(L):
     assert L.cgh_compute_complex(None, 0, ctypes.c_void_p(16), None) == cgh.EINVAL
     assert L.cgh_kinoform(None, 0, ctypes.c_void_p(16), None) == cgh.EINVAL
     assert L.cgh_tune(None, 0, 1, None, 0, None) == cgh.EINVAL
+    assert L.cgh_tune_batch(None, f, 1, 0, ctypes.c_void_p(16), 1, None, 0, None) == cgh.EINVAL
     assert L.cgh_fresnel_run(None, ctypes.c_void_p(16), ctypes.c_void_p(16), None) == cgh.EINVAL
     L.cgh_fresnel_destroy(None)
     assert L.cgh_batch_compute(None, f, 1, 0, ctypes.c_void_p(16), None) == cgh.EINVAL

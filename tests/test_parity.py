@@ -444,6 +444,50 @@ def test_batch_graph_replays_match_eager(mode):
     octx.close()
 
 
+@pytest.mark.parametrize("mode", (cgh.SPLIT_FP16, cgh.FP16, cgh.DIRECT_FP32),
+                         ids=["split_fp16", "fp16", "direct_fp32"])
+def test_tune_batch_then_batch_matches_oracle(mode, tmp_path, monkeypatch):
+    """cgh_tune_batch times every candidate launch of the batch, keeps the
+    fastest under the batch's key (also in the cache file, which a new
+    context reads back), and later batch calls -- eager and graph replays --
+    use it and still match the oracle frame by frame."""
+    import torch
+    cache = tmp_path / "tune.jsonl"
+    monkeypatch.setenv("CGH_TUNE_CACHE", str(cache))
+    b = _batch_case()
+    frames = cgh.batch_frames(b)
+    ctx = cgh.Context(b.width, b.height, b.pitch, 532e-9)
+    ctx.upload_cloud(b)
+    out = torch.empty((len(frames), b.height, b.width), device="cuda")
+    rep = ctx.tune_batch(frames, out, mode, repeats=1)
+    say(f"tune batch {NAMES[mode]}: {rep}")
+    assert "/batch/" in rep and "(0 candidates)" not in rep
+    assert "/batch/" in cache.read_text()
+    side = torch.cuda.Stream()
+    for rep_i in range(3):                        # eager, captured, replayed
+        out.fill_(-1.0)
+        torch.cuda.synchronize()
+        ctx.batch_compute(frames, out, mode, stream=side)
+        side.synchronize()
+        got = out.cpu().numpy().astype(np.float64)
+        for f, (o, n, lam) in enumerate(frames):
+            if n == 0:
+                assert np.all(got[f] == 0.0)
+                continue
+            sl = slice(o, o + n)
+            ref = oracle.fresnel(b.width, b.height, b.pitch, lam, b.x[sl], b.y[sl], b.z[sl],
+                                 b.amp[sl])
+            check(f"tuned batch frame {f} (call {rep_i})", got[f], ref, mode)
+    ctx2 = cgh.Context(b.width, b.height, b.pitch, 532e-9)
+    ctx2.upload_cloud(b)
+    out2 = torch.empty_like(out)
+    ctx2.batch_compute(frames, out2, mode)
+    torch.cuda.synchronize()
+    assert torch.equal(out2, out)                 # the cached choice, the same numbers
+    ctx.close()
+    ctx2.close()
+
+
 @pytest.mark.parametrize("mode", (cgh.SPLIT_FP16, cgh.SPLIT_BF16, cgh.DIRECT_FP32,
                                   cgh.SEPARABLE_FP32),
                          ids=["split_fp16", "split_bf16", "direct_fp32", "separable_fp32"])

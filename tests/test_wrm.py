@@ -112,6 +112,34 @@ def test_record_full_size_workload(n_pts, step):
     assert np.array_equal(a, got)              # bitwise repeatable
 
 
+@pytest.mark.parametrize("n_small", [1000, 992, 999, 1017])
+def test_record_after_a_larger_cloud_on_the_same_context(n_small):
+    """Regression: a smaller cloud recorded on a context whose workspace
+    still holds a larger cloud's constants.  Point counts whose last group of
+    256 ends inside a wave (lanes 31 and up of the fourth wave in use, or
+    not) exercise the hit masks' upper halves; a mask bit for a point past
+    the cloud would read the stale constants left in the workspace."""
+    import torch
+    big, small = cghgen.make_wrm(5000), cghgen.make_wrm(n_small)
+    zw, n = cghgen.WRM_PLANE_Z, cghgen.WRM_PLANE_N
+    ctx = cgh.Context(big.width, big.height, big.pitch, big.wavelength)
+    field = torch.empty((n, n), dtype=torch.complex64, device="cuda")
+    ctx.upload_cloud(big)
+    ctx.wrm_record(zw, field)
+    ctx.upload_cloud(small)
+    ctx.wrm_record(zw, field)
+    torch.cuda.synchronize()
+    rows = np.arange(600, 1450, 3)
+    got = field.cpu().numpy()[rows].astype(np.complex128)
+    ref = oracle.wrm_record(n, small.pitch, small.wavelength, zw, small.x, small.y, small.z,
+                            small.amp, rows=rows)
+    e = _nrms(got, ref)
+    say(f"record N={n_small} after N=5000: nrms {e:.3e}")
+    assert e <= TOL
+    assert np.array_equal(got == 0, ref == 0)
+    ctx.close()
+
+
 @pytest.mark.parametrize("w,h,n,zw", [(48, 40, 64, 0.02), (120, 64, 128, 0.05)])
 def test_wrm_compute_matches_oracle_composition(w, h, n, zw):
     """Step 1, Fresnel diffraction to the hologram, Re O over the centred
