@@ -85,12 +85,23 @@ struct FrameList {
     FrameDesc inl[kInlineFrames];
 };
 
+// A 64-bit value every lane holds, made scalar (each half through uint32_t:
+// readfirstlane returns int).
+__device__ __forceinline__ int64_t uniform_i64(int64_t v)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// Frame i (i the same in every lane).  The fields are made scalar
+// explicitly: the compiler does not prove a value chosen between the device
+// table and the kernel arguments uniform, and would otherwise keep the
+// frame's per-point loads (amplitudes) in vector registers.
 __device__ __forceinline__ FrameDesc frame_at(const FrameList &f, int i)
 {
-    if (f.dev)
-        return f.dev[i];
-    // uniform selects rather than an indexed kernel-argument array
-    return i == 0 ? f.inl[0] : i == 1 ? f.inl[1] : i == 2 ? f.inl[2] : f.inl[3];
+    const FrameDesc d = f.dev ? f.dev[i] : f.inl[i];
+    return FrameDesc{uniform_i64(d.first), uniform_i64(d.groups), uniform_i64(d.out_off)};
 }
 
 // ---------------------------------------------------------------- launchers
