@@ -509,7 +509,7 @@ ModeInfo mode_info(int mode)
 // LDS ring depth); each must be built in gemm.hip.
 const int kShapes[][5] = {{192, 384, 2, 4, 2}, {384, 192, 4, 2, 2}, {192, 256, 2, 4, 2},
                           {256, 256, 2, 4, 2}, {192, 192, 2, 2, 3}, {192, 192, 2, 4, 3},
-                          {128, 256, 2, 4, 2}};
+                          {128, 256, 2, 4, 2}, {192, 128, 2, 2, 2}, {128, 192, 2, 2, 2}};
 
 // Lines padded to whole tiles of every shape (factor sets are sized for any
 // of them).
@@ -609,8 +609,10 @@ Plan plan_gemm(int M, int N, int64_t slots, const ModeInfo &mi, const TuneEntry 
     best.tiles_n = (N + best.g.bn - 1) / best.g.bn;
     const int tiles = best.tiles_m * best.tiles_n;
     const int64_t kblocks = slots / mi.kbp;
-    // as many K splits as fit the device (one workgroup per CU) in one wave
-    int splits = forced_splits > 0 ? forced_splits : std::max(1, 256 / tiles);
+    // as many K splits as fit the device in one wave of workgroups
+    const int resident = 256 * gemm_groups_per_cu(best.g.bm, best.g.bn, best.g.waves_m,
+                                                  best.g.waves_n, best.g.stages, mi.products);
+    int splits = forced_splits > 0 ? forced_splits : std::max(1, resident / tiles);
     while (splits > 1 && kblocks / splits < 8)
         --splits;
     best.g.splits = splits;
@@ -872,9 +874,10 @@ cgh_status ev_run_direct_one(Eval &ev, int mode, const FrameDesc &fd, int64_t to
 
 // Matrix-core modes for `slots` constant slots from slot 0.  With `cplx`, L
 // holds the real- and imaginary-part rows stacked (M = 2H) and `out`
-// receives [Re; Im] as two consecutive H x W planes.
+// receives [Re; Im] as two consecutive H x W planes.  With `raw` the factor
+// kernel evaluates the points' constants itself (ev.pc is not read).
 cgh_status ev_run_gemm(Eval &ev, int mode, int64_t slots, float *out, bool cplx, bool accumulate,
-                       hipStream_t s)
+                       hipStream_t s, const RawPoints *raw = nullptr)
 {
     const ModeInfo mi = mode_info(mode);
     const int M = cplx ? 2 * ev.g.height : ev.g.height;
@@ -900,9 +903,14 @@ cgh_status ev_run_gemm(Eval &ev, int mode, int64_t slots, float *out, bool cplx,
     }
     {
         Bracket br(ev.c, mi.fac_name, s);
-        CGH_HIP(launch_factors(ev.pc, 0, ev.g.width, ev.g.height, cplx, p.g.kblocks, p.g.mblocks,
-                               p.g.nblocks, mi.ft, fs, s),
-                "factor launch");
+        if (raw)
+            CGH_HIP(launch_factors_points(*raw, ev.g.width, ev.g.height, cplx, p.g.kblocks,
+                                          p.g.mblocks, p.g.nblocks, mi.ft, fs, s),
+                    "factor launch");
+        else
+            CGH_HIP(launch_factors(ev.pc, 0, ev.g.width, ev.g.height, cplx, p.g.kblocks,
+                                   p.g.mblocks, p.g.nblocks, mi.ft, fs, s),
+                    "factor launch");
         br.done();
     }
     {
@@ -948,17 +956,21 @@ cgh_status ev_one(Eval &ev, int mode, int64_t p0, int64_t count, double lam, flo
         const int64_t cnt = std::min(chunk, count - off);
         const int64_t padded = round_up(cnt, kSlotAlign);
         const int64_t slots = std::max<int64_t>(padded, kSlotAlign);
-        SegList sl{};
-        sl.dev = nullptr;
-        sl.one = {p0 + off, cnt, 0, lam};
-        CGH_TRY(ev_consts(ev, sl, 1, cnt, slots, s));
         const bool acc = off > 0;
         if (is_direct(mode) || cnt == 0) {
+            SegList sl{};
+            sl.dev = nullptr;
+            sl.one = {p0 + off, cnt, 0, lam};
+            CGH_TRY(ev_consts(ev, sl, 1, cnt, slots, s));
             const FrameDesc fd{0, padded / kGroup, 0};
             CGH_TRY(ev_run_direct_one(ev, is_direct(mode) ? mode : CGH_DIRECT_FP32, fd, padded,
                                       out, out_im, acc, s));
         } else {
-            CGH_TRY(ev_run_gemm(ev, mode, slots, out, cplx, acc, s));
+            // the factor kernel takes the points themselves: no constants launch
+            const RawPoints rp{ev.x, ev.y, ev.z, ev.a, p0 + off, cnt, lam,
+                               0.5 * (double)(ev.g.width - 1), 0.5 * (double)(ev.g.height - 1),
+                               ev.g.pitch};
+            CGH_TRY(ev_run_gemm(ev, mode, slots, out, cplx, acc, s, &rp));
         }
         off += chunk;
     } while (off < count);
@@ -2135,16 +2147,19 @@ cgh_status cgh_tune(cgh_ctx *c, cgh_mode mode, int32_t repeats, char *report, in
             if (!gemm_tile_supported(sh[0], sh[1], sh[2], sh[3], sh[4]))
                 continue;
             const int tiles = (int)((c->height + sh[0] - 1) / sh[0] * ((c->width + sh[1] - 1) / sh[1]));
-            // split counts around "one workgroup per CU", each split >= 8 K blocks
+            // split counts around "one wave of workgroups fills the device",
+            // each split >= 8 K blocks
+            const int resident =
+                256 * gemm_groups_per_cu(sh[0], sh[1], sh[2], sh[3], sh[4], mi.products);
             const int smax = (int)std::max<int64_t>(1, kblocks / 8);
-            const int s0 = std::min(std::max(1, 256 / tiles), smax);
+            const int s0 = std::min(std::max(1, resident / tiles), smax);
             std::vector<int> cands{s0};
-            if (s0 / 2 >= 1 && s0 / 2 != s0)
-                cands.push_back(s0 / 2);
-            if (2 * s0 <= smax && 2 * s0 * tiles <= 512)
-                cands.push_back(2 * s0);
-            if (s0 != 1 && s0 / 2 != 1)
-                cands.push_back(1);
+            for (int sp : {s0 - 1, s0 / 2, 2 * s0, 1}) {
+                if (sp < 1 || sp > smax || sp * tiles > 2 * resident ||
+                    std::find(cands.begin(), cands.end(), sp) != cands.end())
+                    continue;
+                cands.push_back(sp);
+            }
             for (int sp : cands) {
                 GemmPlan gp;
                 gp.bm = sh[0];

@@ -165,10 +165,23 @@ struct FactorSet {
 // real-part factors of rows 0 .. height-1, then the imaginary-part factors of
 // the same rows, so that L R^T is [Re O; Im O].
 enum class FactorType { BF16 = 0, FP16 = 1, FP32 = 2 };
+// Points [src, src + count) of a cloud seen at `wavelength`, for kernels that
+// evaluate the per-point constants themselves (half_w = (W-1)/2, half_h =
+// (H-1)/2).  Slots past `count` are padding (zero amplitude).
+struct RawPoints {
+    const float *x, *y, *z, *amp;
+    int64_t src, count;
+    double wavelength, half_w, half_h, pitch;
+};
 constexpr int kblock_points(FactorType ft) { return ft == FactorType::FP32 ? 8 : 16; }
 hipError_t launch_factors(PointConsts pc, int64_t slot0, int width, int height, bool cplx,
                           int64_t kblocks, int mblocks, int nblocks, FactorType ft,
                           const FactorSet &fs, hipStream_t s);
+// a1 + a4 in one launch for a single hologram: the same factors from the
+// points (constants evaluated in the kernel, as k_point_consts does).
+hipError_t launch_factors_points(const RawPoints &rp, int width, int height, bool cplx,
+                                 int64_t kblocks, int mblocks, int nblocks, FactorType ft,
+                                 const FactorSet &fs, hipStream_t s);
 
 // a5: split GEMM on MFMA.  See gemm.hip for the tiling.
 struct GemmPlan {
@@ -185,6 +198,9 @@ struct GemmPlan {
 hipError_t launch_gemm(const GemmPlan &plan, FactorType ft, const FactorSet &fs, int M, int N,
                        float *out, int64_t ldo, float *partials, bool accumulate, hipStream_t s);
 bool gemm_tile_supported(int bm, int bn, int waves_m, int waves_n, int stages);
+// Workgroups of a shape that fit one CU at once (registers for two waves per
+// SIMD, LDS for the copy ring).
+int gemm_groups_per_cu(int bm, int bn, int waves_m, int waves_n, int stages, int products);
 // Raises the GEMM kernels' LDS limit on the current device; called once per
 // context, before any launch or capture.
 hipError_t gemm_prepare_kernels();

@@ -53,19 +53,45 @@ struct alignas(16) Vec16B {
 // several blocks' loads in flight and its stores follow back to back.
 constexpr int kKBlocks = 2;
 
-template <typename T, bool SPLIT>
-__global__ __launch_bounds__(256) void k_factors(PointConsts pc, int64_t slot0, int64_t kblocks,
-                                                 int height, int width, int cplx, int mblocks,
-                                                 FactorSet fs)
+// With RAW, the per-point constants come from the points themselves instead
+// of precomputed arrays: the workgroup's threads first evaluate those of its
+// own points (4 waves x kKBlocks K blocks) into LDS, with the formulas of the
+// point-constant kernel, so a single hologram needs no separate constants
+// launch.
+template <typename T, bool SPLIT, bool RAW>
+__global__ __launch_bounds__(256) void k_factors(PointConsts pc, RawPoints rp, int64_t slot0,
+                                                 int64_t kblocks, int height, int width, int cplx,
+                                                 int mblocks, FactorSet fs)
 {
     constexpr int kLanePoints = Vec16B<T>::kValues / 2;      // (cos, sin) pairs per lane
     constexpr int kBlockPoints = 4 * kLanePoints;
+    constexpr int kWgPoints = 4 * kKBlocks * kBlockPoints;   // points of the workgroup
+    __shared__ double s_ctr[RAW ? kWgPoints : 1], s_beta[RAW ? kWgPoints : 1];
+    __shared__ float s_amp[RAW ? kWgPoints : 1];
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t kb0 = (t >> 6) * kKBlocks;
+    const bool is_l = (int)blockIdx.y < mblocks;
+    if (RAW) {
+        if ((int)threadIdx.x < kWgPoints) {
+            const int64_t slot = (int64_t)blockIdx.x * kWgPoints + threadIdx.x;
+            double ctr = 0.0, beta = 0.0;
+            float a = 0.0f;
+            if (slot < rp.count) {   // padding slots: zero amplitude, zero phase
+                const int64_t src = rp.src + slot;
+                beta = rp.pitch * rp.pitch / (2.0 * rp.wavelength * (double)rp.z[src]);
+                ctr = is_l ? rp.half_h + (double)rp.y[src] / rp.pitch
+                           : rp.half_w + (double)rp.x[src] / rp.pitch;
+                a = rp.amp[src];
+            }
+            s_ctr[threadIdx.x] = ctr;
+            s_beta[threadIdx.x] = beta;
+            s_amp[threadIdx.x] = a;
+        }
+        __syncthreads();
+    }
     if (kb0 >= kblocks)
         return;
     const int lane = (int)(t & 63);
-    const bool is_l = (int)blockIdx.y < mblocks;
     const int rb = is_l ? (int)blockIdx.y : (int)blockIdx.y - mblocks;
     const int line = rb * kFragLines + (lane & (kFragLines - 1));
     const int lines = is_l ? (cplx ? 2 * height : height) : width;
@@ -85,9 +111,16 @@ __global__ __launch_bounds__(256) void k_factors(PointConsts pc, int64_t slot0, 
         const int64_t j0 = slot0 + kb * kBlockPoints + kLanePoints * (lane / kFragLines);
 #pragma unroll
         for (int p = 0; p < kLanePoints; ++p) {
-            ctr[b][p] = is_l ? pc.cy[j0 + p] : pc.cx[j0 + p];
-            beta[b][p] = pc.beta[j0 + p];
-            amp[b][p] = pc.amp[j0 + p];
+            if (RAW) {
+                const int64_t q = j0 - slot0 - (int64_t)blockIdx.x * kWgPoints + p;
+                ctr[b][p] = s_ctr[q];
+                beta[b][p] = s_beta[q];
+                amp[b][p] = s_amp[q];
+            } else {
+                ctr[b][p] = is_l ? pc.cy[j0 + p] : pc.cx[j0 + p];
+                beta[b][p] = pc.beta[j0 + p];
+                amp[b][p] = pc.amp[j0 + p];
+            }
         }
     }
 
@@ -134,20 +167,27 @@ __global__ __launch_bounds__(256) void k_factors(PointConsts pc, int64_t slot0, 
     }
 }
 
-template <typename T>
-hipError_t launch_t(PointConsts pc, int64_t slot0, int width, int height, int cplx,
-                    int64_t kblocks, int mblocks, int nblocks, const FactorSet &fs,
+template <typename T, bool RAW>
+hipError_t launch_t(PointConsts pc, const RawPoints &rp, int64_t slot0, int width, int height,
+                    int cplx, int64_t kblocks, int mblocks, int nblocks, const FactorSet &fs,
                     hipStream_t s)
 {
     const int64_t groups = (kblocks + kKBlocks - 1) / kKBlocks;
     const dim3 grid((unsigned)((groups * 64 + 255) / 256), (unsigned)(mblocks + nblocks));
     if (fs.hl == 2)
-        hipLaunchKernelGGL((k_factors<T, sizeof(T) == 2>), grid, dim3(256), 0, s, pc, slot0,
-                           kblocks, height, width, cplx, mblocks, fs);
+        hipLaunchKernelGGL((k_factors<T, sizeof(T) == 2, RAW>), grid, dim3(256), 0, s, pc, rp,
+                           slot0, kblocks, height, width, cplx, mblocks, fs);
     else
-        hipLaunchKernelGGL((k_factors<T, false>), grid, dim3(256), 0, s, pc, slot0, kblocks,
-                           height, width, cplx, mblocks, fs);
+        hipLaunchKernelGGL((k_factors<T, false, RAW>), grid, dim3(256), 0, s, pc, rp, slot0,
+                           kblocks, height, width, cplx, mblocks, fs);
     return hipGetLastError();
+}
+
+bool factors_fit(int64_t kblocks, int mblocks, int nblocks, FactorType ft, const FactorSet &fs)
+{
+    return fs.base != nullptr && kblocks <= fs.kblocks && mblocks <= fs.amb &&
+           nblocks <= fs.anb && (fs.hl == 1 || fs.hl == 2) &&
+           !(ft == FactorType::FP32 && fs.hl != 1);
 }
 
 }  // namespace
@@ -158,16 +198,38 @@ hipError_t launch_factors(PointConsts pc, int64_t slot0, int width, int height, 
 {
     if (kblocks <= 0 || mblocks + nblocks <= 0)
         return hipSuccess;
-    // the written blocks must lie in the set
-    if (fs.base == nullptr || kblocks > fs.kblocks || mblocks > fs.amb || nblocks > fs.anb ||
-        (fs.hl != 1 && fs.hl != 2) || (ft == FactorType::FP32 && fs.hl != 1))
+    if (!factors_fit(kblocks, mblocks, nblocks, ft, fs))   // the written blocks must lie in the set
         return hipErrorInvalidValue;
     const int cx = cplx ? 1 : 0;
+    const RawPoints none{};
     if (ft == FactorType::BF16)
-        return launch_t<__bf16>(pc, slot0, width, height, cx, kblocks, mblocks, nblocks, fs, s);
+        return launch_t<__bf16, false>(pc, none, slot0, width, height, cx, kblocks, mblocks,
+                                       nblocks, fs, s);
     if (ft == FactorType::FP32)
-        return launch_t<float>(pc, slot0, width, height, cx, kblocks, mblocks, nblocks, fs, s);
-    return launch_t<_Float16>(pc, slot0, width, height, cx, kblocks, mblocks, nblocks, fs, s);
+        return launch_t<float, false>(pc, none, slot0, width, height, cx, kblocks, mblocks,
+                                      nblocks, fs, s);
+    return launch_t<_Float16, false>(pc, none, slot0, width, height, cx, kblocks, mblocks,
+                                     nblocks, fs, s);
+}
+
+hipError_t launch_factors_points(const RawPoints &rp, int width, int height, bool cplx,
+                                 int64_t kblocks, int mblocks, int nblocks, FactorType ft,
+                                 const FactorSet &fs, hipStream_t s)
+{
+    if (kblocks <= 0 || mblocks + nblocks <= 0)
+        return hipSuccess;
+    if (!factors_fit(kblocks, mblocks, nblocks, ft, fs))
+        return hipErrorInvalidValue;
+    const int cx = cplx ? 1 : 0;
+    const PointConsts none{};
+    if (ft == FactorType::BF16)
+        return launch_t<__bf16, true>(none, rp, 0, width, height, cx, kblocks, mblocks, nblocks,
+                                      fs, s);
+    if (ft == FactorType::FP32)
+        return launch_t<float, true>(none, rp, 0, width, height, cx, kblocks, mblocks, nblocks,
+                                     fs, s);
+    return launch_t<_Float16, true>(none, rp, 0, width, height, cx, kblocks, mblocks, nblocks,
+                                    fs, s);
 }
 
 }  // namespace cgh

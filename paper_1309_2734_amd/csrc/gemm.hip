@@ -37,6 +37,8 @@
 // its L2 shares.
 // Split-K partial tiles go to a workspace and are summed in a fixed order by
 // k_splitk_reduce, so results are bitwise reproducible (no float atomics).
+#include <algorithm>
+
 #include "common.h"
 
 namespace cgh {
@@ -288,7 +290,7 @@ __device__ __forceinline__ void gemm_tile(const FactorSet &fs, int64_t kb_begin,
 
 // One hologram, split-K: workgroup -> (split, tile).
 template <int BM, int BN, int WM, int WN, int PRODUCTS, typename T, int STAGES>
-__global__ __launch_bounds__(64 * WM * WN, 1) void k_gemm(
+__global__ __launch_bounds__(64 * WM * WN, 2) void k_gemm(
     FactorSet fs, int64_t kblocks, int tiles_m, int tiles_n, int splits, int64_t kb_per_split,
     int M, int N, float *__restrict__ out, int64_t ldo, float *__restrict__ partials,
     int accumulate)
@@ -319,7 +321,7 @@ __global__ __launch_bounds__(64 * WM * WN, 1) void k_gemm(
 // range and writes its tile of that frame's output.  Items are ordered
 // largest K first.  The counter starts at 0 (k_reset_counter).
 template <int BM, int BN, int WM, int WN, int PRODUCTS, typename T, int STAGES>
-__global__ __launch_bounds__(64 * WM * WN, 1) void k_gemm_batch(
+__global__ __launch_bounds__(64 * WM * WN, 2) void k_gemm_batch(
     FactorSet fs, const BatchItem *__restrict__ items, int n_items, int *__restrict__ counter,
     int M, int N, float *__restrict__ out)
 {
@@ -444,7 +446,10 @@ hipError_t launch_tile_batch(const GemmPlan &plan, const FactorSet &fs, const Ba
     X(256, 256, 2, 4, 2)                                                                       \
     X(192, 192, 2, 2, 3)                                                                       \
     X(192, 192, 2, 4, 3)                                                                       \
-    X(128, 256, 2, 4, 2)
+    X(192, 192, 2, 4, 2)                                                                       \
+    X(128, 256, 2, 4, 2)                                                                       \
+    X(192, 128, 2, 2, 2)                                                                       \
+    X(128, 192, 2, 2, 2)
 
 template <int PRODUCTS, typename T>
 hipError_t launch_products(const GemmPlan &plan, const FactorSet &fs, int M, int N, float *out,
@@ -536,6 +541,15 @@ hipError_t launch_gemm_batch(const GemmPlan &plan, FactorType ft, const FactorSe
                                                 grid, s);
     return launch_products_batch<1, _Float16>(plan, fs, items, n_items, counter, M, N, out, grid,
                                               s);
+}
+
+int gemm_groups_per_cu(int bm, int bn, int waves_m, int waves_n, int stages, int products)
+{
+    // two waves per SIMD (the register budget) and the 160 KB of LDS
+    const int ring = stages * (products == 3 ? 2 : 1) * (bm + bn) / kFragLines * kBlockBytes;
+    const int by_waves = 8 / (waves_m * waves_n);
+    const int by_lds = (160 * 1024) / ring;
+    return std::max(1, std::min(by_waves, by_lds));
 }
 
 bool gemm_tile_supported(int bm, int bn, int waves_m, int waves_n, int stages)
