@@ -1418,7 +1418,9 @@ cgh_status wrm_record(cgh_ctx *c, double zw, int n, float2 *field, hipStream_t s
     const int64_t np = c->n;
     const size_t cap = (size_t)std::max<int64_t>(np, 1);
     void *p = nullptr;
-    CGH_HIP(ensure_ws(c, c->consts, cap * kWrmBytesPerPoint + 8 * 256), "workspace allocation");
+    const size_t groups = (cap + kWrmGroup - 1) / kWrmGroup;
+    CGH_HIP(ensure_ws(c, c->consts, cap * kWrmBytesPerPoint + groups * sizeof(float4) + 4 * 256),
+            "workspace allocation");
     p = c->consts.p;
     char *b = (char *)p;
     auto take = [&](size_t bytes) {
@@ -1427,14 +1429,10 @@ cgh_status wrm_record(cgh_ctx *c, double zw, int n, float2 *field, hipStream_t s
         return r;
     };
     WrmConsts wc;
-    wc.x = (double *)take(cap * sizeof(double));
-    wc.y = (double *)take(cap * sizeof(double));
-    wc.r2 = (double *)take(cap * sizeof(double));
-    wc.beta = (double *)take(cap * sizeof(double));
-    wc.cx = (double *)take(cap * sizeof(double));
-    wc.cy = (double *)take(cap * sizeof(double));
-    wc.amp = (float *)take(cap * sizeof(float));
     wc.box = (float4 *)take(cap * sizeof(float4));
+    wc.raw = (float4 *)take(cap * sizeof(float4));
+    wc.gbox = (float4 *)take(groups * sizeof(float4));
+    wc.next_tile = (int *)take(sizeof(int));
     {
         Bracket br(c, "wrm_consts", s);
         CGH_HIP(launch_wrm_consts(pts_x(c), pts_y(c), pts_z(c), pts_a(c), np, n, c->pitch,
@@ -1443,7 +1441,8 @@ cgh_status wrm_record(cgh_ctx *c, double zw, int n, float2 *field, hipStream_t s
         br.done();
     }
     Bracket br(c, "wrm_record", s);
-    CGH_HIP(launch_wrm_record(wc, np, n, c->pitch, field, s), "recording launch");
+    CGH_HIP(launch_wrm_record(wc, np, n, c->pitch, c->wavelength, zw, field, s),
+            "recording launch");
     br.done();
     return CGH_OK;
 }

@@ -239,24 +239,26 @@ hipError_t fresnel_run(int n, int m, const float2 *tw, const float2 *hc, float2 
 hipError_t launch_splitk_reduce(const float *partials, int splits, int M, int N, float *out,
                                 int64_t ldo, bool accumulate, hipStream_t s);
 
-// Wavefront recording, first step (wrm.hip): per-point constants of the
-// recording on an n x n virtual plane at distance zw from the hologram, SoA
-// over the points.  r2 < 0 (and box.z < 0) marks a point not beyond the plane.
+// Wavefront recording, first step (wrm.hip): per-point data of the recording
+// on an n x n virtual plane at distance zw from the hologram.  box.z < 0 marks
+// a point not beyond the plane.
 struct WrmConsts {
-    double *x, *y;        // x_j, y_j in metres (the float inputs widened)
-    double *r2;           // squared disc radius (lambda d_j / (2 p))^2, metres^2
-    double *beta;         // p^2 / (2 lambda d_j), revolutions per sample^2
-    double *cx, *cy;      // disc centre in samples: (n-1)/2 + x_j / p
-    float *amp;           // A_j
     float4 *box;          // (cx, cy, disc radius in samples, 0) in FP32, for culling
+    float4 *raw;          // (x, y, z, A) as uploaded; the FP64 constants of a point
+                          // are evaluated from these where it is used
+    // per group of kWrmGroup consecutive points: (x lo, x hi, y lo, y hi) in
+    // samples bounding their discs (a sample wider), for culling whole groups
+    float4 *gbox;
+    int *next_tile;       // the recording kernel's tile queue (reset by the constants kernel)
 };
-constexpr size_t kWrmBytesPerPoint = 6 * sizeof(double) + sizeof(float) + sizeof(float4);
+constexpr int64_t kWrmGroup = 1024;
+constexpr size_t kWrmBytesPerPoint = 2 * sizeof(float4);
 hipError_t launch_wrm_consts(const float *x, const float *y, const float *z, const float *amp,
                              int64_t n_points, int n, double pitch, double lam, double zw,
                              const WrmConsts &wc, hipStream_t s);
 // The recorded plane, n x n complex (re, im) pairs, every sample written.
 hipError_t launch_wrm_record(const WrmConsts &wc, int64_t n_points, int n, double pitch,
-                             float2 *field, hipStream_t s);
+                             double lam, double zw, float2 *field, hipStream_t s);
 // out[iy][ix] = Re field[iy + oy][ix + ox] for the width x height window.
 hipError_t launch_window_real(const float2 *field, int n, int ox, int oy, int width, int height,
                               float *out, hipStream_t s);

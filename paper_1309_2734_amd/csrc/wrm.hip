@@ -18,17 +18,32 @@
 // squared and summed in FP64, against r_j^2 in FP64, with no fused
 // multiply-add anywhere in this file (the contraction pragma below).  The
 // phase is reduced per (point, column) and per (point, row) in FP64, as for
-// the hologram, and the FP32 cosine and sine see the sum of the two reduced
-// parts, in [0, 2) revolutions.
+// the hologram; each reduced part gets its FP32 cosine and sine, and a
+// sample takes their product:
+//     A cos(2 pi (U + V)) = A cos 2piU cos 2piV - A sin 2piU sin 2piV,
+//     A sin(2 pi (U + V)) = A sin 2piU cos 2piV + A cos 2piU sin 2piV.
 //
-// Mapping: a workgroup of four waves owns a tile of 64 columns x 32 rows;
-// a wave owns 8 rows, a lane one column of them.  The workgroup walks the
-// points in index order, 256 at a time: each wave tests 64 points' discs
-// against the tile's box (a conservative FP32 test that only decides what to
-// skip), the hit masks meet in LDS, and every wave then adds the hit points
-// to its 8 x 64 samples in index order.  Every sample's sum is therefore
-// formed in point order by one lane: deterministic, with no atomics.
+// Mapping: a workgroup of eight waves owns a tile of 64 columns x 32 rows;
+// a wave owns 4 rows, a lane one column of them.  The workgroup walks the
+// cloud in index order, one group of 1024 points per round, skipping groups
+// whose disc bounding box (made by the constants kernel) misses the tile:
+// each thread tests two points' discs against the tile's box (a
+// conservative FP32 test that only decides what to skip; the next round's
+// boxes and raw inputs load meanwhile), and the hit points, compacted in
+// index order, go to LDS in batches of up to 32 with their FP64 constants
+// (evaluated from the raw inputs by the one function the culling box also
+// uses).  Per batch the workgroup tabulates in LDS each hit's column terms
+// (dx^2, A cos 2piU, A sin 2piU) for the 64 columns and row terms (dy^2,
+// cos 2piV, sin 2piV) for the 32 rows; then every wave adds the hits to its
+// 4 x 64 samples in index order, branch-free (a sample outside the disc
+// adds zero products).  Every sample's sum is formed in point order by one
+// lane: deterministic, with no atomics.  Large clouds reach few tiles with
+// a lot of work each, so their tiles come from a queue drained by
+// persistent workgroups (row-major order, the next free workgroup takes
+// the next tile).
 #pragma clang fp contract(off)
+
+#include <algorithm>
 
 #include "common.h"
 
@@ -36,62 +51,162 @@ namespace cgh {
 namespace {
 
 constexpr int kTileCols = 64;
-constexpr int kWaveRows = 8;
-constexpr int kWaves = 4;
+constexpr int kWaveRows = 4;
+constexpr int kWaves = 8;
+constexpr int kThreads = 64 * kWaves;
 constexpr int kTileRows = kWaveRows * kWaves;
+constexpr int kPerThread = 2;                      // points a thread tests per round
+constexpr int kRound = kPerThread * kThreads;      // points per round = per group
+static_assert(kRound == kWrmGroup, "a recording round covers one point group");
+constexpr int kBatch = 32;                         // hits tabulated at once
 
-// a1 of the recording: constants of point i (see WrmConsts in common.h).
-__global__ __launch_bounds__(256) void k_wrm_consts(const float *__restrict__ x,
-                                                    const float *__restrict__ y,
-                                                    const float *__restrict__ z,
-                                                    const float *__restrict__ amp,
-                                                    int64_t n_points, double pitch, double lam,
-                                                    double zw, double half, WrmConsts wc)
+// Disc of the point with box b (cx, cy, radius in samples, -) against a
+// sample box: a conservative FP32 test that only decides what to skip.
+__device__ __forceinline__ float reach_of(float4 b) { return b.z * 1.0001f + 0.05f; }
+__device__ __forceinline__ bool box_hit(float4 b, float bx0, float bx1, float by0, float by1)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_points)
-        return;
-    const double xj = (double)x[i], yj = (double)y[i];
-    const double d = (double)z[i] - zw;
-    double r2 = -1.0, beta = 0.0;
-    float rho = -1.0f;
-    if (d > 0.0) {
-        const double rj = lam * d / (2.0 * pitch);   // disc radius, metres
-        r2 = rj * rj;
-        beta = pitch * pitch / (2.0 * lam * d);      // revolutions per sample^2
-        rho = (float)(rj / pitch);                   // disc radius, samples
-    }
-    const double cx = half + xj / pitch, cy = half + yj / pitch;
-    wc.x[i] = xj;
-    wc.y[i] = yj;
-    wc.r2[i] = r2;
-    wc.beta[i] = beta;
-    wc.cx[i] = cx;
-    wc.cy[i] = cy;
-    wc.amp[i] = amp[i];
-    wc.box[i] = float4{(float)cx, (float)cy, rho, 0.0f};
+    const float ex = fmaxf(fmaxf(bx0 - b.x, b.x - bx1), 0.0f);
+    const float ey = fmaxf(fmaxf(by0 - b.y, b.y - by1), 0.0f);
+    const float reach = reach_of(b);
+    return b.z >= 0.0f && ex * ex + ey * ey <= reach * reach;
 }
 
-__global__ __launch_bounds__(256) void k_wrm_record(WrmConsts wc, int64_t n_points, int n,
-                                                    double pitch, double half,
-                                                    float2 *__restrict__ field)
+// FP64 constants of a point (x, y, z, A as uploaded): disc radius rj and
+// its square r2 (metres; r2 < 0 when the point is not beyond the plane),
+// beta (revolutions per sample^2) and the disc centre in samples.  The one
+// place they are computed, so the culling box and the disc test agree.
+struct PointFp64 {
+    double x, y, rj, r2, beta, cx, cy;
+};
+__device__ __forceinline__ PointFp64 point_fp64(float4 raw, double pitch, double lam, double zw,
+                                                double half)
 {
-    __shared__ uint64_t hits[kWaves];
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int col0 = blockIdx.x * kTileCols;
-    const int trow0 = blockIdx.y * kTileRows;
+    PointFp64 p;
+    p.x = (double)raw.x;
+    p.y = (double)raw.y;
+    const double d = (double)raw.z - zw;
+    p.rj = 0.0;
+    p.r2 = -1.0;
+    p.beta = 0.0;
+    if (d > 0.0) {
+        p.rj = lam * d / (2.0 * pitch);      // disc radius, metres
+        p.r2 = p.rj * p.rj;
+        p.beta = pitch * pitch / (2.0 * lam * d);
+    }
+    p.cx = half + p.x / pitch;
+    p.cy = half + p.y / pitch;
+    return p;
+}
+
+// a1 of the recording: the culling box and raw inputs of point i (see
+// WrmConsts in common.h), and per group of kRound points (one workgroup)
+// the box of their discs.
+constexpr int kConstsThreads = 1024;
+static_assert(kRound % kConstsThreads == 0, "a group is whole passes of the constants block");
+
+__global__ __launch_bounds__(kConstsThreads) void k_wrm_consts(const float *__restrict__ x,
+                                                               const float *__restrict__ y,
+                                                               const float *__restrict__ z,
+                                                               const float *__restrict__ amp,
+                                                               int64_t n_points, double pitch,
+                                                               double lam, double zw, double half,
+                                                               WrmConsts wc)
+{
+    __shared__ float4 part[kConstsThreads / 64];
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        *wc.next_tile = 0;   // the recording's tile queue starts empty
+    // (x lo, x hi, y lo, y hi) of this thread's discs, widened by a sample;
+    // empty for points outside the cloud or not beyond the plane
+    float4 ext{__builtin_inff(), -__builtin_inff(), __builtin_inff(), -__builtin_inff()};
+    for (int k = 0; k < kRound / kConstsThreads; ++k) {
+        const int64_t i = (int64_t)blockIdx.x * kRound + k * kConstsThreads + threadIdx.x;
+        if (i >= n_points)
+            break;
+        const float4 raw{x[i], y[i], z[i], amp[i]};
+        const PointFp64 pt = point_fp64(raw, pitch, lam, zw, half);
+        const float rho = pt.r2 < 0.0 ? -1.0f : (float)(pt.rj / pitch);   // radius, samples
+        const float4 b{(float)pt.cx, (float)pt.cy, rho, 0.0f};
+        wc.box[i] = b;
+        wc.raw[i] = raw;
+        if (rho >= 0.0f) {
+            const float r = reach_of(b) + 1.0f;
+            ext.x = fminf(ext.x, b.x - r);
+            ext.y = fmaxf(ext.y, b.x + r);
+            ext.z = fminf(ext.z, b.y - r);
+            ext.w = fmaxf(ext.w, b.y + r);
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        ext.x = fminf(ext.x, __shfl_xor(ext.x, o));
+        ext.y = fmaxf(ext.y, __shfl_xor(ext.y, o));
+        ext.z = fminf(ext.z, __shfl_xor(ext.z, o));
+        ext.w = fmaxf(ext.w, __shfl_xor(ext.w, o));
+    }
+    if ((threadIdx.x & 63) == 0)
+        part[threadIdx.x >> 6] = ext;
+    __syncthreads();
+    if (threadIdx.x == 0 && (int64_t)blockIdx.x * kRound < n_points) {
+        float4 g = part[0];
+        for (int w = 1; w < kConstsThreads / 64; ++w) {
+            g.x = fminf(g.x, part[w].x);
+            g.y = fmaxf(g.y, part[w].y);
+            g.z = fminf(g.z, part[w].z);
+            g.w = fmaxf(g.w, part[w].w);
+        }
+        wc.gbox[blockIdx.x] = g;
+    }
+}
+
+// A hit's terms for one row: dy^2 (metres^2, FP64) and the cosine and sine
+// of its reduced row phase; for one column: dx^2 and A times the cosine and
+// sine of its reduced column phase.  One 16-byte LDS read each.
+struct alignas(16) RowTerm {
+    double dy2;
+    float c, s;
+};
+struct alignas(16) ColTerm {
+    double dx2;
+    float ac, as;
+};
+
+// LDS of a recording workgroup.
+struct RecordLds {
+    uint64_t gmask[4];                   // groups of the window (256) reaching the tile
+    uint64_t masks[kPerThread][kWaves];  // points of the round hitting the tile
+    // constants of the batch's hits
+    double h_x[kBatch], h_y[kBatch], h_r2[kBatch], h_beta[kBatch], h_cx[kBatch], h_cy[kBatch];
+    float h_a[kBatch];
+    RowTerm rt[kBatch][kTileRows];
+    ColTerm ct[kBatch][kTileCols];
+};
+
+// One tile (64 columns from col0, 32 rows from trow0) of the plane.
+__device__ __forceinline__ void record_tile(const WrmConsts &wc, int64_t n_points, int n,
+                                            double pitch, double lam, double zw, double half,
+                                            int col0, int trow0, float2 *__restrict__ field,
+                                            RecordLds &L)
+{
+    auto &gmask = L.gmask;
+    auto &masks = L.masks;
+    auto &h_x = L.h_x;
+    auto &h_y = L.h_y;
+    auto &h_r2 = L.h_r2;
+    auto &h_beta = L.h_beta;
+    auto &h_cx = L.h_cx;
+    auto &h_cy = L.h_cy;
+    auto &h_a = L.h_a;
+    auto &rt = L.rt;
+    auto &ct = L.ct;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int row0 = trow0 + wave * kWaveRows;
     const int col = col0 + lane;
 
     // the tile's sample centres span [col0, col0 + 63] x [trow0, trow0 + 31]
     const float bx0 = (float)col0, bx1 = (float)(col0 + kTileCols - 1);
     const float by0 = (float)trow0, by1 = (float)(trow0 + kTileRows - 1);
-    const double xw = ((double)col - half) * pitch;
-    double yw[kWaveRows];
-#pragma unroll
-    for (int r = 0; r < kWaveRows; ++r)
-        yw[r] = ((double)(row0 + r) - half) * pitch;
     float acc_re[kWaveRows], acc_im[kWaveRows];
 #pragma unroll
     for (int r = 0; r < kWaveRows; ++r) {
@@ -99,61 +214,188 @@ __global__ __launch_bounds__(256) void k_wrm_record(WrmConsts wc, int64_t n_poin
         acc_im[r] = 0.0f;
     }
 
-    for (int64_t base = 0; base < n_points; base += kWaves * 64) {
-        const int64_t i = base + wave * 64 + lane;
-        bool hit = false;
-        if (i < n_points) {
-            const float4 b = wc.box[i];
-            const float ex = fmaxf(fmaxf(bx0 - b.x, b.x - bx1), 0.0f);
-            const float ey = fmaxf(fmaxf(by0 - b.y, b.y - by1), 0.0f);
-            const float reach = b.z * 1.0001f + 0.05f;   // margin over FP32 rounding
-            hit = b.z >= 0.0f && ex * ex + ey * ey <= reach * reach;
-        }
-        const uint64_t m = __ballot(hit);
-        if (lane == 0)
-            hits[wave] = m;
-        __syncthreads();
-#pragma unroll 1
-        for (int w = 0; w < kWaves; ++w) {
-            // the same mask in every lane: made scalar, so the loop and the
-            // point loads below are scalar too (readfirstlane returns int:
-            // each half goes through uint32_t so the low one is not
-            // sign-extended into the high bits)
-            const uint64_t hw = hits[w];
-            const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)hw);
-            const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(hw >> 32));
-            uint64_t mm = ((uint64_t)hi << 32) | (uint64_t)lo;
-            while (mm) {
-                const int bit = __builtin_ctzll(mm);
-                mm &= mm - 1;
-                const int64_t j = base + w * 64 + bit;
-                const double xj = wc.x[j], yj = wc.y[j], r2 = wc.r2[j];
-                const double beta = wc.beta[j], cx = wc.cx[j], cy = wc.cy[j];
-                const float a = wc.amp[j];
-                const double dx = xw - xj;
-                const double dx2 = dx * dx;
-                const double uc = (double)col - cx;
-                const float u = (float)__builtin_amdgcn_fract(beta * (uc * uc));
+    // a round's boxes and raw inputs, loaded a round ahead
+    float4 box[kPerThread], raw[kPerThread];
+    auto load_boxes = [&](int64_t base) {
 #pragma unroll
-                for (int r = 0; r < kWaveRows; ++r) {
-                    const double dy = yw[r] - yj;
-                    const double rr = dx2 + dy * dy;
-                    if (rr <= r2) {
-                        const double vr = (double)(row0 + r) - cy;
-                        const float t = u + (float)__builtin_amdgcn_fract(beta * (vr * vr));
-                        acc_re[r] = __builtin_fmaf(a, __builtin_amdgcn_cosf(t), acc_re[r]);
-                        acc_im[r] = __builtin_fmaf(a, __builtin_amdgcn_sinf(t), acc_im[r]);
-                    }
+        for (int k = 0; k < kPerThread; ++k) {
+            const int64_t i = base + k * kThreads + tid;
+            box[k] = i < n_points ? wc.box[i] : float4{0.0f, 0.0f, -1.0f, 0.0f};
+            raw[k] = i < n_points ? wc.raw[i] : float4{0.0f, 0.0f, 0.0f, 0.0f};
+        }
+    };
+    const int64_t n_groups = (n_points + kRound - 1) / kRound;
+    // windows of 256 groups: which of them can reach the tile (one test per
+    // thread), then the rounds of those in order
+    for (int64_t w0 = 0; w0 < n_groups; w0 += 256) {
+        {
+            const int64_t g = w0 + tid;
+            bool reach = false;
+            if (tid < 256 && g < n_groups) {
+                const float4 gb = wc.gbox[g];
+                reach = !(gb.y < bx0 || gb.x > bx1 || gb.w < by0 || gb.z > by1);
+            }
+            const uint64_t m = __ballot(reach);
+            if (lane == 0 && wave < 4)
+                gmask[wave] = m;
+        }
+        __syncthreads();
+        uint64_t gm[4];   // the same in every lane, made scalar
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            const uint64_t v = gmask[w];
+            const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)v);
+            const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+            gm[w] = ((uint64_t)hi << 32) | (uint64_t)lo;
+        }
+        __syncthreads();   // gmask is read before the next window rewrites it
+        // first reaching group at or after q of the window (256: none)
+        auto next_group = [&](int q) {
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                if (q < (w + 1) * 64) {
+                    const int sh = q > w * 64 ? q - w * 64 : 0;
+                    const uint64_t v = gm[w] & (~0ull << sh);
+                    if (v)
+                        return w * 64 + (int)__builtin_ctzll(v);
                 }
             }
+            return 256;
+        };
+        int q = next_group(0);
+        if (q < 256)
+            load_boxes((w0 + q) * kRound);
+        while (q < 256) {
+            const int64_t base = (w0 + q) * kRound;
+            bool hit[kPerThread];
+            float4 hraw[kPerThread];   // this round's raw inputs (the prefetch reuses raw)
+#pragma unroll
+            for (int k = 0; k < kPerThread; ++k) {
+                hit[k] = box_hit(box[k], bx0, bx1, by0, by1);
+                hraw[k] = raw[k];
+                const uint64_t m = __ballot(hit[k]);
+                if (lane == 0)
+                    masks[k][wave] = m;
+            }
+            q = q + 1 < 256 ? next_group(q + 1) : 256;
+            if (q < 256)
+                load_boxes((w0 + q) * kRound);   // in flight while this round's hits add
+            __syncthreads();
+            // this thread's places among the round's hits (index order
+            // (k, wave, lane)), and their count
+            int pos[kPerThread];
+            int total = 0;
+#pragma unroll
+            for (int k = 0; k < kPerThread; ++k) {
+#pragma unroll
+                for (int w = 0; w < kWaves; ++w) {
+                    const uint64_t mw = masks[k][w];
+                    if (w == wave)
+                        pos[k] = total + (int)__builtin_amdgcn_mbcnt_hi(
+                                             (uint32_t)(mw >> 32),
+                                             __builtin_amdgcn_mbcnt_lo((uint32_t)mw, 0));
+                    total += __builtin_popcountll(mw);
+                }
+            }
+            __syncthreads();   // the masks are read before the next round rewrites them
+            for (int b0 = 0; b0 < total; b0 += kBatch) {
+                const int nb = total - b0 < kBatch ? total - b0 : kBatch;
+#pragma unroll
+                for (int k = 0; k < kPerThread; ++k) {
+                    if (hit[k] && pos[k] >= b0 && pos[k] < b0 + kBatch) {
+                        const int h = pos[k] - b0;
+                        const PointFp64 pt = point_fp64(hraw[k], pitch, lam, zw, half);
+                        h_x[h] = pt.x;
+                        h_y[h] = pt.y;
+                        h_r2[h] = pt.r2;
+                        h_beta[h] = pt.beta;
+                        h_cx[h] = pt.cx;
+                        h_cy[h] = pt.cy;
+                        h_a[h] = hraw[k].w;
+                    }
+                }
+                __syncthreads();
+                // the batch's column terms (hits x 64) and row terms (hits x 32)
+                for (int e = tid; e < nb * (kTileCols + kTileRows); e += kThreads) {
+                    if (e < nb * kTileCols) {
+                        const int h = e / kTileCols, c = e % kTileCols;
+                        const double dx = ((double)(col0 + c) - half) * pitch - h_x[h];
+                        const double uc = (double)(col0 + c) - h_cx[h];
+                        const float u = (float)__builtin_amdgcn_fract(h_beta[h] * (uc * uc));
+                        const float a = h_a[h];
+                        ct[h][c] = ColTerm{dx * dx, a * __builtin_amdgcn_cosf(u),
+                                           a * __builtin_amdgcn_sinf(u)};
+                    } else {
+                        const int f = e - nb * kTileCols;
+                        const int h = f / kTileRows, r = f % kTileRows;
+                        const double dy = ((double)(trow0 + r) - half) * pitch - h_y[h];
+                        const double vr = (double)(trow0 + r) - h_cy[h];
+                        const float v = (float)__builtin_amdgcn_fract(h_beta[h] * (vr * vr));
+                        rt[h][r] = RowTerm{dy * dy, __builtin_amdgcn_cosf(v),
+                                           __builtin_amdgcn_sinf(v)};
+                    }
+                }
+                __syncthreads();
+                // branch-free: samples outside the disc add zero products
+#pragma unroll 2
+                for (int h = 0; h < nb; ++h) {
+                    const ColTerm cu = ct[h][lane];
+                    const double r2 = h_r2[h];
+                    RowTerm t[kWaveRows];
+#pragma unroll
+                    for (int r = 0; r < kWaveRows; ++r)
+                        t[r] = rt[h][wave * kWaveRows + r];
+#pragma unroll
+                    for (int r = 0; r < kWaveRows; ++r) {
+                        const bool in = cu.dx2 + t[r].dy2 <= r2;
+                        const float c = in ? cu.ac : 0.0f, sn = in ? cu.as : 0.0f;
+                        acc_re[r] =
+                            __builtin_fmaf(-sn, t[r].s, __builtin_fmaf(c, t[r].c, acc_re[r]));
+                        acc_im[r] =
+                            __builtin_fmaf(c, t[r].s, __builtin_fmaf(sn, t[r].c, acc_im[r]));
+                    }
+                }
+                __syncthreads();   // the batch is consumed before the next one is written
+            }
         }
-        __syncthreads();   // every wave has read the masks before they are rewritten
     }
     if (col < n) {
 #pragma unroll
         for (int r = 0; r < kWaveRows; ++r)
             if (row0 + r < n)
                 field[(int64_t)(row0 + r) * n + col] = float2{acc_re[r], acc_im[r]};
+    }
+}
+
+// Tiles in row-major order, one per workgroup (`queue` false: the grid
+// covers the tiles), or, for clouds of more than a few point groups, from a
+// queue (the counter reset by the constants kernel) that persistent
+// workgroups drain: the few tiles the cloud reaches, each hundreds of times
+// the work of an empty one, then run side by side on all CUs as soon as a
+// workgroup is free.
+__global__ __launch_bounds__(kThreads) void k_wrm_record(WrmConsts wc, int64_t n_points, int n,
+                                                         double pitch, double lam, double zw,
+                                                         double half, int queue,
+                                                         float2 *__restrict__ field)
+{
+    __shared__ RecordLds L;
+    __shared__ int next;
+    const int tiles_x = (n + kTileCols - 1) / kTileCols;
+    const int tiles = tiles_x * ((n + kTileRows - 1) / kTileRows);
+    for (int t = blockIdx.x;;) {
+        if (queue) {
+            if (threadIdx.x == 0)
+                next = atomicAdd(wc.next_tile, 1);
+            __syncthreads();        // next is visible; the previous tile's LDS use is over
+            t = next;
+            __syncthreads();        // everyone has read next before thread 0 rewrites it
+        }
+        if (t >= tiles)
+            break;
+        record_tile(wc, n_points, n, pitch, lam, zw, half, (t % tiles_x) * kTileCols,
+                    (t / tiles_x) * kTileRows, field, L);
+        if (!queue)
+            break;
     }
 }
 
@@ -176,23 +418,36 @@ hipError_t launch_wrm_consts(const float *x, const float *y, const float *z, con
                              int64_t n_points, int n, double pitch, double lam, double zw,
                              const WrmConsts &wc, hipStream_t s)
 {
-    if (n_points <= 0)
-        return hipSuccess;
-    const int64_t blocks = (n_points + 255) / 256;
-    hipLaunchKernelGGL(k_wrm_consts, dim3((unsigned)blocks), dim3(256), 0, s, x, y, z, amp,
-                       n_points, pitch, lam, zw, 0.5 * (double)(n - 1), wc);
+    // at least one block: it also resets the recording's tile queue
+    const int64_t blocks = n_points > 0 ? (n_points + kRound - 1) / kRound : 1;
+    hipLaunchKernelGGL(k_wrm_consts, dim3((unsigned)blocks), dim3(kConstsThreads), 0, s, x, y, z,
+                       amp, n_points, pitch, lam, zw, 0.5 * (double)(n - 1), wc);
     return hipGetLastError();
 }
 
 hipError_t launch_wrm_record(const WrmConsts &wc, int64_t n_points, int n, double pitch,
-                             float2 *field, hipStream_t s)
+                             double lam, double zw, float2 *field, hipStream_t s)
 {
     if (n <= 0)
         return hipSuccess;
-    const dim3 grid((unsigned)((n + kTileCols - 1) / kTileCols),
-                    (unsigned)((n + kTileRows - 1) / kTileRows));
-    hipLaunchKernelGGL(k_wrm_record, grid, dim3(64 * kWaves), 0, s, wc, n_points, n, pitch,
-                       0.5 * (double)(n - 1), field);
+    const int64_t tiles = (int64_t)((n + kTileCols - 1) / kTileCols) *
+                          ((n + kTileRows - 1) / kTileRows);
+    const int queue = n_points > 4 * kRound ? 1 : 0;
+    int64_t grid = tiles;
+    if (queue) {
+        // persistent: as many workgroups as are resident at once
+        int dev = 0, cus = 0, per_cu = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e == hipSuccess)
+            e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e == hipSuccess)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_wrm_record, kThreads, 0);
+        if (e != hipSuccess)
+            return e;
+        grid = std::min<int64_t>(tiles, (int64_t)cus * std::max(per_cu, 1));
+    }
+    hipLaunchKernelGGL(k_wrm_record, dim3((unsigned)grid), dim3(kThreads), 0, s, wc, n_points,
+                       n, pitch, lam, zw, 0.5 * (double)(n - 1), queue, field);
     return hipGetLastError();
 }
 
