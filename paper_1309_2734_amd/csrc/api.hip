@@ -1535,9 +1535,9 @@ cgh_status cgh_fresnel_create(cgh_fresnel **out, int32_t n, double pitch_m, doub
     if (e == hipSuccess)
         e = f->hc.ensure((size_t)L * sizeof(float2));
     if (e == hipSuccess)
-        e = f->x.ensure((size_t)n * L * sizeof(float2));
+        e = f->x.ensure((size_t)n * n * sizeof(float2));
     if (e == hipSuccess)
-        e = f->y.ensure((size_t)n * L * sizeof(float2));
+        e = f->y.ensure((size_t)n * n * sizeof(float2));
     if (e == hipSuccess)
         e = fresnel_tables(n, m, pitch_m * pitch_m / (2.0 * wavelength_m * z_m),
                            (float2 *)f->tw.p, (float2 *)f->hc.p, nullptr);

@@ -7,11 +7,12 @@
 // the grid zero-padded to L x L, L = 2n (no wrap-around), cropped to n x n.
 //
 // Design for this chip:
-//   - h is separable, h(a, b) = h1(a) h1(b), so F[h] is the outer product of
-//     one length-L transform of the chirp h1: computed once per plan, and the
-//     2-D transform of h never exists.  The chirp phase (revolutions,
-//     p^2 a^2 / (2 lambda z), up to ~1e5) is reduced in FP64 before the FP32
-//     exponential.
+//   - h is separable, h(a, b) = h1(a) h1(b), so the 2-D linear convolution
+//     is a 1-D one along every row followed by one along every column, each
+//     zero-padded to L and cropped to n: F[h1] (one length-L transform of the
+//     chirp, computed once per plan) is the only spectrum there is.  The
+//     chirp phase (revolutions, p^2 a^2 / (2 lambda z), up to ~1e5) is
+//     reduced in FP64 before the FP32 exponential.
 //   - 2-D transforms are row transforms with transposes between them.  A
 //     row (up to L = 16384 complex) is one workgroup's: each thread holds 16
 //     of its values (32 for rows of 8192 and more) in registers through a
@@ -25,11 +26,12 @@
 //     Workgroups are persistent, and the loads of a workgroup's next row are
 //     in flight while it transforms the current one (its barriers order LDS
 //     only).  Inverse transforms are conj(F[conj(x)]).
-//   - Zero padding and cropping are pruned: rows that are all zero are never
-//     transformed, zeros are never loaded, and outputs outside the crop are
-//     never stored.  The forward column transform, the spectrum product and
-//     the inverse column transform of a column are one kernel, so the L x L
-//     spectrum never reaches HBM.  Five kernels, HBM traffic 18 n^2 x 8 bytes.
+//   - Zero padding and cropping are pruned: zeros are never loaded, and
+//     outputs outside the crop are never stored.  A row's forward transform,
+//     spectrum product and inverse transform are one kernel, so no padded
+//     plane or spectrum ever reaches HBM.  Four kernels (row convolutions,
+//     transpose, row convolutions, transpose), HBM traffic 8 n^2 x 8 bytes:
+//     four times the floor of reading u and writing O.
 #include <atomic>
 
 #include "common.h"
@@ -305,7 +307,7 @@ __device__ __forceinline__ void fft_row(float2 (&x)[Fft<M>::V], float2 *s, int j
     }
 }
 
-enum class RowOp { Forward, Fresnel, Inverse };
+enum class RowOp { Forward, Fresnel };
 
 // Row inputs of this thread: x[r] = in[row][j + r TR] for r < NIN, zeros
 // beyond.  No branch: a load under a branch is waited for where the branch
@@ -325,10 +327,9 @@ __device__ __forceinline__ void load_row(float2 (&x)[Fft<M>::V], const float2 *s
 // current one.  Per row: loads in[row][0 .. n_in) (zeros beyond; n_in = L/2
 // if HALF_IN, else L), then
 //   Forward: F (all L outputs stored);
-//   Inverse: conj F conj (outputs 0 .. L/2 stored);
-//   Fresnel: F, times hc[i] hc[row] scale (the spectrum of the separable
-//            impulse response at frequency (row, i), and the constant), then
-//            conj F conj (outputs 0 .. L/2 stored);
+//   Fresnel: F, times hc[i] (the spectrum of the one-dimensional impulse
+//            response at frequency i), then conj F conj (outputs 0 .. L/2
+//            stored, times `scale`): the row's linear convolution with h1;
 // into out[row], rows < n_rows.  in and out may be the same rows (a
 // thread's loads of a row precede its stores, and a row is read by its own
 // threads only).  Rows of a last, partial group are computed from a
@@ -379,7 +380,7 @@ __global__ __launch_bounds__(Fft<M>::T) __attribute__((amdgpu_waves_per_eu(
         float2 x[V];
 #pragma unroll
         for (int r = 0; r < V; ++r)
-            x[r] = OP == RowOp::Inverse ? conjf2(xn[r]) : xn[r];
+            x[r] = xn[r];
         // The next group's loads, in flight through this group's transforms
         // (their barriers wait for LDS operations only).  The Fresnel row
         // issues them after its spectrum loads, which it waits for mid-row.
@@ -388,24 +389,22 @@ __global__ __launch_bounds__(Fft<M>::T) __attribute__((amdgpu_waves_per_eu(
         fft_row<M>(x, s, j, sets, lt);
         float2 crow{1.0f, 0.0f};
         if (OP == RowOp::Fresnel) {
-            // All V + 1 spectrum loads in flight at once, then the products.
+            // All V spectrum loads in flight at once, then the products.
             // The empty asm hides the index from the compiler, so the loads
             // cannot be hoisted into the transform, where they would hold
-            // 2 V more registers.  The row's factor hc[row] scale is one
-            // constant of the whole row: it commutes with the inverse
-            // transform and is applied to the stored outputs.
+            // 2 V more registers.  The constant `scale` commutes with the
+            // inverse transform and is applied to the stored outputs.
             int jj = j;
             asm volatile("" : "+v"(jj));
             float2 h[V];
 #pragma unroll
             for (int r = 0; r < V; ++r)
                 h[r] = hc[jj + r * F::TR];
-            const float2 hrow = hc[row_of(g)];
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int r = 0; r < V; ++r)
                 x[r] = conjf2(cmul(x[r], h[r]));
-            crow = cmul(hrow, scale);
+            crow = scale;
             if (more)
                 load_row<M, NIN>(xn, in + row_of(g + gridDim.x) * in_ld, j);
             fft_row<M>(x, s, j, sets, lt);
@@ -418,9 +417,7 @@ __global__ __launch_bounds__(Fft<M>::T) __attribute__((amdgpu_waves_per_eu(
 #pragma unroll
             for (int q = 0; q < NOUT; ++q) {
                 float2 v = x[q];
-                if (OP == RowOp::Inverse)
-                    v = conjf2(v);
-                else if (OP == RowOp::Fresnel)
+                if (OP == RowOp::Fresnel)
                     v = cmul(conjf2(v), crow);
                 dst[q * F::TR] = v;
             }
@@ -551,25 +548,14 @@ hipError_t rows(const float2 *in, int64_t in_ld, int n_in, float2 *out, int64_t 
         if (m != M)
             return rows<OP, M + 1>(in, in_ld, n_in, out, out_ld, n_rows, m, tw, hc, scale, s);
         using F = Fft<M>;
-        const bool half = n_in == F::L / 2;
-        if ((!half && n_in != F::L) || (OP == RowOp::Fresnel && !half) ||
-            (OP == RowOp::Inverse && half))
+        // Fresnel rows take L/2 inputs, forward rows (the chirp) all L
+        if (n_in != (OP == RowOp::Fresnel ? F::L / 2 : F::L))
             return hipErrorInvalidValue;
         if (n_rows <= 0)
             return hipSuccess;
         const int64_t groups = ((int64_t)n_rows + F::ROWS - 1) / F::ROWS;
-        if constexpr (OP == RowOp::Fresnel)
-            return launch_rows<OP, M, true>(in, in_ld, out, out_ld, n_rows, groups, tw, hc, scale,
-                                            s);
-        else if constexpr (OP == RowOp::Inverse)
-            return launch_rows<OP, M, false>(in, in_ld, out, out_ld, n_rows, groups, tw, hc,
-                                             scale, s);
-        else if (half)
-            return launch_rows<OP, M, true>(in, in_ld, out, out_ld, n_rows, groups, tw, hc, scale,
-                                            s);
-        else
-            return launch_rows<OP, M, false>(in, in_ld, out, out_ld, n_rows, groups, tw, hc,
-                                             scale, s);
+        return launch_rows<OP, M, OP == RowOp::Fresnel>(in, in_ld, out, out_ld, n_rows, groups,
+                                                       tw, hc, scale, s);
     }
 }
 
@@ -580,23 +566,17 @@ hipError_t prepare_rows()
         return hipSuccess;
     } else {
         const int lds = (int)Fft<M>::lds_bytes;
-        const void *kernels[] = {(const void *)k_fft_rows<RowOp::Forward, M, true>,
-                                 (const void *)k_fft_rows<RowOp::Forward, M, false>,
-                                 (const void *)k_fft_rows<RowOp::Fresnel, M, true>,
-                                 (const void *)k_fft_rows<RowOp::Inverse, M, false>};
+        const void *kernels[] = {(const void *)k_fft_rows<RowOp::Forward, M, false>,
+                                 (const void *)k_fft_rows<RowOp::Fresnel, M, true>};
         for (const void *k : kernels) {
             hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
             if (e != hipSuccess)
                 return e;
         }
         int r = 0;
-        hipError_t e = resident_groups<RowOp::Forward, M, true>(&r);
-        if (e == hipSuccess)
-            e = resident_groups<RowOp::Forward, M, false>(&r);
+        hipError_t e = resident_groups<RowOp::Forward, M, false>(&r);
         if (e == hipSuccess)
             e = resident_groups<RowOp::Fresnel, M, true>(&r);
-        if (e == hipSuccess)
-            e = resident_groups<RowOp::Inverse, M, false>(&r);
         if (e != hipSuccess)
             return e;
         return prepare_rows<M + 1>();
@@ -642,26 +622,20 @@ hipError_t fresnel_run(int n, int m, const float2 *tw, const float2 *hc, float2 
 {
     if (n < 1 || m < kMinLog2 || m > kMaxLog2 || (2 * n) != (1 << m))
         return hipErrorInvalidValue;
-    const int L = 1 << m;
-    const float2 none{0.0f, 0.0f};
+    const float2 one{1.0f, 0.0f};
     hipError_t e;
-    // rows of u, zero-padded: X[k][0 .. L) = F_row(u[k]), k < n (rows >= n are zero)
-    e = rows<RowOp::Forward>(u, n, n, x, L, n, m, tw, nullptr, none, s);
+    // h(a, b) = h1(a) h1(b): the 2-D linear convolution is the 1-D one along
+    // every row, then along every column.  Rows of u: V = (u * h1 along x) C p^2
+    e = rows<RowOp::Fresnel>(u, n, n, x, n, n, m, tw, hc, scale, s);
     if (e != hipSuccess)
         return e;
-    e = transpose(x, L, y, n, n, L, s);                       // Y = X^T: L x n
+    e = transpose(x, n, y, n, n, n, s);                       // W = V^T
     if (e != hipSuccess)
         return e;
-    // columns: forward transform (n nonzeros), spectrum product, inverse, crop to n
-    e = rows<RowOp::Fresnel>(y, n, n, y, n, L, m, tw, hc, scale, s);
+    e = rows<RowOp::Fresnel>(y, n, n, y, n, n, m, tw, hc, one, s);   // columns of V
     if (e != hipSuccess)
         return e;
-    e = transpose(y, n, x, L, L, n, s);                       // X = Y^T: n x L
-    if (e != hipSuccess)
-        return e;
-    // rows: inverse transform, crop to n
-    e = rows<RowOp::Inverse>(x, L, L, out, n, n, m, tw, nullptr, none, s);
-    return e;
+    return transpose(y, n, out, n, n, n, s);                  // O = W^T
 }
 
 }  // namespace cgh
