@@ -674,9 +674,9 @@ def traffic_driver(torch, cghgen, cgh) -> int:
     """Kernel sequence for `rocprofv3 --pmc FETCH_SIZE|WRITE_SIZE -- python bench.py
     --traffic-driver`: the per-launch counters of the split-BF16 GEMM in each recorded
     launch shape (3 computes each), of the direct kernel at each recorded row count
-    (2 computes each), of the five kernels of a Fresnel diffraction at each recorded
-    size (2 runs), and of a plain 256 MiB device copy (3 copies) whose true byte
-    counts calibrate them."""
+    (2 computes each), of the four kernels of a Fresnel diffraction at each recorded
+    size (2 runs), of the wavefront recording of 10^5 points (2 runs), and of a plain
+    256 MiB device copy (3 copies) whose true byte counts calibrate them."""
     c = cghgen.make_config(2)
     ctx = cgh.Context(c.width, c.height, c.pitch, c.wavelength)
     ctx.upload_cloud(c)
@@ -708,6 +708,17 @@ def traffic_driver(torch, cghgen, cgh) -> int:
         plan.close()
         del u, o
         log(f"traffic driver: Fresnel diffraction n={n}")
+    w = cghgen.make_wrm(100000)
+    wctx = cgh.Context(w.width, w.height, w.pitch, w.wavelength)
+    wctx.upload_cloud(w)
+    field = torch.empty((cghgen.WRM_PLANE_N, cghgen.WRM_PLANE_N), dtype=torch.complex64,
+                        device="cuda:0")
+    for _ in range(2):
+        wctx.wrm_record(cghgen.WRM_PLANE_Z, field)
+    torch.cuda.synchronize()
+    wctx.close()
+    del field
+    log("traffic driver: wavefront recording, 1e5 points")
     src = torch.ones(64 << 20, device="cuda:0")       # 256 MiB of float32
     dst = torch.empty_like(src)
     for _ in range(3):
@@ -861,6 +872,12 @@ def main() -> int:
         "nrms_set": f"every {args.sample_row_step}-th row of the hologram vs the FP64 oracle",
         "roofline": h.get("roofline"),
         "cpu_baseline": cpu,
+        # the same workload in FP32 arithmetic (the paper's precision), beside the split
+        "fp32": {m: {"value": results[m]["pp_per_s"], "unit": "point*pixel/s",
+                     "ms_per_step": results[m]["ms_per_step"],
+                     "frac": (results[m].get("roofline") or {}).get("frac"),
+                     "nrms": results[m].get("nrms")}
+                 for m in ("direct_fp32", "separable_fp32") if m in results},
         "modes": results,
     }
     for name, (res, _) in legs.items():
