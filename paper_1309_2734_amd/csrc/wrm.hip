@@ -159,16 +159,10 @@ __global__ __launch_bounds__(kConstsThreads) void k_wrm_consts(const float *__re
 
 // A hit's terms for one row: dy^2 (metres^2, FP64) and the cosine and sine
 // of its reduced row phase; for one column: dx^2 and A times the cosine and
-// sine of its reduced column phase.  One 16-byte LDS read each.
-struct alignas(16) RowTerm {
-    double dy2;
-    float c, s;
-};
-struct alignas(16) ColTerm {
-    double dx2;
-    float ac, as;
-};
-
+// sine of its reduced column phase.  Kept as separate arrays of 8-byte
+// values, so lanes reading or writing consecutive entries touch consecutive
+// 8-byte words (no LDS bank conflicts; 16-byte records are accessed as two
+// 8-byte halves with a 16-byte stride).
 // LDS of a recording workgroup.
 struct RecordLds {
     uint64_t gmask[4];                   // groups of the window (256) reaching the tile
@@ -176,8 +170,10 @@ struct RecordLds {
     // constants of the batch's hits
     double h_x[kBatch], h_y[kBatch], h_r2[kBatch], h_beta[kBatch], h_cx[kBatch], h_cy[kBatch];
     float h_a[kBatch];
-    RowTerm rt[kBatch][kTileRows];
-    ColTerm ct[kBatch][kTileCols];
+    double rt_dy2[kBatch][kTileRows];
+    float2 rt_cs[kBatch][kTileRows];    // (cos 2piV, sin 2piV)
+    double ct_dx2[kBatch][kTileCols];
+    float2 ct_acs[kBatch][kTileCols];   // A (cos 2piU, sin 2piU)
 };
 
 // One tile (64 columns from col0, 32 rows from trow0) of the plane.
@@ -195,8 +191,10 @@ __device__ __forceinline__ void record_tile(const WrmConsts &wc, int64_t n_point
     auto &h_cx = L.h_cx;
     auto &h_cy = L.h_cy;
     auto &h_a = L.h_a;
-    auto &rt = L.rt;
-    auto &ct = L.ct;
+    auto &rt_dy2 = L.rt_dy2;
+    auto &rt_cs = L.rt_cs;
+    auto &ct_dx2 = L.ct_dx2;
+    auto &ct_acs = L.ct_acs;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -323,36 +321,41 @@ __device__ __forceinline__ void record_tile(const WrmConsts &wc, int64_t n_point
                         const double uc = (double)(col0 + c) - h_cx[h];
                         const float u = (float)__builtin_amdgcn_fract(h_beta[h] * (uc * uc));
                         const float a = h_a[h];
-                        ct[h][c] = ColTerm{dx * dx, a * __builtin_amdgcn_cosf(u),
-                                           a * __builtin_amdgcn_sinf(u)};
+                        ct_dx2[h][c] = dx * dx;
+                        ct_acs[h][c] =
+                            float2{a * __builtin_amdgcn_cosf(u), a * __builtin_amdgcn_sinf(u)};
                     } else {
                         const int f = e - nb * kTileCols;
                         const int h = f / kTileRows, r = f % kTileRows;
                         const double dy = ((double)(trow0 + r) - half) * pitch - h_y[h];
                         const double vr = (double)(trow0 + r) - h_cy[h];
                         const float v = (float)__builtin_amdgcn_fract(h_beta[h] * (vr * vr));
-                        rt[h][r] = RowTerm{dy * dy, __builtin_amdgcn_cosf(v),
-                                           __builtin_amdgcn_sinf(v)};
+                        rt_dy2[h][r] = dy * dy;
+                        rt_cs[h][r] = float2{__builtin_amdgcn_cosf(v), __builtin_amdgcn_sinf(v)};
                     }
                 }
                 __syncthreads();
                 // branch-free: samples outside the disc add zero products
 #pragma unroll 2
                 for (int h = 0; h < nb; ++h) {
-                    const ColTerm cu = ct[h][lane];
+                    const double dx2 = ct_dx2[h][lane];
+                    const float2 acs = ct_acs[h][lane];
                     const double r2 = h_r2[h];
-                    RowTerm t[kWaveRows];
-#pragma unroll
-                    for (int r = 0; r < kWaveRows; ++r)
-                        t[r] = rt[h][wave * kWaveRows + r];
+                    double dy2[kWaveRows];
+                    float2 cs[kWaveRows];
 #pragma unroll
                     for (int r = 0; r < kWaveRows; ++r) {
-                        const bool in = cu.dx2 + t[r].dy2 <= r2;
-                        const float c = in ? cu.ac : 0.0f, sn = in ? cu.as : 0.0f;
+                        dy2[r] = rt_dy2[h][wave * kWaveRows + r];
+                        cs[r] = rt_cs[h][wave * kWaveRows + r];
+                    }
+#pragma unroll
+                    for (int r = 0; r < kWaveRows; ++r) {
+                        const bool in = dx2 + dy2[r] <= r2;
+                        const float c = in ? acs.x : 0.0f, sn = in ? acs.y : 0.0f;
                         acc_re[r] =
-                            __builtin_fmaf(-sn, t[r].s, __builtin_fmaf(c, t[r].c, acc_re[r]));
+                            __builtin_fmaf(-sn, cs[r].y, __builtin_fmaf(c, cs[r].x, acc_re[r]));
                         acc_im[r] =
-                            __builtin_fmaf(c, t[r].s, __builtin_fmaf(sn, t[r].c, acc_im[r]));
+                            __builtin_fmaf(c, cs[r].y, __builtin_fmaf(sn, cs[r].x, acc_im[r]));
                     }
                 }
                 __syncthreads();   // the batch is consumed before the next one is written
