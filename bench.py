@@ -90,16 +90,16 @@ MODE_DTYPE = {"split_bf16": "bf16", "split_fp16": "f16", "fp16": "f16", "direct_
 TRAFFIC_SCALE = {"fetch": 2.0, "write": 1.0}
 TRAFFIC = [
     {"kernel": "gemm_split_mfma", "plan": "384,192,4,2,2,8", "src": "paper_1309_2734_amd/csrc/gemm.hip",
-     "sha": "c2a5d793680ad21f", "fetch_kib": 120352.0, "write_kib": 64800.1},
+     "sha": "dcb455c64a307a95", "fetch_kib": 120352.0, "write_kib": 64800.3},
     {"kernel": "gemm_split_mfma", "plan": "192,384,2,4,2,8", "src": "paper_1309_2734_amd/csrc/gemm.hip",
-     "sha": "c2a5d793680ad21f", "fetch_kib": 120352.0, "write_kib": 64800.6},
+     "sha": "dcb455c64a307a95", "fetch_kib": 120348.5, "write_kib": 64801.1},
     {"kernel": "direct_fp32", "plan": "8", "src": "paper_1309_2734_amd/csrc/direct.hip",
-     "sha": "d5d17ae7d96a2dcc", "fetch_kib": 776234.7, "write_kib": 8100.0},
+     "sha": "a2c8df779d41e487", "fetch_kib": 776157.0, "write_kib": 8100.0},
     {"kernel": "direct_fp32", "plan": "16", "src": "paper_1309_2734_amd/csrc/direct.hip",
-     "sha": "d5d17ae7d96a2dcc", "fetch_kib": 474243.2, "write_kib": 8100.0},
+     "sha": "a2c8df779d41e487", "fetch_kib": 473997.4, "write_kib": 8100.0},
     # the four kernels of one n = 8192 diffraction, summed
     {"kernel": "fresnel_diffraction", "plan": "8192", "src": "paper_1309_2734_amd/csrc/fresnel.hip",
-     "sha": "901dbb79b87cb5d5", "fetch_kib": 2376938.1, "write_kib": 4718593.0},
+     "sha": "3bc5b66c6c31c4ff", "fetch_kib": 1066787.8, "write_kib": 2097152.1},
 ]
 TRAFFIC_PLANS = {"gemm_split_mfma": ["384,192,4,2,2,8", "192,384,2,4,2,8"],
                  "direct_fp32": ["8", "16"], "fresnel_diffraction": ["8192"]}
@@ -670,6 +670,35 @@ def bench_fresnel(args, torch, cgh):
     return out_res, check
 
 
+def bench_vendor_gemm(args, torch, kblocks_points: int):
+    """Context, not the path: the vendor BLAS (torch.matmul, hipBLASLt) on a
+    plain BF16 GEMM of the split GEMM's flop count at 1920x1080 -- the three
+    products as one product over K = 3 x 2 x (points padded), both operands
+    contiguous -- so the matrix-core fraction of the hand-written kernel can
+    be read against the library's on the same shape."""
+    M, N, K = 1080, 1920, 3 * 2 * kblocks_points
+    g = torch.Generator(device="cuda:0").manual_seed(11)
+    a = torch.randn((M, K), dtype=torch.bfloat16, device="cuda:0", generator=g)
+    b = torch.randn((K, N), dtype=torch.bfloat16, device="cuda:0", generator=g)
+    stream = torch.cuda.current_stream()
+    for _ in range(3):
+        c = torch.matmul(a, b)
+    torch.cuda.synchronize()
+    reps = 10
+    e0, e1 = _events(torch, stream)
+    for _ in range(reps):
+        c = torch.matmul(a, b)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    tf = 2.0 * M * N * K / (ms * 1e-3) / 1e12
+    del a, b, c
+    log(f"vendor GEMM {M}x{N}x{K}: {ms:.3f} ms, {tf:.0f} TFLOP/s")
+    return {"shape": [M, N, K], "ms": ms, "tflops": tf, "frac": tf / PEAK_MFMA_BF16_TFLOPS,
+            "note": "context only: torch.matmul (hipBLASLt), BF16 in and out, FP32 "
+                    "accumulation, on the split GEMM's flop count; not part of the path"}
+
+
 def traffic_driver(torch, cghgen, cgh) -> int:
     """Kernel sequence for `rocprofv3 --pmc FETCH_SIZE|WRITE_SIZE -- python bench.py
     --traffic-driver`: the per-launch counters of the split-BF16 GEMM in each recorded
@@ -792,6 +821,7 @@ def main() -> int:
         legs["wrm"] = bench_wrm(args, torch, cghgen, cgh)
     if not args.no_fresnel:
         legs["fresnel_diffraction"] = bench_fresnel(args, torch, cgh)
+    vendor = bench_vendor_gemm(args, torch, (c.n + 31) // 32 * 32)
 
     # ---- host phase: the oracle alone on the host cores
     cpu = None
@@ -879,6 +909,7 @@ def main() -> int:
                      "nrms": results[m].get("nrms")}
                  for m in ("direct_fp32", "separable_fp32") if m in results},
         "modes": results,
+        "vendor_gemm": vendor,
     }
     for name, (res, _) in legs.items():
         line[name] = res
