@@ -69,6 +69,11 @@ PEAK_DIRECT_ISSUE_PPS = CUS * CLOCK_HZ * VALU_PER_CLK / 4      # 9.830e12 point*
 # exact spherical wave: 2 v_add_f32_dpp, 2 v_add_f32, 2 v_mul_f32, v_fma_f32,
 # v_fmac_f32 and v_sqrt_f32, v_rcp_f32, v_cos_f32 per point*pixel
 PEAK_SPHERE_PPS = alu_peak_pps(11, 3)         # 3.575e12 point*pixel/s
+# wavefront recording, per point*sample pair inside a disc: the FP64 disc test
+# (v_add_f64 and v_cmp_f64, two issue slots each at FP64's half rate), two
+# v_cndmask_b32 and four v_fma_f32 -- 10 slots; the line terms' cosines are per
+# point and line, not per pair
+PEAK_WRM_PAIRS = CUS * CLOCK_HZ * VALU_PER_CLK / 10             # 3.932e12 pairs/s
 ALU_MODES = {"direct_fp32": ("direct_fp32", PEAK_DIRECT_PPS),
              "spherical_fp32": ("direct_sphere", PEAK_SPHERE_PPS)}
 
@@ -575,8 +580,16 @@ def bench_wrm(args, torch, cghgen, cgh):
         pairs = float(np.sum(np.pi * rad * rad))
         kms = {k: v[1] / v[0] for k, v in kern.items()}
         rec = kms.get("wrm_record")
+        rate = pairs / (rec * 1e-3) if rec else None
         r = {"ms_per_hologram": ms, "kernels_ms": kms, "disc_pairs": pairs,
-             "record_pairs_per_s": pairs / (rec * 1e-3) if rec else None,
+             "record_pairs_per_s": rate,
+             "roofline": {"bound": "alu", "achieved": rate, "peak": PEAK_WRM_PAIRS,
+                          "unit": "point*sample/s", "frac": rate / PEAK_WRM_PAIRS if rate else None,
+                          "traffic": None, "kernel": "wrm_record",
+                          "note": "achieved = point*sample pairs inside the discs over the "
+                                  "recording kernel's time; peak = 10 VALU issue slots per "
+                                  "pair (FP64 disc test, selects, complex multiply-add); the "
+                                  "tiles visit ~3.5x the pairs inside the discs"},
              "paper_table8_gpu_ms": PAPER_TABLE8_GPU_S[str(npts)] * 1e3}
         log(f"wrm N={npts}: {ms:.3f} ms per hologram, kernels {kms}")
         res[str(npts)] = r
