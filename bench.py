@@ -32,6 +32,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -74,6 +75,9 @@ PEAK_SPHERE_PPS = alu_peak_pps(11, 3)         # 3.575e12 point*pixel/s
 # v_cndmask_b32 and four v_fma_f32 -- 10 slots; the line terms' cosines are per
 # point and line, not per pair
 PEAK_WRM_PAIRS = CUS * CLOCK_HZ * VALU_PER_CLK / 10             # 3.932e12 pairs/s
+# FP32 vector arithmetic without packed operations: one multiply-add (2 flop)
+# per lane and issue slot
+PEAK_FP32_VALU_TFLOPS = CUS * CLOCK_HZ * VALU_PER_CLK * 2 / 1e12   # 78.6 TFLOP/s
 ALU_MODES = {"direct_fp32": ("direct_fp32", PEAK_DIRECT_PPS),
              "spherical_fp32": ("direct_sphere", PEAK_SPHERE_PPS)}
 
@@ -102,12 +106,15 @@ TRAFFIC = [
      "sha": "a2c8df779d41e487", "fetch_kib": 776157.0, "write_kib": 8100.0},
     {"kernel": "direct_fp32", "plan": "16", "src": "paper_1309_2734_amd/csrc/direct.hip",
      "sha": "a2c8df779d41e487", "fetch_kib": 473997.4, "write_kib": 8100.0},
-    # the four kernels of one n = 8192 diffraction, summed
+    # the kernels of one diffraction, summed (n = 1024: two column passes;
+    # n = 8192: row pass, transpose, row pass, transpose)
+    {"kernel": "fresnel_diffraction", "plan": "1024", "src": "paper_1309_2734_amd/csrc/fresnel.hip",
+     "sha": "135fcc6b9fcdd374", "fetch_kib": 8510.2, "write_kib": 16384.0},
     {"kernel": "fresnel_diffraction", "plan": "8192", "src": "paper_1309_2734_amd/csrc/fresnel.hip",
-     "sha": "3bc5b66c6c31c4ff", "fetch_kib": 1066787.8, "write_kib": 2097152.1},
+     "sha": "135fcc6b9fcdd374", "fetch_kib": 1065685.7, "write_kib": 2097152.1},
 ]
 TRAFFIC_PLANS = {"gemm_split_mfma": ["384,192,4,2,2,8", "192,384,2,4,2,8"],
-                 "direct_fp32": ["8", "16"], "fresnel_diffraction": ["8192"]}
+                 "direct_fp32": ["8", "16"], "fresnel_diffraction": ["1024", "8192"]}
 
 # the paper's wavefront-recording times on its K20 (Table 8; context only)
 PAPER_TABLE8_GPU_S = {"1000": 0.029, "10000": 0.030, "100000": 0.035}
@@ -624,10 +631,11 @@ def bench_fresnel(args, torch, cgh):
     of the wavefront-recording method) at the paper's plane sizes (Table 7:
     n = 1024 .. 8192), random complex fields, z = 0.05 m, 8 um, 532 nm.
     Reports ms per diffraction, the roofline against the algorithm's floor
-    (read u, write O: 2 n^2 complex values) and the rate of the pipeline's
-    own traffic (8 n^2 complex values: row convolutions, transpose, column
-    convolutions, transpose); the NRMS of n = 1024 against the oracle's FP64
-    Fourier form."""
+    (read u, write O: 2 n^2 complex values), the rate of the pipeline's own
+    traffic (n <= 1024: 4 n^2 complex values, column convolutions and row
+    convolutions read as columns; larger n: 8 n^2, row convolutions,
+    transpose, column convolutions, transpose) and the transforms' arithmetic
+    rate; the NRMS of n = 1024 against the oracle's FP64 Fourier form."""
     p, lam, z = 8e-6, 532e-9, 0.05
     res, kept = {}, None
     for n in (1024, 2048, 4096, 8192):
@@ -647,15 +655,28 @@ def bench_fresnel(args, torch, cgh):
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / reps
         floor = 2.0 * n * n * 8 / (ms * 1e-3) / 1e9
-        pipe = 8.0 * n * n * 8 / (ms * 1e-3) / 1e9
+        planes = 4.0 if n <= 1024 else 8.0
+        pipe = planes * n * n * 8 / (ms * 1e-3) / 1e9
+        # 2n line convolutions of length L = 2n: two transforms (5 L log2 L
+        # flop each, the radix-2 count) and the spectrum product (6 L)
+        L = 2 * n
+        flop = 2.0 * n * (2 * 5.0 * L * math.log2(L) + 6.0 * L)
+        tf = flop / (ms * 1e-3) / 1e12
         r = {"ms": ms, "pipeline_gb_per_s": pipe, "pipeline_frac": pipe / PEAK_HBM_GBS,
              "roofline": {"bound": "hbm", "achieved": floor, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                           "frac": floor / PEAK_HBM_GBS,
                           "traffic": traffic_bytes("fresnel_diffraction", str(n)),
                           "note": "achieved = the algorithm's floor, 2 n^2 x 8 B (read u, write "
-                                  "O), over the whole diffraction time; the pipeline moves 4x "
-                                  "that (pipeline_gb_per_s); traffic = counter-measured HBM "
-                                  "bytes of one diffraction (recorded for n = 8192)"}}
+                                  f"O), over the whole diffraction time; the pipeline moves "
+                                  f"{planes / 2:.0f}x that (pipeline_gb_per_s); traffic = "
+                                  "counter-measured HBM bytes of one diffraction (recorded for "
+                                  "n = 1024 and 8192)"},
+             "alu": {"achieved": tf, "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
+                     "frac": tf / PEAK_FP32_VALU_TFLOPS,
+                     "note": "the transforms' arithmetic, 2n lines x (2 x 5 L log2 L + 6 L) "
+                             "flop, L = 2n, over the whole diffraction time, against FP32 "
+                             "vector multiply-adds without packed operations (256 CUs x 64 "
+                             "lanes x 2 flop x 2.4 GHz)"}}
         if n == 1024:
             kept = (u.cpu().numpy().astype(np.complex128), out.cpu().numpy().astype(np.complex128))
         plan.close()

@@ -281,17 +281,18 @@ CGH_API cgh_status cgh_tune_batch(cgh_ctx *c, const cgh_frame *frames, int32_t n
  *             sum_k sum_l u[k][l] exp(i pi p^2 ((m-k)^2 + (c-l)^2) / (lambda z)),
  * the integral of Eq. (10) taken as a sum over the samples times the sample
  * area.  Evaluated by FFT, as the equation's second line writes it, with the
- * impulse response's separability: the linear convolution along every row,
- * then along every column, each on the line zero-padded to 2n (no
- * wrap-around) and cropped to n; FP32 transforms with FP64-reduced chirp
- * phases and twiddles.
+ * impulse response's separability: the linear convolution along every
+ * column and every row (n <= 1024: columns first; larger n: rows first),
+ * each on the line zero-padded to 2n (no wrap-around) and cropped to n;
+ * FP32 transforms with FP64-reduced chirp phases and twiddles.
  * --------------------------------------------------------------------- */
 typedef struct cgh_fresnel cgh_fresnel;
 
 /* Plan for n x n fields: n a power of two in [16, 8192]; pitch_m and
  * wavelength_m finite and > 0; z_m finite and non-zero (negative z
- * propagates backwards); device as for cgh_create.  Allocates 16 n^2 + 16 n
- * bytes of device workspace plus a twiddle table of at most 5 n bytes, and
+ * propagates backwards); device as for cgh_create.  Allocates 8 n^2 + 16 n
+ * bytes of device workspace (16 n^2 + 16 n for n >= 2048) plus a twiddle
+ * table of at most 5 n bytes, and
  * computes the transform of the impulse response (blocks until done).
  * Errors: CGH_EINVAL, CGH_EDEVICE, CGH_ENOMEM.  Free with cgh_fresnel_destroy. */
 CGH_API cgh_status cgh_fresnel_create(cgh_fresnel **out, int32_t n, double pitch_m,
@@ -300,9 +301,9 @@ CGH_API cgh_status cgh_fresnel_create(cgh_fresnel **out, int32_t n, double pitch
 /* Propagate u_dev to out_dev, both device buffers of n*n complex values
  * stored as interleaved float pairs (re, im), row-major; caller-owned; they
  * may be the same buffer.  Ordered on `stream`.  Calls on one plan must not
- * overlap (they share its workspace).  Four kernel launches and nothing
- * else, so a call may be captured into a HIP graph (the plan must then
- * outlive the graph).
+ * overlap (they share its workspace).  Two kernel launches (four for
+ * n >= 2048) and nothing else, so a call may be captured into a HIP graph
+ * (the plan must then outlive the graph).
  * Errors: CGH_EINVAL (NULL plan or buffer, or a buffer not 8-byte aligned),
  * CGH_EDEVICE (launch failure). */
 CGH_API cgh_status cgh_fresnel_run(cgh_fresnel *f, const float *u_dev, float *out_dev,

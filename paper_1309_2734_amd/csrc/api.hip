@@ -1487,7 +1487,7 @@ struct cgh_fresnel {
     int n = 0, m = 0;              // field size, log2 of the padded size 2n
     double pitch = 0.0, wavelength = 0.0, z = 0.0;
     float2 scale{0.0f, 0.0f};      // exp(i 2 pi z / lambda) / (i lambda z) p^2 / (2n)^2
-    DevBuf tw, hc, x, y;
+    DevBuf tw, hc, x, y;          // y only for the pipeline with transposes
 };
 
 cgh_status cgh_fresnel_create(cgh_fresnel **out, int32_t n, double pitch_m, double wavelength_m,
@@ -1536,7 +1536,7 @@ cgh_status cgh_fresnel_create(cgh_fresnel **out, int32_t n, double pitch_m, doub
         e = f->hc.ensure((size_t)L * sizeof(float2));
     if (e == hipSuccess)
         e = f->x.ensure((size_t)n * n * sizeof(float2));
-    if (e == hipSuccess)
+    if (e == hipSuccess && fresnel_workspace_planes(m) > 1)
         e = f->y.ensure((size_t)n * n * sizeof(float2));
     if (e == hipSuccess)
         e = fresnel_tables(n, m, pitch_m * pitch_m / (2.0 * wavelength_m * z_m),

@@ -227,11 +227,14 @@ hipError_t launch_kinoform(const float *re, const float *im, int64_t n, uint8_t 
 // twiddle table tw (fresnel_twiddle_bytes(m) bytes) and the transform hc[L]
 // of the 1-D chirp for q = p^2 / (2 lambda z) revolutions per pixel^2;
 // fresnel_run propagates u (n x n complex) to out (n x n), scale =
-// exp(i 2 pi z / lambda) / (i lambda z) p^2 / L^2, with workspaces x and y of
-// n * L complex each.  fresnel_prepare_kernels raises the kernels' LDS limit
-// (once, before any capture).
+// exp(i 2 pi z / lambda) / (i lambda z) p^2 / L^2, with workspaces x and y
+// of n * n complex each (y only if fresnel_workspace_planes(m) is 2) that
+// overlap neither u nor out (u and out may be the same buffer).
+// fresnel_prepare_kernels raises the kernels' LDS limit (once, before any
+// capture).
 hipError_t fresnel_prepare_kernels();
 size_t fresnel_twiddle_bytes(int m);
+size_t fresnel_workspace_planes(int m);
 hipError_t fresnel_tables(int n, int m, double q, float2 *tw, float2 *hc, hipStream_t s);
 hipError_t fresnel_run(int n, int m, const float2 *tw, const float2 *hc, float2 scale,
                        const float2 *u, float2 *out, float2 *x, float2 *y, hipStream_t s);

@@ -13,25 +13,35 @@
 //     chirp, computed once per plan) is the only spectrum there is.  The
 //     chirp phase (revolutions, p^2 a^2 / (2 lambda z), up to ~1e5) is
 //     reduced in FP64 before the FP32 exponential.
-//   - 2-D transforms are row transforms with transposes between them.  A
-//     row (up to L = 16384 complex) is one workgroup's: each thread holds 16
-//     of its values (32 for rows of 8192 and more) in registers through a
-//     Stockham autosort FFT of radix-16 (radix-32) passes plus one smaller
-//     pass, and LDS only carries the exchange
-//     between two passes (the first pass runs on the values as loaded, the
-//     last leaves the results in registers).  Twiddles come from an
-//     FP64-computed table of log2 V values per butterfly and pass (w^e,
-//     w^2e, w^4e, ..; the other twiddles are products of these), expanded
-//     into LDS for the early passes and held in registers for the last one.
-//     Workgroups are persistent, and the loads of a workgroup's next row are
-//     in flight while it transforms the current one (its barriers order LDS
-//     only).  Inverse transforms are conj(F[conj(x)]).
+//   - A line (up to L = 16384 complex) is one workgroup's: each thread
+//     holds 16 of its values (32 for lines of 8192 and more) in registers
+//     through a Stockham autosort FFT of radix-16 (radix-32) passes plus one
+//     smaller pass, and LDS only carries the exchange between two passes
+//     (the first pass runs on the values as loaded, the last leaves the
+//     results in registers).  Twiddles come from an FP64-computed table of
+//     log2 V values per butterfly and pass (w^e, w^2e, w^4e, ..; the other
+//     twiddles are products of these), expanded into LDS for the early
+//     passes and held in registers for the last one.  Workgroups are
+//     persistent, and the loads of a workgroup's next line are in flight
+//     while it transforms the current one (its barriers order LDS only).
+//     Inverse transforms are conj(F[conj(x)]).
+//   - Up to n = 1024 there are no transposes: both passes read their lines
+//     as columns (lane j of a wave loads element j + r L/V of its column,
+//     one 8-byte load per row) and store them as contiguous rows.  The
+//     first pass convolves the columns of u and stores Z^T; the second
+//     convolves the columns of Z^T, which are the rows of Z, and stores the
+//     rows of O.  A turn of the persistent grid gives each XCD adjacent
+//     columns, so the row segments its workgroups read are whole cache
+//     lines of its own L2.  Two kernels, HBM traffic 4 n^2 x 8 bytes.
+//   - From n = 2048 on, column loads cost more than a transpose (strided
+//     rows of 16-64 KB: n = 8192 takes 0.8-1.0 ms per column pass against
+//     0.5 ms per row pass and 0.2 ms per transpose), so the rows of u are
+//     convolved, transposed, convolved as rows again and transposed back:
+//     four kernels, 8 n^2 x 8 bytes.
 //   - Zero padding and cropping are pruned: zeros are never loaded, and
-//     outputs outside the crop are never stored.  A row's forward transform,
-//     spectrum product and inverse transform are one kernel, so no padded
-//     plane or spectrum ever reaches HBM.  Four kernels (row convolutions,
-//     transpose, row convolutions, transpose), HBM traffic 8 n^2 x 8 bytes:
-//     four times the floor of reading u and writing O.
+//     outputs outside the crop are never stored.  A line's forward
+//     transform, spectrum product and inverse transform are one kernel, so
+//     no padded plane or spectrum ever reaches HBM.
 #include <atomic>
 
 #include "common.h"
@@ -41,6 +51,7 @@ namespace {
 
 constexpr int kMinLog2 = 5;                // L >= 32 (n >= 16)
 constexpr int kMaxLog2 = 14;               // L <= 16384: a row is 136 KB of LDS, 512 threads
+constexpr int kColsMaxLog2 = 11;           // column-load pipeline up to L = 2048 (n = 1024)
 
 __device__ __forceinline__ float2 cmul(float2 a, float2 b)
 {
@@ -309,32 +320,66 @@ __device__ __forceinline__ void fft_row(float2 (&x)[Fft<M>::V], float2 *s, int j
 
 enum class RowOp { Forward, Fresnel };
 
-// Row inputs of this thread: x[r] = in[row][j + r TR] for r < NIN, zeros
-// beyond.  No branch: a load under a branch is waited for where the branch
-// joins, which would serialise the loads and end the prefetch.
-template <int M, int NIN>
-__device__ __forceinline__ void load_row(float2 (&x)[Fft<M>::V], const float2 *src, int j)
+// Inputs of this thread for one line: x[r] = element j + r TR of the line
+// for r < NIN, zeros beyond.  A line is a row of `in` (element i at
+// in[line * ld + i]) or, if COLS, a column (element i at in[i * ld + line]).
+// No branch: a load under a branch is waited for where the branch joins,
+// which would serialise the loads and end the prefetch.
+template <int M, int NIN, bool COLS>
+__device__ __forceinline__ void load_line(float2 (&x)[Fft<M>::V], const float2 *in, int64_t ld,
+                                          int64_t line, int j)
 {
     using F = Fft<M>;
+    if constexpr (COLS) {
+        // Buffer loads over the NIN TR rows of `in` (fewer than 2^31 bytes,
+        // which the launch checks): one offset register per thread, and the
+        // distance between a thread's loads, TR rows, in a scalar register.
+        const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<float2 *>(in), (short)0, (int)((int64_t)NIN * F::TR * ld * 8), 0x00020000);
+        const uint32_t voff = (uint32_t)((line + (int64_t)j * ld) * 8);
+        const uint32_t step = (uint32_t)((int64_t)F::TR * ld * 8);
 #pragma unroll
-    for (int r = 0; r < F::V; ++r)
-        x[r] = r < NIN ? src[j + r * F::TR] : float2{0.0f, 0.0f};
+        for (int r = 0; r < F::V; ++r)
+            x[r] = r < NIN ? __builtin_bit_cast(
+                                 float2, __builtin_amdgcn_raw_buffer_load_b64(rsrc, voff, r * step, 0))
+                           : float2{0.0f, 0.0f};
+    } else {
+        const float2 *src = in + line * ld;
+#pragma unroll
+        for (int r = 0; r < F::V; ++r)
+            x[r] = r < NIN ? src[j + r * F::TR] : float2{0.0f, 0.0f};
+    }
 }
 
-// Persistent over row groups (ROWS rows each): workgroup b takes groups
+// Line group of workgroup b's k-th turn (G = gridDim.x workgroups, `full`
+// = the number of turns in which all G take a group): b + k G in general.
+// The hardware deals consecutive workgroups to the eight XCDs in turn; when
+// the lines are columns, a full turn is dealt so that each XCD takes G/8
+// adjacent groups, whose loads then share cache lines in that XCD's L2 (a
+// row's segment of G/8 columns) instead of every line reaching all eight.
+template <bool COLS>
+__device__ __forceinline__ int group_of(int b, int k, int G, int full)
+{
+    if (!COLS || G % 8 != 0 || k >= full)
+        return b + k * G;
+    return k * G + (b % 8) * (G / 8) + b / 8;
+}
+
+// Persistent over line groups (ROWS lines each): workgroup b takes groups
 // b, b + G, b + 2G, ... (G = gridDim.x, sized to what is resident at once),
 // and the loads of its next group are in flight while it transforms the
-// current one.  Per row: loads in[row][0 .. n_in) (zeros beyond; n_in = L/2
-// if HALF_IN, else L), then
+// current one.  Per line (a row of `in`, or a column if COLS): loads its
+// elements 0 .. n_in) (zeros beyond; n_in = L/2 if HALF_IN, else L), then
 //   Forward: F (all L outputs stored);
 //   Fresnel: F, times hc[i] (the spectrum of the one-dimensional impulse
 //            response at frequency i), then conj F conj (outputs 0 .. L/2
-//            stored, times `scale`): the row's linear convolution with h1;
-// into out[row], rows < n_rows.  in and out may be the same rows (a
-// thread's loads of a row precede its stores, and a row is read by its own
-// threads only).  Rows of a last, partial group are computed from a
-// repeated row and not stored.
-template <RowOp OP, int M, bool HALF_IN>
+//            stored, times `scale`): the line's linear convolution with h1;
+// into row `line` of out, lines < n_lines.  Without COLS, in and out may
+// be the same rows (a thread's loads of a row precede its stores, and a row
+// is read by its own threads only); with COLS they must not overlap.  Lines
+// of a last, partial group are computed from a repeated line and not
+// stored.
+template <RowOp OP, int M, bool HALF_IN, bool COLS>
 __global__ __launch_bounds__(Fft<M>::T) __attribute__((amdgpu_waves_per_eu(
     Fft<M>::WAVES_PER_EU))) void k_fft_rows(const float2 *in, int64_t in_ld, float2 *out,
                                             int64_t out_ld, int n_rows,
@@ -350,10 +395,12 @@ __global__ __launch_bounds__(Fft<M>::T) __attribute__((amdgpu_waves_per_eu(
     const int j = threadIdx.x % F::TR;
     float2 *s = lds + rl * F::ROW_SLOTS;
     float2 *sets = lds + F::ROWS * F::ROW_SLOTS;
-    const int64_t groups = ((int64_t)n_rows + F::ROWS - 1) / F::ROWS;
-    auto row_of = [&](int64_t g) {
-        const int64_t r = g * F::ROWS + rl;
-        return F::ROWS == 1 || r < n_rows ? r : (int64_t)n_rows - 1;
+    const int groups = (n_rows + F::ROWS - 1) / F::ROWS;
+    const int G = (int)gridDim.x, b0 = (int)blockIdx.x;
+    const int full = groups / G;
+    auto row_of = [&](int k) -> int64_t {
+        const int r = group_of<COLS>(b0, k, G, full) * F::ROWS + rl;
+        return F::ROWS == 1 || r < n_rows ? r : n_rows - 1;
     };
 
     // twiddle sets of passes 1 .. NP-1, expanded to their V - 1 values in
@@ -372,11 +419,11 @@ __global__ __launch_bounds__(Fft<M>::T) __attribute__((amdgpu_waves_per_eu(
         lt[b] = twp[F::LV * (F::tw_first(F::NP) + j) + b];
 
     float2 xn[V];
-    load_row<M, NIN>(xn, in + row_of(blockIdx.x) * in_ld, j);
-    for (int64_t g = blockIdx.x; g < groups; g += gridDim.x) {
-        const int64_t row = g * F::ROWS + rl;
+    load_line<M, NIN, COLS>(xn, in, in_ld, row_of(0), j);
+    for (int k = 0; b0 + k * G < groups; ++k) {
+        const int64_t row = (int64_t)group_of<COLS>(b0, k, G, full) * F::ROWS + rl;
         const bool live = F::ROWS == 1 || row < n_rows;
-        const bool more = g + gridDim.x < groups;
+        const bool more = b0 + (k + 1) * G < groups;
         float2 x[V];
 #pragma unroll
         for (int r = 0; r < V; ++r)
@@ -385,7 +432,7 @@ __global__ __launch_bounds__(Fft<M>::T) __attribute__((amdgpu_waves_per_eu(
         // (their barriers wait for LDS operations only).  The Fresnel row
         // issues them after its spectrum loads, which it waits for mid-row.
         if (OP != RowOp::Fresnel && more)
-            load_row<M, NIN>(xn, in + row_of(g + gridDim.x) * in_ld, j);
+            load_line<M, NIN, COLS>(xn, in, in_ld, row_of(k + 1), j);
         fft_row<M>(x, s, j, sets, lt);
         float2 crow{1.0f, 0.0f};
         if (OP == RowOp::Fresnel) {
@@ -406,7 +453,7 @@ __global__ __launch_bounds__(Fft<M>::T) __attribute__((amdgpu_waves_per_eu(
                 x[r] = conjf2(cmul(x[r], h[r]));
             crow = scale;
             if (more)
-                load_row<M, NIN>(xn, in + row_of(g + gridDim.x) * in_ld, j);
+                load_line<M, NIN, COLS>(xn, in, in_ld, row_of(k + 1), j);
             fft_row<M>(x, s, j, sets, lt);
         }
         if (live) {
@@ -492,7 +539,7 @@ __global__ void k_chirp(int m, int n, double q, float2 *h)
 // run that is being captured into a graph makes no query.
 constexpr int kMaxDevices = 64;
 
-template <RowOp OP, int M, bool HALF_IN>
+template <RowOp OP, int M, bool HALF_IN, bool COLS>
 hipError_t resident_groups(int *out)
 {
     static std::atomic<int> cached[kMaxDevices];   // zero-initialised (static storage)
@@ -508,7 +555,8 @@ hipError_t resident_groups(int *out)
         e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         if (e == hipSuccess)
             e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                &per_cu, (const void *)k_fft_rows<OP, M, HALF_IN>, Fft<M>::T, Fft<M>::lds_bytes);
+                &per_cu, (const void *)k_fft_rows<OP, M, HALF_IN, COLS>, Fft<M>::T,
+                Fft<M>::lds_bytes);
         if (e != hipSuccess)
             return e;
         r = (per_cu > 0 ? per_cu : 1) * (cus > 0 ? cus : 1);
@@ -518,25 +566,37 @@ hipError_t resident_groups(int *out)
     return hipSuccess;
 }
 
-template <RowOp OP, int M, bool HALF_IN>
+// The two line kernels of a length 2^M: Forward over rows with all L inputs
+// (the chirp's transform), and Fresnel with L/2 inputs, over columns for
+// M <= kColsMaxLog2 and over rows above.
+template <RowOp OP>
+constexpr bool fresnel_op = OP == RowOp::Fresnel;
+constexpr bool cols_pipeline(int m) { return m <= kColsMaxLog2; }
+template <RowOp OP, int M>
+constexpr bool line_cols = fresnel_op<OP> && cols_pipeline(M);
+
+template <RowOp OP, int M>
 hipError_t launch_rows(const float2 *in, int64_t in_ld, float2 *out, int64_t out_ld, int n_rows,
                        int64_t groups, const float2 *tw, const float2 *hc, float2 scale,
                        hipStream_t s)
 {
     using F = Fft<M>;
+    constexpr bool FR = fresnel_op<OP>, COLS = line_cols<OP, M>;
     int resident = 0;
-    hipError_t e = resident_groups<OP, M, HALF_IN>(&resident);
+    hipError_t e = resident_groups<OP, M, FR, COLS>(&resident);
     if (e != hipSuccess)
         return e;
     const unsigned grid = (unsigned)(groups < resident ? groups : resident);
-    hipLaunchKernelGGL((k_fft_rows<OP, M, HALF_IN>), dim3(grid), dim3(F::T), F::lds_bytes, s, in,
-                       in_ld, out, out_ld, n_rows, tw, hc, scale);
+    hipLaunchKernelGGL((k_fft_rows<OP, M, FR, COLS>), dim3(grid), dim3(F::T), F::lds_bytes, s,
+                       in, in_ld, out, out_ld, n_rows, tw, hc, scale);
     return hipGetLastError();
 }
 
-// Row transforms of n_rows rows of length L = 2^m: n_in inputs per row
-// (L/2 or L; the Fresnel rows take L/2, the inverse rows L) and the stored
-// outputs of the operation (Forward: L, else L/2).
+// Line transforms of n_rows lines of length L = 2^m into rows of out:
+// Forward takes rows of `in` with all L inputs and stores all L outputs;
+// Fresnel takes L/2 inputs per line and stores L/2 outputs, its lines being
+// columns of `in` (element i of column c at in[i * in_ld + c]) if
+// cols_pipeline(m), else rows.
 template <RowOp OP, int M = kMinLog2>
 hipError_t rows(const float2 *in, int64_t in_ld, int n_in, float2 *out, int64_t out_ld,
                 int n_rows, int m, const float2 *tw, const float2 *hc, float2 scale,
@@ -548,14 +608,17 @@ hipError_t rows(const float2 *in, int64_t in_ld, int n_in, float2 *out, int64_t 
         if (m != M)
             return rows<OP, M + 1>(in, in_ld, n_in, out, out_ld, n_rows, m, tw, hc, scale, s);
         using F = Fft<M>;
-        // Fresnel rows take L/2 inputs, forward rows (the chirp) all L
-        if (n_in != (OP == RowOp::Fresnel ? F::L / 2 : F::L))
+        if (n_in != (fresnel_op<OP> ? F::L / 2 : F::L))
             return hipErrorInvalidValue;
         if (n_rows <= 0)
             return hipSuccess;
+        // column lines c < n_rows of an n_in-row input are read through one
+        // buffer resource (a 31-bit byte range)
+        if (line_cols<OP, M> &&
+            (n_rows > in_ld || (int64_t)n_in * in_ld * (int64_t)sizeof(float2) > INT32_MAX))
+            return hipErrorInvalidValue;
         const int64_t groups = ((int64_t)n_rows + F::ROWS - 1) / F::ROWS;
-        return launch_rows<OP, M, OP == RowOp::Fresnel>(in, in_ld, out, out_ld, n_rows, groups,
-                                                       tw, hc, scale, s);
+        return launch_rows<OP, M>(in, in_ld, out, out_ld, n_rows, groups, tw, hc, scale, s);
     }
 }
 
@@ -566,17 +629,18 @@ hipError_t prepare_rows()
         return hipSuccess;
     } else {
         const int lds = (int)Fft<M>::lds_bytes;
-        const void *kernels[] = {(const void *)k_fft_rows<RowOp::Forward, M, false>,
-                                 (const void *)k_fft_rows<RowOp::Fresnel, M, true>};
+        constexpr bool COLS = line_cols<RowOp::Fresnel, M>;
+        const void *kernels[] = {(const void *)k_fft_rows<RowOp::Forward, M, false, false>,
+                                 (const void *)k_fft_rows<RowOp::Fresnel, M, true, COLS>};
         for (const void *k : kernels) {
             hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
             if (e != hipSuccess)
                 return e;
         }
         int r = 0;
-        hipError_t e = resident_groups<RowOp::Forward, M, false>(&r);
+        hipError_t e = resident_groups<RowOp::Forward, M, false, false>(&r);
         if (e == hipSuccess)
-            e = resident_groups<RowOp::Fresnel, M, true>(&r);
+            e = resident_groups<RowOp::Fresnel, M, true, COLS>(&r);
         if (e != hipSuccess)
             return e;
         return prepare_rows<M + 1>();
@@ -594,6 +658,8 @@ hipError_t transpose(const float2 *in, int64_t in_ld, float2 *out, int64_t out_l
 }  // namespace
 
 hipError_t fresnel_prepare_kernels() { return prepare_rows(); }
+
+size_t fresnel_workspace_planes(int m) { return cols_pipeline(m) ? 1 : 2; }
 
 size_t fresnel_twiddle_bytes(int m)
 {
@@ -625,17 +691,28 @@ hipError_t fresnel_run(int n, int m, const float2 *tw, const float2 *hc, float2 
     const float2 one{1.0f, 0.0f};
     hipError_t e;
     // h(a, b) = h1(a) h1(b): the 2-D linear convolution is the 1-D one along
-    // every row, then along every column.  Rows of u: V = (u * h1 along x) C p^2
+    // every column and then along every row, or the other way round.
+    if (cols_pipeline(m)) {
+        // Columns of u: x = Z^T, Z = (u * h1 along the first index) C p^2,
+        // a column of Z per row of x; then the columns of x (the rows of Z):
+        // O = Z * h1 along the second index, row by row.
+        e = rows<RowOp::Fresnel>(u, n, n, x, n, n, m, tw, hc, scale, s);
+        if (e != hipSuccess)
+            return e;
+        return rows<RowOp::Fresnel>(x, n, n, out, n, n, m, tw, hc, one, s);
+    }
+    // Rows of u: V = (u * h1 along the second index) C p^2; W = V^T; the rows
+    // of W (the columns of V) convolved in place; O = W^T.
     e = rows<RowOp::Fresnel>(u, n, n, x, n, n, m, tw, hc, scale, s);
     if (e != hipSuccess)
         return e;
-    e = transpose(x, n, y, n, n, n, s);                       // W = V^T
+    e = transpose(x, n, y, n, n, n, s);
     if (e != hipSuccess)
         return e;
-    e = rows<RowOp::Fresnel>(y, n, n, y, n, n, m, tw, hc, one, s);   // columns of V
+    e = rows<RowOp::Fresnel>(y, n, n, y, n, n, m, tw, hc, one, s);
     if (e != hipSuccess)
         return e;
-    return transpose(y, n, out, n, n, n, s);                  // O = W^T
+    return transpose(y, n, out, n, n, n, s);
 }
 
 }  // namespace cgh
