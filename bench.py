@@ -71,10 +71,11 @@ PEAK_DIRECT_ISSUE_PPS = CUS * CLOCK_HZ * VALU_PER_CLK / 4      # 9.830e12 point*
 # v_fmac_f32 and v_sqrt_f32, v_rcp_f32, v_cos_f32 per point*pixel
 PEAK_SPHERE_PPS = alu_peak_pps(11, 3)         # 3.575e12 point*pixel/s
 # wavefront recording, per point*sample pair inside a disc: the FP64 disc test
-# (v_add_f64 and v_cmp_f64, two issue slots each at FP64's half rate), two
-# v_cndmask_b32 and four v_fma_f32 -- 10 slots; the line terms' cosines are per
+# (v_add_f64 and v_cmp_le_f64; FP64 arithmetic issues at the FP32 rate here,
+# v_fma_f64 57 lane-operations per clock per CU in the microbenchmark), two
+# v_cndmask_b32 and four v_fma_f32 -- 8 slots; the line terms' cosines are per
 # point and line, not per pair
-PEAK_WRM_PAIRS = CUS * CLOCK_HZ * VALU_PER_CLK / 10             # 3.932e12 pairs/s
+PEAK_WRM_PAIRS = CUS * CLOCK_HZ * VALU_PER_CLK / 8              # 4.915e12 pairs/s
 # FP32 vector arithmetic without packed operations: one multiply-add (2 flop)
 # per lane and issue slot
 PEAK_FP32_VALU_TFLOPS = CUS * CLOCK_HZ * VALU_PER_CLK * 2 / 1e12   # 78.6 TFLOP/s
@@ -594,9 +595,10 @@ def bench_wrm(args, torch, cghgen, cgh):
                           "unit": "point*sample/s", "frac": rate / PEAK_WRM_PAIRS if rate else None,
                           "traffic": None, "kernel": "wrm_record",
                           "note": "achieved = point*sample pairs inside the discs over the "
-                                  "recording kernel's time; peak = 10 VALU issue slots per "
-                                  "pair (FP64 disc test, selects, complex multiply-add); the "
-                                  "tiles visit ~3.5x the pairs inside the discs"},
+                                  "recording kernel's time (chunk planes and their sum "
+                                  "included); peak = 8 VALU issue slots per pair (FP64 disc "
+                                  "test, selects, complex multiply-add); the tiles visit ~3.8x "
+                                  "the pairs inside the discs"},
              "paper_table8_gpu_ms": PAPER_TABLE8_GPU_S[str(npts)] * 1e3}
         log(f"wrm N={npts}: {ms:.3f} ms per hologram, kernels {kms}")
         res[str(npts)] = r

@@ -328,7 +328,10 @@ CGH_API void cgh_fresnel_destroy(cgh_fresnel *f);
  *   u_w = sum over j with d_j > 0, (x_w - x_j)^2 + (y_w - y_j)^2 <= r_j^2 of
  *         A_j exp(i pi ((x_w - x_j)^2 + (y_w - y_j)^2) / (lambda d_j)).
  * The membership test is evaluated in FP64 exactly as written; the phase is
- * range-reduced in FP64 and the sum accumulated in FP32, in point order.
+ * range-reduced in FP64 and the sum accumulated in FP32, in point order
+ * (clouds of more than 4096 points: in point order within each of up to 4
+ * chunks of consecutive points, whose sums are then added in chunk order,
+ * with (chunks - 1) n^2 complex values of context workspace).
  * --------------------------------------------------------------------- */
 
 /* Step 1 for the uploaded cloud: the plane at distance plane_z_m (finite;

@@ -1440,8 +1440,20 @@ cgh_status wrm_record(cgh_ctx *c, double zw, int n, float2 *field, hipStream_t s
                 "recording constants launch");
         br.done();
     }
+    int chunks = wrm_record_chunks(np, n);
+    if (const char *env = std::getenv("CGH_WRM_CHUNKS")) {
+        const int v = std::atoi(env);
+        if (v >= 1 && v <= 16 && np > kWrmQueueMinPoints)
+            chunks = v;
+    }
+    float2 *parts = nullptr;
+    if (chunks > 1) {
+        CGH_HIP(ensure_ws(c, c->partials, (size_t)(chunks - 1) * n * n * sizeof(float2)),
+                "workspace allocation");
+        parts = (float2 *)c->partials.p;
+    }
     Bracket br(c, "wrm_record", s);
-    CGH_HIP(launch_wrm_record(wc, np, n, c->pitch, c->wavelength, zw, field, s),
+    CGH_HIP(launch_wrm_record(wc, np, n, c->pitch, c->wavelength, zw, chunks, field, parts, s),
             "recording launch");
     br.done();
     return CGH_OK;

@@ -259,9 +259,19 @@ constexpr size_t kWrmBytesPerPoint = 2 * sizeof(float4);
 hipError_t launch_wrm_consts(const float *x, const float *y, const float *z, const float *amp,
                              int64_t n_points, int n, double pitch, double lam, double zw,
                              const WrmConsts &wc, hipStream_t s);
-// The recorded plane, n x n complex (re, im) pairs, every sample written.
+// Clouds above kWrmQueueMinPoints points are recorded by persistent
+// workgroups from a tile queue, their groups cut into `chunks` ranges of
+// about kWrmPointsPerChunk points (at most kWrmMaxChunks), recorded as
+// separate planes and summed in chunk order.
+constexpr int64_t kWrmQueueMinPoints = 4 * kWrmGroup;
+constexpr int64_t kWrmPointsPerChunk = 15000;
+constexpr int kWrmMaxChunks = 4;
+int wrm_record_chunks(int64_t n_points, int n);
+// The recorded plane, n x n complex (re, im) pairs, every sample written;
+// parts holds chunks - 1 further n x n planes (unused when chunks is 1).
 hipError_t launch_wrm_record(const WrmConsts &wc, int64_t n_points, int n, double pitch,
-                             double lam, double zw, float2 *field, hipStream_t s);
+                             double lam, double zw, int chunks, float2 *field, float2 *parts,
+                             hipStream_t s);
 // out[iy][ix] = Re field[iy + oy][ix + ox] for the width x height window.
 hipError_t launch_window_real(const float2 *field, int n, int ox, int oy, int width, int height,
                               float *out, hipStream_t s);

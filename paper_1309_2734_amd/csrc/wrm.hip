@@ -40,7 +40,10 @@
 // lane: deterministic, with no atomics.  Large clouds reach few tiles with
 // a lot of work each, so their tiles come from a queue drained by
 // persistent workgroups (row-major order, the next free workgroup takes
-// the next tile).
+// the next item), and their points are cut into a few chunks of
+// consecutive groups: a (tile, chunk) item is one workgroup's, each chunk
+// is recorded as a plane of its own, and the planes are added in chunk
+// order afterwards (still one fixed order per sample).
 #pragma clang fp contract(off)
 
 #include <algorithm>
@@ -176,11 +179,12 @@ struct RecordLds {
     float2 ct_acs[kBatch][kTileCols];   // A (cos 2piU, sin 2piU)
 };
 
-// One tile (64 columns from col0, 32 rows from trow0) of the plane.
+// One tile (64 columns from col0, 32 rows from trow0) of the plane, summed
+// over the points of groups [g_lo, g_hi) into dst (an n x n plane).
 __device__ __forceinline__ void record_tile(const WrmConsts &wc, int64_t n_points, int n,
                                             double pitch, double lam, double zw, double half,
-                                            int col0, int trow0, float2 *__restrict__ field,
-                                            RecordLds &L)
+                                            int col0, int trow0, int64_t g_lo, int64_t g_hi,
+                                            float2 *__restrict__ dst, RecordLds &L)
 {
     auto &gmask = L.gmask;
     auto &masks = L.masks;
@@ -222,14 +226,13 @@ __device__ __forceinline__ void record_tile(const WrmConsts &wc, int64_t n_point
             raw[k] = i < n_points ? wc.raw[i] : float4{0.0f, 0.0f, 0.0f, 0.0f};
         }
     };
-    const int64_t n_groups = (n_points + kRound - 1) / kRound;
     // windows of 256 groups: which of them can reach the tile (one test per
     // thread), then the rounds of those in order
-    for (int64_t w0 = 0; w0 < n_groups; w0 += 256) {
+    for (int64_t w0 = g_lo; w0 < g_hi; w0 += 256) {
         {
             const int64_t g = w0 + tid;
             bool reach = false;
-            if (tid < 256 && g < n_groups) {
+            if (tid < 256 && g < g_hi) {
                 const float4 gb = wc.gbox[g];
                 reach = !(gb.y < bx0 || gb.x > bx1 || gb.w < by0 || gb.z > by1);
             }
@@ -366,25 +369,31 @@ __device__ __forceinline__ void record_tile(const WrmConsts &wc, int64_t n_point
 #pragma unroll
         for (int r = 0; r < kWaveRows; ++r)
             if (row0 + r < n)
-                field[(int64_t)(row0 + r) * n + col] = float2{acc_re[r], acc_im[r]};
+                dst[(int64_t)(row0 + r) * n + col] = float2{acc_re[r], acc_im[r]};
     }
 }
 
-// Tiles in row-major order, one per workgroup (`queue` false: the grid
-// covers the tiles), or, for clouds of more than a few point groups, from a
-// queue (the counter reset by the constants kernel) that persistent
-// workgroups drain: the few tiles the cloud reaches, each hundreds of times
-// the work of an empty one, then run side by side on all CUs as soon as a
-// workgroup is free.
+// Work items are (tile, point chunk) pairs, tile-major: the points' groups
+// are cut into `chunks` consecutive ranges, chunk 0 recorded into `field`
+// and chunk c > 0 into plane c - 1 of `parts`, which k_wrm_sum then adds to
+// the field in chunk order.  Items go one per workgroup (`queue` false: the
+// grid covers them; chunks is then 1), or, for clouds of more than a few
+// point groups, come from a queue (the counter reset by the constants
+// kernel) that persistent workgroups drain: the few tiles the cloud
+// reaches, each hundreds of times the work of an empty one, run side by
+// side on all CUs as soon as a workgroup is free, and their chunks spread
+// one tile's work over several workgroups.
 __global__ __launch_bounds__(kThreads) void k_wrm_record(WrmConsts wc, int64_t n_points, int n,
                                                          double pitch, double lam, double zw,
-                                                         double half, int queue,
-                                                         float2 *__restrict__ field)
+                                                         double half, int queue, int chunks,
+                                                         float2 *__restrict__ field,
+                                                         float2 *__restrict__ parts)
 {
     __shared__ RecordLds L;
     __shared__ int next;
     const int tiles_x = (n + kTileCols - 1) / kTileCols;
-    const int tiles = tiles_x * ((n + kTileRows - 1) / kTileRows);
+    const int items = tiles_x * ((n + kTileRows - 1) / kTileRows) * chunks;
+    const int64_t n_groups = (n_points + kRound - 1) / kRound;
     for (int t = blockIdx.x;;) {
         if (queue) {
             if (threadIdx.x == 0)
@@ -393,12 +402,44 @@ __global__ __launch_bounds__(kThreads) void k_wrm_record(WrmConsts wc, int64_t n
             t = next;
             __syncthreads();        // everyone has read next before thread 0 rewrites it
         }
-        if (t >= tiles)
+        if (t >= items)
             break;
-        record_tile(wc, n_points, n, pitch, lam, zw, half, (t % tiles_x) * kTileCols,
-                    (t / tiles_x) * kTileRows, field, L);
+        const int tile = t / chunks, chunk = t - tile * chunks;
+        float2 *dst = chunk == 0 ? field : parts + (int64_t)(chunk - 1) * n * n;
+        record_tile(wc, n_points, n, pitch, lam, zw, half, (tile % tiles_x) * kTileCols,
+                    (tile / tiles_x) * kTileRows, n_groups * chunk / chunks,
+                    n_groups * (chunk + 1) / chunks, dst, L);
         if (!queue)
             break;
+    }
+}
+
+// field[i] += parts[0][i] + ... in chunk order, two samples per thread.
+__global__ __launch_bounds__(256) void k_wrm_sum(float2 *__restrict__ field,
+                                                 const float2 *__restrict__ parts, int planes,
+                                                 int64_t samples)
+{
+    const int64_t i = 2 * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+    if (i >= samples)
+        return;
+    if (i + 1 < samples) {
+        float4 a = *(const float4 *)(field + i);
+        for (int c = 0; c < planes; ++c) {
+            const float4 b = *(const float4 *)(parts + (int64_t)c * samples + i);
+            a.x += b.x;
+            a.y += b.y;
+            a.z += b.z;
+            a.w += b.w;
+        }
+        *(float4 *)(field + i) = a;
+    } else {
+        float2 a = field[i];
+        for (int c = 0; c < planes; ++c) {
+            const float2 b = parts[(int64_t)c * samples + i];
+            a.x += b.x;
+            a.y += b.y;
+        }
+        field[i] = a;
     }
 }
 
@@ -428,15 +469,26 @@ hipError_t launch_wrm_consts(const float *x, const float *y, const float *z, con
     return hipGetLastError();
 }
 
+int wrm_record_chunks(int64_t n_points, int n)
+{
+    if (n <= 0 || n_points <= kWrmQueueMinPoints)
+        return 1;
+    const int64_t n_groups = (n_points + kRound - 1) / kRound;
+    return (int)std::min<int64_t>({kWrmMaxChunks, n_groups, std::max<int64_t>(1, n_points / kWrmPointsPerChunk)});
+}
+
 hipError_t launch_wrm_record(const WrmConsts &wc, int64_t n_points, int n, double pitch,
-                             double lam, double zw, float2 *field, hipStream_t s)
+                             double lam, double zw, int chunks, float2 *field, float2 *parts,
+                             hipStream_t s)
 {
     if (n <= 0)
         return hipSuccess;
-    const int64_t tiles = (int64_t)((n + kTileCols - 1) / kTileCols) *
-                          ((n + kTileRows - 1) / kTileRows);
-    const int queue = n_points > 4 * kRound ? 1 : 0;
-    int64_t grid = tiles;
+    const int queue = n_points > kWrmQueueMinPoints ? 1 : 0;
+    if (chunks < 1 || (!queue && chunks != 1) || (chunks > 1 && !parts))
+        return hipErrorInvalidValue;
+    const int64_t items = (int64_t)((n + kTileCols - 1) / kTileCols) *
+                          ((n + kTileRows - 1) / kTileRows) * chunks;
+    int64_t grid = items;
     if (queue) {
         // persistent: as many workgroups as are resident at once
         int dev = 0, cus = 0, per_cu = 0;
@@ -447,10 +499,17 @@ hipError_t launch_wrm_record(const WrmConsts &wc, int64_t n_points, int n, doubl
             e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_wrm_record, kThreads, 0);
         if (e != hipSuccess)
             return e;
-        grid = std::min<int64_t>(tiles, (int64_t)cus * std::max(per_cu, 1));
+        grid = std::min<int64_t>(items, (int64_t)cus * std::max(per_cu, 1));
     }
     hipLaunchKernelGGL(k_wrm_record, dim3((unsigned)grid), dim3(kThreads), 0, s, wc, n_points,
-                       n, pitch, lam, zw, 0.5 * (double)(n - 1), queue, field);
+                       n, pitch, lam, zw, 0.5 * (double)(n - 1), queue, chunks, field, parts);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || chunks == 1)
+        return e;
+    const int64_t samples = (int64_t)n * n;
+    const int64_t threads = (samples + 1) / 2;
+    hipLaunchKernelGGL(k_wrm_sum, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, field,
+                       parts, chunks - 1, samples);
     return hipGetLastError();
 }
 

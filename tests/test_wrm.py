@@ -112,6 +112,27 @@ def test_record_full_size_workload(n_pts, step):
     assert np.array_equal(a, got)              # bitwise repeatable
 
 
+@pytest.mark.parametrize("chunks", [2, 3, 7])
+def test_record_point_chunks(chunks, monkeypatch):
+    """Clouds above 4096 points are recorded in chunks of consecutive point
+    groups, each into a plane of its own, the planes then added in chunk
+    order.  Forced chunk counts on the 10^4-point workload (10 groups; 7
+    chunks leaves chunks of one and of two groups) against the oracle on
+    rows at a stride coprime to the tiles, and bitwise repeatable."""
+    c = cghgen.make_wrm(10000)
+    zw, n = cghgen.WRM_PLANE_Z, cghgen.WRM_PLANE_N
+    monkeypatch.setenv("CGH_WRM_CHUNKS", str(chunks))
+    rows = np.arange(7, n, 29)
+    say(f"record N=10000 in {chunks} chunks, {len(rows)} rows")
+    ref = oracle.wrm_record(n, c.pitch, c.wavelength, zw, c.x, c.y, c.z, c.amp, rows=rows)
+    got = _record(c, zw, n)
+    e = _nrms(got[rows], ref)
+    say(f"  nrms {e:.3e}")
+    assert e <= TOL
+    assert np.array_equal(got[rows] == 0, ref == 0)
+    assert np.array_equal(_record(c, zw, n), got)
+
+
 @pytest.mark.parametrize("n_small", [1000, 992, 999, 1017])
 def test_record_after_a_larger_cloud_on_the_same_context(n_small):
     """Regression: a smaller cloud recorded on a context whose workspace
