@@ -24,7 +24,8 @@
 //     A sin(2 pi (U + V)) = A sin 2piU cos 2piV + A cos 2piU sin 2piV.
 //
 // Mapping: a workgroup of eight waves owns a tile of 64 columns x 32 rows;
-// a wave owns 4 rows, a lane one column of them.  The workgroup walks the
+// a wave owns a 16 x 16 sub-tile, a lane 4 rows of one column of it.  The
+// workgroup walks the
 // cloud in index order, one group of 1024 points per round, skipping groups
 // whose disc bounding box (made by the constants kernel) misses the tile:
 // each thread tests two points' discs against the tile's box (a
@@ -32,11 +33,12 @@
 // boxes and raw inputs load meanwhile), and the hit points, compacted in
 // index order, go to LDS in batches of up to 32 with their FP64 constants
 // (evaluated from the raw inputs by the one function the culling box also
-// uses).  Per batch the workgroup tabulates in LDS each hit's column terms
-// (dx^2, A cos 2piU, A sin 2piU) for the 64 columns and row terms (dy^2,
-// cos 2piV, sin 2piV) for the 32 rows; then every wave adds the hits to its
-// 4 x 64 samples in index order, branch-free (a sample outside the disc
-// adds zero products).  Every sample's sum is formed in point order by one
+// uses) and the set of sub-tiles the hit's disc can reach (the same FP32
+// test per sub-tile).  Per batch the workgroup tabulates in LDS each hit's
+// column terms (dx^2, A cos 2piU, A sin 2piU) for the 64 columns and row
+// terms (dy^2, cos 2piV, sin 2piV) for the 32 rows; then every wave adds
+// to its 16 x 16 samples, in index order, the hits that can reach them,
+// branch-free (a sample outside the disc adds zero products).  Every sample's sum is formed in point order by one
 // lane: deterministic, with no atomics.  Large clouds reach few tiles with
 // a lot of work each, so their tiles come from a queue drained by
 // persistent workgroups (row-major order, the next free workgroup takes
@@ -54,10 +56,13 @@ namespace cgh {
 namespace {
 
 constexpr int kTileCols = 64;
-constexpr int kWaveRows = 4;
-constexpr int kWaves = 8;
+constexpr int kTileRows = 32;
+constexpr int kSub = 16;                           // a wave's sub-tile: 16 x 16 samples
+constexpr int kSubX = kTileCols / kSub;            // sub-tiles per tile row
+constexpr int kLaneRows = kSub * kSub / 64;        // samples (rows) per lane
+constexpr int kWaves = kSubX * (kTileRows / kSub);
 constexpr int kThreads = 64 * kWaves;
-constexpr int kTileRows = kWaveRows * kWaves;
+static_assert(kWaves == 8 && kLaneRows == 4, "eight waves of 16 x 16 samples");
 constexpr int kPerThread = 2;                      // points a thread tests per round
 constexpr int kRound = kPerThread * kThreads;      // points per round = per group
 static_assert(kRound == kWrmGroup, "a recording round covers one point group");
@@ -173,6 +178,7 @@ struct RecordLds {
     // constants of the batch's hits
     double h_x[kBatch], h_y[kBatch], h_r2[kBatch], h_beta[kBatch], h_cx[kBatch], h_cy[kBatch];
     float h_a[kBatch];
+    uint32_t h_sub[kBatch];              // sub-tiles (waves) the hit's disc can reach
     double rt_dy2[kBatch][kTileRows];
     float2 rt_cs[kBatch][kTileRows];    // (cos 2piV, sin 2piV)
     double ct_dx2[kBatch][kTileCols];
@@ -195,6 +201,7 @@ __device__ __forceinline__ void record_tile(const WrmConsts &wc, int64_t n_point
     auto &h_cx = L.h_cx;
     auto &h_cy = L.h_cy;
     auto &h_a = L.h_a;
+    auto &h_sub = L.h_sub;
     auto &rt_dy2 = L.rt_dy2;
     auto &rt_cs = L.rt_cs;
     auto &ct_dx2 = L.ct_dx2;
@@ -203,15 +210,19 @@ __device__ __forceinline__ void record_tile(const WrmConsts &wc, int64_t n_point
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int row0 = trow0 + wave * kWaveRows;
-    const int col = col0 + lane;
+    // the wave's sub-tile, and the lane's column and first row in it (the
+    // lane's samples: kLaneRows consecutive rows of one column)
+    const int sub_c = (wave % kSubX) * kSub, sub_r = (wave / kSubX) * kSub;
+    const int lc = sub_c + (lane % kSub), lr = sub_r + (lane / kSub) * kLaneRows;
+    const int row0 = trow0 + lr;
+    const int col = col0 + lc;
 
     // the tile's sample centres span [col0, col0 + 63] x [trow0, trow0 + 31]
     const float bx0 = (float)col0, bx1 = (float)(col0 + kTileCols - 1);
     const float by0 = (float)trow0, by1 = (float)(trow0 + kTileRows - 1);
-    float acc_re[kWaveRows], acc_im[kWaveRows];
+    float acc_re[kLaneRows], acc_im[kLaneRows];
 #pragma unroll
-    for (int r = 0; r < kWaveRows; ++r) {
+    for (int r = 0; r < kLaneRows; ++r) {
         acc_re[r] = 0.0f;
         acc_im[r] = 0.0f;
     }
@@ -269,10 +280,12 @@ __device__ __forceinline__ void record_tile(const WrmConsts &wc, int64_t n_point
         while (q < 256) {
             const int64_t base = (w0 + q) * kRound;
             bool hit[kPerThread];
-            float4 hraw[kPerThread];   // this round's raw inputs (the prefetch reuses raw)
+            // this round's boxes and raw inputs (the prefetch reuses box and raw)
+            float4 hbox[kPerThread], hraw[kPerThread];
 #pragma unroll
             for (int k = 0; k < kPerThread; ++k) {
                 hit[k] = box_hit(box[k], bx0, bx1, by0, by1);
+                hbox[k] = box[k];
                 hraw[k] = raw[k];
                 const uint64_t m = __ballot(hit[k]);
                 if (lane == 0)
@@ -313,6 +326,16 @@ __device__ __forceinline__ void record_tile(const WrmConsts &wc, int64_t n_point
                         h_cx[h] = pt.cx;
                         h_cy[h] = pt.cy;
                         h_a[h] = hraw[k].w;
+                        uint32_t sub = 0;
+#pragma unroll
+                        for (int w = 0; w < kWaves; ++w) {
+                            const float sx0 = bx0 + (float)((w % kSubX) * kSub);
+                            const float sy0 = by0 + (float)((w / kSubX) * kSub);
+                            if (box_hit(hbox[k], sx0, sx0 + (float)(kSub - 1), sy0,
+                                        sy0 + (float)(kSub - 1)))
+                                sub |= 1u << w;
+                        }
+                        h_sub[h] = sub;
                     }
                 }
                 __syncthreads();
@@ -338,21 +361,25 @@ __device__ __forceinline__ void record_tile(const WrmConsts &wc, int64_t n_point
                     }
                 }
                 __syncthreads();
-                // branch-free: samples outside the disc add zero products
-#pragma unroll 2
-                for (int h = 0; h < nb; ++h) {
-                    const double dx2 = ct_dx2[h][lane];
-                    const float2 acs = ct_acs[h][lane];
+                // The wave's hits: those whose disc can reach its sub-tile,
+                // in index order; within them branch-free (samples outside
+                // the disc add zero products).
+                uint32_t mine = (uint32_t)__ballot(lane < nb && ((h_sub[lane & (kBatch - 1)] >> wave) & 1u));
+                while (mine) {
+                    const int h = __builtin_ctz(mine);
+                    mine &= mine - 1u;
+                    const double dx2 = ct_dx2[h][lc];
+                    const float2 acs = ct_acs[h][lc];
                     const double r2 = h_r2[h];
-                    double dy2[kWaveRows];
-                    float2 cs[kWaveRows];
+                    double dy2[kLaneRows];
+                    float2 cs[kLaneRows];
 #pragma unroll
-                    for (int r = 0; r < kWaveRows; ++r) {
-                        dy2[r] = rt_dy2[h][wave * kWaveRows + r];
-                        cs[r] = rt_cs[h][wave * kWaveRows + r];
+                    for (int r = 0; r < kLaneRows; ++r) {
+                        dy2[r] = rt_dy2[h][lr + r];
+                        cs[r] = rt_cs[h][lr + r];
                     }
 #pragma unroll
-                    for (int r = 0; r < kWaveRows; ++r) {
+                    for (int r = 0; r < kLaneRows; ++r) {
                         const bool in = dx2 + dy2[r] <= r2;
                         const float c = in ? acs.x : 0.0f, sn = in ? acs.y : 0.0f;
                         acc_re[r] =
@@ -367,7 +394,7 @@ __device__ __forceinline__ void record_tile(const WrmConsts &wc, int64_t n_point
     }
     if (col < n) {
 #pragma unroll
-        for (int r = 0; r < kWaveRows; ++r)
+        for (int r = 0; r < kLaneRows; ++r)
             if (row0 + r < n)
                 dst[(int64_t)(row0 + r) * n + col] = float2{acc_re[r], acc_im[r]};
     }
