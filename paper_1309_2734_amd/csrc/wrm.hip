@@ -67,6 +67,7 @@ constexpr int kPerThread = 2;                      // points a thread tests per 
 constexpr int kRound = kPerThread * kThreads;      // points per round = per group
 static_assert(kRound == kWrmGroup, "a recording round covers one point group");
 constexpr int kBatch = 32;                         // hits tabulated at once
+static_assert(kBatch <= 64, "a batch's constants are one wave's");
 
 // Disc of the point with box b (cx, cy, radius in samples, -) against a
 // sample box: a conservative FP32 test that only decides what to skip.
@@ -179,6 +180,7 @@ struct RecordLds {
     double h_x[kBatch], h_y[kBatch], h_r2[kBatch], h_beta[kBatch], h_cx[kBatch], h_cy[kBatch];
     float h_a[kBatch];
     uint32_t h_sub[kBatch];              // sub-tiles (waves) the hit's disc can reach
+    float4 h_raw[kBatch], h_box[kBatch]; // the hits' raw inputs and culling boxes
     double rt_dy2[kBatch][kTileRows];
     float2 rt_cs[kBatch][kTileRows];    // (cos 2piV, sin 2piV)
     double ct_dx2[kBatch][kTileCols];
@@ -202,6 +204,8 @@ __device__ __forceinline__ void record_tile(const WrmConsts &wc, int64_t n_point
     auto &h_cy = L.h_cy;
     auto &h_a = L.h_a;
     auto &h_sub = L.h_sub;
+    auto &h_raw = L.h_raw;
+    auto &h_box = L.h_box;
     auto &rt_dy2 = L.rt_dy2;
     auto &rt_cs = L.rt_cs;
     auto &ct_dx2 = L.ct_dx2;
@@ -314,29 +318,37 @@ __device__ __forceinline__ void record_tile(const WrmConsts &wc, int64_t n_point
             __syncthreads();   // the masks are read before the next round rewrites them
             for (int b0 = 0; b0 < total; b0 += kBatch) {
                 const int nb = total - b0 < kBatch ? total - b0 : kBatch;
+                // the batch's hits: raw inputs and culling boxes from their
+                // owners, then the FP64 constants and sub-tile sets of all of
+                // them in one pass of the first wave (one lane per hit), not
+                // once in every wave that owns one
 #pragma unroll
                 for (int k = 0; k < kPerThread; ++k) {
                     if (hit[k] && pos[k] >= b0 && pos[k] < b0 + kBatch) {
-                        const int h = pos[k] - b0;
-                        const PointFp64 pt = point_fp64(hraw[k], pitch, lam, zw, half);
-                        h_x[h] = pt.x;
-                        h_y[h] = pt.y;
-                        h_r2[h] = pt.r2;
-                        h_beta[h] = pt.beta;
-                        h_cx[h] = pt.cx;
-                        h_cy[h] = pt.cy;
-                        h_a[h] = hraw[k].w;
-                        uint32_t sub = 0;
-#pragma unroll
-                        for (int w = 0; w < kWaves; ++w) {
-                            const float sx0 = bx0 + (float)((w % kSubX) * kSub);
-                            const float sy0 = by0 + (float)((w / kSubX) * kSub);
-                            if (box_hit(hbox[k], sx0, sx0 + (float)(kSub - 1), sy0,
-                                        sy0 + (float)(kSub - 1)))
-                                sub |= 1u << w;
-                        }
-                        h_sub[h] = sub;
+                        h_raw[pos[k] - b0] = hraw[k];
+                        h_box[pos[k] - b0] = hbox[k];
                     }
+                }
+                __syncthreads();
+                if (tid < nb) {
+                    const float4 rw = h_raw[tid], bx = h_box[tid];
+                    const PointFp64 pt = point_fp64(rw, pitch, lam, zw, half);
+                    h_x[tid] = pt.x;
+                    h_y[tid] = pt.y;
+                    h_r2[tid] = pt.r2;
+                    h_beta[tid] = pt.beta;
+                    h_cx[tid] = pt.cx;
+                    h_cy[tid] = pt.cy;
+                    h_a[tid] = rw.w;
+                    uint32_t sub = 0;
+#pragma unroll
+                    for (int w = 0; w < kWaves; ++w) {
+                        const float sx0 = bx0 + (float)((w % kSubX) * kSub);
+                        const float sy0 = by0 + (float)((w / kSubX) * kSub);
+                        if (box_hit(bx, sx0, sx0 + (float)(kSub - 1), sy0, sy0 + (float)(kSub - 1)))
+                            sub |= 1u << w;
+                    }
+                    h_sub[tid] = sub;
                 }
                 __syncthreads();
                 // the batch's column terms (hits x 64) and row terms (hits x 32)
