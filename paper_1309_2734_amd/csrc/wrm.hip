@@ -66,6 +66,8 @@ static_assert(kWaves == 8 && kLaneRows == 4, "eight waves of 16 x 16 samples");
 constexpr int kPerThread = 2;                      // points a thread tests per round
 constexpr int kRound = kPerThread * kThreads;      // points per round = per group
 static_assert(kRound == kWrmGroup, "a recording round covers one point group");
+constexpr int kMasks = kPerThread * kWaves;        // hit masks of a round
+static_assert((kMasks & (kMasks - 1)) == 0 && kMasks <= 64, "a round's masks are scanned in a wave");
 constexpr int kBatch = 32;                         // hits tabulated at once
 static_assert(kBatch <= 64, "a batch's constants are one wave's");
 
@@ -286,35 +288,40 @@ __device__ __forceinline__ void record_tile(const WrmConsts &wc, int64_t n_point
             bool hit[kPerThread];
             // this round's boxes and raw inputs (the prefetch reuses box and raw)
             float4 hbox[kPerThread], hraw[kPerThread];
+            uint64_t own[kPerThread];   // this wave's hit masks
 #pragma unroll
             for (int k = 0; k < kPerThread; ++k) {
                 hit[k] = box_hit(box[k], bx0, bx1, by0, by1);
                 hbox[k] = box[k];
                 hraw[k] = raw[k];
-                const uint64_t m = __ballot(hit[k]);
+                own[k] = __ballot(hit[k]);
                 if (lane == 0)
-                    masks[k][wave] = m;
+                    masks[k][wave] = own[k];
             }
             q = q + 1 < 256 ? next_group(q + 1) : 256;
             if (q < 256)
                 load_boxes((w0 + q) * kRound);   // in flight while this round's hits add
             __syncthreads();
             // this thread's places among the round's hits (index order
-            // (k, wave, lane)), and their count
-            int pos[kPerThread];
-            int total = 0;
+            // (k, wave, lane)), and their count: lane j of every wave counts
+            // mask j mod 16 (k kWaves + w order) and the counts are scanned
+            // across the lanes
+            const int mi = lane & (kMasks - 1);
+            const int cnt = __builtin_popcountll((&masks[0][0])[mi]);
+            int incl = cnt;
 #pragma unroll
-            for (int k = 0; k < kPerThread; ++k) {
-#pragma unroll
-                for (int w = 0; w < kWaves; ++w) {
-                    const uint64_t mw = masks[k][w];
-                    if (w == wave)
-                        pos[k] = total + (int)__builtin_amdgcn_mbcnt_hi(
-                                             (uint32_t)(mw >> 32),
-                                             __builtin_amdgcn_mbcnt_lo((uint32_t)mw, 0));
-                    total += __builtin_popcountll(mw);
-                }
+            for (int o = 1; o < kMasks; o <<= 1) {
+                const int t = __shfl_up(incl, o, kMasks);
+                if (mi >= o)
+                    incl += t;
             }
+            const int total = __builtin_amdgcn_readfirstlane(__shfl(incl, kMasks - 1));
+            int pos[kPerThread];
+#pragma unroll
+            for (int k = 0; k < kPerThread; ++k)
+                pos[k] = __shfl(incl - cnt, k * kWaves + wave) +
+                         (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(own[k] >> 32),
+                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)own[k], 0));
             __syncthreads();   // the masks are read before the next round rewrites them
             for (int b0 = 0; b0 < total; b0 += kBatch) {
                 const int nb = total - b0 < kBatch ? total - b0 : kBatch;
