@@ -71,8 +71,8 @@ def test_fields_match_fourier_form(n):
     assert e <= TOL
 
 
-def test_in_place_and_repeated_runs():
-    n = 256
+@pytest.mark.parametrize("n", [256, 2048])       # column passes; row passes and transposes
+def test_in_place_and_repeated_runs(n):
     u = field(n, 3)
     p, lam, z = 6e-6, 473e-9, 0.03
     ref = oracle.diffraction_fft(u.astype(np.complex128), p, lam, z)
@@ -125,12 +125,14 @@ def test_run_argument_checks():
     plan.close()
 
 
-def test_graph_replays_match_eager():
+@pytest.mark.parametrize("n", [512, 2048])
+def test_graph_replays_match_eager(n):
     """A run captured into a HIP graph (torch's graph capture) replays the
     eager result bit for bit, with other eager diffraction work and
-    synchronisations between the replays."""
+    synchronisations between the replays (both pipelines: column passes up
+    to n = 1024, row passes and transposes above)."""
     import torch
-    n, p, lam, z = 512, 8e-6, 532e-9, 0.04
+    p, lam, z = 8e-6, 532e-9, 0.04
     u = torch.from_numpy(field(n, 11)).cuda()
     plan = cgh.FresnelPlan(n, p, lam, z)
     eager = torch.empty_like(u)

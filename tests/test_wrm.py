@@ -191,6 +191,34 @@ def test_wrm_compute_matches_oracle_composition(w, h, n, zw):
     ctx.close()
 
 
+def test_wrm_compute_full_size(monkeypatch):
+    """The whole method at the workload's sizes: 1920 x 1080 hologram, 2048^2
+    plane (the diffraction's row passes and transposes, in place), 5000
+    points recorded in 3 forced chunks, against the oracle's full-plane
+    step 1 and FP64 Fourier form."""
+    import torch
+    c = cghgen.make_wrm(5000)
+    zw, n = cghgen.WRM_PLANE_Z, cghgen.WRM_PLANE_N
+    monkeypatch.setenv("CGH_WRM_CHUNKS", "3")
+    say("compute 1920x1080 on 2048, N=5000 in 3 chunks")
+    u = oracle.wrm_record(n, c.pitch, c.wavelength, zw, c.x, c.y, c.z, c.amp)
+    o = oracle.diffraction_fft(u, c.pitch, c.wavelength, zw)
+    oy, ox = (n - c.height) // 2, (n - c.width) // 2
+    ref = o[oy:oy + c.height, ox:ox + c.width].real
+    ctx = cgh.Context(c.width, c.height, c.pitch, c.wavelength)
+    ctx.upload_cloud(c)
+    plan = cgh.FresnelPlan(n, c.pitch, c.wavelength, zw)
+    field = torch.empty((n, n), dtype=torch.complex64, device="cuda")
+    out = torch.empty((c.height, c.width), device="cuda")
+    ctx.wrm_compute(plan, field, out)
+    torch.cuda.synchronize()
+    e = oracle.nrms(out.cpu().numpy().astype(np.float64), ref)
+    say(f"  nrms {e:.3e}")
+    assert e <= TOL
+    plan.close()
+    ctx.close()
+
+
 def test_wrm_compute_argument_checks():
     import torch
     ctx = cgh.Context(48, 40, 8e-6, 532e-9)
