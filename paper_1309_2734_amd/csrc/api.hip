@@ -1446,6 +1446,9 @@ cgh_status wrm_record(cgh_ctx *c, double zw, int n, float2 *field, hipStream_t s
         if (v >= 1 && v <= 16 && np > kWrmQueueMinPoints)
             chunks = v;
     }
+    // chunks 1 .. chunks-1 take an n x n plane of workspace each, within the budget
+    const size_t plane = (size_t)n * n * sizeof(float2);
+    chunks = (int)std::min<size_t>((size_t)chunks, 1 + workspace_budget() / plane);
     float2 *parts = nullptr;
     if (chunks > 1) {
         CGH_HIP(ensure_ws(c, c->partials, (size_t)(chunks - 1) * n * n * sizeof(float2)),

@@ -112,16 +112,20 @@ def test_record_full_size_workload(n_pts, step):
     assert np.array_equal(a, got)              # bitwise repeatable
 
 
-@pytest.mark.parametrize("chunks", [2, 3, 7])
-def test_record_point_chunks(chunks, monkeypatch):
+@pytest.mark.parametrize("chunks,budget", [(2, None), (3, None), (7, None), (4, 40 << 20)])
+def test_record_point_chunks(chunks, budget, monkeypatch):
     """Clouds above 4096 points are recorded in chunks of consecutive point
     groups, each into a plane of its own, the planes then added in chunk
     order.  Forced chunk counts on the 10^4-point workload (10 groups; 7
-    chunks leaves chunks of one and of two groups) against the oracle on
-    rows at a stride coprime to the tiles, and bitwise repeatable."""
+    chunks leaves chunks of one and of two groups; 4 chunks under a 40 MiB
+    workspace budget, which holds one extra 2048^2 plane, run as 2) against
+    the oracle on rows at a stride coprime to the tiles, and bitwise
+    repeatable."""
     c = cghgen.make_wrm(10000)
     zw, n = cghgen.WRM_PLANE_Z, cghgen.WRM_PLANE_N
     monkeypatch.setenv("CGH_WRM_CHUNKS", str(chunks))
+    if budget:
+        monkeypatch.setenv("CGH_WORKSPACE_BYTES", str(budget))
     rows = np.arange(7, n, 29)
     say(f"record N=10000 in {chunks} chunks, {len(rows)} rows")
     ref = oracle.wrm_record(n, c.pitch, c.wavelength, zw, c.x, c.y, c.z, c.amp, rows=rows)
