@@ -137,6 +137,48 @@ def test_record_point_chunks(chunks, budget, monkeypatch):
     assert np.array_equal(_record(c, zw, n), got)
 
 
+def test_record_graph_replays_match_eager():
+    """A recording of 30,000 points (tile queue, 2 chunk planes and their
+    sum) captured into a HIP graph once the workspace has grown replays the
+    eager plane bit for bit, with other eager recording work and
+    synchronisations between the replays (the queue counter is reset by a
+    kernel, not a memset)."""
+    import torch
+    c = cghgen.make_wrm(30000)
+    zw, n = cghgen.WRM_PLANE_Z, cghgen.WRM_PLANE_N
+    ctx = cgh.Context(c.width, c.height, c.pitch, c.wavelength)
+    ctx.upload_cloud(c)
+    eager = torch.empty((n, n), dtype=torch.complex64, device="cuda")
+    ctx.wrm_record(zw, eager)
+    torch.cuda.synchronize()
+    ref = eager.cpu().numpy()
+    other = cgh.Context(c.width, c.height, c.pitch, c.wavelength)
+    other.upload_cloud(cghgen.make_wrm(1000))
+    scratch = torch.empty_like(eager)
+    out = torch.empty_like(eager)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(side):
+        ctx.wrm_record(zw, out, side)                     # warm-up on the side stream
+        side.synchronize()
+        with torch.cuda.graph(g, stream=side):
+            ctx.wrm_record(zw, out, side)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        say(f"recording graph replay {rep}")
+        out.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), ref), f"replay {rep}"
+        other.wrm_record(zw, scratch)                     # eager work between replays
+        torch.cuda.synchronize()
+    del g
+    other.close()
+    ctx.close()
+
+
 @pytest.mark.parametrize("n_small", [1000, 992, 999, 1017])
 def test_record_after_a_larger_cloud_on_the_same_context(n_small):
     """Regression: a smaller cloud recorded on a context whose workspace
