@@ -107,6 +107,11 @@ TRAFFIC = [
      "sha": "a2c8df779d41e487", "fetch_kib": 776157.0, "write_kib": 8100.0},
     {"kernel": "direct_fp32", "plan": "16", "src": "paper_1309_2734_amd/csrc/direct.hip",
      "sha": "a2c8df779d41e487", "fetch_kib": 473997.4, "write_kib": 8100.0},
+    # the persistent batch GEMM's two launches (one per frame group) of one
+    # 64-frame batch, summed
+    {"kernel": "gemm_split_mfma_batch", "plan": "384,192,4,2,2",
+     "src": "paper_1309_2734_amd/csrc/gemm.hip", "sha": "dcb455c64a307a95",
+     "fetch_kib": 20629177.3, "write_kib": 518476.1},
     # the kernels of one diffraction, summed (n = 1024: two column passes;
     # n = 8192: row pass, transpose, row pass, transpose)
     {"kernel": "fresnel_diffraction", "plan": "1024", "src": "paper_1309_2734_amd/csrc/fresnel.hip",
@@ -115,6 +120,7 @@ TRAFFIC = [
      "sha": "135fcc6b9fcdd374", "fetch_kib": 1065685.7, "write_kib": 2097152.1},
 ]
 TRAFFIC_PLANS = {"gemm_split_mfma": ["384,192,4,2,2,8", "192,384,2,4,2,8"],
+                 "gemm_split_mfma_batch": ["384,192,4,2,2"],
                  "direct_fp32": ["8", "16"], "fresnel_diffraction": ["1024", "8192"]}
 
 # the paper's wavefront-recording times on its K20 (Table 8; context only)
@@ -124,6 +130,9 @@ PAPER_TABLE8_GPU_S = {"1000": 0.029, "10000": 0.030, "100000": 0.035}
 def _plan_in_tuned(kernel: str, plan: str, tuned) -> bool:
     if kernel == "fresnel_diffraction":
         return plan == tuned
+    if kernel == "gemm_split_mfma_batch":
+        bm, bn, wm, wn, st = plan.split(",")
+        return bool(tuned and f"bm={bm} bn={bn} waves={wm}x{wn} stages={st} " in tuned)
     if kernel.startswith("direct"):
         # the recorded traffic is that of an unsplit launch
         unsplit = bool(tuned and ("splits=1 " in tuned or "splits=0 " in tuned))
@@ -346,7 +355,9 @@ def bench_batch(args, torch, cghgen, cgh):
            "mode": "split_fp16", "ms_per_batch": ms, "pp_per_s": pp / (ms * 1e-3),
            "launch": "hipGraph replay", "tuned": tuned, "kernels_ms_per_batch": kms,
            "roofline": _mfma_roofline(12 * pp, gemm_ms, PEAK_MFMA_FP16_TFLOPS,
-                                      "gemm_split_mfma_batch") if gemm_ms else None}
+                                      "gemm_split_mfma_batch",
+                                      traffic_bytes("gemm_split_mfma_batch", tuned))
+                       if gemm_ms else None}
 
     def check():
         import oracle
@@ -740,8 +751,10 @@ def traffic_driver(torch, cghgen, cgh) -> int:
     --traffic-driver`: the per-launch counters of the split-BF16 GEMM in each recorded
     launch shape (3 computes each), of the direct kernel at each recorded row count
     (2 computes each), of the four kernels of a Fresnel diffraction at each recorded
-    size (2 runs), of the wavefront recording of 10^5 points (2 runs), and of a plain
-    256 MiB device copy (3 copies) whose true byte counts calibrate them."""
+    size (2 runs), of the wavefront recording of 10^5 points (2 runs), of the 64-frame
+    batch's persistent GEMM in each recorded shape (one eager batch: one launch per
+    frame group), and of a plain 256 MiB device copy (3 copies) whose true byte counts
+    calibrate them."""
     c = cghgen.make_config(2)
     ctx = cgh.Context(c.width, c.height, c.pitch, c.wavelength)
     ctx.upload_cloud(c)
@@ -784,6 +797,20 @@ def traffic_driver(torch, cghgen, cgh) -> int:
     wctx.close()
     del field
     log("traffic driver: wavefront recording, 1e5 points")
+    b = cghgen.make_batch(64)
+    frames = cgh.batch_frames(b)
+    bctx = cgh.Context(b.width, b.height, b.pitch, 532e-9)
+    bctx.upload_cloud(b)
+    bout = torch.empty((len(frames), b.height, b.width), device="cuda:0")
+    bctx.profile(True)                      # profiled calls run eagerly (no graph)
+    for plan in TRAFFIC_PLANS["gemm_split_mfma_batch"]:
+        os.environ["CGH_GEMM_PLAN"] = plan
+        bctx.batch_compute(frames, bout, cgh.SPLIT_FP16)
+        torch.cuda.synchronize()
+        log(f"traffic driver: batch plan {plan}")
+    os.environ.pop("CGH_GEMM_PLAN", None)
+    bctx.close()
+    del bout
     src = torch.ones(64 << 20, device="cuda:0")       # 256 MiB of float32
     dst = torch.empty_like(src)
     for _ in range(3):
