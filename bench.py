@@ -203,7 +203,7 @@ def measured_clock_mhz(run, sync, seconds: float = 0.5):
         return None
     return {"mean": sum(busy) / len(busy), "median": busy[len(busy) // 2], "min": busy[0],
             "max": busy[-1], "samples": len(busy), "source": "pp_dpm_sclk, sampled every ~2 ms "
-            "while the step repeats for ~0.5 s after its timing"}
+            f"while the step repeats for ~{seconds:g} s after its timing"}
 
 
 def _events(torch, stream):
@@ -344,6 +344,9 @@ def bench_batch(args, torch, cghgen, cgh):
     side.synchronize()
     kms = {k: v[1] / 2 for k, v in kern.items()}
     gemm_ms = kms.get("gemm_split_mfma_batch")
+    # the shader clock while the batch repeats (a sustained matrix-core load)
+    clock = measured_clock_mhz(lambda: ctx.batch_compute(frames, out, mode, stream=side),
+                               side.synchronize, seconds=1.0)
     cols, rows = cghgen.strided_pixels(b.width, b.height, 8)
     got = out.cpu().numpy()[:, rows][:, :, cols].astype(np.float64)
     ctx.close()
@@ -354,10 +357,14 @@ def bench_batch(args, torch, cghgen, cgh):
                        f"[1e3,5e4] (seeds 400+f), {int(b.counts.sum())} points",
            "mode": "split_fp16", "ms_per_batch": ms, "pp_per_s": pp / (ms * 1e-3),
            "launch": "hipGraph replay", "tuned": tuned, "kernels_ms_per_batch": kms,
+           "clock_mhz": clock,
            "roofline": _mfma_roofline(12 * pp, gemm_ms, PEAK_MFMA_FP16_TFLOPS,
                                       "gemm_split_mfma_batch",
                                       traffic_bytes("gemm_split_mfma_batch", tuned))
                        if gemm_ms else None}
+    if res["roofline"] and clock:
+        res["roofline"]["frac_at_measured_clock"] = (
+            res["roofline"]["frac"] * CLOCK_HZ / (clock["median"] * 1e6))
 
     def check():
         import oracle
