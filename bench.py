@@ -758,7 +758,8 @@ def traffic_driver(torch, cghgen, cgh) -> int:
     --traffic-driver`: the per-launch counters of the split-BF16 GEMM in each recorded
     launch shape (3 computes each), of the direct kernel at each recorded row count
     (2 computes each), of the four kernels of a Fresnel diffraction at each recorded
-    size (2 runs), of the wavefront recording of 10^5 points (2 runs), of the 64-frame
+    size (2 runs), of the exact spherical wave (2 computes, unsplit), of the
+    wavefront recording of 10^5 points (2 runs), of the 64-frame
     batch's persistent GEMM in each recorded shape (one eager batch: one launch per
     frame group), and of a plain 256 MiB device copy (3 copies) whose true byte counts
     calibrate them."""
@@ -781,6 +782,10 @@ def traffic_driver(torch, cghgen, cgh) -> int:
         torch.cuda.synchronize()
         log(f"traffic driver: direct rows {rows}")
     os.environ.pop("CGH_DIRECT_ROWS", None)
+    for _ in range(2):                              # the exact spherical wave, default shape
+        ctx.compute(out, cgh.SPHERICAL_FP32)
+    torch.cuda.synchronize()
+    log("traffic driver: spherical")
     os.environ.pop("CGH_DIRECT_SPLITS", None)
     for n in TRAFFIC_PLANS["fresnel_diffraction"]:
         g = torch.Generator(device="cuda:0").manual_seed(int(n))
