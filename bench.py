@@ -756,7 +756,8 @@ def bench_vendor_gemm(args, torch, kblocks_points: int):
 def traffic_driver(torch, cghgen, cgh) -> int:
     """Kernel sequence for `rocprofv3 --pmc FETCH_SIZE|WRITE_SIZE -- python bench.py
     --traffic-driver`: the per-launch counters of the split-BF16 GEMM in each recorded
-    launch shape (3 computes each), of the direct kernel at each recorded row count
+    launch shape (3 computes each), of the one-product FP16 GEMM in the first of them
+    (2 computes), of the direct kernel at each recorded row count
     (2 computes each), of the four kernels of a Fresnel diffraction at each recorded
     size (2 runs), of the exact spherical wave (2 computes, unsplit), of the
     wavefront recording of 10^5 points (2 runs), of the 64-frame
@@ -773,6 +774,11 @@ def traffic_driver(torch, cghgen, cgh) -> int:
             ctx.compute(out, cgh.SPLIT_BF16)
         torch.cuda.synchronize()
         log(f"traffic driver: split_bf16 plan {plan}")
+    os.environ["CGH_GEMM_PLAN"] = TRAFFIC_PLANS["gemm_split_mfma"][0]
+    for _ in range(2):                              # one product, FP16, the same shape
+        ctx.compute(out, cgh.FP16)
+    torch.cuda.synchronize()
+    log("traffic driver: fp16")
     os.environ.pop("CGH_GEMM_PLAN", None)
     os.environ["CGH_DIRECT_SPLITS"] = "1"           # the recorded launches are unsplit
     for rows in TRAFFIC_PLANS["direct_fp32"]:
