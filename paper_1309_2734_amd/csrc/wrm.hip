@@ -25,27 +25,28 @@
 //
 // Mapping: a workgroup of eight waves owns a tile of 64 columns x 32 rows;
 // a wave owns a 16 x 16 sub-tile, a lane 4 rows of one column of it.  The
-// workgroup walks the
-// cloud in index order, one group of 1024 points per round, skipping groups
-// whose disc bounding box (made by the constants kernel) misses the tile:
-// each thread tests two points' discs against the tile's box (a
-// conservative FP32 test that only decides what to skip; the next round's
-// boxes and raw inputs load meanwhile), and the hit points, compacted in
-// index order, go to LDS in batches of up to 32 with their FP64 constants
-// (evaluated from the raw inputs by the one function the culling box also
-// uses) and the set of sub-tiles the hit's disc can reach (the same FP32
-// test per sub-tile).  Per batch the workgroup tabulates in LDS each hit's
-// column terms (dx^2, A cos 2piU, A sin 2piU) for the 64 columns and row
-// terms (dy^2, cos 2piV, sin 2piV) for the 32 rows; then every wave adds
-// to its 16 x 16 samples, in index order, the hits that can reach them,
-// branch-free (a sample outside the disc adds zero products).  Every sample's sum is formed in point order by one
-// lane: deterministic, with no atomics.  Large clouds reach few tiles with
-// a lot of work each, so their tiles come from a queue drained by
-// persistent workgroups (row-major order, the next free workgroup takes
-// the next item), and their points are cut into a few chunks of
-// consecutive groups: a (tile, chunk) item is one workgroup's, each chunk
-// is recorded as a plane of its own, and the planes are added in chunk
-// order afterwards (still one fixed order per sample).
+// workgroup walks the cloud in index order, one group of 1024 points per
+// round, skipping groups whose disc bounding box (made by the constants
+// kernel) misses the tile: each thread tests two points' discs against the
+// tile's box (a conservative FP32 test that only decides what to skip; the
+// next round's boxes and raw inputs load meanwhile), and the hit points,
+// compacted in index order (their places from a shuffle scan of the
+// round's 16 hit-mask counts), go to LDS in batches of up to 32.  The first
+// wave evaluates a batch's FP64 constants, one lane per hit, from the raw
+// inputs (by the one function the culling box also uses), and the set of
+// sub-tiles each hit's disc can reach (the same FP32 test per sub-tile).
+// Per batch the workgroup tabulates in LDS each hit's column terms (dx^2,
+// A cos 2piU, A sin 2piU) for the 64 columns and row terms (dy^2, cos 2piV,
+// sin 2piV) for the 32 rows; then every wave adds to its 16 x 16 samples,
+// in index order, the hits that can reach them, branch-free (a sample
+// outside the disc adds zero products).  Every sample's sum is formed in
+// point order by one lane: deterministic, with no atomics.  Large clouds
+// reach few tiles with a lot of work each, so their tiles come from a
+// queue drained by persistent workgroups (row-major order, the next free
+// workgroup takes the next item), and their points are cut into a few
+// chunks of consecutive groups: a (tile, chunk) item is one workgroup's,
+// each chunk is recorded as a plane of its own, and the planes are added
+// in chunk order afterwards (still one fixed order per sample).
 #pragma clang fp contract(off)
 
 #include <algorithm>
