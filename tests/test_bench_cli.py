@@ -21,3 +21,35 @@ def test_world_size_above_one_is_refused():
                        text=True, timeout=120, env=env)
     assert p.returncode == 2
     assert "--gpus must be 1" in p.stderr
+
+
+def test_recorded_traffic_holds_only_for_its_source_and_shape():
+    """A counter-measured HBM traffic entry is reported only for the launch
+    shape it was taken on and while its kernel source is unchanged (a
+    changed source reads as no record, never as stale bytes)."""
+    import hashlib
+    import sys
+    sys.path.insert(0, ROOT)
+    import bench
+
+    def current(kernel):
+        for t in bench.TRAFFIC:
+            if t["kernel"] == kernel:
+                with open(os.path.join(bench.ROOT, t["src"]), "rb") as f:
+                    return hashlib.sha256(f.read()).hexdigest()[:16] == t["sha"]
+        return False
+
+    split = "gfx950/1920x1080/mode1/kb10: bm=384 bn=192 waves=4x2 stages=2 splits=8 rows=0 1 us"
+    batch = "gfx950/1920x1080/mode2/batch/kb12: bm=384 bn=192 waves=4x2 stages=2 rows=0 1 us"
+    # other shapes and sizes never match a record
+    assert bench.traffic_bytes("gemm_split_mfma", split.replace("splits=8", "splits=6")) is None
+    assert bench.traffic_bytes("gemm_split_mfma_batch", batch.replace("bm=384", "bm=192")) is None
+    assert bench.traffic_bytes("fresnel_diffraction", "2048") is None
+    assert bench.traffic_bytes("gemm_split_mfma", None) is None
+    # recorded shapes: the calibrated bytes while the source is the recorded one
+    want = (120352.0 * 2.0 + 64800.3) * 1024.0 if current("gemm_split_mfma") else None
+    assert bench.traffic_bytes("gemm_split_mfma", split) == want
+    got = bench.traffic_bytes("gemm_split_mfma_batch", batch)
+    assert (got is not None and got > 4e10) if current("gemm_split_mfma_batch") else got is None
+    got = bench.traffic_bytes("fresnel_diffraction", "1024")
+    assert (got is not None and got > 3e7) if current("fresnel_diffraction") else got is None
