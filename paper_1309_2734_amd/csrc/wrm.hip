@@ -461,15 +461,27 @@ __global__ __launch_bounds__(kThreads) void k_wrm_record(WrmConsts wc, int64_t n
     }
 }
 
-// field[i] += parts[0][i] + ... in chunk order, two samples per thread.
+// field[i] += parts[0][i] + ... in chunk order, two samples per thread, as
+// one 16-byte access each when `wide` (field and planes 16-byte aligned).
 __global__ __launch_bounds__(256) void k_wrm_sum(float2 *__restrict__ field,
                                                  const float2 *__restrict__ parts, int planes,
-                                                 int64_t samples)
+                                                 int64_t samples, int wide)
 {
     const int64_t i = 2 * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x);
     if (i >= samples)
         return;
-    if (i + 1 < samples) {
+    if (!wide) {
+        const int64_t end = i + 2 < samples ? i + 2 : samples;
+        for (int64_t k = i; k < end; ++k) {
+            float2 a = field[k];
+            for (int c = 0; c < planes; ++c) {
+                const float2 b = parts[(int64_t)c * samples + k];
+                a.x += b.x;
+                a.y += b.y;
+            }
+            field[k] = a;
+        }
+    } else if (i + 1 < samples) {
         float4 a = *(const float4 *)(field + i);
         for (int c = 0; c < planes; ++c) {
             const float4 b = *(const float4 *)(parts + (int64_t)c * samples + i);
@@ -555,8 +567,10 @@ hipError_t launch_wrm_record(const WrmConsts &wc, int64_t n_points, int n, doubl
         return e;
     const int64_t samples = (int64_t)n * n;
     const int64_t threads = (samples + 1) / 2;
+    // the caller's field need only be 8-byte aligned
+    const int wide = (uintptr_t)field % 16 == 0 && (uintptr_t)parts % 16 == 0 && samples % 2 == 0;
     hipLaunchKernelGGL(k_wrm_sum, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, field,
-                       parts, chunks - 1, samples);
+                       parts, chunks - 1, samples, wide);
     return hipGetLastError();
 }
 

@@ -137,6 +137,30 @@ def test_record_point_chunks(chunks, budget, monkeypatch):
     assert np.array_equal(_record(c, zw, n), got)
 
 
+def test_record_point_chunks_into_an_8_byte_aligned_field(monkeypatch):
+    """The chunk planes are added to a caller's field that is only 8-byte
+    aligned (the documented minimum) as they are to an aligned one: the same
+    plane bit for bit."""
+    import torch
+    c = cghgen.make_wrm(10000)
+    zw, n = cghgen.WRM_PLANE_Z, cghgen.WRM_PLANE_N
+    monkeypatch.setenv("CGH_WRM_CHUNKS", "3")
+    say("record N=10000 in 3 chunks into a field at a 16-byte offset + 8")
+    want = _record(c, zw, n)
+    ctx = cgh.Context(c.width, c.height, c.pitch, c.wavelength)
+    ctx.upload_cloud(c)
+    flat = torch.full((n * n + 1,), complex(float("nan"), 0.0), dtype=torch.complex64,
+                      device="cuda")
+    field = flat[1:].view(n, n)
+    assert field.data_ptr() % 16 == 8
+    ctx.wrm_record(zw, field)
+    torch.cuda.synchronize()
+    ctx.close()
+    got = field.cpu().numpy().astype(np.complex128)
+    assert np.isnan(flat[0].real.item())               # the sample before is untouched
+    assert np.array_equal(got, want)
+
+
 def test_record_graph_replays_match_eager():
     """A recording of 30,000 points (tile queue, 2 chunk planes and their
     sum) captured into a HIP graph once the workspace has grown replays the
