@@ -100,9 +100,12 @@ MODE_DTYPE = {"split_bf16": "bf16", "split_fp16": "f16", "fp16": "f16", "direct_
 TRAFFIC_SCALE = {"fetch": 2.0, "write": 1.0}
 TRAFFIC = [
     {"kernel": "gemm_split_mfma", "plan": "384,192,4,2,2,8", "src": "paper_1309_2734_amd/csrc/gemm.hip",
-     "sha": "dcb455c64a307a95", "fetch_kib": 120352.0, "write_kib": 64800.3},
+     "sha": "84eae018c8c7908b", "fetch_kib": 120352.9, "write_kib": 64800.3},
     {"kernel": "gemm_split_mfma", "plan": "192,384,2,4,2,8", "src": "paper_1309_2734_amd/csrc/gemm.hip",
-     "sha": "dcb455c64a307a95", "fetch_kib": 120348.5, "write_kib": 64801.1},
+     "sha": "84eae018c8c7908b", "fetch_kib": 120349.0, "write_kib": 64801.1},
+    # 36 tiles x 7 splits over 8 XCDs: six XCDs each hold tiles of two K ranges
+    {"kernel": "gemm_split_mfma", "plan": "192,320,2,4,2,7", "src": "paper_1309_2734_amd/csrc/gemm.hip",
+     "sha": "84eae018c8c7908b", "fetch_kib": 172166.0, "write_kib": 56982.9},
     {"kernel": "direct_fp32", "plan": "8", "src": "paper_1309_2734_amd/csrc/direct.hip",
      "sha": "a2c8df779d41e487", "fetch_kib": 776157.0, "write_kib": 8100.0},
     {"kernel": "direct_fp32", "plan": "16", "src": "paper_1309_2734_amd/csrc/direct.hip",
@@ -110,8 +113,8 @@ TRAFFIC = [
     # the persistent batch GEMM's two launches (one per frame group) of one
     # 64-frame batch, summed
     {"kernel": "gemm_split_mfma_batch", "plan": "384,192,4,2,2",
-     "src": "paper_1309_2734_amd/csrc/gemm.hip", "sha": "dcb455c64a307a95",
-     "fetch_kib": 20629177.3, "write_kib": 518476.1},
+     "src": "paper_1309_2734_amd/csrc/gemm.hip", "sha": "84eae018c8c7908b",
+     "fetch_kib": 23017475.7, "write_kib": 518476.4},
     # the kernels of one diffraction, summed (n = 1024: two column passes;
     # n = 8192: row pass, transpose, row pass, transpose)
     {"kernel": "fresnel_diffraction", "plan": "1024", "src": "paper_1309_2734_amd/csrc/fresnel.hip",
@@ -119,7 +122,8 @@ TRAFFIC = [
     {"kernel": "fresnel_diffraction", "plan": "8192", "src": "paper_1309_2734_amd/csrc/fresnel.hip",
      "sha": "135fcc6b9fcdd374", "fetch_kib": 1065685.7, "write_kib": 2097152.1},
 ]
-TRAFFIC_PLANS = {"gemm_split_mfma": ["384,192,4,2,2,8", "192,384,2,4,2,8"],
+TRAFFIC_PLANS = {"gemm_split_mfma": ["384,192,4,2,2,8", "192,384,2,4,2,8",
+                                     "192,320,2,4,2,7"],
                  "gemm_split_mfma_batch": ["384,192,4,2,2"],
                  "direct_fp32": ["8", "16"], "fresnel_diffraction": ["1024", "8192"]}
 

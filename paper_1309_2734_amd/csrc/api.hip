@@ -507,9 +507,10 @@ ModeInfo mode_info(int mode)
 // ---------------------------------------------------------------- planning
 // GEMM launch shapes the tuner tries: (BM, BN, waves along M, waves along N,
 // LDS ring depth); each must be built in gemm.hip.
-const int kShapes[][5] = {{192, 384, 2, 4, 2}, {384, 192, 4, 2, 2}, {192, 256, 2, 4, 2},
-                          {256, 256, 2, 4, 2}, {192, 192, 2, 2, 3}, {192, 192, 2, 4, 3},
-                          {128, 256, 2, 4, 2}, {192, 128, 2, 2, 2}, {128, 192, 2, 2, 2}};
+const int kShapes[][5] = {{192, 384, 2, 4, 2}, {384, 192, 4, 2, 2}, {192, 320, 2, 4, 2},
+                          {192, 256, 2, 4, 2}, {256, 256, 2, 4, 2}, {192, 192, 2, 2, 3},
+                          {192, 192, 2, 4, 3}, {128, 256, 2, 4, 2}, {192, 128, 2, 2, 2},
+                          {128, 192, 2, 2, 2}};
 
 // Lines padded to whole tiles of every shape (factor sets are sized for any
 // of them).

@@ -34,7 +34,10 @@
 // Workgroup order: consecutive workgroup ids are dispatched round-robin over
 // the 8 XCDs, so ids are remapped to give each XCD a contiguous run of
 // (split, tile) work -- same K range, neighbouring tiles -- whose operands
-// its L2 shares.
+// its L2 shares.  Tiles are numbered down the columns of tiles, so a run
+// that ends or starts part of the way through a split's tiles (splits that do
+// not divide evenly over the XCDs) covers whole tile columns, sharing their
+// B blocks.
 // Split-K partial tiles go to a workspace and are summed in a fixed order by
 // k_splitk_reduce, so results are bitwise reproducible (no float atomics).
 #include <algorithm>
@@ -311,8 +314,8 @@ __global__ __launch_bounds__(64 * WM * WN, 2) void k_gemm(
     const int64_t n_st = kb_end > kb_begin ? kb_end - kb_begin : 0;
     float *dst = splits == 1 ? out : partials + (int64_t)split * M * N;
     const int64_t ld = splits == 1 ? ldo : (int64_t)N;
-    gemm_tile<BM, BN, WM, WN, PRODUCTS, T, STAGES>(fs, kb_begin, n_st, tile / tiles_n,
-                                                   tile % tiles_n, M, N, dst, ld,
+    gemm_tile<BM, BN, WM, WN, PRODUCTS, T, STAGES>(fs, kb_begin, n_st, tile % tiles_m,
+                                                   tile / tiles_m, M, N, dst, ld,
                                                    splits == 1 && accumulate != 0, lds);
 }
 
@@ -442,6 +445,7 @@ hipError_t launch_tile_batch(const GemmPlan &plan, const FactorSet &fs, const Ba
 #define CGH_GEMM_SHAPES(X)                                                                     \
     X(192, 384, 2, 4, 2)                                                                       \
     X(384, 192, 4, 2, 2)                                                                       \
+    X(192, 320, 2, 4, 2)                                                                       \
     X(192, 256, 2, 4, 2)                                                                       \
     X(256, 256, 2, 4, 2)                                                                       \
     X(192, 192, 2, 2, 3)                                                                       \

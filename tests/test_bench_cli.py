@@ -47,8 +47,18 @@ def test_recorded_traffic_holds_only_for_its_source_and_shape():
     assert bench.traffic_bytes("fresnel_diffraction", "2048") is None
     assert bench.traffic_bytes("gemm_split_mfma", None) is None
     # recorded shapes: the calibrated bytes while the source is the recorded one
-    want = (120352.0 * 2.0 + 64800.3) * 1024.0 if current("gemm_split_mfma") else None
+    rec = next(t for t in bench.TRAFFIC
+               if t["kernel"] == "gemm_split_mfma" and t["plan"] == "384,192,4,2,2,8")
+    want = ((rec["fetch_kib"] * bench.TRAFFIC_SCALE["fetch"] +
+             rec["write_kib"] * bench.TRAFFIC_SCALE["write"]) * 1024.0
+            if current("gemm_split_mfma") else None)
     assert bench.traffic_bytes("gemm_split_mfma", split) == want
+    if want is not None:
+        assert 2.5e8 < want < 5e8      # factor reads and split partials, not more
+    other = split.replace("bm=384 bn=192 waves=4x2", "bm=192 bn=320 waves=2x4").replace(
+        "splits=8", "splits=7")
+    got = bench.traffic_bytes("gemm_split_mfma", other)
+    assert (got is not None and got != want) if current("gemm_split_mfma") else got is None
     got = bench.traffic_bytes("gemm_split_mfma_batch", batch)
     assert (got is not None and got > 4e10) if current("gemm_split_mfma_batch") else got is None
     got = bench.traffic_bytes("fresnel_diffraction", "1024")

@@ -242,10 +242,9 @@ def test_point_chunking_matches_oracle(monkeypatch):
 
 @pytest.mark.parametrize("splits", [0, 2, 9, 11, 24], ids=lambda s: f"splits{s or '_auto'}")
 def test_split_k_counts(splits, monkeypatch):
-    """K split counts across the reduce kernel's load batches of eight
-    partials (9, 11: one whole batch and a ragged one; 24: three; 0: the
-    library's own count: 24 in BF16, 48 in FP32) on a small hologram of many points (one
-    output tile), including a width that leaves the 4-wide reduce path."""
+    """K split counts 2, 9, 11, 24 and the library's own (24 in BF16, 48 in
+    FP32) on a small hologram of many points (one output tile), including a
+    width that leaves the 4-wide reduce path."""
     for w, h in ((96, 80), (97, 80)):
         c0 = cghgen.make_config(1, n=3072)
         c = cghgen.Cloud("splits", w, h, c0.pitch, c0.wavelength, c0.x, c0.y, c0.z, c0.amp)
@@ -554,6 +553,24 @@ def test_tune_full_hd_covers_every_tile_shape():
         got = gpu_hologram(c, mode, ctx)[np.ix_(rows, cols)]
         check("tuned full HD", got, ref, mode)
     ctx.close()
+
+
+@pytest.mark.parametrize("plan", ["192,320,2,4,2,7", "192,320,2,4,2,3"])
+def test_forced_192x320_tiles_full_hd(plan, monkeypatch):
+    """The 192 x 320 tile shape at 1920 x 1080 (6 x 6 tiles, 1152 padded
+    rows; 7 splits of 89-90 K blocks fill 252 workgroups) in every matrix
+    mode, on rows and columns at stride 9 (coprime to the 16 x 16 MFMA
+    blocks and the tiles)."""
+    c = cghgen.make_config(2, n=3000)
+    cols, rows = np.arange(4, c.width, 9), np.arange(2, c.height, 9)
+    key = "c2_3000_stride9"
+    if key not in _REFS:
+        _REFS[key] = oracle.cloud_fresnel(c, cols=cols, rows=rows)
+    monkeypatch.setenv("CGH_GEMM_PLAN", plan)
+    for mode in GEMM_MODES:
+        say(f"plan {plan} {NAMES[mode]} full HD")
+        got = gpu_hologram(c, mode)[np.ix_(rows, cols)]
+        check(f"plan {plan}", got, _REFS[key], mode)
 
 
 # ------------------------------------------------------------ error paths
