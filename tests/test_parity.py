@@ -513,6 +513,31 @@ def test_batch_full_size_frames(mode):
     ctx.close()
 
 
+@pytest.mark.parametrize("mode", (cgh.SPLIT_FP16, cgh.FP16), ids=["split_fp16", "fp16"])
+def test_batch_forced_192x320_tiles(mode, monkeypatch):
+    """The persistent batch launch with 192 x 320 tiles (6 x 6 per 1920 x 1080
+    frame): the first three frames of the batch workload on rows and columns
+    at stride 7 (coprime to the MFMA blocks and the tiles)."""
+    import torch
+    monkeypatch.setenv("CGH_GEMM_PLAN", "192,320,2,4,2,0")
+    b = cghgen.make_batch(n_frames=3)
+    frames = cgh.batch_frames(b)
+    say(f"batch 3 x 1920x1080 N={list(b.counts)} {NAMES[mode]} 192x320 tiles")
+    ctx = cgh.Context(b.width, b.height, b.pitch, 532e-9)
+    ctx.upload_cloud(b)
+    out = torch.empty((len(frames), b.height, b.width), device="cuda")
+    ctx.batch_compute(frames, out, mode)
+    torch.cuda.synchronize()
+    cols, rows = np.arange(3, b.width, 7), np.arange(1, b.height, 7)
+    for f, (o, n, lam) in enumerate(frames):
+        sl = slice(o, o + n)
+        ref = oracle.fresnel(b.width, b.height, b.pitch, lam, b.x[sl], b.y[sl], b.z[sl],
+                             b.amp[sl], cols=cols, rows=rows)
+        got = out[f].cpu().numpy().astype(np.float64)[np.ix_(rows, cols)]
+        check(f"192x320 batch frame {f} N={n}", got, ref, mode)
+    ctx.close()
+
+
 def test_tune_picks_a_plan_and_caches_it(tmp_path, monkeypatch):
     import torch
     cache = tmp_path / "tune.jsonl"
