@@ -566,6 +566,68 @@ def bench_large(args, torch, cghgen, cgh):
     return res, check
 
 
+SMALL_MODES = ("direct_fp32", "split_bf16", "separable_fp32")
+
+
+def bench_small(args, torch, cghgen, cgh):
+    """The small cloud of the plain method -- 256 x 256, 128 points (8 um,
+    632.8 nm) -- in direct FP32 (the form it is specified for) and, beside
+    it, split BF16 and FP32 separable: 3 warm-ups, then 20 steps each timed
+    with HIP events (median and mean).  A launch of this size is bound by
+    launch latency, not by the kernels' arithmetic.  NRMS and max error
+    against the FP64 oracle on the full grid."""
+    c = cghgen.make_config(1)
+    W, H, N = c.width, c.height, c.n
+    pp = W * H * N
+    ctx = cgh.Context(W, H, c.pitch, c.wavelength, device=0)
+    ctx.upload_cloud(c)
+    out = torch.empty((H, W), dtype=torch.float32, device="cuda:0")
+    stream = torch.cuda.current_stream()
+    modes = {}
+    for m in SMALL_MODES:
+        mode = cgh.MODES[m]
+        for _ in range(3):
+            ctx.compute(out, mode, stream)
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(20):
+            e0, e1 = _events(torch, stream)
+            ctx.compute(out, mode, stream)
+            e1.record(stream)
+            e1.synchronize()
+            times.append(e0.elapsed_time(e1))
+        med = float(np.median(times))
+        modes[m] = {"ms_per_step_median": med, "ms_per_step_mean": float(np.mean(times)),
+                    "pp_per_s": pp / (med * 1e-3),
+                    "_got": out.cpu().numpy().astype(np.float64)}
+        log(f"small {m}: {med:.4f} ms/step (median of 20), {pp / (med * 1e-3):.3e} pp/s")
+    ctx.close()
+    res = {f"{W}x{H}_{N}": {
+        "workload": (f"{W}x{H} hologram, {N} points, pitch {c.pitch * 1e6:g} um, "
+                     f"{c.wavelength * 1e9:g} nm, x,y ~ U(+-1 mm), z ~ U[0.1,0.2] m, "
+                     f"A ~ U[0,1] (seed 1)"),
+        "point_pixels_per_step": pp, "evaluation_set": "the full grid", "modes": modes,
+        "_cloud": c}}
+
+    def check():
+        import oracle
+        threads = oracle.host_threads()
+        for key, e in res.items():
+            cl = e.pop("_cloud")
+            t0 = time.perf_counter()
+            ref = oracle.cloud_fresnel(cl, threads=threads)
+            dt = time.perf_counter() - t0
+            e["cpu_oracle"] = _oracle_rate(pp, dt, threads,
+                                           f"the full {W}x{H} grid, all {N} points: "
+                                           f"{pp:.3e} point*pixels in {dt:.3f} s")
+            for m, r in e["modes"].items():
+                got = r.pop("_got")
+                r["nrms"] = oracle.nrms(got, ref)
+                r["max_err"] = oracle.max_err(got, ref)
+                log(f"small {key} {m}: nrms {r['nrms']:.3e} max {r['max_err']:.3e}")
+    return res, check
+
+
 def bench_wrm(args, torch, cghgen, cgh):
     """The wavefront-recording method (Section 2.3, Table 8's conditions:
     1920 x 1080 hologram, 8 um, 10^3 .. 10^5 points): per call, the recording
@@ -861,6 +923,8 @@ def main() -> int:
                     help="skip the Fresnel-diffraction side measurement")
     ap.add_argument("--no-large", action="store_true",
                     help="skip the 2048x2048 / 4096x4096 side measurement")
+    ap.add_argument("--no-small", action="store_true",
+                    help="skip the 256x256, 128-point side measurement")
     ap.add_argument("--no-wrm", action="store_true",
                     help="skip the wavefront-recording side measurement")
     ap.add_argument("--batch-frames", type=int, default=64,
@@ -900,6 +964,8 @@ def main() -> int:
         legs["batch"] = bench_batch(args, torch, cghgen, cgh)
     if not args.no_kinoform:
         legs["kinoform"] = bench_kinoform(args, torch, cghgen, cgh)
+    if not args.no_small:
+        legs["small"] = bench_small(args, torch, cghgen, cgh)
     if not args.no_large:
         legs["large"] = bench_large(args, torch, cghgen, cgh)
     if not args.no_wrm:
@@ -957,7 +1023,7 @@ def main() -> int:
             check()
     for r in results.values():
         r.pop("_sample", None)
-    for name in ("large",):
+    for name in ("small", "large"):
         if name in legs:
             for e in legs[name][0].values():
                 e.pop("_cloud", None)
