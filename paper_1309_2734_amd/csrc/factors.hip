@@ -31,20 +31,19 @@
 namespace cgh {
 namespace {
 
+// A (cos, sin) pair in the storage type, converted as one two-wide vector
+// (round to nearest even; one packed convert where the target has it).
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 template <typename T>
-__device__ __forceinline__ T to_t(float v);
-template <>
-__device__ __forceinline__ __bf16 to_t<__bf16>(float v) { return (__bf16)v; }
-template <>
-__device__ __forceinline__ _Float16 to_t<_Float16>(float v) { return (_Float16)v; }
-template <>
-__device__ __forceinline__ float to_t<float>(float v) { return v; }
+struct PairOf {
+    typedef T type __attribute__((ext_vector_type(2)));
+};
 
-// one lane's 16 bytes of a block
+// one lane's 16 bytes of a block: consecutive (cos, sin) pairs
 template <typename T>
 struct alignas(16) Vec16B {
     static constexpr int kValues = 16 / sizeof(T);
-    T v[kValues];
+    typename PairOf<T>::type pair[kValues / 2];
 };
 
 // Grid: x = (group of kKBlocks consecutive K blocks) * 64 + lane, y = line
@@ -152,13 +151,12 @@ __global__ __launch_bounds__(256) void k_factors(PointConsts pc, RawPoints rp, i
                 c = 0.0f;
                 s = 0.0f;
             }
-            const T ch = to_t<T>(c), sh = to_t<T>(s);
-            hi.v[2 * p] = ch;
-            hi.v[2 * p + 1] = sh;
-            if (SPLIT) {
-                lo.v[2 * p] = to_t<T>(c - (float)ch);
-                lo.v[2 * p + 1] = to_t<T>(s - (float)sh);
-            }
+            using P2 = typename PairOf<T>::type;
+            const f32x2 v = {c, s};
+            const P2 h = __builtin_convertvector(v, P2);
+            hi.pair[p] = h;
+            if (SPLIT)   // v - hi is exact in FP32
+                lo.pair[p] = __builtin_convertvector(v - __builtin_convertvector(h, f32x2), P2);
         }
         const int64_t slab = (kb0 + b) * fs.slab_blocks();
         out[(slab + hi_blk) * 64 + lane] = hi;
