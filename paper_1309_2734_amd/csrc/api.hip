@@ -560,9 +560,10 @@ std::string batch_tune_key(const cgh_ctx *c, int mode, int64_t max_kblocks)
            std::to_string(mode) + "/batch/kb" + std::to_string(kblock_bucket(max_kblocks));
 }
 
-// Tile shape and split count for an M x N output over `slots` points.
-// CGH_GEMM_PLAN="bm,bn,waves_m,waves_n,stages,splits" overrides the choice
-// (used to sweep shapes; an unsupported shape is ignored, splits 0 = auto).
+// Tile shape and split count for an M x N output over `slots` points: the
+// tuned plan `tuned` when there is one, else
+// CGH_GEMM_PLAN="bm,bn,waves_m,waves_n,stages,splits" (used to sweep shapes;
+// an unsupported shape is ignored, splits 0 = auto), else the default choice.
 Plan plan_gemm(int M, int N, int64_t slots, const ModeInfo &mi, const TuneEntry *tuned = nullptr)
 {
     struct Shape {
