@@ -829,7 +829,9 @@ def traffic_driver(torch, cghgen, cgh) -> int:
     wavefront recording of 10^5 points (2 runs), of the 64-frame
     batch's persistent GEMM in each recorded shape (one eager batch: one launch per
     frame group), and of a plain 256 MiB device copy (3 copies) whose true byte counts
-    calibrate them."""
+    calibrate them.  Tuned plans are not read (a tuned plan would take precedence over
+    the launch shapes set here)."""
+    os.environ.pop("CGH_TUNE_CACHE", None)
     c = cghgen.make_config(2)
     ctx = cgh.Context(c.width, c.height, c.pitch, c.wavelength)
     ctx.upload_cloud(c)
