@@ -681,8 +681,9 @@ def bench_wrm(args, torch, cghgen, cgh):
                           "note": "achieved = point*sample pairs inside the discs over the "
                                   "recording kernel's time (chunk planes and their sum "
                                   "included); peak = 8 VALU issue slots per pair (FP64 disc "
-                                  "test, selects, complex multiply-add); the tiles visit ~3.8x "
-                                  "the pairs inside the discs"},
+                                  "test, selects, complex multiply-add); each wave visits its "
+                                  "16x16 sub-tile for every disc that reaches it, ~1.7x the "
+                                  "pairs inside the discs at 10^5 points"},
              "paper_table8_gpu_ms": PAPER_TABLE8_GPU_S[str(npts)] * 1e3}
         log(f"wrm N={npts}: {ms:.3f} ms per hologram, kernels {kms}")
         res[str(npts)] = r
